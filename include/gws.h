@@ -1,0 +1,211 @@
+/*
+ * gws.h -- C ABI of the MI355X (gfx950) Gaussian Wave Splatting library.
+ *
+ * The library turns a set of in-plane 2D Gaussians into the complex field they produce
+ * at the SLM plane, with the fast (order-invariant transparency) form of alpha wave
+ * blending: every Gaussian's closed-form angular spectrum (Sec. 4.1, Eq. 10) is
+ * multiplied by its colour, opacity and the angular-spectrum transfer function for its
+ * depth (Eq. 3-4 at distance -z), summed per frequency (Sec. 4.2, Eq. 12; Alg. 1 and
+ * Alg. 4 of the supplement) and brought to the SLM plane by one inverse 2D DFT.  It also
+ * gives the exact adjoint of that map (gradients of a real loss with respect to every
+ * Gaussian parameter).
+ *
+ * Conventions (the paper mixes angular and ordinary frequency; these are fixed here):
+ *   - spatial frequency nu in cycles per metre; frequency index m in FFT order, with
+ *     signed index m' = m if 2m < N else m - N and nu = m' / (N * pitch);
+ *   - a Gaussian centred at mu carries the ramp exp(-j 2 pi nu . mu);
+ *   - H(nu, d) = exp(+j 2 pi d sqrt(1/lambda^2 - |nu|^2)) for |nu| < 1/lambda, else 0,
+ *     applied with d = -z_i (the viewer sits at +z);
+ *   - the field sample n (row n_y, column n_x) sits at x = ((n_x - nx/2) px, (n_y - ny/2) py),
+ *     so the SLM centre is pixel (nx/2, ny/2);
+ *   - u_c[n] = 1/(nx ny px py) * sum_m U_c(nu_m) exp(+j 2 pi nu_m . x_n): a z = 0 Gaussian
+ *     with amplitude a and opacity o peaks at a*o.
+ *
+ * Every pointer is a device pointer unless its comment says "host".  The caller owns
+ * every input, output and workspace buffer; the context owns only per-shape plans
+ * (tile order, twiddle tables, DFT matrices), the tuning cache and a small statistics
+ * buffer.  All work is enqueued on the caller's stream (a hipStream_t passed as void*);
+ * no call synchronises the device except gws_get_stats, gws_autotune and gws_create.
+ * One context must not be used from two host threads at once.
+ */
+#ifndef GWS_H
+#define GWS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GWS_ABI_VERSION 1
+#define GWS_MAX_LAMBDA 4
+
+/* Return codes.  Launch-time validation returns the code at once and leaves the
+ * outputs untouched; an asynchronous device fault surfaces at a later call or at the
+ * caller's synchronisation, and gws_last_error() holds its text. */
+typedef enum gws_status {
+    GWS_OK = 0,
+    GWS_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, bad enum value */
+    GWS_ERR_SHAPE = -2,       /* grid not supported: odd, < 16, > 8192, or a prime factor > 5 */
+    GWS_ERR_UNSUPPORTED = -3, /* valid request this build does not implement (exact blending) */
+    GWS_ERR_WORKSPACE = -4,   /* workspace null, misaligned (256 B) or smaller than required */
+    GWS_ERR_NO_DEVICE = -5,   /* no HIP device, or the device is not gfx950 */
+    GWS_ERR_HIP = -6,         /* a HIP runtime call failed; see gws_last_error */
+    GWS_ERR_OOM = -7          /* the context could not allocate a per-shape plan */
+} gws_status;
+
+/* Blending model.  OIT is Eq. 12 (transmittance taken as 1).  EXACT is alpha wave
+ * blending with a spatial transmittance map (Eq. 5-6, Alg. 2): not built yet, every
+ * call with it returns GWS_ERR_UNSUPPORTED. */
+typedef enum gws_blend { GWS_BLEND_OIT = 0, GWS_BLEND_EXACT = 1 } gws_blend;
+
+/* Inverse transform: mixed-radix FP32 FFT, or the DFT as two dense complex GEMMs on the
+ * matrix cores with bf16 hi/lo operand splitting (three products, FP32 accumulation). */
+typedef enum gws_xform { GWS_XFORM_FFT_FP32 = 0, GWS_XFORM_DFT_BF16X3 = 1 } gws_xform;
+
+typedef struct gws_problem {
+    int32_t nx, ny;            /* hologram columns and rows; even, 16..8192, factors 2,3,5 */
+    double pitch_x, pitch_y;   /* SLM pixel pitch in metres, > 0 */
+    int32_t n_lambda;          /* number of wavelengths (colour channels), 1..4 */
+    double lambdas[GWS_MAX_LAMBDA]; /* wavelengths in metres, > 0 */
+    int32_t blend;             /* gws_blend */
+    int32_t xform;             /* gws_xform */
+    double eps_support;        /* spectral-support cut: terms whose Gaussian envelope is below
+                                  eps * (its peak) are skipped; 0 selects 1e-7; must be in
+                                  (0, 1e-3].  The relative L2 error it adds is about eps. */
+    int32_t phase_mode;        /* 0: FP32 phase with exact per-tile FP64 base (default);
+                                  2: also reduce the per-tile base in FP64 for every Gaussian
+                                  (no effect on results beyond rounding; kept for testing) */
+    int32_t tile_config;       /* 0: tuned or default tiling; k > 0: explicit tiling k
+                                  (see gws_tile_config_count) */
+} gws_problem;
+
+/* Gaussians as structure-of-arrays float32 device buffers of length n.  amplitude is
+ * [n_lambda][n] (channel-major).  Covariance is the 2x2 matrix [[cov_xx, cov_xy],
+ * [cov_xy, cov_yy]] in m^2; mean and depth in metres; phase in radians; opacity is used
+ * as given (no sigmoid).  A Gaussian whose covariance is not positive definite or whose
+ * values are not finite is skipped and counted in gws_stats.n_culled; forward also skips
+ * Gaussians with zero opacity or all-zero amplitude (they add exactly nothing). */
+typedef struct gws_gaussians {
+    int64_t n;
+    const float *mean_x, *mean_y, *depth;
+    const float *cov_xx, *cov_xy, *cov_yy;
+    const float *opacity, *amplitude, *phase;
+} gws_gaussians;
+
+typedef struct gws_output {
+    void *field;    /* complex64 [n_lambda][ny][nx], (re, im) interleaved, row-major, x fastest */
+    void *spectrum; /* optional (NULL to skip): complex64 [n_lambda][ny][nx] in FFT index order,
+                       holding U_c(nu_m) * (-1)^(m_x'+m_y') / (nx ny px py), i.e. exactly the
+                       array whose unnormalised inverse DFT is the field */
+} gws_output;
+
+/* Gradient outputs, float32, same layout as the inputs; overwritten, never accumulated.
+ * depth may be NULL to skip the depth gradient; every other pointer is required. */
+typedef struct gws_grads {
+    float *mean_x, *mean_y, *depth;
+    float *cov_xx, *cov_xy, *cov_yy;
+    float *opacity, *amplitude, *phase;
+} gws_grads;
+
+typedef struct gws_stats {
+    int64_t n_input;          /* Gaussians passed to the last forward/backward */
+    int64_t n_culled;         /* skipped (see gws_gaussians) */
+    int64_t n_tiles;          /* frequency tiles of the grid */
+    int64_t n_items;          /* accumulation work items launched */
+    int64_t chunk;            /* candidate Gaussians per work item */
+    int64_t n_tile_gaussian;  /* (tile, Gaussian) pairs evaluated */
+    int64_t n_candidates;     /* (tile, Gaussian) pairs tested */
+    int32_t tile_config;      /* tiling used */
+    int32_t graph_replayed;   /* batched call replayed a captured graph */
+} gws_stats;
+
+typedef struct gws_ctx gws_ctx;
+
+/* ABI version this library was built with (GWS_ABI_VERSION). */
+int gws_abi_version(void);
+
+/* Static text for a status code; never NULL. */
+const char *gws_status_string(gws_status status);
+
+/* Create a context bound to HIP device `device`.  Returns GWS_ERR_NO_DEVICE when there is
+ * no such device or it is not gfx950, GWS_ERR_INVALID_ARG when ctx is NULL.  Allocates a
+ * small statistics buffer on the device. */
+gws_status gws_create(gws_ctx **ctx, int device);
+
+/* Free the context and every plan it holds.  NULL is accepted. */
+gws_status gws_destroy(gws_ctx *ctx);
+
+/* Text of the last error recorded on ctx (empty string if none); ctx may be NULL for the
+ * last error of a call that had no context. */
+const char *gws_last_error(const gws_ctx *ctx);
+
+/* Validate a problem description without touching the device.  Returns the code the
+ * other entry points would return for it. */
+gws_status gws_check_problem(const gws_problem *problem);
+
+/* Bytes of workspace gws_forward / gws_backward need for n Gaussians (host-only; ctx may
+ * be NULL).  The same workspace serves both calls. */
+gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *problem, int64_t n, size_t *bytes);
+
+/* Forward: the field (and optionally the spectrum) of n Gaussians, Eq. 12 + inverse DFT.
+ * Steps on the stream: per-Gaussian preprocessing and keys, depth-within-support-radius
+ * radix sort, binning into frequency tiles, spectrum accumulation, inverse 2D transform. */
+gws_status gws_forward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
+                       const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward: given grad_field = dL/dRe(u) + j dL/dIm(u) (complex64 [n_lambda][ny][nx], the
+ * convention torch uses for complex tensors), write dL/d(parameter) for every Gaussian.
+ * Recomputes preprocessing, sort and binning (no state is kept from gws_forward) and
+ * recomputes every (Gaussian, frequency) term instead of storing it. */
+gws_status gws_backward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
+                        const void *grad_field, const gws_grads *grads,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/* Several independent scenes sharing one problem: scene s owns Gaussians
+ * [offsets[s], offsets[s+1]) of g (offsets is a host array of n_scenes + 1 entries,
+ * offsets[0] = 0, non-decreasing, offsets[n_scenes] = g->n).  Fields are written to
+ * out->field + s * n_lambda*ny*nx complex64 (spectrum likewise if non-NULL).  All scenes
+ * run through one persistent accumulation launch; the whole sequence is captured into a
+ * hipGraph on first use for a given (problem, offsets, pointers) and replayed after. */
+gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,
+                                      const int64_t *offsets, size_t *bytes);
+gws_status gws_forward_batched(gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,
+                               const int64_t *offsets, const gws_gaussians *g, const gws_output *out,
+                               void *workspace, size_t workspace_bytes, void *stream);
+/* grad_field holds n_scenes consecutive fields; grads are per Gaussian of the concatenation. */
+gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,
+                                const int64_t *offsets, const gws_gaussians *g, const void *grad_field,
+                                const gws_grads *grads, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+/* Unnormalised 2D DFT of `batch` complex64 arrays [ny][nx] (in and out may alias):
+ * direction +1: out[n] = sum_m in[m] exp(+j 2 pi m.n/N); -1: exp(-j 2 pi ...).
+ * xform selects the FP32 FFT or the split-bf16 matrix-core DFT.  workspace may be NULL
+ * for the FFT; the bf16 DFT needs gws_dft_workspace_size bytes. */
+gws_status gws_dft_workspace_size(const gws_ctx *ctx, int32_t nx, int32_t ny, int32_t batch,
+                                  int32_t xform, size_t *bytes);
+gws_status gws_dft2d(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t batch, int32_t direction,
+                     int32_t xform, const void *in, void *out, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+/* Number of explicit tilings gws_problem.tile_config may name (1..count). */
+int gws_tile_config_count(void);
+
+/* Time every tiling on the device for this problem with n_hint synthetic Gaussians drawn
+ * on the device, keep the fastest in the context for problems of this shape, and if
+ * cache_path (host string) is non-NULL merge the choice into that JSON file, which later
+ * contexts read at gws_create time if GWS_TUNE_CACHE names it.  Synchronises. */
+gws_status gws_autotune(gws_ctx *ctx, const gws_problem *problem, int64_t n_hint, const char *cache_path,
+                        void *stream);
+
+/* Copy the statistics of the last forward/backward on ctx to *out (host).  Synchronises
+ * the device. */
+gws_status gws_get_stats(gws_ctx *ctx, gws_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWS_H */

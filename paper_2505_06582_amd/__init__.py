@@ -1,0 +1,326 @@
+"""Gaussian Wave Splatting hot path on MI355X (gfx950): thin Python binding of libgws.
+
+The library (``include/gws.h``) does every step of the path on the GPU: per-Gaussian
+preprocessing, the depth / support-radius sort, binning into frequency tiles, the
+order-invariant spectrum accumulation of Eq. 12, the inverse 2D transform, and the
+adjoint.  This module only marshals arguments: torch supplies device memory and the
+stream, and the raw pointers go through ctypes.  If ``libgws.so`` has not been built the
+import of the binding fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import threading
+from typing import Dict, Optional, Sequence
+
+__all__ = ["LIB_PATH", "GwsError", "Problem", "Context", "load_library", "render", "GaussianWaveSplat",
+           "STATUS", "XFORM_FFT_FP32", "XFORM_DFT_BF16X3"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgws.so")
+
+XFORM_FFT_FP32 = 0
+XFORM_DFT_BF16X3 = 1
+BLEND_OIT = 0
+BLEND_EXACT = 1
+MAX_LAMBDA = 4
+
+STATUS = {0: "GWS_OK", -1: "GWS_ERR_INVALID_ARG", -2: "GWS_ERR_SHAPE", -3: "GWS_ERR_UNSUPPORTED",
+          -4: "GWS_ERR_WORKSPACE", -5: "GWS_ERR_NO_DEVICE", -6: "GWS_ERR_HIP", -7: "GWS_ERR_OOM"}
+
+
+class GwsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pitch_x", ctypes.c_double),
+                ("pitch_y", ctypes.c_double), ("n_lambda", ctypes.c_int32),
+                ("lambdas", ctypes.c_double * MAX_LAMBDA), ("blend", ctypes.c_int32), ("xform", ctypes.c_int32),
+                ("eps_support", ctypes.c_double), ("phase_mode", ctypes.c_int32), ("tile_config", ctypes.c_int32)]
+
+
+_fp = ctypes.c_void_p
+
+
+class _Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, _fp) for k in (
+        "mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity", "amplitude", "phase")]
+
+
+class _Output(ctypes.Structure):
+    _fields_ = [("field", _fp), ("spectrum", _fp)]
+
+
+class _Grads(ctypes.Structure):
+    _fields_ = [(k, _fp) for k in ("mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity",
+                                   "amplitude", "phase")]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_input", ctypes.c_int64), ("n_culled", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+                ("n_items", ctypes.c_int64), ("chunk", ctypes.c_int64), ("n_tile_gaussian", ctypes.c_int64),
+                ("n_candidates", ctypes.c_int64), ("tile_config", ctypes.c_int32), ("graph_replayed", ctypes.c_int32)]
+
+
+PARAMS = ("mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity", "amplitude", "phase")
+
+# exported symbol -> (restype, argtypes)
+_SIGNATURES = {
+    "gws_abi_version": (ctypes.c_int, []),
+    "gws_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gws_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    "gws_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "gws_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "gws_check_problem": (ctypes.c_int, [ctypes.POINTER(_Problem)]),
+    "gws_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "gws_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
+                                   ctypes.POINTER(_Output), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gws_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
+                                    ctypes.c_void_p, ctypes.POINTER(_Grads), ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p]),
+    "gws_workspace_size_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]),
+    "gws_forward_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_Gaussians),
+                                           ctypes.POINTER(_Output), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gws_backward_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_Gaussians),
+                                            ctypes.c_void_p, ctypes.POINTER(_Grads), ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_void_p]),
+    "gws_dft_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gws_dft2d": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.c_void_p]),
+    "gws_tile_config_count": (ctypes.c_int, []),
+    "gws_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int64, ctypes.c_char_p,
+                                    ctypes.c_void_p]),
+    "gws_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Stats)]),
+}
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgws.so and declare every entry point.  Raises if it has not been built."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise ImportError("libgws.so is not built (%s); run python -m paper_2505_06582_amd.build" % path)
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in _SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+@dataclasses.dataclass
+class Problem:
+    """Mirror of gws_problem."""
+
+    nx: int
+    ny: int
+    pitch_x: float = 8e-6
+    pitch_y: float = 8e-6
+    lambdas: Sequence[float] = (520e-9,)
+    xform: int = XFORM_FFT_FP32
+    eps_support: float = 0.0
+    phase_mode: int = 0
+    tile_config: int = 0
+    blend: int = BLEND_OIT
+
+    @staticmethod
+    def from_grid(grid, **kw) -> "Problem":
+        return Problem(nx=grid.nx, ny=grid.ny, pitch_x=grid.px, pitch_y=grid.py, lambdas=tuple(grid.lambdas), **kw)
+
+    @property
+    def n_lambda(self) -> int:
+        return len(self.lambdas)
+
+    def _c(self) -> _Problem:
+        p = _Problem()
+        p.nx, p.ny, p.pitch_x, p.pitch_y = self.nx, self.ny, self.pitch_x, self.pitch_y
+        p.n_lambda = len(self.lambdas)
+        for i in range(MAX_LAMBDA):
+            p.lambdas[i] = float(self.lambdas[i]) if i < len(self.lambdas) else 0.0
+        p.blend, p.xform, p.eps_support = self.blend, self.xform, self.eps_support
+        p.phase_mode, p.tile_config = self.phase_mode, self.tile_config
+        return p
+
+
+def _check(status: int, ctx_handle=None):
+    if status != 0:
+        lib = load_library()
+        msg = lib.gws_last_error(ctx_handle)
+        raise GwsError(status, (msg or b"").decode(errors="replace"))
+
+
+def _torch():
+    import torch  # imported lazily so the ABI tests run without touching torch.cuda
+    return torch
+
+
+def _gaussians_struct(g: Dict[str, "object"], n: int) -> _Gaussians:
+    s = _Gaussians()
+    s.n = n
+    for k in PARAMS:
+        t = g[k]
+        if n > 0:
+            if not (t.is_cuda and t.dtype == _torch().float32 and t.is_contiguous()):
+                raise ValueError("%s must be a contiguous float32 CUDA tensor" % k)
+        setattr(s, k, t.data_ptr() if n > 0 else None)
+    return s
+
+
+class Context:
+    """A libgws context on one device, with a cached workspace."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self.lib.gws_create(ctypes.byref(h), device))
+        self.handle = h
+        self._ws = None
+        self.torch_device = torch.device("cuda", device)
+
+    def close(self):
+        if self.handle:
+            self.lib.gws_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
+
+    def workspace(self, nbytes: int):
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.torch_device)
+        return self._ws
+
+    def workspace_size(self, prob: Problem, n: int) -> int:
+        sz = ctypes.c_size_t()
+        _check(self.lib.gws_workspace_size(self.handle, ctypes.byref(prob._c()), n, ctypes.byref(sz)), self.handle)
+        return sz.value
+
+    def forward(self, prob: Problem, g: Dict[str, "object"], want_spectrum: bool = False, out=None):
+        """Field (n_lambda, ny, nx) complex64 (and the DFT-ready spectrum if asked)."""
+        torch = _torch()
+        n = int(g["mean_x"].numel())
+        field = out if out is not None else torch.empty((prob.n_lambda, prob.ny, prob.nx), dtype=torch.complex64,
+                                                        device=self.torch_device)
+        spec = torch.empty_like(field) if want_spectrum else None
+        o = _Output()
+        o.field = field.data_ptr()
+        o.spectrum = spec.data_ptr() if spec is not None else None
+        ws = self.workspace(self.workspace_size(prob, n))
+        gs = _gaussians_struct(g, n)
+        _check(self.lib.gws_forward(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
+        return (field, spec) if want_spectrum else field
+
+    def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True):
+        """dL/d(parameter) for every Gaussian, given dL/dRe u + j dL/dIm u."""
+        torch = _torch()
+        n = int(g["mean_x"].numel())
+        grad_field = grad_field.to(torch.complex64).contiguous()
+        grads = {k: torch.empty_like(g[k]) for k in PARAMS}
+        gr = _Grads()
+        for k in PARAMS:
+            setattr(gr, k, grads[k].data_ptr() if n > 0 else None)
+        if not want_depth:
+            gr.depth = None
+        ws = self.workspace(self.workspace_size(prob, n))
+        gs = _gaussians_struct(g, n)
+        if n == 0:
+            return grads
+        _check(self.lib.gws_backward(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs),
+                                     ctypes.c_void_p(grad_field.data_ptr()), ctypes.byref(gr),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
+        if not want_depth:
+            grads["depth"] = None
+        return grads
+
+    def dft2d(self, x, direction: int, xform: int = XFORM_FFT_FP32, out=None):
+        """Unnormalised 2D DFT of (batch, ny, nx) complex64: exp(+j..) for direction +1."""
+        torch = _torch()
+        x = x.to(torch.complex64).contiguous()
+        b, ny, nx = x.shape
+        out = out if out is not None else torch.empty_like(x)
+        sz = ctypes.c_size_t()
+        _check(self.lib.gws_dft_workspace_size(self.handle, nx, ny, b, xform, ctypes.byref(sz)), self.handle)
+        ws = self.workspace(sz.value) if sz.value else None
+        _check(self.lib.gws_dft2d(self.handle, nx, ny, b, direction, xform, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+                                  ws.numel() if ws is not None else 0, self._stream()), self.handle)
+        return out
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(self.lib.gws_get_stats(self.handle, ctypes.byref(s)), self.handle)
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+
+_ctx_cache: Dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _ctx_cache:
+        _ctx_cache[device] = Context(device)
+    return _ctx_cache[device]
+
+
+class GaussianWaveSplat:
+    """torch.autograd.Function wrapper: field = GWS(params); backward through gws_backward."""
+
+    _fn = None
+
+    @classmethod
+    def function(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(fctx, prob, mean_x, mean_y, depth, cov_xx, cov_xy, cov_yy, opacity, amplitude, phase):
+                    g = dict(mean_x=mean_x, mean_y=mean_y, depth=depth, cov_xx=cov_xx, cov_xy=cov_xy, cov_yy=cov_yy,
+                             opacity=opacity, amplitude=amplitude, phase=phase)
+                    g = {k: v.detach().contiguous() for k, v in g.items()}
+                    fctx.prob = prob
+                    fctx.save_for_backward(*[g[k] for k in PARAMS])
+                    return context(mean_x.device.index or 0).forward(prob, g)
+
+                @staticmethod
+                def backward(fctx, grad_field):
+                    saved = dict(zip(PARAMS, fctx.saved_tensors))
+                    dev = saved["mean_x"].device.index or 0
+                    grads = context(dev).backward(fctx.prob, saved, grad_field,
+                                                  want_depth=fctx.needs_input_grad[3])
+                    return (None,) + tuple(grads[k] if fctx.needs_input_grad[i + 1] else None
+                                           for i, k in enumerate(PARAMS))
+
+            cls._fn = _F
+        return cls._fn
+
+
+def render(prob: Problem, mean_x, mean_y, depth, cov_xx, cov_xy, cov_yy, opacity, amplitude, phase):
+    """Differentiable field of the Gaussians at the SLM plane, (n_lambda, ny, nx) complex64."""
+    return GaussianWaveSplat.function().apply(prob, mean_x, mean_y, depth, cov_xx, cov_xy, cov_yy, opacity,
+                                              amplitude, phase)

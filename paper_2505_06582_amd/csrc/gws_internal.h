@@ -1,0 +1,154 @@
+// Internal declarations shared by the gfx950 kernels and the host side of libgws.
+// Nothing here is part of the C ABI (include/gws.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "gws.h"
+
+namespace gws {
+
+// ---------------------------------------------------------------------------------
+// Frequency tiling.  The centred frequency plane m' in [-nx/2, nx/2) x [-ny/2, ny/2)
+// (index units) is cut into DC-aligned tiles of TILE x TILE frequencies: tile (tx, ty)
+// covers m'_x in [TILE tx, TILE tx + TILE) and likewise in y, clipped to the grid.  A
+// work-group of 4 wavefronts owns one tile; wavefront w owns the SUB x SUB sub-tile
+// (w & 1, w >> 1); lane l of a wavefront owns column l % SUB and rows l / SUB + 4 f for
+// f = 0..F-1 of its sub-tile.
+// ---------------------------------------------------------------------------------
+constexpr int TILE = 32;
+constexpr int SUB = 16;
+constexpr int F = 4;                 // frequencies per lane
+constexpr int WAVES = 4;             // wavefronts per work-group
+constexpr int WG = 64 * WAVES;       // threads per work-group
+constexpr int NBUCKET = 4096;        // support-radius buckets (index units)
+constexpr int BWD_CHUNK = 64;        // Gaussians per backward work item (one per lane)
+constexpr int NACC = 16;             // per-Gaussian adjoint accumulators (padded)
+
+// Per-Gaussian record in sorted order, 64 bytes, written by k_records.
+struct alignas(16) GRec {
+    float alpha, beta2, gamma, z;   // exp2-units quadratic form in index units; depth (m)
+    uint32_t rx, ry;                // ramp fraction frac(mu/(N p) + 1/2) in 0.32 fixed point
+    float rxf, ryf;                 // the same as signed float in [-1/2, 1/2)
+    float kappa[4];                 // carrier frac(phi/2pi - z/lambda_c), revolutions
+    float amp[4];                   // a_c o 2 pi sqrt(det) / (px py nx ny)
+};
+static_assert(sizeof(GRec) == 64, "record must stay 64 B");
+
+// Forward work item: candidates [chunk*CH, min((chunk+1)*CH, L)) of sorted tile k.
+struct Item {
+    int32_t tile;    // index into the rho-sorted tile list
+    int32_t chunk;
+    int32_t slot;    // partial-sum slot, or -1 when the tile has a single item (direct write)
+    int32_t pad;
+};
+
+// Backward work item: Gaussians [chunk*BWD_CHUNK, +BWD_CHUNK) over sorted tiles [k0, k1).
+struct BItem {
+    int32_t chunk;
+    int32_t k0, k1;
+    int32_t slot;
+};
+
+// Scalar problem constants passed by value to kernels.
+struct Consts {
+    int32_t nx, ny, C, pad0;
+    double px, py;
+    double lambda[4];
+    double inv_lambda[4];
+    double tau2;        // log2(1/eps)
+    double K2;          // 2 pi^2 log2(e)
+    int32_t forward;    // 1: cull zero-amplitude Gaussians too
+    int32_t phase_mode; // 0 exact base, 1 FP32 base (precision study)
+};
+
+// Per-shape plan owned by the context.
+struct Plan {
+    int32_t nx = 0, ny = 0, tile_config = 0;
+    int32_t ntx = 0, nty = 0, ntiles = 0;
+    int32_t tx_min = 0, ty_min = 0;
+    // device arrays
+    int32_t *tile_xy = nullptr;       // [ntiles] packed (tx & 0xffff) | (ty << 16), rho-sorted
+    int32_t *tile_bucket = nullptr;   // [ntiles] floor(rho) of each sorted tile
+    int32_t *tile_cum = nullptr;      // [NBUCKET] number of sorted tiles with bucket <= b
+    float2 *tw_x = nullptr;           // [nx] exp(-j 2 pi k / nx)
+    float2 *tw_y = nullptr;           // [ny]
+    int32_t radix_x[16] = {0}, nrad_x = 0;
+    int32_t radix_y[16] = {0}, nrad_y = 0;
+    // split-bf16 DFT matrices (lazily built)
+    void *dft_mats = nullptr;
+    size_t dft_bytes = 0;
+};
+
+// Workspace layout for one scene batch.
+struct Layout {
+    size_t total = 0;
+    size_t off_keys_a, off_keys_b, off_vals_a, off_vals_b, off_sort_hist, off_bucket_hist, off_cum;
+    size_t off_counters, off_records, off_tile_L, off_tile_slots, off_items, off_bitems, off_partials, off_bpartials;
+    size_t off_spectrum, off_gspec, off_dtab, off_d0tab, off_chunk_items;
+    int32_t nsx = 0, nsy = 0, sx_min = 0, sy_min = 0;
+    int64_t n = 0;
+    int32_t sort_blocks = 0;
+    int64_t max_items = 0, max_slots = 0, max_bitems = 0, max_bslots = 0;
+};
+
+// Device counters block (int64 for sums; the first entries are the scheduling counters).
+enum Counter {
+    CTR_WORK = 0,        // forward persistent-queue head
+    CTR_BWORK = 1,       // backward persistent-queue head
+    CTR_NVALID = 2,
+    CTR_NCULLED = 3,
+    CTR_NITEMS = 4,
+    CTR_CHUNK = 5,
+    CTR_NBITEMS = 6,
+    CTR_TRB = 7,
+    CTR_PAIRS = 8,       // (tile, Gaussian) pairs evaluated
+    CTR_CAND = 9,        // (tile, Gaussian) candidates tested
+    CTR_COUNT = 16
+};
+
+// ---- kernel launchers (each enqueues on `stream`, returns hipError_t) ----
+hipError_t launch_keys(const gws_gaussians &g, const Consts &k, uint64_t *keys, uint32_t *vals,
+                       uint32_t *bucket_hist, long long *counters, hipStream_t s);
+hipError_t radix_sort_48(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b,
+                         uint32_t *block_hist, int64_t n, int nblocks, hipStream_t s,
+                         uint64_t **keys_out, uint32_t **vals_out);
+hipError_t launch_records(const gws_gaussians &g, const Consts &k, const uint64_t *keys,
+                          const uint32_t *vals, GRec *rec, int64_t n, const long long *counters,
+                          hipStream_t s);
+hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32_t *cum, int32_t *tile_L,
+                              int2 *tile_slots, Item *items, int64_t max_items, int64_t max_slots,
+                              long long *counters, hipStream_t s);
+hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
+                               int64_t max_bitems, long long *counters, int64_t n, hipStream_t s);
+hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
+                             const Item *items, float2 *partials, float2 *spectrum, long long *counters,
+                             int grid, hipStream_t s);
+hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const int2 *tile_slots,
+                                  const float2 *partials, float2 *spectrum, hipStream_t s);
+hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min,
+                         hipStream_t s);
+hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
+                           const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
+                           float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s);
+hipError_t launch_grad_final2(const gws_gaussians &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
+                              const float *bpartials, const gws_grads &grads, int64_t n, const long long *counters,
+                              hipStream_t s);
+int accumulate_occupancy(int C);
+hipError_t launch_zero_counters(long long *counters, uint32_t *bucket_hist, hipStream_t s);
+hipError_t launch_copy_counters(const long long *src, long long *dst, hipStream_t s);
+int fft_col_batch(int n);
+hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
+                        hipStream_t s);
+hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in, float2 *out,
+                             void *ws, hipStream_t s);
+size_t dft_bf16x3_workspace(int nx, int ny, int batch);
+hipError_t build_dft_mats(Plan &p);
+
+int occupancy_blocks(const void *kernel, int block, size_t dyn_smem);
+
+}  // namespace gws

@@ -1,0 +1,347 @@
+// Spectrum accumulation (gfx950): the order-invariant sum of Sec. 4.2, Eq. 12,
+//   S_c[m] = sum_i A_{c,i} exp2(-q_i(m)) exp(j 2 pi Theta_{c,i}(m)),
+// evaluated only where the Gaussian envelope exceeds eps of its peak.  The paper's own
+// kernel (supplement Alg. 4) gives every thread one pixel and loops over all Gaussians;
+// here a work-group owns a 32 x 32 tile of frequencies and a chunk of the Gaussians whose
+// support reaches it, stages the accepted Gaussians in LDS, and every lane evaluates four
+// frequencies per Gaussian with hardware exp2 / sin / cos.
+//
+// Phase, in revolutions, for Gaussian i, wavelength c, frequency m' = m0' + d (m0' the
+// centre of the lane's 16 x 16 sub-tile):
+//   Theta = kappa_c - m'.r - z D_c(nu_m)
+//         = [kappa_c - m0'.r - z D_c(nu_0)]            exact: fixed point + FP64, per (sub-tile, i)
+//           - d.r_f32 - z (D_c(nu_m) - D_c(nu_0))      small: FP32, per lane
+// with r = frac(mu / (N p) + 1/2) (the +1/2 folds the SLM centring), kappa_c =
+// frac(phi/2pi - z/lambda_c), and D_c(nu) = sqrt(1/lambda_c^2 - |nu|^2) - 1/lambda_c
+// written without cancellation as -|nu|^2 / (1/lambda_c + sqrt(1/lambda_c^2 - |nu|^2)).
+// v_sin_f32 / v_cos_f32 take revolutions, so no 2 pi scaling is needed.
+#include "gws_internal.h"
+
+namespace gws {
+
+static __device__ __forceinline__ double frac_d(double v) { return v - floor(v); }
+
+// D_c(nu) in cycles per metre (negative), or +inf marker when evanescent.
+static __device__ __forceinline__ double dprop(double nu2, double inv_l)
+{
+    const double w2 = inv_l * inv_l - nu2;
+    if (!(w2 > 0.0)) return 0.0;
+    return -nu2 / (inv_l + sqrt(w2));
+}
+
+// Does the ellipse q(x, y) = a x^2 + b2 x y + g y^2 <= lim meet the rectangle
+// [x0, x1] x [y0, y1]?  Exact for a convex quadratic: if the rectangle holds the origin
+// the minimum is 0, otherwise it lies on an edge, where q is a 1-D parabola.
+static __device__ __forceinline__ bool ellipse_meets_rect(float a, float b2, float g, float lim, float x0, float x1,
+                                                          float y0, float y1)
+{
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+    const float ia = 0.5f / a, ig = 0.5f / g;
+    float m = 3.0e38f;
+    {
+        float y = fminf(fmaxf(-b2 * x0 * ig, y0), y1);
+        m = fminf(m, x0 * (a * x0 + b2 * y) + g * y * y);
+        y = fminf(fmaxf(-b2 * x1 * ig, y0), y1);
+        m = fminf(m, x1 * (a * x1 + b2 * y) + g * y * y);
+        float x = fminf(fmaxf(-b2 * y0 * ia, x0), x1);
+        m = fminf(m, x * (a * x + b2 * y0) + g * y0 * y0);
+        x = fminf(fmaxf(-b2 * y1 * ia, x0), x1);
+        m = fminf(m, x * (a * x + b2 * y1) + g * y1 * y1);
+    }
+    return m <= lim;
+}
+
+// Compacted per-(sub-tile, Gaussian) entry, 16 floats.
+struct alignas(16) WEntry {
+    float alpha, beta2, gamma, z;
+    float rxf, ryf, pad0, pad1;
+    float amp[4];
+    float base[4];
+};
+
+template <int C, bool EVAN>
+__global__ void __launch_bounds__(WG) k_accumulate(Consts k, int32_t tx_lo, const int32_t *__restrict__ tile_xy,
+                                                   const GRec *__restrict__ rec, const int32_t *__restrict__ tile_L,
+                                                   const Item *__restrict__ items, float2 *__restrict__ partials,
+                                                   float2 *__restrict__ spectrum, long long *__restrict__ counters)
+{
+    __shared__ GRec s_rec[WG];
+    __shared__ WEntry s_w[WAVES][64];
+    __shared__ int s_item;
+    __shared__ int s_cnt[WAVES];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nitems = (int)counters[CTR_NITEMS];
+    const int CH = (int)counters[CTR_CHUNK];
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    const double Wx = k.nx * k.px, Wy = k.ny * k.py;
+    const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    (void)tx_lo;
+    long long pairs = 0;
+
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd((unsigned long long *)&counters[CTR_WORK], 1ull);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= nitems) break;
+        const Item it = items[item];
+        const int32_t txy = tile_xy[it.tile];
+        const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
+        const int L = tile_L[it.tile];
+        const int c0 = it.chunk * CH, c1 = min(c0 + CH, L);
+        // work-group tile rectangle, clipped to the grid
+        const float X0 = (float)max(tx * TILE, -hx), X1 = (float)min(tx * TILE + TILE - 1, hx - 1);
+        const float Y0 = (float)max(ty * TILE, -hy), Y1 = (float)min(ty * TILE + TILE - 1, hy - 1);
+        // this wave's sub-tile
+        const int sx0 = tx * TILE + (wave & 1) * SUB, sy0 = ty * TILE + (wave >> 1) * SUB;
+        const int cx = sx0 + SUB / 2, cy = sy0 + SUB / 2;
+        const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUB - 1, hx - 1);
+        const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SUB - 1, hy - 1);
+        const bool wave_live = (x0 <= x1) && (y0 <= y1);
+        // per-lane frequency constants
+        const int col = lane & (SUB - 1), row0 = lane >> 4;
+        const int mxp = sx0 + col;
+        const float fmx = (float)mxp;
+        const float mxx = fmx * fmx, dxf = (float)(col - SUB / 2);
+        float mxy[F], myy[F], dyf[F], dD[F][C], msk[F][C];
+        double D0[C];
+        {
+            const double ncx = cx / Wx, ncy = cy / Wy;
+            for (int c = 0; c < C; ++c) D0[c] = dprop(ncx * ncx + ncy * ncy, k.inv_lambda[c]);
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const int myp = sy0 + row0 + 4 * f;
+            const float fmy = (float)myp;
+            mxy[f] = fmx * fmy;
+            myy[f] = fmy * fmy;
+            dyf[f] = (float)(row0 + 4 * f - SUB / 2);
+            const double nux = mxp / Wx, nuy = myp / Wy;
+            const double nu2 = nux * nux + nuy * nuy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double il = k.inv_lambda[c];
+                dD[f][c] = (float)(dprop(nu2, il) - D0[c]);
+                msk[f][c] = (nu2 < il * il) ? 1.0f : 0.0f;
+            }
+        }
+        float acc_re[F][C], acc_im[F][C];
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc_re[f][c] = acc_im[f][c] = 0.0f;
+
+        for (int base = c0; base < c1; base += WG) {
+            const int gi = base + tid;
+            bool pred = false;
+            GRec r;
+            if (gi < c1) {
+                r = rec[gi];
+                pred = ellipse_meets_rect(r.alpha, r.beta2, r.gamma, lim, X0, X1, Y0, Y1);
+            }
+            const uint64_t bal = __ballot(pred);
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            if (lane == 0) s_cnt[wave] = __popcll(bal);
+            __syncthreads();
+            int off = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const int cw = s_cnt[w];
+                off += (w < wave) ? cw : 0;
+                total += cw;
+            }
+            if (pred) s_rec[off + __popcll(bal & lt)] = r;
+            __syncthreads();
+            if (wave_live) {
+                for (int j0 = 0; j0 < total; j0 += 64) {
+                    const int j = j0 + lane;
+                    bool p = false;
+                    WEntry e;
+                    if (j < total) {
+                        const GRec q = s_rec[j];
+                        p = ellipse_meets_rect(q.alpha, q.beta2, q.gamma, lim, x0, x1, y0, y1);
+                        if (p) {
+                            e.alpha = q.alpha; e.beta2 = q.beta2; e.gamma = q.gamma; e.z = q.z;
+                            e.rxf = q.rxf; e.ryf = q.ryf; e.pad0 = 0.0f; e.pad1 = 0.0f;
+                            // exact ramp at the sub-tile centre: 0.32 fixed point, wraps mod 1
+                            const uint32_t ramp = (uint32_t)cx * q.rx + (uint32_t)cy * q.ry;
+                            const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                e.amp[c] = q.amp[c];
+                                if (c < C) {
+                                    if (k.phase_mode == 1) {
+                                        // plain FP32 phase (precision study only)
+                                        const float rr = (float)cx * q.rxf + (float)cy * q.ryf;
+                                        const float v = q.kappa[c] - rr - q.z * (float)D0[c];
+                                        e.base[c] = v - floorf(v);
+                                    } else {
+                                        e.base[c] = (float)frac_d((double)q.kappa[c] - ramp_rev - (double)q.z * D0[c]);
+                                    }
+                                } else {
+                                    e.base[c] = 0.0f;
+                                }
+                            }
+                        }
+                    }
+                    const uint64_t b2 = __ballot(p);
+                    const int cnt = __popcll(b2);
+                    if (p) s_w[wave][__popcll(b2 & lt)] = e;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    pairs += cnt;
+                    for (int ei = 0; ei < cnt; ++ei) {
+                        const WEntry &w = s_w[wave][ei];
+                        const float alpha = w.alpha, beta2 = w.beta2, gamma = w.gamma, z = w.z;
+                        const float rxf = w.rxf, ryf = w.ryf;
+                        float amp[C], bx[C];
+                        const float ax = alpha * mxx;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            amp[c] = w.amp[c];
+                            bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, w.base[c]));
+                        }
+#pragma unroll
+                        for (int f = 0; f < F; ++f) {
+                            const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
+                            const float E = __builtin_amdgcn_exp2f(-q);
+#pragma unroll
+                            for (int c = 0; c < C; ++c) {
+                                const float t = fmaf(-dyf[f], ryf, bx[c]);
+                                const float th = fmaf(-z, dD[f][c], t);
+                                const float sn = __builtin_amdgcn_sinf(th);
+                                const float cs = __builtin_amdgcn_cosf(th);
+                                float wgt = amp[c] * E;
+                                if (EVAN) wgt *= msk[f][c];
+                                acc_re[f][c] = fmaf(wgt, cs, acc_re[f][c]);
+                                acc_im[f][c] = fmaf(wgt, sn, acc_im[f][c]);
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __syncthreads();
+        }
+        // write out
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const int myp = sy0 + row0 + 4 * f;
+            const bool valid = mxp >= -hx && mxp < hx && myp >= -hy && myp < hy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float2 v = make_float2(acc_re[f][c], acc_im[f][c]);
+                if (it.slot < 0) {
+                    if (valid) {
+                        const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
+                        spectrum[((int64_t)c * k.ny + my) * k.nx + mx] = v;
+                    }
+                } else {
+                    partials[(((int64_t)it.slot * C + c) * F + f) * WG + tid] = v;
+                }
+            }
+        }
+    }
+    if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
+}
+
+template <int C>
+__global__ void __launch_bounds__(WG) k_reduce_partials(Consts k, const int32_t *__restrict__ tile_xy,
+                                                        const int2 *__restrict__ tile_slots,
+                                                        const float2 *__restrict__ partials, float2 *__restrict__ spectrum)
+{
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int2 ts = tile_slots[t];
+    if (ts.x == 1) return;  // written directly by the accumulation
+    const int32_t txy = tile_xy[t];
+    const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    const int sx0 = tx * TILE + (wave & 1) * SUB, sy0 = ty * TILE + (wave >> 1) * SUB;
+    const int mxp = sx0 + (lane & (SUB - 1)), row0 = lane >> 4;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const int myp = sy0 + row0 + 4 * f;
+        const bool valid = mxp >= -hx && mxp < hx && myp >= -hy && myp < hy;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float2 s = make_float2(0.0f, 0.0f);
+            for (int j = 0; j < ts.x; ++j) {
+                const float2 v = partials[(((int64_t)(ts.y + j) * C + c) * F + f) * WG + tid];
+                s.x += v.x;
+                s.y += v.y;
+            }
+            if (valid) {
+                const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
+                spectrum[((int64_t)c * k.ny + my) * k.nx + mx] = s;
+            }
+        }
+    }
+}
+
+static bool tile_needs_evanescent(const Plan &p, const Consts &k)
+{
+    // the farthest frequency of the grid against the shortest-wavelength... any channel
+    const double nux = (p.nx / 2) / (p.nx * k.px), nuy = (p.ny / 2) / (p.ny * k.py);
+    const double nu2 = nux * nux + nuy * nuy;
+    for (int c = 0; c < k.C; ++c)
+        if (!(nu2 < k.inv_lambda[c] * k.inv_lambda[c])) return true;
+    return false;
+}
+
+template <int C>
+static hipError_t launch_acc_c(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
+                               const Item *items, float2 *partials, float2 *spectrum, long long *counters, int grid,
+                               hipStream_t s)
+{
+    if (tile_needs_evanescent(p, k))
+        hipLaunchKernelGGL((k_accumulate<C, true>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
+                           items, partials, spectrum, counters);
+    else
+        hipLaunchKernelGGL((k_accumulate<C, false>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
+                           items, partials, spectrum, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L, const Item *items,
+                             float2 *partials, float2 *spectrum, long long *counters, int grid, hipStream_t s)
+{
+    switch (k.C) {
+    case 1: return launch_acc_c<1>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    case 2: return launch_acc_c<2>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    case 3: return launch_acc_c<3>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    case 4: return launch_acc_c<4>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const int2 *tile_slots, const float2 *partials,
+                                  float2 *spectrum, hipStream_t s)
+{
+    const dim3 grid(p.ntiles), block(WG);
+    switch (k.C) {
+    case 1: hipLaunchKernelGGL(k_reduce_partials<1>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    case 2: hipLaunchKernelGGL(k_reduce_partials<2>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    case 3: hipLaunchKernelGGL(k_reduce_partials<3>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    case 4: hipLaunchKernelGGL(k_reduce_partials<4>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int accumulate_occupancy(int C)
+{
+    int nb = 0;
+    const void *kp = nullptr;
+    switch (C) {
+    case 1: kp = (const void *)k_accumulate<1, false>; break;
+    case 2: kp = (const void *)k_accumulate<2, false>; break;
+    case 3: kp = (const void *)k_accumulate<3, false>; break;
+    default: kp = (const void *)k_accumulate<4, false>; break;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, WG, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+}  // namespace gws

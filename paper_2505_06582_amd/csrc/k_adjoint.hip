@@ -1,0 +1,410 @@
+// Adjoint of the order-invariant sum (Sec. 4.2, Eq. 12) for gfx950.
+//
+// Given Gs = dL/dS (the forward DFT of dL/du, torch's complex-gradient convention), the
+// gradient with respect to a real parameter t of Gaussian i is
+//   dL/dt = Re sum_{c,m} conj(Gs_c[m]) dT_{c,i}[m]/dt,   T = A_c exp2(-q) exp(j 2 pi Theta_c).
+// Every derivative of T is T times a factor that is constant, linear or quadratic in the
+// frequency, so per Gaussian it suffices to accumulate, with g_c = conj(Gs_c) exp2(-q)
+// exp(j 2 pi Theta_c) and rho = sum_c A_c g_c,
+//   P_c = sum_m g_c,  W_c = sum_m D_c(m) Im g_c,
+//   Sfx = sum_m m_x' Im rho, Sfy = sum_m m_y' Im rho,
+//   Qxx = sum_m m_x'^2 Re rho, Qxy = sum_m m_x' m_y' Re rho, Qyy = sum_m m_y'^2 Re rho,
+// and apply the chain rule once per Gaussian (k_grad_final).  Terms are recomputed exactly
+// as the forward computes them; nothing per (Gaussian, frequency) is stored.
+//
+// Work: a wavefront owns 64 consecutive sorted Gaussians (one per lane, its record in
+// registers) and a range of tiles.  For each 16 x 16 sub-tile, lanes test their own
+// Gaussian against it and stage the accepted ones in LDS; then every lane evaluates its 4
+// frequencies for each accepted Gaussian and the wave reduces the 3C + 5 sums across
+// lanes into that Gaussian's LDS accumulator.  Item partials are summed per Gaussian in a
+// fixed order, so results are bitwise reproducible.
+#include "gws_internal.h"
+
+namespace gws {
+
+static __device__ __forceinline__ double frac_d(double v) { return v - floor(v); }
+
+static __device__ __forceinline__ bool ellipse_meets_rect_b(float a, float b2, float g, float lim, float x0, float x1,
+                                                            float y0, float y1)
+{
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+    const float ia = 0.5f / a, ig = 0.5f / g;
+    float m = 3.0e38f;
+    float y = fminf(fmaxf(-b2 * x0 * ig, y0), y1);
+    m = fminf(m, x0 * (a * x0 + b2 * y) + g * y * y);
+    y = fminf(fmaxf(-b2 * x1 * ig, y0), y1);
+    m = fminf(m, x1 * (a * x1 + b2 * y) + g * y * y);
+    float x = fminf(fmaxf(-b2 * y0 * ia, x0), x1);
+    m = fminf(m, x * (a * x + b2 * y0) + g * y0 * y0);
+    x = fminf(fmaxf(-b2 * y1 * ia, x0), x1);
+    m = fminf(m, x * (a * x + b2 * y1) + g * y1 * y1);
+    return m <= lim;
+}
+
+struct alignas(16) BEntry {
+    float alpha, beta2, gamma, z;
+    float rxf, ryf;
+    int32_t owner;   // lane (0..63) that owns this Gaussian
+    float pad;
+    float amp[4];
+    float base[4];
+};
+
+// Per-frequency FP32 table D_c(nu_m) - D_c(nu_0(sub-tile of m)) in FFT order, and the FP64
+// sub-tile centre values D_c(nu_0).  Sub-tiles are the 16 x 16 DC-aligned blocks.
+__global__ void __launch_bounds__(256) k_dtable(Consts k, float *__restrict__ dD, double *__restrict__ D0, int nsx,
+                                                int nsy, int sx_min, int sy_min)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t M = (int64_t)k.nx * k.ny;
+    const double Wx = k.nx * k.px, Wy = k.ny * k.py;
+    if (idx < M) {
+        const int mx = (int)(idx % k.nx), my = (int)(idx / k.nx);
+        const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
+        const int sx = (int)floor(mxp / (double)SUB), sy = (int)floor(myp / (double)SUB);
+        const int cx = sx * SUB + SUB / 2, cy = sy * SUB + SUB / 2;
+        const double nux = mxp / Wx, nuy = myp / Wy, ncx = cx / Wx, ncy = cy / Wy;
+        const double nu2 = nux * nux + nuy * nuy, nc2 = ncx * ncx + ncy * ncy;
+        for (int c = 0; c < k.C; ++c) {
+            const double il = k.inv_lambda[c];
+            const double w2 = il * il - nu2, wc = il * il - nc2;
+            const double d = w2 > 0.0 ? -nu2 / (il + sqrt(w2)) : 0.0;
+            const double d0 = wc > 0.0 ? -nc2 / (il + sqrt(wc)) : 0.0;
+            dD[(int64_t)c * M + idx] = (float)(d - d0);
+        }
+    }
+    const int64_t ns = (int64_t)nsx * nsy;
+    if (idx < ns) {
+        const int sx = (int)(idx % nsx) + sx_min, sy = (int)(idx / nsx) + sy_min;
+        const double ncx = (sx * SUB + SUB / 2) / Wx, ncy = (sy * SUB + SUB / 2) / Wy;
+        const double nc2 = ncx * ncx + ncy * ncy;
+        for (int c = 0; c < k.C; ++c) {
+            const double il = k.inv_lambda[c];
+            const double wc = il * il - nc2;
+            D0[(int64_t)c * ns + idx] = wc > 0.0 ? -nc2 / (il + sqrt(wc)) : 0.0;
+        }
+    }
+}
+
+hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, hipStream_t s)
+{
+    const int64_t M = (int64_t)k.nx * k.ny;
+    const int64_t n = M > (int64_t)nsx * nsy ? M : (int64_t)nsx * nsy;
+    hipLaunchKernelGGL(k_dtable, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, dD, D0, nsx, nsy, sx_min, sy_min);
+    return hipGetLastError();
+}
+
+// Transposed butterfly reduction of V (<= 16) per-lane values over 64 lanes.  On return
+// lane l holds the full sum of value v(l) = bit5(l)*8 + bit4(l)*4 + bit3(l)*2 + bit2(l).
+template <int V>
+static __device__ __forceinline__ float reduce16(float (&x)[16], int lane)
+{
+#pragma unroll
+    for (int i = V; i < 16; ++i) x[i] = 0.0f;
+    // xor 32: keep half 0..7 or 8..15
+    {
+        const bool up = lane & 32;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float keep = up ? x[i + 8] : x[i];
+            const float send = up ? x[i] : x[i + 8];
+            x[i] = keep + __shfl_xor(send, 32);
+        }
+    }
+    {
+        const bool up = lane & 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float keep = up ? x[i + 4] : x[i];
+            const float send = up ? x[i] : x[i + 4];
+            x[i] = keep + __shfl_xor(send, 16);
+        }
+    }
+    {
+        const bool up = lane & 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float keep = up ? x[i + 2] : x[i];
+            const float send = up ? x[i] : x[i + 2];
+            x[i] = keep + __shfl_xor(send, 8);
+        }
+    }
+    float r;
+    {
+        const bool up = lane & 4;
+        const float keep = up ? x[1] : x[0];
+        const float send = up ? x[0] : x[1];
+        r = keep + __shfl_xor(send, 4);
+    }
+    r += __shfl_xor(r, 2);
+    r += __shfl_xor(r, 1);
+    return r;
+}
+
+template <int C>
+__global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy, const GRec *__restrict__ rec,
+                                                const float2 *__restrict__ gspec, const float *__restrict__ dtab,
+                                                const double *__restrict__ d0tab, int nsx, int nsy, int sx_min,
+                                                int sy_min, const BItem *__restrict__ bitems,
+                                                float *__restrict__ bpartials, long long *__restrict__ counters,
+                                                int64_t n)
+{
+    constexpr int NV = 3 * C + 5;
+    static_assert(NV <= 16, "too many accumulators");
+    __shared__ BEntry s_w[WAVES][64];
+    __shared__ float s_acc[WAVES][64][NACC];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nitems = (int)counters[CTR_NBITEMS];
+    const int64_t nvalid = n - counters[CTR_NCULLED];
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    const int64_t M = (int64_t)k.nx * k.ny;
+    const int64_t ns = (int64_t)nsx * nsy;
+    const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int col = lane & (SUB - 1), row0 = lane >> 4;
+    const float dxf = (float)(col - SUB / 2);
+    long long pairs = 0;
+
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd((unsigned long long *)&counters[CTR_BWORK], 1ull);
+        item = __shfl(item, 0);
+        if (item >= nitems) break;
+        const BItem bi = bitems[item];
+        const int64_t gidx = (int64_t)bi.chunk * 64 + lane;
+        const bool gvalid = gidx < nvalid;
+        GRec r;
+        if (gvalid) r = rec[gidx];
+        else {
+            r.alpha = r.beta2 = r.gamma = 1.0f; r.z = 0.0f; r.rx = r.ry = 0u; r.rxf = r.ryf = 0.0f;
+            for (int c = 0; c < 4; ++c) { r.kappa[c] = 0.0f; r.amp[c] = 0.0f; }
+        }
+#pragma unroll
+        for (int v = 0; v < NACC; ++v) s_acc[wave][lane][v] = 0.0f;
+
+        for (int kt = bi.k0; kt < bi.k1; ++kt) {
+            const int32_t txy = tile_xy[kt];
+            const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
+            for (int st = 0; st < 4; ++st) {
+                const int sx0 = tx * TILE + (st & 1) * SUB, sy0 = ty * TILE + (st >> 1) * SUB;
+                const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUB - 1, hx - 1);
+                const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SUB - 1, hy - 1);
+                if (x0 > x1 || y0 > y1) continue;
+                const int cx = sx0 + SUB / 2, cy = sy0 + SUB / 2;
+                const int64_t sidx = (int64_t)(sy0 / SUB - sy_min) * nsx + (sx0 / SUB - sx_min);
+                // stage this sub-tile's accepted Gaussians
+                const bool p = gvalid && ellipse_meets_rect_b(r.alpha, r.beta2, r.gamma, lim, x0, x1, y0, y1);
+                const uint64_t bal = __ballot(p);
+                const int cnt = __popcll(bal);
+                if (cnt == 0) continue;
+                if (p) {
+                    BEntry e;
+                    e.alpha = r.alpha; e.beta2 = r.beta2; e.gamma = r.gamma; e.z = r.z;
+                    e.rxf = r.rxf; e.ryf = r.ryf; e.owner = lane; e.pad = 0.0f;
+                    const uint32_t ramp = (uint32_t)cx * r.rx + (uint32_t)cy * r.ry;
+                    const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        e.amp[c] = r.amp[c];
+                        e.base[c] = c < C ? (float)frac_d((double)r.kappa[c] - ramp_rev - (double)r.z * d0tab[c * ns + sidx])
+                                          : 0.0f;
+                    }
+                    s_w[wave][__popcll(bal & lt)] = e;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // per-lane frequency data
+                const int mxp = sx0 + col;
+                const float fmx = (float)mxp;
+                const float mxx = fmx * fmx;
+                const int mx = mxp < 0 ? mxp + k.nx : mxp;
+                const bool xin = mxp >= -hx && mxp < hx;
+                float fmy[F], mxy[F], myy[F], dyf[F], dD[F][C], gr[F][C], gi[F][C];
+                float D0f[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) D0f[c] = (float)d0tab[c * ns + sidx];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int myp = sy0 + row0 + 4 * f;
+                    fmy[f] = (float)myp;
+                    mxy[f] = fmx * fmy[f];
+                    myy[f] = fmy[f] * fmy[f];
+                    dyf[f] = (float)(row0 + 4 * f - SUB / 2);
+                    const bool in = xin && myp >= -hy && myp < hy;
+                    const int my = myp < 0 ? myp + k.ny : myp;
+                    const int64_t o = (int64_t)my * k.nx + mx;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        if (in) {
+                            const float2 gv = gspec[c * M + o];
+                            gr[f][c] = gv.x;
+                            gi[f][c] = gv.y;
+                            dD[f][c] = dtab[c * M + o];
+                        } else {
+                            gr[f][c] = gi[f][c] = 0.0f;
+                            dD[f][c] = 0.0f;
+                        }
+                    }
+                }
+                pairs += cnt;
+                for (int ei = 0; ei < cnt; ++ei) {
+                    const BEntry &w = s_w[wave][ei];
+                    const float alpha = w.alpha, beta2 = w.beta2, gamma = w.gamma, z = w.z, rxf = w.rxf, ryf = w.ryf;
+                    const int owner = w.owner;
+                    float amp[C], bx[C];
+                    const float ax = alpha * mxx;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        amp[c] = w.amp[c];
+                        bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, w.base[c]));
+                    }
+                    float Pr[C], Pi[C], Wc[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) Pr[c] = Pi[c] = Wc[c] = 0.0f;
+                    float sfx = 0.0f, sfy = 0.0f, qxx = 0.0f, qxy = 0.0f, qyy = 0.0f;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
+                        const float E = __builtin_amdgcn_exp2f(-q);
+                        float rr = 0.0f, ri = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            const float th = fmaf(-z, dD[f][c], fmaf(-dyf[f], ryf, bx[c]));
+                            const float sn = __builtin_amdgcn_sinf(th);
+                            const float cs = __builtin_amdgcn_cosf(th);
+                            const float h = fmaf(gr[f][c], cs, gi[f][c] * sn);
+                            const float kk = fmaf(gr[f][c], sn, -gi[f][c] * cs);
+                            const float Eh = E * h, Ek = E * kk;
+                            Pr[c] += Eh;
+                            Pi[c] += Ek;
+                            Wc[c] = fmaf(dD[f][c], Ek, Wc[c]);
+                            rr = fmaf(amp[c], Eh, rr);
+                            ri = fmaf(amp[c], Ek, ri);
+                        }
+                        sfx = fmaf(fmx, ri, sfx);
+                        sfy = fmaf(fmy[f], ri, sfy);
+                        qxx = fmaf(mxx, rr, qxx);
+                        qxy = fmaf(mxy[f], rr, qxy);
+                        qyy = fmaf(myy[f], rr, qyy);
+                    }
+                    float x[16];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        x[2 * c] = Pr[c];
+                        x[2 * c + 1] = Pi[c];
+                        x[2 * C + c] = fmaf(D0f[c], Pi[c], Wc[c]);
+                    }
+                    x[3 * C + 0] = sfx;
+                    x[3 * C + 1] = sfy;
+                    x[3 * C + 2] = qxx;
+                    x[3 * C + 3] = qxy;
+                    x[3 * C + 4] = qyy;
+                    const float red = reduce16<NV>(x, lane);
+                    const int v = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+                    if ((lane & 3) == 0 && v < NV) s_acc[wave][owner][v] += red;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        float *dst = bpartials + ((int64_t)bi.slot * 64 + lane) * NACC;
+#pragma unroll
+        for (int v = 0; v < NACC; ++v) dst[v] = s_acc[wave][lane][v];
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
+}
+
+template <int C>
+static hipError_t launch_adj_c(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
+                               const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
+                               float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adjoint<C>, dim3(grid), dim3(WG), 0, s, k, p.tile_xy, rec, gspec, dtab, d0tab, nsx, nsy, sx_min,
+                       sy_min, bitems, bpartials, counters, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
+                           const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
+                           float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
+{
+    switch (k.C) {
+    case 1: return launch_adj_c<1>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    case 2: return launch_adj_c<2>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    case 3: return launch_adj_c<3>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    default: return hipErrorInvalidValue;  // 3C + 5 accumulators must fit 16
+    }
+}
+
+// Per Gaussian: sum the item partials of its chunk in order (FP64), then the chain rule.
+__global__ void __launch_bounds__(256) k_grad_final(gws_gaussians g, Consts k, const uint32_t *__restrict__ vals,
+                                                    const int2 *__restrict__ chunk_items,
+                                                    const float *__restrict__ bpartials, gws_grads grads, int64_t n,
+                                                    const long long *__restrict__ counters)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t nvalid = n - counters[CTR_NCULLED];
+    const int64_t i = vals[s];
+    const int C = k.C;
+    if (s >= nvalid) {
+        grads.mean_x[i] = grads.mean_y[i] = 0.0f;
+        if (grads.depth) grads.depth[i] = 0.0f;
+        grads.cov_xx[i] = grads.cov_xy[i] = grads.cov_yy[i] = 0.0f;
+        grads.opacity[i] = grads.phase[i] = 0.0f;
+        for (int c = 0; c < C; ++c) grads.amplitude[(int64_t)c * g.n + i] = 0.0f;
+        return;
+    }
+    const int64_t b = s / 64;
+    const int lane = (int)(s - b * 64);
+    const int2 ci = chunk_items[b];
+    const long long nbitems = counters[CTR_NBITEMS];
+    double acc[NACC];
+    for (int v = 0; v < NACC; ++v) acc[v] = 0.0;
+    for (int j = 0; j < ci.y && (long long)ci.x + j < nbitems; ++j) {
+        const float *src = bpartials + ((int64_t)(ci.x + j) * 64 + lane) * NACC;
+        for (int v = 0; v < NACC; ++v) acc[v] += (double)src[v];
+    }
+    const double PI = 3.14159265358979323846;
+    const double sxx = g.cov_xx[i], sxy = g.cov_xy[i], syy = g.cov_yy[i];
+    const double det = sxx * syy - sxy * sxy;
+    const double o = g.opacity[i];
+    const double fx = 1.0 / (k.nx * k.px), fy = 1.0 / (k.ny * k.py);
+    const double K = 2.0 * PI * sqrt(det) / (k.px * k.py * (double)k.nx * (double)k.ny);
+    double Sre = 0.0, Sim = 0.0, gz = 0.0, go = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double a = g.amplitude[(int64_t)c * g.n + i];
+        const double A = a * o * K;
+        const double Pr = acc[2 * c], Pi = acc[2 * c + 1], Wc = acc[2 * C + c];
+        Sre += A * Pr;
+        Sim += A * Pi;
+        gz += A * (k.inv_lambda[c] * Pi + Wc);
+        go += a * K * Pr;
+        grads.amplitude[(int64_t)c * g.n + i] = (float)(o * K * Pr);
+    }
+    const double Sfx = acc[3 * C], Sfy = acc[3 * C + 1], Qxx = acc[3 * C + 2], Qxy = acc[3 * C + 3], Qyy = acc[3 * C + 4];
+    grads.phase[i] = (float)(-Sim);
+    grads.mean_x[i] = (float)(2.0 * PI * fx * Sfx);
+    grads.mean_y[i] = (float)(2.0 * PI * fy * Sfy);
+    grads.opacity[i] = (float)go;
+    grads.cov_xx[i] = (float)(syy / (2.0 * det) * Sre - 2.0 * PI * PI * fx * fx * Qxx);
+    grads.cov_yy[i] = (float)(sxx / (2.0 * det) * Sre - 2.0 * PI * PI * fy * fy * Qyy);
+    grads.cov_xy[i] = (float)(-sxy / det * Sre - 4.0 * PI * PI * fx * fy * Qxy);
+    if (grads.depth) grads.depth[i] = (float)(2.0 * PI * gz);
+}
+
+hipError_t launch_grad_final2(const gws_gaussians &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
+                              const float *bpartials, const gws_grads &grads, int64_t n, const long long *counters,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, k, vals, chunk_items, bpartials,
+                       grads, n, counters);
+    return hipGetLastError();
+}
+
+}  // namespace gws

@@ -1,0 +1,109 @@
+"""The C-ABI library builds, loads and exports every entry point of include/gws.h, and its
+host-side validation returns the documented codes -- all without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2505_06582_amd as gws
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gws.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gws_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_compiles_as_c_and_cxx(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "gws.h"\nint main(void){gws_problem p; gws_stats s; (void)p; (void)s; return GWS_ABI_VERSION == 1 ? 0 : 1;}\n')
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)])
+    subprocess.check_call(["g++", "-std=c++17", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", "-I",
+                           os.path.dirname(HEADER), str(src)])
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gws.load_library()
+    syms = declared_symbols()
+    assert len(syms) >= 17
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(syms) == set(gws._SIGNATURES), set(syms) ^ set(gws._SIGNATURES)
+    out = subprocess.check_output(["nm", "-D", "--defined-only", gws.LIB_PATH], text=True)
+    exported = set(re.findall(r"\bT (gws_[a-z0-9_]+)", out))
+    assert set(syms) <= exported
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gws.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
+                   ' sizeof(gws_problem), offsetof(gws_problem, eps_support), offsetof(gws_problem, tile_config),'
+                   ' sizeof(gws_gaussians), sizeof(gws_output), sizeof(gws_grads), sizeof(gws_stats)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
+    want = [ctypes.sizeof(gws._Problem), gws._Problem.eps_support.offset, gws._Problem.tile_config.offset,
+            ctypes.sizeof(gws._Gaussians), ctypes.sizeof(gws._Output), ctypes.sizeof(gws._Grads),
+            ctypes.sizeof(gws._Stats)]
+    assert got == want
+
+
+def _check(prob):
+    lib = gws.load_library()
+    return lib.gws_check_problem(ctypes.byref(prob._c()))
+
+
+def test_problem_validation_codes():
+    lib = gws.load_library()
+    assert lib.gws_abi_version() == 1
+    ok = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9))
+    assert _check(ok) == 0
+    assert _check(gws.Problem(1921, 1080)) == -2          # odd
+    assert _check(gws.Problem(1022, 1080)) == -2          # factor 7 * 73
+    assert _check(gws.Problem(8, 1080)) == -2             # too small
+    assert _check(gws.Problem(256, 256, pitch_x=0.0)) == -1
+    assert _check(gws.Problem(256, 256, lambdas=())) == -1
+    assert _check(gws.Problem(256, 256, lambdas=(1e-6,) * 5)) == -1
+    assert _check(gws.Problem(256, 256, lambdas=(-5e-7,))) == -1
+    assert _check(gws.Problem(256, 256, eps_support=0.5)) == -1
+    assert _check(gws.Problem(256, 256, xform=7)) == -1
+    assert _check(gws.Problem(256, 256, blend=gws.BLEND_EXACT)) == -3
+    assert lib.gws_check_problem(None) == -1
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert lib.gws_status_string(code)
+
+
+def test_workspace_size_is_host_only_and_grows_with_n():
+    lib = gws.load_library()
+    prob = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9))._c()
+    sizes = []
+    for n in (0, 64, 10_000, 100_000):
+        sz = ctypes.c_size_t()
+        assert lib.gws_workspace_size(None, ctypes.byref(prob), n, ctypes.byref(sz)) == 0
+        sizes.append(sz.value)
+    assert sizes == sorted(sizes) and sizes[0] > 0
+    sz = ctypes.c_size_t()
+    assert lib.gws_workspace_size(None, ctypes.byref(prob), -1, ctypes.byref(sz)) == -1
+    assert lib.gws_workspace_size(None, ctypes.byref(prob), 10, None) == -1
+
+
+def test_entry_points_reject_bad_arguments_without_a_device():
+    lib = gws.load_library()
+    h = ctypes.c_void_p()
+    st = lib.gws_create(ctypes.byref(h), 0)
+    if st == 0:
+        lib.gws_destroy(h)
+        pytest.skip("a gfx950 device is present")
+    assert st == -5
+    assert lib.gws_last_error(None)
+    assert lib.gws_create(None, 0) == -1
+    prob = gws.Problem(256, 256)._c()
+    assert lib.gws_forward(None, ctypes.byref(prob), None, None, None, 0, None) == -1
+    assert lib.gws_backward(None, ctypes.byref(prob), None, None, None, None, 0, None) == -1
+    assert lib.gws_dft2d(None, 256, 256, 1, 1, 0, None, None, None, 0, None) == -1
+    assert lib.gws_destroy(None) == 0
