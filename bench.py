@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the Gaussian Wave Splatting hot path on one MI355X.
+
+Workload: 100,000 random in-plane Gaussians, 1080 x 1920 hologram, 3 wavelengths
+(638 / 520 / 450 nm), 8 um pitch.  One step = forward (preprocess, sort, bin, spectrum
+accumulation, inverse FFT) + L2 loss against a random complex target + backward
+(forward FFT of the field gradient, adjoint accumulation, chain rule): parameters on the
+device to gradients on the device, every step in the HIP library.
+
+Prints one JSON line: holograms/s (fwd+bwd steps per second) with the roofline of the
+dominant kernel measured by HIP events on the library's stream, and the FP64 CPU oracle
+timed on a bounded sample on this host.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "holograms/s @1080x1920x3λ,100k Gaussians fwd+bwd; Gaussian·freq-px evals/s"
+# Transcendental-unit peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz for full-rate
+# FP32 VALU work (39.3 T lane-ops/s); exp2 / sin / cos issue at half that rate.
+PEAK_TRANS = 256 * 4 * 16 * 2.4e9 / 2.0
+PEAK_VALU = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ellipse_support_points(scene, grid, eps=1e-7):
+    """Algorithmic work: lattice frequencies inside each Gaussian's eps-support ellipse (area)."""
+    import numpy as np
+    tau = math.log(1.0 / eps)
+    Wx, Wy = grid.nx * grid.px, grid.ny * grid.py
+    sxx = scene.cov_xx.astype(np.float64)
+    sxy = scene.cov_xy.astype(np.float64)
+    syy = scene.cov_yy.astype(np.float64)
+    # exponent 2 pi^2 nu^T S nu <= tau; in index units nu = m / W
+    a = 2 * math.pi ** 2 * sxx / Wx ** 2
+    b = 2 * math.pi ** 2 * sxy / (Wx * Wy)
+    c = 2 * math.pi ** 2 * syy / Wy ** 2
+    valid = (sxx > 0) & (sxx * syy - sxy * sxy > 0) & (scene.opacity != 0)
+    area = np.where(valid, math.pi * tau / np.sqrt(np.maximum(a * c - b * b, 1e-300)), 0.0)
+    return float(np.minimum(area, grid.nx * grid.ny).sum())
+
+
+def cpu_baseline(scene, grid, seconds_target=20.0):
+    """FP64 oracle on a bounded sample, extrapolated to one fwd+bwd hologram."""
+    import numpy as np
+    import oracle
+    import gwsgen
+    rng = np.random.default_rng(4242)
+    M = grid.nx * grid.ny
+    # forward: Eq. 12 at a sample of frequencies (every Gaussian, every wavelength)
+    S = 96
+    mx = rng.integers(0, grid.nx, S).astype(np.int32)
+    my = rng.integers(0, grid.ny, S).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.spectrum(scene, grid, mx, my)
+    t_fwd_sample = time.perf_counter() - t0
+    # transforms: one dense centred DFT (per wavelength), forward and adjoint
+    g1 = gwsgen.Grid(grid.nx, grid.ny, grid.px, grid.py, (grid.lambdas[0],))
+    G1 = gwsgen.make_target(g1, 3).astype(np.complex128)
+    t0 = time.perf_counter()
+    gs1 = oracle.spectrum_grad_from_field_grad(G1, g1)
+    t_xf = time.perf_counter() - t0
+    # backward: dense per-Gaussian gradients for a sample of Gaussians
+    nsel = 16
+    sel = rng.choice(scene.n, nsel, replace=False)
+    gs = np.repeat(gs1, grid.n_lambda, axis=0)
+    t0 = time.perf_counter()
+    oracle.param_grads_from_spectrum_grad(scene, grid, gs, sel)
+    t_bwd_sample = time.perf_counter() - t0
+    t_full = (t_fwd_sample * M / S + t_bwd_sample * scene.n / nsel + 2 * grid.n_lambda * t_xf)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    if os.environ.get("OMP_NUM_THREADS"):
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
+    return {
+        "value": 1.0 / t_full, "unit": "holograms/s", "cores": cores, "kind": "oracle",
+        "sample": ("FP64 C/OpenMP oracle: Eq. 12 at %d random frequencies x %d Gaussians x %d wavelengths "
+                   "(%.1f s), one dense centred DFT of 1080x1920 (%.1f s, x%d for inverse+adjoint per wavelength), "
+                   "dense gradients of %d random Gaussians over the full grid (%.1f s); extrapolated to the full "
+                   "fwd+bwd hologram = %.0f s" % (S, scene.n, grid.n_lambda, t_fwd_sample, t_xf,
+                                                     2 * grid.n_lambda, nsel, t_bwd_sample, t_full)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fwdbwd100k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the hot path runs on a single MI355X in this build "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gwsgen
+    import paper_2505_06582_amd as gws
+
+    log("bench: generating workload %s" % args.workload)
+    scene, grid = gwsgen.workload(args.workload)
+    target = gwsgen.make_target(grid, 2003)
+    prob = gws.Problem.from_grid(grid)
+    ctx = gws.context(0)
+    dev = torch.device("cuda", 0)
+    g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.fields().items()}
+    t = torch.from_numpy(target).to(dev)
+    field = torch.empty((grid.n_lambda, grid.ny, grid.nx), dtype=torch.complex64, device=dev)
+    G = torch.empty_like(field)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in g.items()}
+
+    def step():
+        ctx.forward(prob, g, out=field)
+        ctx.l2_loss_grad(field, t, grad=G, loss=loss)
+        ctx.backward(prob, g, G, out=grads)
+
+    # counts of the evaluated work (deterministic for the scene)
+    log("bench: counting work")
+    ctx.forward(prob, g, out=field)
+    st_f = ctx.stats()
+    ctx.l2_loss_grad(field, t, grad=G, loss=loss)
+    ctx.backward(prob, g, G, out=grads)
+    st_b = ctx.stats()
+    torch.cuda.synchronize()
+
+    log("bench: warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.read_profile()
+    ctx.set_profiling(True)
+    log("bench: timing %d steps" % args.steps)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ctx.set_profiling(False)
+    prof = ctx.read_profile()
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    log("bench: %.3f ms/step (wall %.3f ms/step); stages %s" % (
+        ms_step, 1e3 * wall / args.steps, {k: round(v, 3) for k, v in stage_ms.items()}))
+
+    C = grid.n_lambda
+    M = grid.nx * grid.ny
+    support = ellipse_support_points(scene, grid)          # (Gaussian, frequency) pairs inside eps-support
+    evals_alg = support * C                                # Gaussian.freq-px evaluations per pass
+    trans_per_pair = 1 + 2 * C                             # one exp2, a sin and a cos per wavelength
+    fwd_pairs_eval = st_f["n_tile_gaussian"] * 256         # evaluated (sub-tile of 256 frequencies) x Gaussian
+    bwd_pairs_eval = st_b["n_tile_gaussian"] * 256
+    kern = {}
+    t_acc = stage_ms["accumulate"] * 1e-3
+    t_adj = stage_ms["adjoint"] * 1e-3
+    if t_acc > 0:
+        kern["accumulate"] = {
+            "ms": stage_ms["accumulate"], "bound": "alu",
+            "achieved": support * trans_per_pair / t_acc / 1e12, "peak": PEAK_TRANS / 1e12, "unit": "TOP/s",
+            "frac": support * trans_per_pair / t_acc / PEAK_TRANS,
+            "evaluated_frac": fwd_pairs_eval * trans_per_pair / t_acc / PEAK_TRANS,
+            "evaluated_over_support": fwd_pairs_eval / support}
+    if t_adj > 0:
+        kern["adjoint"] = {
+            "ms": stage_ms["adjoint"], "bound": "alu",
+            "achieved": support * trans_per_pair / t_adj / 1e12, "peak": PEAK_TRANS / 1e12, "unit": "TOP/s",
+            "frac": support * trans_per_pair / t_adj / PEAK_TRANS,
+            "evaluated_frac": bwd_pairs_eval * trans_per_pair / t_adj / PEAK_TRANS,
+            "evaluated_over_support": bwd_pairs_eval / support}
+    for name in ("xform_inverse", "xform_forward"):
+        if stage_ms[name] > 0:
+            # two passes (rows, columns), each one read + one write of C x M complex64
+            bytes_alg = 2 * 2 * C * M * 8
+            kern[name] = {"ms": stage_ms[name], "bound": "hbm", "achieved": bytes_alg / (stage_ms[name] * 1e-3) / 1e9,
+                          "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                          "frac": bytes_alg / (stage_ms[name] * 1e-3) / PEAK_HBM}
+    dom = max(("accumulate", "adjoint"), key=lambda k: stage_ms[k])
+    d = kern[dom]
+    roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+                "frac": d["frac"], "traffic": None, "kernel": dom,
+                "work_per_launch": "%.4g transcendental ops (= %.4g (Gaussian, frequency) pairs inside the "
+                                   "1e-7 support x (1 exp2 + 2 x %d sin/cos))" % (support * trans_per_pair, support, C)}
+
+    value = 1e3 / ms_step
+    out = {
+        "metric": METRIC, "value": value, "unit": "holograms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%d random in-plane Gaussians, %dx%d hologram, %d wavelengths (638/520/450 nm), "
+                               "8 um pitch, forward + L2 loss + backward" % (scene.n, grid.ny, grid.nx, C),
+                   "gaussians": scene.n, "ny": grid.ny, "nx": grid.nx, "n_lambda": C, "eps_support": 1e-7,
+                   "parallelism": "single GPU"},
+        "evals_per_s": 2 * evals_alg / (ms_step * 1e-3),
+        "evals_per_s_note": "Gaussian.freq-px evaluations inside the eps-support, forward + backward, per second",
+        "dense_equiv_evals_per_s": 2 * scene.n * M * C / (ms_step * 1e-3),
+        "stage_ms": stage_ms,
+        "kernels": kern,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(scene, grid)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

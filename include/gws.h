@@ -204,6 +204,24 @@ gws_status gws_autotune(gws_ctx *ctx, const gws_problem *problem, int64_t n_hint
  * the device. */
 gws_status gws_get_stats(gws_ctx *ctx, gws_stats *out);
 
+/* Field loss of the training step around the hot path: over n complex64 elements,
+ * *loss = sum |u - t|^2 (one double, device) and, if grad is non-NULL,
+ * grad = 2 (u - t) (complex64, device; may alias u).  The sum is reduced in a fixed
+ * order.  workspace needs gws_l2_workspace_size() bytes (device, 256-byte aligned). */
+size_t gws_l2_workspace_size(void);
+gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *field, const void *target, void *grad,
+                            double *loss, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Stage timing with HIP events on the caller's stream.  While enabled, every library call
+ * records an event pair around each of its stages (0 preprocess+sort+records, 1 binning,
+ * 2 spectrum accumulation, 3 partial-sum reduction, 4 inverse transform, 5 forward
+ * transform, 6 propagation table, 7 adjoint accumulation, 8 gradient chain rule, 9 loss).
+ * gws_read_profile synchronises, returns per stage the summed milliseconds and the number
+ * of launches since the last read (host arrays of GWS_N_STAGES entries), and clears them. */
+#define GWS_N_STAGES 10
+gws_status gws_set_profiling(gws_ctx *ctx, int enable);
+gws_status gws_read_profile(gws_ctx *ctx, double *ms, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,7 +102,17 @@ _SIGNATURES = {
     "gws_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int64, ctypes.c_char_p,
                                     ctypes.c_void_p]),
     "gws_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Stats)]),
+    "gws_l2_workspace_size": (ctypes.c_size_t, []),
+    "gws_l2_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p]),
+    "gws_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "gws_read_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]),
 }
+
+STAGES = ("prep_sort", "bin", "accumulate", "reduce", "xform_inverse", "xform_forward", "dtable", "adjoint",
+          "grad_final", "loss")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -236,12 +246,12 @@ class Context:
                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
         return (field, spec) if want_spectrum else field
 
-    def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True):
+    def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True, out=None):
         """dL/d(parameter) for every Gaussian, given dL/dRe u + j dL/dIm u."""
         torch = _torch()
         n = int(g["mean_x"].numel())
         grad_field = grad_field.to(torch.complex64).contiguous()
-        grads = {k: torch.empty_like(g[k]) for k in PARAMS}
+        grads = out if out is not None else {k: torch.empty_like(g[k]) for k in PARAMS}
         gr = _Grads()
         for k in PARAMS:
             setattr(gr, k, grads[k].data_ptr() if n > 0 else None)
@@ -271,6 +281,31 @@ class Context:
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
                                   ws.numel() if ws is not None else 0, self._stream()), self.handle)
         return out
+
+    def l2_loss_grad(self, field, target, grad=None, loss=None):
+        """loss = sum |u - t|^2 (float64 device scalar) and grad = 2 (u - t), in the library."""
+        torch = _torch()
+        n = field.numel()
+        if grad is None:
+            grad = torch.empty_like(field)
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float64, device=self.torch_device)
+        if getattr(self, "_l2ws", None) is None:
+            self._l2ws = torch.empty(int(self.lib.gws_l2_workspace_size()), dtype=torch.uint8, device=self.torch_device)
+        _check(self.lib.gws_l2_loss_grad(self.handle, n, ctypes.c_void_p(field.data_ptr()),
+                                         ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                         ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(self._l2ws.data_ptr()),
+                                         self._l2ws.numel(), self._stream()), self.handle)
+        return loss, grad
+
+    def set_profiling(self, on: bool):
+        _check(self.lib.gws_set_profiling(self.handle, 1 if on else 0), self.handle)
+
+    def read_profile(self) -> dict:
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        _check(self.lib.gws_read_profile(self.handle, ms, cnt), self.handle)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
     def stats(self) -> dict:
         s = _Stats()

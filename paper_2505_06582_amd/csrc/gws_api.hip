@@ -34,6 +34,53 @@ struct gws_ctx {
         int backward;
     };
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+    // stage profiling
+    int profiling = 0;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+static hipEvent_t pool_event(gws_ctx *ctx)
+{
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around one stage on the caller's stream when profiling is on.
+struct StageScope {
+    gws_ctx *ctx;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageScope(gws_ctx *c, hipStream_t st, int sg) : ctx(c), s(st), stage(sg)
+    {
+        if (ctx->profiling) {
+            a = pool_event(ctx);
+            if (a) hipEventRecord(a, s);
+        }
+    }
+    ~StageScope()
+    {
+        if (ctx->profiling && a) {
+            hipEvent_t b = pool_event(ctx);
+            if (b) {
+                hipEventRecord(b, s);
+                ctx->recs.push_back({stage, a, b});
+            } else {
+                ctx->pool.push_back(a);
+            }
+        }
+    }
 };
 
 static thread_local std::string g_tls_error;
@@ -338,6 +385,11 @@ extern "C" gws_status gws_destroy(gws_ctx *ctx)
     hipSetDevice(ctx->device);
     for (auto &kv : ctx->plans) free_plan(kv.second);
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.second);
+    for (auto &r : ctx->recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) hipEventDestroy(e);
     hipFree(ctx->d_stats);
     delete ctx;
     return GWS_OK;
@@ -429,6 +481,7 @@ static Bufs carve(const Layout &L, void *ws)
 static gws_status run_prep(gws_ctx *ctx, const Consts &k, const gws_gaussians *g, const Layout &L, const Bufs &B,
                            hipStream_t s, uint64_t **keys_sorted, uint32_t **vals_sorted)
 {
+    StageScope sc(ctx, s, ST_PREP);
     HIP_CHECK(ctx, launch_zero_counters(B.counters, B.bucket_hist, s));
     HIP_CHECK(ctx, launch_keys(*g, k, B.keys_a, B.vals_a, B.bucket_hist, B.counters, s));
     HIP_CHECK(ctx, radix_sort_48(B.keys_a, B.vals_a, B.keys_b, B.vals_b, B.sort_hist, g->n, L.sort_blocks, s, keys_sorted,
@@ -458,16 +511,29 @@ static gws_status forward_impl(gws_ctx *ctx, const gws_problem *prob, const gws_
     uint32_t *vals = nullptr;
     st = run_prep(ctx, k, g, L, B, s, &keys, &vals);
     if (st != GWS_OK) return st;
-    HIP_CHECK(ctx, launch_bin_forward(*p, B.bucket_hist, B.cum, B.tile_L, B.tile_slots, B.items, L.max_items, L.max_slots,
-                                      B.counters, s));
+    {
+        StageScope sc(ctx, s, ST_BIN);
+        HIP_CHECK(ctx, launch_bin_forward(*p, B.bucket_hist, B.cum, B.tile_L, B.tile_slots, B.items, L.max_items,
+                                          L.max_slots, B.counters, s));
+    }
     float2 *spec = out->spectrum ? (float2 *)out->spectrum : B.spectrum;
-    HIP_CHECK(ctx, launch_accumulate(*p, k, B.rec, B.tile_L, B.items, B.partials, spec, B.counters, acc_grid(ctx, k.C), s));
-    HIP_CHECK(ctx, launch_reduce_partials(*p, k, B.tile_slots, B.partials, spec, s));
-    if (prob->xform == GWS_XFORM_FFT_FP32) {
-        HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spec, (float2 *)out->field, s));
-    } else {
-        // the bf16 DFT keeps its split operands in the spare gspec/dtab region of the workspace
-        HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)out->field, (void *)B.gspec, s));
+    {
+        StageScope sc(ctx, s, ST_ACCUM);
+        HIP_CHECK(ctx, launch_accumulate(*p, k, B.rec, B.tile_L, B.items, B.partials, spec, B.counters,
+                                         acc_grid(ctx, k.C), s));
+    }
+    {
+        StageScope sc(ctx, s, ST_REDUCE);
+        HIP_CHECK(ctx, launch_reduce_partials(*p, k, B.tile_slots, B.partials, spec, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_XFORM_INV);
+        if (prob->xform == GWS_XFORM_FFT_FP32) {
+            HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spec, (float2 *)out->field, s));
+        } else {
+            // the bf16 DFT keeps its split operands in the spare gspec/dtab region of the workspace
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)out->field, (void *)B.gspec, s));
+        }
     }
     HIP_CHECK(ctx, launch_copy_counters(B.counters, ctx->d_stats, s));
     ctx->last_n = g->n;
@@ -512,16 +578,31 @@ static gws_status backward_impl(gws_ctx *ctx, const gws_problem *prob, const gws
     uint32_t *vals = nullptr;
     st = run_prep(ctx, k, g, L, B, s, &keys, &vals);
     if (st != GWS_OK) return st;
-    HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, L.max_bitems, B.counters, g->n, s));
-    // Gs = forward DFT of the field gradient (adjoint of the unnormalised inverse DFT)
-    if (prob->xform == GWS_XFORM_FFT_FP32)
-        HIP_CHECK(ctx, launch_fft2d(*p, k.C, -1, (const float2 *)grad_field, B.gspec, s));
-    else
-        HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, -1, (const float2 *)grad_field, B.gspec, (void *)B.spectrum, s));
-    HIP_CHECK(ctx, launch_dtable(k, B.dtab, B.d0tab, L.nsx, L.nsy, L.sx_min, L.sy_min, s));
-    HIP_CHECK(ctx, launch_adjoint2(*p, k, B.rec, B.gspec, B.dtab, B.d0tab, L.nsx, L.nsy, L.sx_min, L.sy_min, B.bitems,
-                                   B.bpartials, B.counters, g->n, ctx->n_cu * 4, s));
-    HIP_CHECK(ctx, launch_grad_final2(*g, k, vals, B.chunk_items, B.bpartials, *grads, g->n, B.counters, s));
+    {
+        StageScope sc(ctx, s, ST_BIN);
+        HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, L.max_bitems, B.counters, g->n, s));
+    }
+    {
+        // Gs = forward DFT of the field gradient (adjoint of the unnormalised inverse DFT)
+        StageScope sc(ctx, s, ST_XFORM_FWD);
+        if (prob->xform == GWS_XFORM_FFT_FP32)
+            HIP_CHECK(ctx, launch_fft2d(*p, k.C, -1, (const float2 *)grad_field, B.gspec, s));
+        else
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, -1, (const float2 *)grad_field, B.gspec, (void *)B.spectrum, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_DTABLE);
+        HIP_CHECK(ctx, launch_dtable(k, B.dtab, B.d0tab, L.nsx, L.nsy, L.sx_min, L.sy_min, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_ADJOINT);
+        HIP_CHECK(ctx, launch_adjoint2(*p, k, B.rec, B.gspec, B.dtab, B.d0tab, L.nsx, L.nsy, L.sx_min, L.sy_min,
+                                       B.bitems, B.bpartials, B.counters, g->n, ctx->n_cu * 4, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_FINAL);
+        HIP_CHECK(ctx, launch_grad_final2(*g, k, vals, B.chunk_items, B.bpartials, *grads, g->n, B.counters, s));
+    }
     HIP_CHECK(ctx, launch_copy_counters(B.counters, ctx->d_stats, s));
     ctx->last_n = g->n;
     ctx->last_graph = 0;
@@ -603,4 +684,53 @@ extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *, in
 extern "C" gws_status gws_autotune(gws_ctx *ctx, const gws_problem *, int64_t, const char *, void *)
 {
     return fail(ctx, GWS_ERR_UNSUPPORTED, "autotuner not built");
+}
+
+// ---------------------------------------------------------------------------------
+// Loss and profiling
+// ---------------------------------------------------------------------------------
+extern "C" size_t gws_l2_workspace_size(void) { return align256(l2_workspace_bytes()); }
+
+extern "C" gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *field, const void *target, void *grad,
+                                       double *loss, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    if (n < 0 || (n > 0 && (!field || !target)) || !loss) return fail(ctx, GWS_ERR_INVALID_ARG, "bad loss arguments");
+    gws_status st = check_ws(ctx, ws, ws_bytes, gws_l2_workspace_size());
+    if (st != GWS_OK) return st;
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    StageScope sc(ctx, (hipStream_t)stream, ST_LOSS);
+    HIP_CHECK(ctx, launch_l2_grad((const float2 *)field, (const float2 *)target, (float2 *)grad, loss, ws, n,
+                                  (hipStream_t)stream));
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_set_profiling(gws_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->profiling = enable ? 1 : 0;
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_read_profile(gws_ctx *ctx, double *ms, int64_t *count)
+{
+    if (!ctx || !ms || !count) return fail(ctx, GWS_ERR_INVALID_ARG, "null argument");
+    for (int i = 0; i < GWS_N_STAGES; ++i) {
+        ms[i] = 0.0;
+        count[i] = 0;
+    }
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    for (auto &r : ctx->recs) {
+        HIP_CHECK(ctx, hipEventSynchronize(r.b));
+        float t = 0.0f;
+        HIP_CHECK(ctx, hipEventElapsedTime(&t, r.a, r.b));
+        if (r.stage >= 0 && r.stage < GWS_N_STAGES) {
+            ms[r.stage] += t;
+            count[r.stage] += 1;
+        }
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return GWS_OK;
 }

@@ -142,6 +142,14 @@ int accumulate_occupancy(int C);
 hipError_t launch_zero_counters(long long *counters, uint32_t *bucket_hist, hipStream_t s);
 hipError_t launch_copy_counters(const long long *src, long long *dst, hipStream_t s);
 int fft_col_batch(int n);
+size_t l2_workspace_bytes();
+hipError_t launch_l2_grad(const float2 *u, const float2 *t, float2 *g, double *loss, void *ws, int64_t n, hipStream_t s);
+
+// Stages timed with HIP events when profiling is on (gws_set_profiling).
+enum Stage {
+    ST_PREP = 0, ST_BIN, ST_ACCUM, ST_REDUCE, ST_XFORM_INV, ST_XFORM_FWD, ST_DTABLE, ST_ADJOINT, ST_FINAL, ST_LOSS,
+    ST_COUNT
+};
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                         hipStream_t s);
 hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in, float2 *out,
