@@ -7,7 +7,8 @@ accumulation, inverse FFT) + L2 loss against a random complex target + backward
 (forward FFT of the field gradient, adjoint accumulation, chain rule): parameters on the
 device to gradients on the device, every step in the HIP library.
 
-Prints one JSON line: holograms/s (fwd+bwd steps per second) with the roofline of the
+Prints one JSON line: holograms/s (fwd+bwd steps per second; gradients with respect to mean, covariance,
+opacity, amplitude and phase) with the roofline of the
 dominant kernel measured by HIP events on the library's stream, and the FP64 CPU oracle
 timed on a bounded sample on this host.
 
@@ -60,7 +61,7 @@ def cpu_baseline(scene, grid, seconds_target=20.0):
     rng = np.random.default_rng(4242)
     M = grid.nx * grid.ny
     # forward: Eq. 12 at a sample of frequencies (every Gaussian, every wavelength)
-    S = 96
+    S = 1536
     mx = rng.integers(0, grid.nx, S).astype(np.int32)
     my = rng.integers(0, grid.ny, S).astype(np.int32)
     t0 = time.perf_counter()
@@ -73,7 +74,7 @@ def cpu_baseline(scene, grid, seconds_target=20.0):
     gs1 = oracle.spectrum_grad_from_field_grad(G1, g1)
     t_xf = time.perf_counter() - t0
     # backward: dense per-Gaussian gradients for a sample of Gaussians
-    nsel = 16
+    nsel = 256
     sel = rng.choice(scene.n, nsel, replace=False)
     gs = np.repeat(gs1, grid.n_lambda, axis=0)
     t0 = time.perf_counter()
@@ -100,6 +101,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fwdbwd100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-config", type=int, default=0, help="0: tuned/default tiling; k: explicit tiling k")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X in this build "
@@ -115,7 +117,7 @@ def main():
     log("bench: generating workload %s" % args.workload)
     scene, grid = gwsgen.workload(args.workload)
     target = gwsgen.make_target(grid, 2003)
-    prob = gws.Problem.from_grid(grid)
+    prob = gws.Problem.from_grid(grid, tile_config=args.tile_config)
     ctx = gws.context(0)
     dev = torch.device("cuda", 0)
     g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.fields().items()}
@@ -128,14 +130,14 @@ def main():
     def step():
         ctx.forward(prob, g, out=field)
         ctx.l2_loss_grad(field, t, grad=G, loss=loss)
-        ctx.backward(prob, g, G, out=grads)
+        ctx.backward(prob, g, G, out=grads, want_depth=False)
 
     # counts of the evaluated work (deterministic for the scene)
     log("bench: counting work")
     ctx.forward(prob, g, out=field)
     st_f = ctx.stats()
     ctx.l2_loss_grad(field, t, grad=G, loss=loss)
-    ctx.backward(prob, g, G, out=grads)
+    ctx.backward(prob, g, G, out=grads, want_depth=False)
     st_b = ctx.stats()
     torch.cuda.synchronize()
 
@@ -208,6 +210,7 @@ def main():
         "config": {"workload": "%d random in-plane Gaussians, %dx%d hologram, %d wavelengths (638/520/450 nm), "
                                "8 um pitch, forward + L2 loss + backward" % (scene.n, grid.ny, grid.nx, C),
                    "gaussians": scene.n, "ny": grid.ny, "nx": grid.nx, "n_lambda": C, "eps_support": 1e-7,
+                   "tile_config": st_b["tile_config"],
                    "parallelism": "single GPU"},
         "evals_per_s": 2 * evals_alg / (ms_step * 1e-3),
         "evals_per_s_note": "Gaussian.freq-px evaluations inside the eps-support, forward + backward, per second",

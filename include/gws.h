@@ -74,11 +74,17 @@ typedef struct gws_problem {
     double eps_support;        /* spectral-support cut: terms whose Gaussian envelope is below
                                   eps * (its peak) are skipped; 0 selects 1e-7; must be in
                                   (0, 1e-3].  The relative L2 error it adds is about eps. */
-    int32_t phase_mode;        /* 0: FP32 phase with exact per-tile FP64 base (default);
-                                  2: also reduce the per-tile base in FP64 for every Gaussian
-                                  (no effect on results beyond rounding; kept for testing) */
-    int32_t tile_config;       /* 0: tuned or default tiling; k > 0: explicit tiling k
-                                  (see gws_tile_config_count) */
+    int32_t phase_mode;        /* 0: every large phase term (carrier z/lambda, ramp, propagation
+                                  at the tile centre) reduced exactly per (tile, Gaussian) in
+                                  fixed point and FP64, small per-frequency deltas in FP32
+                                  (default); 1: the same terms in plain FP32 (precision study
+                                  only: loses accuracy for far off-axis, deep Gaussians);
+                                  2: same as 0 */
+    int32_t tile_config;       /* 0: the autotuned tiling for this shape if gws_autotune ran,
+                                  else the default; k in 1..gws_tile_config_count(): tiling k,
+                                  a pair (frequencies per lane of the accumulation, of the
+                                  adjoint) from {(4,4),(4,8),(8,8),(8,4),(2,4),(4,2),(2,2),
+                                  (2,8),(8,2)}; the default is 5 = (2,4) */
 } gws_problem;
 
 /* Gaussians as structure-of-arrays float32 device buffers of length n.  amplitude is

@@ -251,12 +251,15 @@ class Context:
         torch = _torch()
         n = int(g["mean_x"].numel())
         grad_field = grad_field.to(torch.complex64).contiguous()
-        grads = out if out is not None else {k: torch.empty_like(g[k]) for k in PARAMS}
+        grads = dict(out) if out is not None else {k: torch.empty_like(g[k]) for k in PARAMS}
+        if not want_depth:
+            grads["depth"] = None
+        elif grads.get("depth") is None:
+            grads["depth"] = torch.empty_like(g["depth"])
         gr = _Grads()
         for k in PARAMS:
-            setattr(gr, k, grads[k].data_ptr() if n > 0 else None)
-        if not want_depth:
-            gr.depth = None
+            t = grads[k]
+            setattr(gr, k, t.data_ptr() if (n > 0 and t is not None) else None)
         ws = self.workspace(self.workspace_size(prob, n))
         gs = _gaussians_struct(g, n)
         if n == 0:
@@ -264,8 +267,6 @@ class Context:
         _check(self.lib.gws_backward(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs),
                                      ctypes.c_void_p(grad_field.data_ptr()), ctypes.byref(gr),
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
-        if not want_depth:
-            grads["depth"] = None
         return grads
 
     def dft2d(self, x, direction: int, xform: int = XFORM_FFT_FP32, out=None):

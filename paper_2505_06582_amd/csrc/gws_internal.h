@@ -14,15 +14,16 @@ namespace gws {
 
 // ---------------------------------------------------------------------------------
 // Frequency tiling.  The centred frequency plane m' in [-nx/2, nx/2) x [-ny/2, ny/2)
-// (index units) is cut into DC-aligned tiles of TILE x TILE frequencies: tile (tx, ty)
-// covers m'_x in [TILE tx, TILE tx + TILE) and likewise in y, clipped to the grid.  A
-// work-group of 4 wavefronts owns one tile; wavefront w owns the SUB x SUB sub-tile
-// (w & 1, w >> 1); lane l of a wavefront owns column l % SUB and rows l / SUB + 4 f for
-// f = 0..F-1 of its sub-tile.
+// (index units) is cut into DC-aligned tiles of TILEX x tile_h(F) frequencies: tile
+// (tx, ty) covers m'_x in [TILEX tx, TILEX (tx + 1)) and m'_y in [tile_h ty, tile_h (ty + 1)),
+// clipped to the grid.  A work-group of 4 wavefronts owns one tile; wavefront w owns the
+// SUBX x sub_h(F) sub-tile (w & 1, w >> 1); lane l of a wavefront owns column l % SUBX
+// and rows l / SUBX + 4 f for f = 0..F-1 of its sub-tile.  F (frequencies per lane) is
+// the tiling parameter the autotuner chooses: 2, 4 or 8.
 // ---------------------------------------------------------------------------------
-constexpr int TILE = 32;
-constexpr int SUB = 16;
-constexpr int F = 4;                 // frequencies per lane
+constexpr int SUBX = 16;
+constexpr int TILEX = 2 * SUBX;
+__host__ __device__ constexpr int sub_h(int f) { return 4 * f; }
 constexpr int WAVES = 4;             // wavefronts per work-group
 constexpr int WG = 64 * WAVES;       // threads per work-group
 constexpr int NBUCKET = 4096;        // support-radius buckets (index units)
@@ -64,11 +65,13 @@ struct Consts {
     double K2;          // 2 pi^2 log2(e)
     int32_t forward;    // 1: cull zero-amplitude Gaussians too
     int32_t phase_mode; // 0 exact base, 1 FP32 base (precision study)
+    int32_t depth_grad; // backward: accumulate the depth-gradient sums
+    int32_t pad1;
 };
 
 // Per-shape plan owned by the context.
 struct Plan {
-    int32_t nx = 0, ny = 0, tile_config = 0;
+    int32_t nx = 0, ny = 0, F = 4, tile_h = 32;
     int32_t ntx = 0, nty = 0, ntiles = 0;
     int32_t tx_min = 0, ty_min = 0;
     // device arrays
@@ -90,10 +93,15 @@ struct Layout {
     size_t off_keys_a, off_keys_b, off_vals_a, off_vals_b, off_sort_hist, off_bucket_hist, off_cum;
     size_t off_counters, off_records, off_tile_L, off_tile_slots, off_items, off_bitems, off_partials, off_bpartials;
     size_t off_spectrum, off_gspec, off_dtab, off_d0tab, off_chunk_items;
-    int32_t nsx = 0, nsy = 0, sx_min = 0, sy_min = 0;
+    int32_t nsx = 0, nsy = 0, sx_min = 0, sy_min = 0, F = 4;
     int64_t n = 0;
     int32_t sort_blocks = 0;
     int64_t max_items = 0, max_slots = 0, max_bitems = 0, max_bslots = 0;
+    // item-table capacity that covers every tiling sharing this byte budget (F = 2 has the most slots)
+    static int64_t max_slots_bound(size_t part_bytes, int C, int ntiles)
+    {
+        return (int64_t)(part_bytes / ((size_t)C * 2 * WG * 8)) / 2 + ntiles + 1;
+    }
 };
 
 // Device counters block (int64 for sums; the first entries are the scheduling counters).
@@ -130,7 +138,7 @@ hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, co
                              int grid, hipStream_t s);
 hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const int2 *tile_slots,
                                   const float2 *partials, float2 *spectrum, hipStream_t s);
-hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min,
+hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
                          hipStream_t s);
 hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
                            const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
@@ -138,7 +146,7 @@ hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, cons
 hipError_t launch_grad_final2(const gws_gaussians &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
                               const float *bpartials, const gws_grads &grads, int64_t n, const long long *counters,
                               hipStream_t s);
-int accumulate_occupancy(int C);
+int accumulate_occupancy(int C, int F);
 hipError_t launch_zero_counters(long long *counters, uint32_t *bucket_hist, hipStream_t s);
 hipError_t launch_copy_counters(const long long *src, long long *dst, hipStream_t s);
 int fft_col_batch(int n);
@@ -156,6 +164,7 @@ hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in
                              void *ws, hipStream_t s);
 size_t dft_bf16x3_workspace(int nx, int ny, int batch);
 hipError_t build_dft_mats(Plan &p);
+void free_dft_mats(Plan &p);
 
 int occupancy_blocks(const void *kernel, int block, size_t dyn_smem);
 

@@ -59,8 +59,8 @@ struct alignas(16) WEntry {
     float base[4];
 };
 
-template <int C, bool EVAN>
-__global__ void __launch_bounds__(WG) k_accumulate(Consts k, int32_t tx_lo, const int32_t *__restrict__ tile_xy,
+template <int C, bool EVAN, int F>
+__global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, int32_t tx_lo, const int32_t *__restrict__ tile_xy,
                                                    const GRec *__restrict__ rec, const int32_t *__restrict__ tile_L,
                                                    const Item *__restrict__ items, float2 *__restrict__ partials,
                                                    float2 *__restrict__ spectrum, long long *__restrict__ counters)
@@ -70,6 +70,7 @@ __global__ void __launch_bounds__(WG) k_accumulate(Consts k, int32_t tx_lo, cons
     __shared__ int s_item;
     __shared__ int s_cnt[WAVES];
 
+    constexpr int SY = sub_h(F), TY = 2 * SY;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = (int)counters[CTR_NITEMS];
     const int CH = (int)counters[CTR_CHUNK];
@@ -91,19 +92,19 @@ __global__ void __launch_bounds__(WG) k_accumulate(Consts k, int32_t tx_lo, cons
         const int L = tile_L[it.tile];
         const int c0 = it.chunk * CH, c1 = min(c0 + CH, L);
         // work-group tile rectangle, clipped to the grid
-        const float X0 = (float)max(tx * TILE, -hx), X1 = (float)min(tx * TILE + TILE - 1, hx - 1);
-        const float Y0 = (float)max(ty * TILE, -hy), Y1 = (float)min(ty * TILE + TILE - 1, hy - 1);
+        const float X0 = (float)max(tx * TILEX, -hx), X1 = (float)min(tx * TILEX + TILEX - 1, hx - 1);
+        const float Y0 = (float)max(ty * TY, -hy), Y1 = (float)min(ty * TY + TY - 1, hy - 1);
         // this wave's sub-tile
-        const int sx0 = tx * TILE + (wave & 1) * SUB, sy0 = ty * TILE + (wave >> 1) * SUB;
-        const int cx = sx0 + SUB / 2, cy = sy0 + SUB / 2;
-        const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUB - 1, hx - 1);
-        const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SUB - 1, hy - 1);
+        const int sx0 = tx * TILEX + (wave & 1) * SUBX, sy0 = ty * TY + (wave >> 1) * SY;
+        const int cx = sx0 + SUBX / 2, cy = sy0 + SY / 2;
+        const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUBX - 1, hx - 1);
+        const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SY - 1, hy - 1);
         const bool wave_live = (x0 <= x1) && (y0 <= y1);
         // per-lane frequency constants
-        const int col = lane & (SUB - 1), row0 = lane >> 4;
+        const int col = lane & (SUBX - 1), row0 = lane >> 4;
         const int mxp = sx0 + col;
         const float fmx = (float)mxp;
-        const float mxx = fmx * fmx, dxf = (float)(col - SUB / 2);
+        const float mxx = fmx * fmx, dxf = (float)(col - SUBX / 2);
         float mxy[F], myy[F], dyf[F], dD[F][C], msk[F][C];
         double D0[C];
         {
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(WG) k_accumulate(Consts k, int32_t tx_lo, cons
             const float fmy = (float)myp;
             mxy[f] = fmx * fmy;
             myy[f] = fmy * fmy;
-            dyf[f] = (float)(row0 + 4 * f - SUB / 2);
+            dyf[f] = (float)(row0 + 4 * f - SY / 2);
             const double nux = mxp / Wx, nuy = myp / Wy;
             const double nu2 = nux * nux + nuy * nuy;
 #pragma unroll
@@ -247,7 +248,7 @@ __global__ void __launch_bounds__(WG) k_accumulate(Consts k, int32_t tx_lo, cons
     if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
 }
 
-template <int C>
+template <int C, int F>
 __global__ void __launch_bounds__(WG) k_reduce_partials(Consts k, const int32_t *__restrict__ tile_xy,
                                                         const int2 *__restrict__ tile_slots,
                                                         const float2 *__restrict__ partials, float2 *__restrict__ spectrum)
@@ -258,8 +259,9 @@ __global__ void __launch_bounds__(WG) k_reduce_partials(Consts k, const int32_t 
     const int32_t txy = tile_xy[t];
     const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
     const int hx = k.nx / 2, hy = k.ny / 2;
-    const int sx0 = tx * TILE + (wave & 1) * SUB, sy0 = ty * TILE + (wave >> 1) * SUB;
-    const int mxp = sx0 + (lane & (SUB - 1)), row0 = lane >> 4;
+    constexpr int SY = sub_h(F), TY = 2 * SY;
+    const int sx0 = tx * TILEX + (wave & 1) * SUBX, sy0 = ty * TY + (wave >> 1) * SY;
+    const int mxp = sx0 + (lane & (SUBX - 1)), row0 = lane >> 4;
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int myp = sy0 + row0 + 4 * f;
@@ -282,7 +284,7 @@ __global__ void __launch_bounds__(WG) k_reduce_partials(Consts k, const int32_t 
 
 static bool tile_needs_evanescent(const Plan &p, const Consts &k)
 {
-    // the farthest frequency of the grid against the shortest-wavelength... any channel
+    // is any grid frequency at or beyond 1/lambda for some channel?
     const double nux = (p.nx / 2) / (p.nx * k.px), nuy = (p.ny / 2) / (p.ny * k.py);
     const double nu2 = nux * nux + nuy * nuy;
     for (int c = 0; c < k.C; ++c)
@@ -290,18 +292,30 @@ static bool tile_needs_evanescent(const Plan &p, const Consts &k)
     return false;
 }
 
+template <int C, int F>
+static hipError_t launch_acc_cf(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
+                                const Item *items, float2 *partials, float2 *spectrum, long long *counters, int grid,
+                                hipStream_t s)
+{
+    if (tile_needs_evanescent(p, k))
+        hipLaunchKernelGGL((k_accumulate<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
+                           items, partials, spectrum, counters);
+    else
+        hipLaunchKernelGGL((k_accumulate<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
+                           items, partials, spectrum, counters);
+    return hipGetLastError();
+}
+
 template <int C>
 static hipError_t launch_acc_c(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
                                const Item *items, float2 *partials, float2 *spectrum, long long *counters, int grid,
                                hipStream_t s)
 {
-    if (tile_needs_evanescent(p, k))
-        hipLaunchKernelGGL((k_accumulate<C, true>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
-                           items, partials, spectrum, counters);
-    else
-        hipLaunchKernelGGL((k_accumulate<C, false>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
-                           items, partials, spectrum, counters);
-    return hipGetLastError();
+    switch (p.F) {
+    case 2: return launch_acc_cf<C, 2>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    case 8: return launch_acc_cf<C, 8>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    default: return launch_acc_cf<C, 4>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    }
 }
 
 hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L, const Item *items,
@@ -316,29 +330,50 @@ hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, co
     }
 }
 
+template <int C>
+static void launch_red_c(const Plan &p, const Consts &k, const int2 *tile_slots, const float2 *partials, float2 *spectrum,
+                         hipStream_t s)
+{
+    const dim3 grid(p.ntiles), block(WG);
+    switch (p.F) {
+    case 2: hipLaunchKernelGGL((k_reduce_partials<C, 2>), grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    case 8: hipLaunchKernelGGL((k_reduce_partials<C, 8>), grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    default: hipLaunchKernelGGL((k_reduce_partials<C, 4>), grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    }
+}
+
 hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const int2 *tile_slots, const float2 *partials,
                                   float2 *spectrum, hipStream_t s)
 {
-    const dim3 grid(p.ntiles), block(WG);
     switch (k.C) {
-    case 1: hipLaunchKernelGGL(k_reduce_partials<1>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
-    case 2: hipLaunchKernelGGL(k_reduce_partials<2>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
-    case 3: hipLaunchKernelGGL(k_reduce_partials<3>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
-    case 4: hipLaunchKernelGGL(k_reduce_partials<4>, grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    case 1: launch_red_c<1>(p, k, tile_slots, partials, spectrum, s); break;
+    case 2: launch_red_c<2>(p, k, tile_slots, partials, spectrum, s); break;
+    case 3: launch_red_c<3>(p, k, tile_slots, partials, spectrum, s); break;
+    case 4: launch_red_c<4>(p, k, tile_slots, partials, spectrum, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-int accumulate_occupancy(int C)
+template <int C>
+static const void *acc_kernel_ptr(int F)
+{
+    switch (F) {
+    case 2: return (const void *)k_accumulate<C, false, 2>;
+    case 8: return (const void *)k_accumulate<C, false, 8>;
+    default: return (const void *)k_accumulate<C, false, 4>;
+    }
+}
+
+int accumulate_occupancy(int C, int F)
 {
     int nb = 0;
     const void *kp = nullptr;
     switch (C) {
-    case 1: kp = (const void *)k_accumulate<1, false>; break;
-    case 2: kp = (const void *)k_accumulate<2, false>; break;
-    case 3: kp = (const void *)k_accumulate<3, false>; break;
-    default: kp = (const void *)k_accumulate<4, false>; break;
+    case 1: kp = acc_kernel_ptr<1>(F); break;
+    case 2: kp = acc_kernel_ptr<2>(F); break;
+    case 3: kp = acc_kernel_ptr<3>(F); break;
+    default: kp = acc_kernel_ptr<4>(F); break;
     }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, WG, 0) != hipSuccess || nb < 1) nb = 1;
     return nb;

@@ -51,9 +51,9 @@ struct alignas(16) BEntry {
 };
 
 // Per-frequency FP32 table D_c(nu_m) - D_c(nu_0(sub-tile of m)) in FFT order, and the FP64
-// sub-tile centre values D_c(nu_0).  Sub-tiles are the 16 x 16 DC-aligned blocks.
+// sub-tile centre values D_c(nu_0).  Sub-tiles are the DC-aligned SUBX x SY blocks.
 __global__ void __launch_bounds__(256) k_dtable(Consts k, float *__restrict__ dD, double *__restrict__ D0, int nsx,
-                                                int nsy, int sx_min, int sy_min)
+                                                int nsy, int sx_min, int sy_min, int SY)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t M = (int64_t)k.nx * k.ny;
@@ -61,8 +61,8 @@ __global__ void __launch_bounds__(256) k_dtable(Consts k, float *__restrict__ dD
     if (idx < M) {
         const int mx = (int)(idx % k.nx), my = (int)(idx / k.nx);
         const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
-        const int sx = (int)floor(mxp / (double)SUB), sy = (int)floor(myp / (double)SUB);
-        const int cx = sx * SUB + SUB / 2, cy = sy * SUB + SUB / 2;
+        const int sx = (int)floor(mxp / (double)SUBX), sy = (int)floor(myp / (double)SY);
+        const int cx = sx * SUBX + SUBX / 2, cy = sy * SY + SY / 2;
         const double nux = mxp / Wx, nuy = myp / Wy, ncx = cx / Wx, ncy = cy / Wy;
         const double nu2 = nux * nux + nuy * nuy, nc2 = ncx * ncx + ncy * ncy;
         for (int c = 0; c < k.C; ++c) {
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) k_dtable(Consts k, float *__restrict__ dD
     const int64_t ns = (int64_t)nsx * nsy;
     if (idx < ns) {
         const int sx = (int)(idx % nsx) + sx_min, sy = (int)(idx / nsx) + sy_min;
-        const double ncx = (sx * SUB + SUB / 2) / Wx, ncy = (sy * SUB + SUB / 2) / Wy;
+        const double ncx = (sx * SUBX + SUBX / 2) / Wx, ncy = (sy * SY + SY / 2) / Wy;
         const double nc2 = ncx * ncx + ncy * ncy;
         for (int c = 0; c < k.C; ++c) {
             const double il = k.inv_lambda[c];
@@ -86,71 +86,103 @@ __global__ void __launch_bounds__(256) k_dtable(Consts k, float *__restrict__ dD
     }
 }
 
-hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, hipStream_t s)
+hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
+                         hipStream_t s)
 {
     const int64_t M = (int64_t)k.nx * k.ny;
     const int64_t n = M > (int64_t)nsx * nsy ? M : (int64_t)nsx * nsy;
-    hipLaunchKernelGGL(k_dtable, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, dD, D0, nsx, nsy, sx_min, sy_min);
+    hipLaunchKernelGGL(k_dtable, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, dD, D0, nsx, nsy, sx_min, sy_min,
+                       sy);
     return hipGetLastError();
 }
 
-// Transposed butterfly reduction of V (<= 16) per-lane values over 64 lanes.  On return
-// lane l holds the full sum of value v(l) = bit5(l)*8 + bit4(l)*4 + bit3(l)*2 + bit2(l).
-template <int V>
-static __device__ __forceinline__ float reduce16(float (&x)[16], int lane)
+// Transposed butterfly reduction of V (8 or 16) per-lane values over the 64 lanes of a
+// wavefront.  Each transposed step pairs value i with value i + h and lane l with lane
+// l ^ d: the lane with the d bit clear keeps and sums the first value of the pair, its
+// partner the second, so a step halves the values per lane with one exchange and one add
+// per pair.  Steps d = 32 and d = 16 use the gfx950 cross-row swaps (v_permlane32_swap,
+// v_permlane16_swap), d = 8 a DPP rotate inside the 16-lane row.  What remains (V / 8
+// values per lane) is summed over the 8 lanes of each half-row with three DPP adds
+// (half-row mirror, then the two quad swaps).  On return register j of lane l holds the
+// total of value (V / 8) (4 b5 + 2 b4 + b3) + j (b_k = bit k of l); no LDS is involved.
+static __device__ __forceinline__ float dpp_ror8(float v)
 {
-#pragma unroll
-    for (int i = V; i < 16; ++i) x[i] = 0.0f;
-    // xor 32: keep half 0..7 or 8..15
-    {
-        const bool up = lane & 32;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float keep = up ? x[i + 8] : x[i];
-            const float send = up ? x[i] : x[i + 8];
-            x[i] = keep + __shfl_xor(send, 32);
-        }
-    }
-    {
-        const bool up = lane & 16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float keep = up ? x[i + 4] : x[i];
-            const float send = up ? x[i] : x[i + 4];
-            x[i] = keep + __shfl_xor(send, 16);
-        }
-    }
-    {
-        const bool up = lane & 8;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const float keep = up ? x[i + 2] : x[i];
-            const float send = up ? x[i] : x[i + 2];
-            x[i] = keep + __shfl_xor(send, 8);
-        }
-    }
-    float r;
-    {
-        const bool up = lane & 4;
-        const float keep = up ? x[1] : x[0];
-        const float send = up ? x[0] : x[1];
-        r = keep + __shfl_xor(send, 4);
-    }
-    r += __shfl_xor(r, 2);
-    r += __shfl_xor(r, 1);
-    return r;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+}
+static __device__ __forceinline__ float dpp_half_mirror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, false));
+}
+static __device__ __forceinline__ float dpp_xor2(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xf, 0xf, false));
+}
+static __device__ __forceinline__ float dpp_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
 }
 
-template <int C>
-__global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy, const GRec *__restrict__ rec,
+// Sum of one value over all 64 lanes (every lane receives the total).
+static __device__ __forceinline__ float reduce_full(float v)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    v += dpp_ror8(v);
+    v += dpp_half_mirror(v);
+    v += dpp_xor1(v);
+    v += dpp_xor2(v);
+    return v;
+}
+
+template <int V>
+static __device__ __forceinline__ void reduce_transposed(float (&x)[V], int lane)
+{
+    static_assert(V == 8 || V == 16, "8 or 16 values");
+    constexpr int H = V / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i + H]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[i + H / 2]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < H / 4; ++i) {
+        const float keep = b3 ? x[i + H / 4] : x[i];
+        const float send = b3 ? x[i] : x[i + H / 4];
+        x[i] = keep + dpp_ror8(send);
+    }
+#pragma unroll
+    for (int i = 0; i < V / 8; ++i) {
+        float r = x[i];
+        r += dpp_half_mirror(r);
+        r += dpp_xor1(r);
+        r += dpp_xor2(r);
+        x[i] = r;
+    }
+}
+
+template <int C, bool DEPTH, int F>
+__global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy, const GRec *__restrict__ rec,
                                                 const float2 *__restrict__ gspec, const float *__restrict__ dtab,
                                                 const double *__restrict__ d0tab, int nsx, int nsy, int sx_min,
                                                 int sy_min, const BItem *__restrict__ bitems,
                                                 float *__restrict__ bpartials, long long *__restrict__ counters,
                                                 int64_t n)
 {
-    constexpr int NV = 3 * C + 5;
+    // reduced values: Re P_c, Sfx, Sfy, Qxx, Qxy, Qyy, and with depth Im P_c, W_c; without
+    // depth the phase gradient's sum_m Im rho rides along as one extra fully reduced value
+    constexpr int NV = (DEPTH ? 3 : 1) * C + 5;
+    constexpr int NR = NV <= 8 ? 8 : 16;
+    constexpr int EXTRA_SLOT = 8;
     static_assert(NV <= 16, "too many accumulators");
+    static_assert(DEPTH || NV <= 8, "without depth the sums must fit 8 transposed values");
     __shared__ BEntry s_w[WAVES][64];
     __shared__ float s_acc[WAVES][64][NACC];
 
@@ -162,8 +194,9 @@ __global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restr
     const int64_t ns = (int64_t)nsx * nsy;
     const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int col = lane & (SUB - 1), row0 = lane >> 4;
-    const float dxf = (float)(col - SUB / 2);
+    constexpr int SY = sub_h(F), TY = 2 * SY;
+    const int col = lane & (SUBX - 1), row0 = lane >> 4;
+    const float dxf = (float)(col - SUBX / 2);
     long long pairs = 0;
 
     for (;;) {
@@ -187,12 +220,12 @@ __global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restr
             const int32_t txy = tile_xy[kt];
             const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
             for (int st = 0; st < 4; ++st) {
-                const int sx0 = tx * TILE + (st & 1) * SUB, sy0 = ty * TILE + (st >> 1) * SUB;
-                const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUB - 1, hx - 1);
-                const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SUB - 1, hy - 1);
+                const int sx0 = tx * TILEX + (st & 1) * SUBX, sy0 = ty * TY + (st >> 1) * SY;
+                const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUBX - 1, hx - 1);
+                const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SY - 1, hy - 1);
                 if (x0 > x1 || y0 > y1) continue;
-                const int cx = sx0 + SUB / 2, cy = sy0 + SUB / 2;
-                const int64_t sidx = (int64_t)(sy0 / SUB - sy_min) * nsx + (sx0 / SUB - sx_min);
+                const int cx = sx0 + SUBX / 2, cy = sy0 + SY / 2;
+                const int64_t sidx = (int64_t)(sy0 / SY - sy_min) * nsx + (sx0 / SUBX - sx_min);
                 // stage this sub-tile's accepted Gaussians
                 const bool p = gvalid && ellipse_meets_rect_b(r.alpha, r.beta2, r.gamma, lim, x0, x1, y0, y1);
                 const uint64_t bal = __ballot(p);
@@ -231,7 +264,7 @@ __global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restr
                     fmy[f] = (float)myp;
                     mxy[f] = fmx * fmy[f];
                     myy[f] = fmy[f] * fmy[f];
-                    dyf[f] = (float)(row0 + 4 * f - SUB / 2);
+                    dyf[f] = (float)(row0 + 4 * f - SY / 2);
                     const bool in = xin && myp >= -hy && myp < hy;
                     const int my = myp < 0 ? myp + k.ny : myp;
                     const int64_t o = (int64_t)my * k.nx + mx;
@@ -263,47 +296,62 @@ __global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restr
                     float Pr[C], Pi[C], Wc[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) Pr[c] = Pi[c] = Wc[c] = 0.0f;
-                    float sfx = 0.0f, sfy = 0.0f, qxx = 0.0f, qxy = 0.0f, qyy = 0.0f;
+                    // R0 = sum Re rho, R1 = sum m_y' Re rho, R2 = sum m_y'^2 Re rho, I0 = sum Im rho, I1 = sum m_y' Im rho
+                    float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f, I0 = 0.0f, I1 = 0.0f;
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
                         const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
                         const float E = __builtin_amdgcn_exp2f(-q);
-                        float rr = 0.0f, ri = 0.0f;
+                        float ur = 0.0f, ui = 0.0f;
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             const float th = fmaf(-z, dD[f][c], fmaf(-dyf[f], ryf, bx[c]));
                             const float sn = __builtin_amdgcn_sinf(th);
                             const float cs = __builtin_amdgcn_cosf(th);
+                            // conj(Gs) e^{j 2 pi th} = h + j k
                             const float h = fmaf(gr[f][c], cs, gi[f][c] * sn);
                             const float kk = fmaf(gr[f][c], sn, -gi[f][c] * cs);
-                            const float Eh = E * h, Ek = E * kk;
-                            Pr[c] += Eh;
-                            Pi[c] += Ek;
-                            Wc[c] = fmaf(dD[f][c], Ek, Wc[c]);
-                            rr = fmaf(amp[c], Eh, rr);
-                            ri = fmaf(amp[c], Ek, ri);
+                            Pr[c] = fmaf(E, h, Pr[c]);
+                            if (DEPTH) Pi[c] = fmaf(E, kk, Pi[c]);
+                            ur = fmaf(amp[c], h, ur);
+                            ui = fmaf(amp[c], kk, ui);
+                            if (DEPTH) Wc[c] = fmaf(dD[f][c] * E, kk, Wc[c]);
                         }
-                        sfx = fmaf(fmx, ri, sfx);
-                        sfy = fmaf(fmy[f], ri, sfy);
-                        qxx = fmaf(mxx, rr, qxx);
-                        qxy = fmaf(mxy[f], rr, qxy);
-                        qyy = fmaf(myy[f], rr, qyy);
+                        const float rr = E * ur, ri = E * ui;
+                        R0 += rr;
+                        R1 = fmaf(fmy[f], rr, R1);
+                        R2 = fmaf(myy[f], rr, R2);
+                        I0 += ri;
+                        I1 = fmaf(fmy[f], ri, I1);
                     }
-                    float x[16];
+                    // value layout: Re P_c (C), Sfx, Sfy, Qxx, Qxy, Qyy, then with depth Im P_c (C), W_c (C)
+                    float x[NR];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        x[2 * c] = Pr[c];
-                        x[2 * c + 1] = Pi[c];
-                        x[2 * C + c] = fmaf(D0f[c], Pi[c], Wc[c]);
+                    for (int c = 0; c < C; ++c) x[c] = Pr[c];
+                    x[C + 0] = fmx * I0;   // Sfx
+                    x[C + 1] = I1;         // Sfy
+                    x[C + 2] = mxx * R0;   // Qxx
+                    x[C + 3] = fmx * R1;   // Qxy
+                    x[C + 4] = R2;         // Qyy
+                    if (DEPTH) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            x[C + 5 + c] = Pi[c];
+                            x[2 * C + 5 + c] = fmaf(D0f[c], Pi[c], Wc[c]);
+                        }
                     }
-                    x[3 * C + 0] = sfx;
-                    x[3 * C + 1] = sfy;
-                    x[3 * C + 2] = qxx;
-                    x[3 * C + 3] = qxy;
-                    x[3 * C + 4] = qyy;
-                    const float red = reduce16<NV>(x, lane);
-                    const int v = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
-                    if ((lane & 3) == 0 && v < NV) s_acc[wave][owner][v] += red;
+#pragma unroll
+                    for (int i = NV; i < NR; ++i) x[i] = 0.0f;
+                    reduce_transposed<NR>(x, lane);
+                    float sim = 0.0f;
+                    if (!DEPTH) sim = reduce_full(I0);
+                    if ((lane & 7) == 0) {
+                        const int v0 = (NR / 8) * (((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1));
+#pragma unroll
+                        for (int j = 0; j < NR / 8; ++j)
+                            if (v0 + j < NV) s_acc[wave][owner][v0 + j] += x[j];
+                    }
+                    if (!DEPTH && lane == 0) s_acc[wave][owner][EXTRA_SLOT] += sim;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -318,14 +366,30 @@ __global__ void __launch_bounds__(WG) k_adjoint(Consts k, const int32_t *__restr
     if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
 }
 
+template <int C, int F>
+static hipError_t launch_adj_cf(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
+                                const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
+                                float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
+{
+    if (k.depth_grad)
+        hipLaunchKernelGGL((k_adjoint<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, rec, gspec, dtab, d0tab, nsx,
+                           nsy, sx_min, sy_min, bitems, bpartials, counters, n);
+    else
+        hipLaunchKernelGGL((k_adjoint<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, rec, gspec, dtab, d0tab,
+                           nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n);
+    return hipGetLastError();
+}
+
 template <int C>
 static hipError_t launch_adj_c(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
                                const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
                                float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adjoint<C>, dim3(grid), dim3(WG), 0, s, k, p.tile_xy, rec, gspec, dtab, d0tab, nsx, nsy, sx_min,
-                       sy_min, bitems, bpartials, counters, n);
-    return hipGetLastError();
+    switch (p.F) {
+    case 2: return launch_adj_cf<C, 2>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    case 8: return launch_adj_cf<C, 8>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    default: return launch_adj_cf<C, 4>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    }
 }
 
 hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
@@ -375,18 +439,25 @@ __global__ void __launch_bounds__(256) k_grad_final(gws_gaussians g, Consts k, c
     const double o = g.opacity[i];
     const double fx = 1.0 / (k.nx * k.px), fy = 1.0 / (k.ny * k.py);
     const double K = 2.0 * PI * sqrt(det) / (k.px * k.py * (double)k.nx * (double)k.ny);
-    double Sre = 0.0, Sim = 0.0, gz = 0.0, go = 0.0;
+    double Sre = 0.0, gz = 0.0, go = 0.0;
     for (int c = 0; c < C; ++c) {
         const double a = g.amplitude[(int64_t)c * g.n + i];
         const double A = a * o * K;
-        const double Pr = acc[2 * c], Pi = acc[2 * c + 1], Wc = acc[2 * C + c];
+        const double Pr = acc[c];
+        const double Pi = k.depth_grad ? acc[C + 5 + c] : 0.0, Wc = k.depth_grad ? acc[2 * C + 5 + c] : 0.0;
         Sre += A * Pr;
-        Sim += A * Pi;
         gz += A * (k.inv_lambda[c] * Pi + Wc);
         go += a * K * Pr;
         grads.amplitude[(int64_t)c * g.n + i] = (float)(o * K * Pr);
     }
-    const double Sfx = acc[3 * C], Sfy = acc[3 * C + 1], Qxx = acc[3 * C + 2], Qxy = acc[3 * C + 3], Qyy = acc[3 * C + 4];
+    const double Sfx = acc[C], Sfy = acc[C + 1], Qxx = acc[C + 2], Qxy = acc[C + 3], Qyy = acc[C + 4];
+    // sum_c A_c Im P_c (= sum_m Im rho): from Im P_c with depth, else the extra reduced slot
+    double Sim = 0.0;
+    if (k.depth_grad) {
+        for (int c = 0; c < C; ++c) Sim += (double)g.amplitude[(int64_t)c * g.n + i] * o * K * acc[C + 5 + c];
+    } else {
+        Sim = acc[8];
+    }
     grads.phase[i] = (float)(-Sim);
     grads.mean_x[i] = (float)(2.0 * PI * fx * Sfx);
     grads.mean_y[i] = (float)(2.0 * PI * fy * Sfy);

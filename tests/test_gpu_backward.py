@@ -21,13 +21,14 @@ def ctx():
     return gws.context(0)
 
 
-def check_grads(ctx, scene, grid, seed, tol=TOL_GRAD):
+def check_grads(ctx, scene, grid, seed, tol=TOL_GRAD, want_depth=True):
     import torch
     G = gwsgen.make_target(grid, seed)
-    got = ctx.backward(problem(grid), scene_to_torch(scene), torch.from_numpy(G).cuda())
+    got = ctx.backward(problem(grid), scene_to_torch(scene), torch.from_numpy(G).cuda(), want_depth=want_depth)
     ref = oracle.backward(scene, grid, G.astype(np.complex128))
     errs = {}
-    for k in ("mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity", "phase", "amplitude"):
+    names = ("mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity", "phase", "amplitude")
+    for k in names if want_depth else [n for n in names if n != "depth"]:
         errs[k] = rel_l2(to_numpy(got[k]), ref[k])
     print({k: "%.2e" % v for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
@@ -37,6 +38,12 @@ def check_grads(ctx, scene, grid, seed, tol=TOL_GRAD):
 def test_backward_small_workload(ctx):
     scene, grid = gwsgen.workload("small")
     check_grads(ctx, scene, grid, 501)
+
+
+def test_backward_without_depth_gradient(ctx):
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_scene(100, grid, 63, depth_range=(-10e-3, 10e-3))
+    check_grads(ctx, scene, grid, 64, want_depth=False)
 
 
 @pytest.mark.parametrize("nx,ny,n,seed", [(96, 80, 150, 61), (48, 40, 30, 62)])
@@ -62,3 +69,33 @@ def test_backward_is_deterministic(ctx):
     b = ctx.backward(problem(grid), scene_to_torch(scene), G)
     for k in a:
         assert torch.equal(a[k], b[k]), k
+
+
+def test_backward_with_bf16x3_transform(ctx):
+    import torch
+    import paper_2505_06582_amd as gws
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_scene(80, grid, 91, depth_range=(-10e-3, 10e-3))
+    G = gwsgen.make_target(grid, 92)
+    got = ctx.backward(problem(grid, xform=gws.XFORM_DFT_BF16X3), scene_to_torch(scene), torch.from_numpy(G).cuda())
+    ref = oracle.backward(scene, grid, G.astype(np.complex128))
+    for k in ref:
+        e = rel_l2(to_numpy(got[k]), ref[k])
+        assert e < 1e-3, (k, e)
+
+
+@pytest.mark.parametrize("cfg", list(range(1, 10)))
+@pytest.mark.parametrize("want_depth", [True, False])
+def test_backward_every_tiling(ctx, cfg, want_depth):
+    import torch
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_scene(60, grid, 200 + cfg, depth_range=(-10e-3, 10e-3))
+    G = gwsgen.make_target(grid, 300 + cfg)
+    got = ctx.backward(problem(grid, tile_config=cfg), scene_to_torch(scene), torch.from_numpy(G).cuda(),
+                       want_depth=want_depth)
+    ref = oracle.backward(scene, grid, G.astype(np.complex128))
+    for k in ref:
+        if k == "depth" and not want_depth:
+            continue
+        e = rel_l2(to_numpy(got[k]), ref[k])
+        assert e < TOL_GRAD, (cfg, k, e)
