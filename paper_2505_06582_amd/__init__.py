@@ -269,6 +269,70 @@ class Context:
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
         return grads
 
+    def workspace_size_batched(self, prob: Problem, offsets) -> int:
+        offs = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
+        sz = ctypes.c_size_t()
+        _check(self.lib.gws_workspace_size_batched(self.handle, ctypes.byref(prob._c()), len(offsets) - 1, offs,
+                                                   ctypes.byref(sz)), self.handle)
+        return sz.value
+
+    def forward_batched(self, prob: Problem, g: Dict[str, "object"], offsets, out=None):
+        """Fields of several scenes (Gaussians [offsets[s], offsets[s+1]) each), shape (S, C, ny, nx).
+
+        The first call for a given set of pointers and offsets captures the launch sequence
+        into a hipGraph (on a non-default stream); later calls replay it."""
+        torch = _torch()
+        S = len(offsets) - 1
+        n = int(g["mean_x"].numel())
+        field = out if out is not None else torch.empty((S, prob.n_lambda, prob.ny, prob.nx), dtype=torch.complex64,
+                                                        device=self.torch_device)
+        o = _Output()
+        o.field = field.data_ptr()
+        o.spectrum = None
+        offs = (ctypes.c_int64 * (S + 1))(*[int(v) for v in offsets])
+        need = self.workspace_size_batched(prob, offsets)
+        ws = self._batch_ws(need)
+        gs = _gaussians_struct(g, n)
+        _check(self.lib.gws_forward_batched(self.handle, ctypes.byref(prob._c()), S, offs, ctypes.byref(gs),
+                                            ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                            self._stream()), self.handle)
+        return field
+
+    def backward_batched(self, prob: Problem, g: Dict[str, "object"], offsets, grad_fields, want_depth: bool = True,
+                         out=None):
+        """Gradients of every Gaussian of the batch, given (S, C, ny, nx) field gradients."""
+        torch = _torch()
+        S = len(offsets) - 1
+        n = int(g["mean_x"].numel())
+        grads = dict(out) if out is not None else {k: torch.empty_like(g[k]) for k in PARAMS}
+        if not want_depth:
+            grads["depth"] = None
+        elif grads.get("depth") is None:
+            grads["depth"] = torch.empty_like(g["depth"])
+        gr = _Grads()
+        for k in PARAMS:
+            t = grads[k]
+            setattr(gr, k, t.data_ptr() if t is not None else None)
+        offs = (ctypes.c_int64 * (S + 1))(*[int(v) for v in offsets])
+        ws = self._batch_ws(self.workspace_size_batched(prob, offsets))
+        gs = _gaussians_struct(g, n)
+        _check(self.lib.gws_backward_batched(self.handle, ctypes.byref(prob._c()), S, offs, ctypes.byref(gs),
+                                             ctypes.c_void_p(grad_fields.data_ptr()), ctypes.byref(gr),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
+        return grads
+
+    def _batch_ws(self, nbytes: int):
+        # the batched workspace is part of the captured graph's key: keep it stable
+        torch = _torch()
+        if getattr(self, "_bws", None) is None or self._bws.numel() < nbytes:
+            self._bws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.torch_device)
+        return self._bws
+
+    def autotune(self, prob: Problem, n_hint: int, cache_path: Optional[str] = None):
+        """Time every tiling on n_hint synthetic Gaussians; later calls of this shape use the fastest."""
+        _check(self.lib.gws_autotune(self.handle, ctypes.byref(prob._c()), int(n_hint),
+                                     cache_path.encode() if cache_path else None, self._stream()), self.handle)
+
     def dft2d(self, x, direction: int, xform: int = XFORM_FFT_FP32, out=None):
         """Unnormalised 2D DFT of (batch, ny, nx) complex64: exp(+j..) for direction +1."""
         torch = _torch()

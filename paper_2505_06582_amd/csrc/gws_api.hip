@@ -2,6 +2,7 @@
 // workspace layout and the launch sequence of the forward and backward hot path.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -84,6 +85,7 @@ struct StageScope {
 };
 
 static thread_local std::string g_tls_error;
+static void load_tune_cache(gws_ctx *ctx, const char *path);
 
 static gws_status fail(gws_ctx *ctx, gws_status st, const std::string &msg)
 {
@@ -310,13 +312,12 @@ static int ntiles_for(int nx, int ny, int F)
     return ntx * nty;
 }
 
-// One workspace serves forward and backward under every tiling: tile arrays are sized
-// for the smallest tiles (F = 2), the partial-sum area is a fixed byte budget whose slot
-// count depends on the forward tiling, and the propagation table on the adjoint tiling.
+// Per-scene region.  One region serves forward and backward under every tiling: tile
+// arrays are sized for the smallest tiles (F = 2), the partial-sum area is a fixed byte
+// budget whose slot count depends on the forward tiling.
 static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
 {
     Layout L;
-    const int64_t M = (int64_t)p->nx * p->ny;
     const int C = p->n_lambda;
     const int ntiles = ntiles_for(p->nx, p->ny, 2);
     L.n = n;
@@ -333,7 +334,6 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
     L.sy_min = floor_div(-hy, SY);
     L.nsx = floor_div(hx - 1, SUBX) - L.sx_min + 1;
     L.nsy = floor_div(hy - 1, SY) - L.sy_min + 1;
-    const int nsy_max = floor_div(hy - 1, sub_h(2)) - floor_div(-hy, sub_h(2)) + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
     L.off_counters = take(sizeof(long long) * CTR_COUNT);
@@ -352,12 +352,55 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
     L.off_bitems = take(sizeof(BItem) * L.max_bitems);
     L.off_chunk_items = take(sizeof(int2) * (nchunks + 1));
     L.off_bpartials = take(sizeof(float) * (size_t)L.max_bslots * 64 * NACC);
-    L.off_spectrum = take(sizeof(float2) * (size_t)C * M);
-    L.off_gspec = take(sizeof(float2) * (size_t)C * M);
-    L.off_dtab = take(sizeof(float) * (size_t)C * M);
-    L.off_d0tab = take(sizeof(double) * (size_t)C * L.nsx * nsy_max);
     L.total = o;
     return L;
+}
+
+// Whole-call layout: a shared head (scene tables, queue heads, spectra, transformed field
+// gradients, propagation tables) followed by one region per scene.
+struct BatchLayout {
+    size_t total = 0;
+    size_t off_ctrl = 0, off_ftab = 0, off_btab = 0, off_prefix = 0, off_spectra = 0, off_gspecs = 0, off_dtab = 0,
+           off_d0tab = 0;
+    std::vector<size_t> scene_off;
+    std::vector<int64_t> n;
+};
+
+static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t *offsets)
+{
+    BatchLayout B;
+    const int64_t M = (int64_t)p->nx * p->ny;
+    const int C = p->n_lambda;
+    const int hx = p->nx / 2, hy = p->ny / 2;
+    const int nsx = floor_div(hx - 1, SUBX) - floor_div(-hx, SUBX) + 1;
+    const int nsy_max = floor_div(hy - 1, sub_h(2)) - floor_div(-hy, sub_h(2)) + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
+    B.off_ctrl = take(sizeof(long long) * 8);
+    B.off_ftab = take(sizeof(FwdScene) * S);
+    B.off_btab = take(sizeof(BwdScene) * S);
+    B.off_prefix = take(sizeof(int32_t) * (S + 1));
+    B.off_spectra = take(sizeof(float2) * (size_t)S * C * M);
+    B.off_gspecs = take(sizeof(float2) * (size_t)S * C * M);
+    B.off_dtab = take(sizeof(float) * (size_t)C * M);
+    B.off_d0tab = take(sizeof(double) * (size_t)C * nsx * nsy_max);
+    for (int i = 0; i < S; ++i) {
+        const int64_t ni = offsets[i + 1] - offsets[i];
+        B.n.push_back(ni);
+        B.scene_off.push_back(o);
+        o = align256(o + make_layout(p, ni, 2, 2).total);
+    }
+    B.total = o;
+    return B;
+}
+
+static gws_status check_offsets(int S, const int64_t *offsets, int64_t n)
+{
+    if (S < 1 || S > MAX_SCENES || !offsets) return GWS_ERR_INVALID_ARG;
+    if (offsets[0] != 0 || offsets[S] != n) return GWS_ERR_INVALID_ARG;
+    for (int i = 0; i < S; ++i)
+        if (offsets[i + 1] < offsets[i]) return GWS_ERR_INVALID_ARG;
+    return GWS_OK;
 }
 
 extern "C" gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *problem, int64_t n, size_t *bytes)
@@ -367,9 +410,23 @@ extern "C" gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *
     const gws_status st = gws_check_problem(problem);
     if (st != GWS_OK) return st;
     if (n > (int64_t)0x7fffffff) return GWS_ERR_INVALID_ARG;
-    *bytes = make_layout(problem, n, 2, 2).total;
+    const int64_t off[2] = {0, n};
+    *bytes = make_batch_layout(problem, 1, off).total;
     return GWS_OK;
 }
+
+extern "C" gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,
+                                                 const int64_t *offsets, size_t *bytes)
+{
+    (void)ctx;
+    if (!bytes || !offsets || n_scenes < 1) return GWS_ERR_INVALID_ARG;
+    const gws_status st = gws_check_problem(problem);
+    if (st != GWS_OK) return st;
+    if (check_offsets(n_scenes, offsets, offsets[n_scenes]) != GWS_OK) return GWS_ERR_INVALID_ARG;
+    *bytes = make_batch_layout(problem, n_scenes, offsets).total;
+    return GWS_OK;
+}
+
 
 // ---------------------------------------------------------------------------------
 // Context
@@ -392,7 +449,8 @@ extern "C" gws_status gws_create(gws_ctx **out, int device)
         delete ctx;
         return fail(nullptr, GWS_ERR_OOM, "cannot allocate the statistics buffer");
     }
-    hipMemset(ctx->d_stats, 0, sizeof(long long) * CTR_COUNT);
+    (void)hipMemset(ctx->d_stats, 0, sizeof(long long) * CTR_COUNT);
+    load_tune_cache(ctx, getenv("GWS_TUNE_CACHE"));
     *out = ctx;
     return GWS_OK;
 }
@@ -435,7 +493,7 @@ extern "C" gws_status gws_get_stats(gws_ctx *ctx, gws_stats *out)
 }
 
 // ---------------------------------------------------------------------------------
-// Forward / backward
+// Forward / backward over a batch of scenes (a single scene is a batch of one)
 // ---------------------------------------------------------------------------------
 static gws_status check_gaussians(gws_ctx *ctx, const gws_gaussians *g)
 {
@@ -444,6 +502,14 @@ static gws_status check_gaussians(gws_ctx *ctx, const gws_gaussians *g)
     if (g->n > 0 && (!g->mean_x || !g->mean_y || !g->depth || !g->cov_xx || !g->cov_xy || !g->cov_yy || !g->opacity ||
                      !g->amplitude || !g->phase))
         return fail(ctx, GWS_ERR_INVALID_ARG, "a Gaussian array is NULL");
+    return GWS_OK;
+}
+
+static gws_status check_grads(gws_ctx *ctx, const gws_grads *gr)
+{
+    if (!gr || !gr->mean_x || !gr->mean_y || !gr->cov_xx || !gr->cov_xy || !gr->cov_yy || !gr->opacity ||
+        !gr->amplitude || !gr->phase)
+        return fail(ctx, GWS_ERR_INVALID_ARG, "a gradient array is NULL");
     return GWS_OK;
 }
 
@@ -463,14 +529,12 @@ struct Bufs {
     int2 *tile_slots, *chunk_items;
     Item *items;
     BItem *bitems;
-    float2 *partials, *spectrum, *gspec;
-    float *bpartials, *dtab;
-    double *d0tab;
+    float2 *partials;
+    float *bpartials;
 };
 
-static Bufs carve(const Layout &L, void *ws)
+static Bufs carve(const Layout &L, char *b)
 {
-    char *b = (char *)ws;
     Bufs r;
     r.counters = (long long *)(b + L.off_counters);
     r.bucket_hist = (uint32_t *)(b + L.off_bucket_hist);
@@ -488,23 +552,51 @@ static Bufs carve(const Layout &L, void *ws)
     r.bitems = (BItem *)(b + L.off_bitems);
     r.chunk_items = (int2 *)(b + L.off_chunk_items);
     r.bpartials = (float *)(b + L.off_bpartials);
-    r.spectrum = (float2 *)(b + L.off_spectrum);
-    r.gspec = (float2 *)(b + L.off_gspec);
-    r.dtab = (float *)(b + L.off_dtab);
-    r.d0tab = (double *)(b + L.off_d0tab);
     return r;
 }
 
-// Preprocess + sort + records: shared by forward and backward.
-static gws_status run_prep(gws_ctx *ctx, const Consts &k, const gws_gaussians *g, const Layout &L, const Bufs &B,
-                           hipStream_t s, uint64_t **keys_sorted, uint32_t **vals_sorted)
+static GView scene_view(const gws_gaussians *g, int64_t off, int64_t n)
 {
-    StageScope sc(ctx, s, ST_PREP);
+    GView v;
+    v.n = n;
+    v.mean_x = g->mean_x ? g->mean_x + off : nullptr;
+    v.mean_y = g->mean_y ? g->mean_y + off : nullptr;
+    v.depth = g->depth ? g->depth + off : nullptr;
+    v.cov_xx = g->cov_xx ? g->cov_xx + off : nullptr;
+    v.cov_xy = g->cov_xy ? g->cov_xy + off : nullptr;
+    v.cov_yy = g->cov_yy ? g->cov_yy + off : nullptr;
+    v.opacity = g->opacity ? g->opacity + off : nullptr;
+    v.amplitude = g->amplitude ? g->amplitude + off : nullptr;
+    v.phase = g->phase ? g->phase + off : nullptr;
+    v.amp_stride = g->n;
+    return v;
+}
+
+static GradView grad_view(const gws_grads *g, int64_t off, int64_t total)
+{
+    GradView v;
+    v.mean_x = g->mean_x + off;
+    v.mean_y = g->mean_y + off;
+    v.depth = g->depth ? g->depth + off : nullptr;
+    v.cov_xx = g->cov_xx + off;
+    v.cov_xy = g->cov_xy + off;
+    v.cov_yy = g->cov_yy + off;
+    v.opacity = g->opacity + off;
+    v.amplitude = g->amplitude + off;
+    v.phase = g->phase + off;
+    v.amp_stride = total;
+    return v;
+}
+
+// Preprocess + sort + records of one scene: shared by forward and backward.
+static gws_status run_prep(gws_ctx *ctx, const Consts &k, const GView &g, const Layout &L, const Bufs &B, hipStream_t s,
+                           uint64_t **keys_sorted, uint32_t **vals_sorted)
+{
     HIP_CHECK(ctx, launch_zero_counters(B.counters, B.bucket_hist, s));
-    HIP_CHECK(ctx, launch_keys(*g, k, B.keys_a, B.vals_a, B.bucket_hist, B.counters, s));
-    HIP_CHECK(ctx, radix_sort_48(B.keys_a, B.vals_a, B.keys_b, B.vals_b, B.sort_hist, g->n, L.sort_blocks, s, keys_sorted,
+    HIP_CHECK(ctx, launch_keys(g, k, B.keys_a, B.vals_a, B.bucket_hist, B.counters, s));
+    HIP_CHECK(ctx, radix_sort_48(B.keys_a, B.vals_a, B.keys_b, B.vals_b, B.sort_hist, g.n, L.sort_blocks, s, keys_sorted,
                                  vals_sorted));
-    HIP_CHECK(ctx, launch_records(*g, k, *keys_sorted, *vals_sorted, B.rec, g->n, B.counters, s));
+    HIP_CHECK(ctx, launch_records(g, k, *keys_sorted, *vals_sorted, B.rec, g.n, B.counters, s));
     return GWS_OK;
 }
 
@@ -523,63 +615,174 @@ static int n_bucket(int64_t n)
     return b;
 }
 
-// Tiling for this call: the explicit one, else the one the autotuner chose for this shape
-// and size class, else the default.
+// Tiling for this call: the explicit one, else the autotuner's choice for this grid and
+// channel count at the nearest size class, else the default.
 static int resolve_tile_config(const gws_ctx *ctx, const gws_problem *prob, int64_t n)
 {
     if (prob->tile_config > 0) return prob->tile_config;
     if (ctx) {
-        auto it = ctx->tuned.find(std::make_tuple(prob->nx, prob->ny, prob->n_lambda, n_bucket(n)));
-        if (it != ctx->tuned.end()) return it->second;
+        const int b = n_bucket(n);
+        int best = -1, dist = 1 << 30;
+        for (auto &kv : ctx->tuned) {
+            if (std::get<0>(kv.first) != prob->nx || std::get<1>(kv.first) != prob->ny ||
+                std::get<2>(kv.first) != prob->n_lambda)
+                continue;
+            const int d = std::abs(std::get<3>(kv.first) - b);
+            if (d < dist) {
+                dist = d;
+                best = kv.second;
+            }
+        }
+        if (best > 0) return best;
     }
     return kDefaultTileCfg;
 }
 
-static gws_status forward_impl(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const gws_output *out,
-                               void *ws, size_t ws_bytes, hipStream_t s)
+static int64_t max_scene(int S, const int64_t *offsets)
 {
-    const int cfg = resolve_tile_config(ctx, prob, g->n);
+    int64_t m = 0;
+    for (int i = 0; i < S; ++i) m = std::max<int64_t>(m, offsets[i + 1] - offsets[i]);
+    return m;
+}
+
+static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, const int64_t *offsets,
+                              const gws_gaussians *g, const gws_output *out, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
     const int F = kTileCfg[cfg - 1][0];
     Plan *p = nullptr;
     gws_status st = get_plan(ctx, prob->nx, prob->ny, F, &p);
     if (st != GWS_OK) return st;
-    const Layout L = make_layout(prob, g->n, F, kTileCfg[cfg - 1][1]);
-    st = check_ws(ctx, ws, ws_bytes, make_layout(prob, g->n, 2, 2).total);
+    const BatchLayout BL = make_batch_layout(prob, S, offsets);
+    st = check_ws(ctx, ws, ws_bytes, BL.total);
     if (st != GWS_OK) return st;
-    const Bufs B = carve(L, ws);
+    char *base = (char *)ws;
     const Consts k = make_consts(prob, 1);
-    uint64_t *keys = nullptr;
-    uint32_t *vals = nullptr;
-    st = run_prep(ctx, k, g, L, B, s, &keys, &vals);
-    if (st != GWS_OK) return st;
+    const int64_t CM = (int64_t)k.C * prob->nx * prob->ny;
+    float2 *spectra = out->spectrum ? (float2 *)out->spectrum : (float2 *)(base + BL.off_spectra);
+    FwdTab tab;
+    memset(&tab, 0, sizeof(tab));
+    tab.n = S;
+    std::vector<long long *> ctrs(S);
+    {
+        StageScope sc(ctx, s, ST_PREP);
+        for (int i = 0; i < S; ++i) {
+            const Layout L = make_layout(prob, BL.n[i], F, kTileCfg[cfg - 1][1]);
+            const Bufs B = carve(L, base + BL.scene_off[i]);
+            uint64_t *keys = nullptr;
+            uint32_t *vals = nullptr;
+            st = run_prep(ctx, k, scene_view(g, offsets[i], BL.n[i]), L, B, s, &keys, &vals);
+            if (st != GWS_OK) return st;
+            HIP_CHECK(ctx, launch_bin_forward(*p, B.bucket_hist, B.cum, B.tile_L, B.tile_slots, B.items, L.max_items,
+                                              L.max_slots, B.counters, s));
+            tab.s[i] = FwdScene{B.rec, B.tile_L, B.items, B.tile_slots, B.partials, spectra + (int64_t)i * CM, B.counters};
+            ctrs[i] = B.counters;
+        }
+    }
+    FwdScene *dtab = (FwdScene *)(base + BL.off_ftab);
+    int32_t *prefix = (int32_t *)(base + BL.off_prefix);
+    long long *queue = (long long *)(base + BL.off_ctrl);
     {
         StageScope sc(ctx, s, ST_BIN);
-        HIP_CHECK(ctx, launch_bin_forward(*p, B.bucket_hist, B.cum, B.tile_L, B.tile_slots, B.items, L.max_items,
-                                          L.max_slots, B.counters, s));
+        HIP_CHECK(ctx, launch_fwd_table(tab, dtab, prefix, queue, s));
     }
-    float2 *spec = out->spectrum ? (float2 *)out->spectrum : B.spectrum;
     {
         StageScope sc(ctx, s, ST_ACCUM);
-        HIP_CHECK(ctx, launch_accumulate(*p, k, B.rec, B.tile_L, B.items, B.partials, spec, B.counters,
-                                         acc_grid(ctx, k.C, F), s));
+        HIP_CHECK(ctx, launch_accumulate(*p, k, dtab, prefix, S, queue, acc_grid(ctx, k.C, F), s));
     }
     {
         StageScope sc(ctx, s, ST_REDUCE);
-        HIP_CHECK(ctx, launch_reduce_partials(*p, k, B.tile_slots, B.partials, spec, s));
+        HIP_CHECK(ctx, launch_reduce_partials(*p, k, dtab, S, s));
     }
     {
         StageScope sc(ctx, s, ST_XFORM_INV);
-        if (prob->xform == GWS_XFORM_FFT_FP32) {
-            HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spec, (float2 *)out->field, s));
-        } else {
-            // the bf16 DFT keeps its split operands in the spare gspec/dtab region of the workspace
-            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)out->field, (void *)B.gspec, s));
-        }
+        if (prob->xform == GWS_XFORM_FFT_FP32)
+            HIP_CHECK(ctx, launch_fft2d(*p, S * k.C, +1, spectra, (float2 *)out->field, s));
+        else  // the bf16 DFT keeps its intermediate in the (forward-idle) gradient-spectrum area
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, S * k.C, +1, spectra, (float2 *)out->field,
+                                             (void *)(base + BL.off_gspecs), s));
     }
-    HIP_CHECK(ctx, launch_copy_counters(B.counters, ctx->d_stats, s));
+    HIP_CHECK(ctx, launch_sum_counters(ctrs.data(), S, ctx->d_stats, s));
     ctx->last_n = g->n;
     ctx->last_tile_config = cfg;
-    ctx->last_graph = 0;
+    return GWS_OK;
+}
+
+static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, const int64_t *offsets,
+                               const gws_gaussians *g, const void *grad_field, const gws_grads *grads, void *ws,
+                               size_t ws_bytes, hipStream_t s)
+{
+    const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
+    const int F = kTileCfg[cfg - 1][1];
+    Plan *p = nullptr;
+    gws_status st = get_plan(ctx, prob->nx, prob->ny, F, &p);
+    if (st != GWS_OK) return st;
+    const BatchLayout BL = make_batch_layout(prob, S, offsets);
+    st = check_ws(ctx, ws, ws_bytes, BL.total);
+    if (st != GWS_OK) return st;
+    char *base = (char *)ws;
+    Consts k = make_consts(prob, 0);
+    k.depth_grad = grads->depth != nullptr;
+    const int64_t CM = (int64_t)k.C * prob->nx * prob->ny;
+    float2 *gspecs = (float2 *)(base + BL.off_gspecs);
+    float *dtab = (float *)(base + BL.off_dtab);
+    double *d0tab = (double *)(base + BL.off_d0tab);
+    BwdTab tab;
+    memset(&tab, 0, sizeof(tab));
+    tab.n = S;
+    std::vector<long long *> ctrs(S);
+    std::vector<uint32_t *> vals_sorted(S);
+    Layout L0;
+    {
+        StageScope sc(ctx, s, ST_PREP);
+        for (int i = 0; i < S; ++i) {
+            const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], F);
+            if (i == 0) L0 = L;
+            const Bufs B = carve(L, base + BL.scene_off[i]);
+            uint64_t *keys = nullptr;
+            uint32_t *vals = nullptr;
+            st = run_prep(ctx, k, scene_view(g, offsets[i], BL.n[i]), L, B, s, &keys, &vals);
+            if (st != GWS_OK) return st;
+            HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, L.max_bitems, B.counters, BL.n[i], s));
+            tab.s[i] = BwdScene{B.rec, gspecs + (int64_t)i * CM, B.bitems, B.bpartials, B.counters, BL.n[i]};
+            ctrs[i] = B.counters;
+            vals_sorted[i] = vals;
+        }
+    }
+    {
+        // Gs = forward DFT of the field gradient (adjoint of the unnormalised inverse DFT)
+        StageScope sc(ctx, s, ST_XFORM_FWD);
+        if (prob->xform == GWS_XFORM_FFT_FP32)
+            HIP_CHECK(ctx, launch_fft2d(*p, S * k.C, -1, (const float2 *)grad_field, gspecs, s));
+        else
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, S * k.C, -1, (const float2 *)grad_field, gspecs,
+                                             (void *)(base + BL.off_spectra), s));
+    }
+    {
+        StageScope sc(ctx, s, ST_DTABLE);
+        HIP_CHECK(ctx, launch_dtable(k, dtab, d0tab, L0.nsx, L0.nsy, L0.sx_min, L0.sy_min, sub_h(F), s));
+    }
+    BwdScene *dscenes = (BwdScene *)(base + BL.off_btab);
+    int32_t *prefix = (int32_t *)(base + BL.off_prefix);
+    long long *queue = (long long *)(base + BL.off_ctrl) + 1;
+    {
+        StageScope sc(ctx, s, ST_ADJOINT);
+        HIP_CHECK(ctx, launch_bwd_table(tab, dscenes, prefix, queue, s));
+        HIP_CHECK(ctx, launch_adjoint(*p, k, dscenes, prefix, S, queue, dtab, d0tab, L0.nsx, L0.nsy, L0.sx_min, L0.sy_min,
+                                      ctx->n_cu * adjoint_occupancy(k.C, F, k.depth_grad), s));
+    }
+    {
+        StageScope sc(ctx, s, ST_FINAL);
+        for (int i = 0; i < S; ++i) {
+            const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], F);
+            const Bufs B = carve(L, base + BL.scene_off[i]);
+            HIP_CHECK(ctx, launch_grad_final(scene_view(g, offsets[i], BL.n[i]), k, vals_sorted[i], B.chunk_items,
+                                             B.bpartials, grad_view(grads, offsets[i], g->n), BL.n[i], B.counters, s));
+        }
+    }
+    HIP_CHECK(ctx, launch_sum_counters(ctrs.data(), S, ctx->d_stats, s));
+    ctx->last_n = g->n;
+    ctx->last_tile_config = cfg;
     return GWS_OK;
 }
 
@@ -593,65 +796,9 @@ extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const g
     if (st != GWS_OK) return st;
     if (!out || !out->field) return fail(ctx, GWS_ERR_INVALID_ARG, "output field is NULL");
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
-    return forward_impl(ctx, prob, g, out, ws, ws_bytes, (hipStream_t)stream);
-}
-
-static gws_status check_grads(gws_ctx *ctx, const gws_grads *gr)
-{
-    if (!gr || !gr->mean_x || !gr->mean_y || !gr->cov_xx || !gr->cov_xy || !gr->cov_yy || !gr->opacity ||
-        !gr->amplitude || !gr->phase)
-        return fail(ctx, GWS_ERR_INVALID_ARG, "a gradient array is NULL");
-    return GWS_OK;
-}
-
-static gws_status backward_impl(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const void *grad_field,
-                                const gws_grads *grads, void *ws, size_t ws_bytes, hipStream_t s)
-{
-    const int cfg = resolve_tile_config(ctx, prob, g->n);
-    const int F = kTileCfg[cfg - 1][1];
-    Plan *p = nullptr;
-    gws_status st = get_plan(ctx, prob->nx, prob->ny, F, &p);
-    if (st != GWS_OK) return st;
-    const Layout L = make_layout(prob, g->n, kTileCfg[cfg - 1][0], F);
-    st = check_ws(ctx, ws, ws_bytes, make_layout(prob, g->n, 2, 2).total);
-    if (st != GWS_OK) return st;
-    const Bufs B = carve(L, ws);
-    Consts k = make_consts(prob, 0);
-    k.depth_grad = grads->depth != nullptr;
-    uint64_t *keys = nullptr;
-    uint32_t *vals = nullptr;
-    st = run_prep(ctx, k, g, L, B, s, &keys, &vals);
-    if (st != GWS_OK) return st;
-    {
-        StageScope sc(ctx, s, ST_BIN);
-        HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, L.max_bitems, B.counters, g->n, s));
-    }
-    {
-        // Gs = forward DFT of the field gradient (adjoint of the unnormalised inverse DFT)
-        StageScope sc(ctx, s, ST_XFORM_FWD);
-        if (prob->xform == GWS_XFORM_FFT_FP32)
-            HIP_CHECK(ctx, launch_fft2d(*p, k.C, -1, (const float2 *)grad_field, B.gspec, s));
-        else
-            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, -1, (const float2 *)grad_field, B.gspec, (void *)B.spectrum, s));
-    }
-    {
-        StageScope sc(ctx, s, ST_DTABLE);
-        HIP_CHECK(ctx, launch_dtable(k, B.dtab, B.d0tab, L.nsx, L.nsy, L.sx_min, L.sy_min, sub_h(F), s));
-    }
-    {
-        StageScope sc(ctx, s, ST_ADJOINT);
-        HIP_CHECK(ctx, launch_adjoint2(*p, k, B.rec, B.gspec, B.dtab, B.d0tab, L.nsx, L.nsy, L.sx_min, L.sy_min,
-                                       B.bitems, B.bpartials, B.counters, g->n, ctx->n_cu * 4, s));
-    }
-    {
-        StageScope sc(ctx, s, ST_FINAL);
-        HIP_CHECK(ctx, launch_grad_final2(*g, k, vals, B.chunk_items, B.bpartials, *grads, g->n, B.counters, s));
-    }
-    HIP_CHECK(ctx, launch_copy_counters(B.counters, ctx->d_stats, s));
-    ctx->last_n = g->n;
-    ctx->last_tile_config = cfg;
+    const int64_t off[2] = {0, g->n};
     ctx->last_graph = 0;
-    return GWS_OK;
+    return forward_run(ctx, prob, 1, off, g, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
 extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const void *grad_field,
@@ -667,7 +814,136 @@ extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const 
     if (st != GWS_OK) return st;
     if (!grad_field) return fail(ctx, GWS_ERR_INVALID_ARG, "grad_field is NULL");
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
-    return backward_impl(ctx, prob, g, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
+    const int64_t off[2] = {0, g->n};
+    ctx->last_graph = 0;
+    return backward_run(ctx, prob, 1, off, g, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------------
+// Batched calls, captured into a hipGraph on first use and replayed afterwards
+// ---------------------------------------------------------------------------------
+static bool same_key(const gws_ctx::GraphKey &a, const gws_ctx::GraphKey &b)
+{
+    return a.backward == b.backward && a.offsets == b.offsets && a.ptrs == b.ptrs &&
+           memcmp(&a.prob, &b.prob, sizeof(gws_problem)) == 0;
+}
+
+template <class Fn>
+static gws_status run_graph(gws_ctx *ctx, const gws_ctx::GraphKey &key, hipStream_t s, Fn &&enqueue)
+{
+    for (auto &e : ctx->graphs)
+        if (same_key(e.first, key)) {
+            HIP_CHECK(ctx, hipGraphLaunch(e.second, s));
+            ctx->last_graph = 1;
+            return GWS_OK;
+        }
+    ctx->last_graph = 0;
+    if (s == nullptr) return enqueue();  // the legacy default stream cannot be captured: run directly
+    const int prof = ctx->profiling;
+    ctx->profiling = 0;  // events are not recorded inside a captured graph
+    hipGraph_t graph = nullptr;
+    HIP_CHECK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const gws_status st = enqueue();
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    ctx->profiling = prof;
+    if (st != GWS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ce != hipSuccess || !graph) return fail(ctx, GWS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(ctx, GWS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    ctx->graphs.emplace_back(key, exec);
+    HIP_CHECK(ctx, hipGraphLaunch(exec, s));
+    return GWS_OK;
+}
+
+static void key_ptrs_g(std::vector<uintptr_t> &v, const gws_gaussians *g)
+{
+    for (const void *q : {(const void *)g->mean_x, (const void *)g->mean_y, (const void *)g->depth, (const void *)g->cov_xx,
+                          (const void *)g->cov_xy, (const void *)g->cov_yy, (const void *)g->opacity,
+                          (const void *)g->amplitude, (const void *)g->phase})
+        v.push_back((uintptr_t)q);
+    v.push_back((uintptr_t)g->n);
+}
+
+// Plans and DFT matrices are built outside the capture (they allocate and copy).
+static gws_status prepare_plans(gws_ctx *ctx, const gws_problem *prob, int S, const int64_t *offsets)
+{
+    const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
+    for (int d = 0; d < 2; ++d) {
+        Plan *p = nullptr;
+        const gws_status st = get_plan(ctx, prob->nx, prob->ny, kTileCfg[cfg - 1][d], &p);
+        if (st != GWS_OK) return st;
+        if (prob->xform == GWS_XFORM_DFT_BF16X3) HIP_CHECK(ctx, build_dft_mats(*p));
+        (void)acc_grid(ctx, prob->n_lambda, kTileCfg[cfg - 1][0]);
+    }
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_forward_batched(gws_ctx *ctx, const gws_problem *prob, int32_t n_scenes, const int64_t *offsets,
+                                          const gws_gaussians *g, const gws_output *out, void *ws, size_t ws_bytes,
+                                          void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = gws_check_problem(prob);
+    if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    st = check_gaussians(ctx, g);
+    if (st != GWS_OK) return st;
+    if (!out || !out->field) return fail(ctx, GWS_ERR_INVALID_ARG, "output field is NULL");
+    if (check_offsets(n_scenes, offsets, g->n) != GWS_OK)
+        return fail(ctx, GWS_ERR_INVALID_ARG, "offsets must be a CSR array of n_scenes + 1 entries (1..64 scenes)");
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    st = prepare_plans(ctx, prob, n_scenes, offsets);
+    if (st != GWS_OK) return st;
+    gws_ctx::GraphKey key;
+    key.offsets.assign(offsets, offsets + n_scenes + 1);
+    key_ptrs_g(key.ptrs, g);
+    key.ptrs.push_back((uintptr_t)out->field);
+    key.ptrs.push_back((uintptr_t)out->spectrum);
+    key.ptrs.push_back((uintptr_t)ws);
+    key.ptrs.push_back((uintptr_t)ws_bytes);
+    key.prob = *prob;
+    key.backward = 0;
+    hipStream_t s = (hipStream_t)stream;
+    return run_graph(ctx, key, s, [&]() { return forward_run(ctx, prob, n_scenes, offsets, g, out, ws, ws_bytes, s); });
+}
+
+extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *prob, int32_t n_scenes, const int64_t *offsets,
+                                           const gws_gaussians *g, const void *grad_field, const gws_grads *grads,
+                                           void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = gws_check_problem(prob);
+    if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
+    st = check_gaussians(ctx, g);
+    if (st != GWS_OK) return st;
+    st = check_grads(ctx, grads);
+    if (st != GWS_OK) return st;
+    if (!grad_field) return fail(ctx, GWS_ERR_INVALID_ARG, "grad_field is NULL");
+    if (check_offsets(n_scenes, offsets, g->n) != GWS_OK)
+        return fail(ctx, GWS_ERR_INVALID_ARG, "offsets must be a CSR array of n_scenes + 1 entries (1..64 scenes)");
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    st = prepare_plans(ctx, prob, n_scenes, offsets);
+    if (st != GWS_OK) return st;
+    gws_ctx::GraphKey key;
+    key.offsets.assign(offsets, offsets + n_scenes + 1);
+    key_ptrs_g(key.ptrs, g);
+    key.ptrs.push_back((uintptr_t)grad_field);
+    for (const void *q : {(const void *)grads->mean_x, (const void *)grads->mean_y, (const void *)grads->depth,
+                          (const void *)grads->cov_xx, (const void *)grads->cov_xy, (const void *)grads->cov_yy,
+                          (const void *)grads->opacity, (const void *)grads->amplitude, (const void *)grads->phase})
+        key.ptrs.push_back((uintptr_t)q);
+    key.ptrs.push_back((uintptr_t)ws);
+    key.ptrs.push_back((uintptr_t)ws_bytes);
+    key.prob = *prob;
+    key.backward = 1;
+    hipStream_t s = (hipStream_t)stream;
+    return run_graph(ctx, key, s,
+                     [&]() { return backward_run(ctx, prob, n_scenes, offsets, g, grad_field, grads, ws, ws_bytes, s); });
 }
 
 // ---------------------------------------------------------------------------------
@@ -710,25 +986,145 @@ extern "C" gws_status gws_dft2d(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t ba
 }
 
 // ---------------------------------------------------------------------------------
-// Batched scenes and autotuning: not yet available.
+// Autotuner: time each accumulation tiling and each adjoint tiling on synthetic
+// Gaussians of the requested count, keep the fastest pair for this grid and size class.
 // ---------------------------------------------------------------------------------
-extern "C" gws_status gws_workspace_size_batched(const gws_ctx *, const gws_problem *, int32_t, const int64_t *, size_t *)
+static std::string tune_line(const gws_problem *p, int nb, int cfg, const double *tf, const double *tb)
 {
-    return GWS_ERR_UNSUPPORTED;
+    char buf[512];
+    snprintf(buf, sizeof(buf),
+             "{\"arch\": \"gfx950\", \"nx\": %d, \"ny\": %d, \"n_lambda\": %d, \"n_bucket\": %d, \"tile_config\": %d, "
+             "\"fwd_ms\": {\"2\": %.4f, \"4\": %.4f, \"8\": %.4f}, \"bwd_ms\": {\"2\": %.4f, \"4\": %.4f, \"8\": %.4f}}",
+             p->nx, p->ny, p->n_lambda, nb, cfg, tf[0], tf[1], tf[2], tb[0], tb[1], tb[2]);
+    return buf;
 }
-extern "C" gws_status gws_forward_batched(gws_ctx *ctx, const gws_problem *, int32_t, const int64_t *, const gws_gaussians *,
-                                          const gws_output *, void *, size_t, void *)
+
+static bool parse_tune_line(const std::string &l, int *nx, int *ny, int *C, int *nb, int *cfg)
 {
-    return fail(ctx, GWS_ERR_UNSUPPORTED, "batched forward not built");
+    return sscanf(l.c_str(),
+                  "{\"arch\": \"gfx950\", \"nx\": %d, \"ny\": %d, \"n_lambda\": %d, \"n_bucket\": %d, \"tile_config\": %d",
+                  nx, ny, C, nb, cfg) == 5;
 }
-extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *, int32_t, const int64_t *, const gws_gaussians *,
-                                           const void *, const gws_grads *, void *, size_t, void *)
+
+static void load_tune_cache(gws_ctx *ctx, const char *path)
 {
-    return fail(ctx, GWS_ERR_UNSUPPORTED, "batched backward not built");
+    FILE *f = path ? fopen(path, "r") : nullptr;
+    if (!f) return;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+        int nx, ny, C, nb, cfg;
+        if (parse_tune_line(line, &nx, &ny, &C, &nb, &cfg) && cfg >= 1 && cfg <= kNumTileCfg)
+            ctx->tuned[std::make_tuple(nx, ny, C, nb)] = cfg;
+    }
+    fclose(f);
 }
-extern "C" gws_status gws_autotune(gws_ctx *ctx, const gws_problem *, int64_t, const char *, void *)
+
+static void merge_tune_cache(const char *path, const gws_problem *p, int nb, const std::string &entry)
 {
-    return fail(ctx, GWS_ERR_UNSUPPORTED, "autotuner not built");
+    std::vector<std::string> keep;
+    if (FILE *f = fopen(path, "r")) {
+        char line[1024];
+        while (fgets(line, sizeof(line), f)) {
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+            int nx, ny, C, b, cfg;
+            if (!parse_tune_line(l, &nx, &ny, &C, &b, &cfg)) continue;
+            if (nx == p->nx && ny == p->ny && C == p->n_lambda && b == nb) continue;
+            keep.push_back(l);
+        }
+        fclose(f);
+    }
+    keep.push_back(entry);
+    if (FILE *f = fopen(path, "w")) {
+        for (auto &l : keep) fprintf(f, "%s\n", l.c_str());
+        fclose(f);
+    }
+}
+
+extern "C" gws_status gws_autotune(gws_ctx *ctx, const gws_problem *prob, int64_t n_hint, const char *cache_path,
+                                   void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = gws_check_problem(prob);
+    if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    if (n_hint < 1 || n_hint > (int64_t)0x7fffffff) return fail(ctx, GWS_ERR_INVALID_ARG, "n_hint out of range");
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int C = prob->n_lambda;
+    const int64_t n = n_hint, M = (int64_t)prob->nx * prob->ny;
+    const int64_t off[2] = {0, n};
+    const size_t ws_bytes = make_batch_layout(prob, 1, off).total;
+    float *gbuf = nullptr, *grbuf = nullptr;
+    float2 *field = nullptr;
+    void *ws = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(gbuf);
+        (void)hipFree(grbuf);
+        (void)hipFree(field);
+        (void)hipFree(ws);
+    };
+    if (hipMalloc(&gbuf, sizeof(float) * (8 + C) * n) != hipSuccess ||
+        hipMalloc(&grbuf, sizeof(float) * (8 + C) * n) != hipSuccess ||
+        hipMalloc(&field, sizeof(float2) * C * M) != hipSuccess || hipMalloc(&ws, ws_bytes) != hipSuccess) {
+        cleanup();
+        return fail(ctx, GWS_ERR_OOM, "autotune buffers");
+    }
+    gws_gaussians g;
+    g.n = n;
+    g.mean_x = gbuf; g.mean_y = gbuf + n; g.depth = gbuf + 2 * n; g.cov_xx = gbuf + 3 * n; g.cov_xy = gbuf + 4 * n;
+    g.cov_yy = gbuf + 5 * n; g.opacity = gbuf + 6 * n; g.phase = gbuf + 7 * n; g.amplitude = gbuf + 8 * n;
+    gws_grads gr;
+    gr.mean_x = grbuf; gr.mean_y = grbuf + n; gr.depth = nullptr; gr.cov_xx = grbuf + 3 * n; gr.cov_xy = grbuf + 4 * n;
+    gr.cov_yy = grbuf + 5 * n; gr.opacity = grbuf + 6 * n; gr.phase = grbuf + 7 * n; gr.amplitude = grbuf + 8 * n;
+    const Consts k = make_consts(prob, 1);
+    GView dummy;
+    memset(&dummy, 0, sizeof(dummy));
+    if (launch_synth(dummy, gbuf, n, 0x5eed5eedull, k, s) != hipSuccess) {
+        cleanup();
+        return fail(ctx, GWS_ERR_HIP, "synthetic Gaussians");
+    }
+    gws_output out{field, nullptr};
+    const int Fs[3] = {2, 4, 8};
+    double tf[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int prof = ctx->profiling;
+    ctx->profiling = 0;
+    gws_problem q = *prob;
+    for (int d = 0; d < 2 && st == GWS_OK; ++d)
+        for (int j = 0; j < 3 && st == GWS_OK; ++j) {
+            // any tiling whose F for this direction is Fs[j]
+            int cfg = 1;
+            for (int c = 0; c < kNumTileCfg; ++c)
+                if (kTileCfg[c][d] == Fs[j]) { cfg = c + 1; break; }
+            q.tile_config = cfg;
+            for (int rep = 0; rep < 3 && st == GWS_OK; ++rep) {
+                if (rep == 1) (void)hipEventRecord(e0, s);
+                st = d == 0 ? forward_run(ctx, &q, 1, off, &g, &out, ws, ws_bytes, s)
+                            : backward_run(ctx, &q, 1, off, &g, field, &gr, ws, ws_bytes, s);
+            }
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            (d == 0 ? tf : tb)[j] = ms / 2.0;
+        }
+    ctx->profiling = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const hipError_t se = hipStreamSynchronize(s);
+    cleanup();
+    if (st != GWS_OK) return st;
+    if (se != hipSuccess) return fail(ctx, GWS_ERR_HIP, hipGetErrorString(se));
+    const int bf = (int)(std::min_element(tf, tf + 3) - tf), bb = (int)(std::min_element(tb, tb + 3) - tb);
+    int best = kDefaultTileCfg;
+    for (int c = 0; c < kNumTileCfg; ++c)
+        if (kTileCfg[c][0] == Fs[bf] && kTileCfg[c][1] == Fs[bb]) best = c + 1;
+    const int nb = n_bucket(n);
+    ctx->tuned[std::make_tuple(prob->nx, prob->ny, C, nb)] = best;
+    if (cache_path) merge_tune_cache(cache_path, prob, nb, tune_line(prob, nb, best, tf, tb));
+    return GWS_OK;
 }
 
 // ---------------------------------------------------------------------------------

@@ -55,6 +55,53 @@ struct BItem {
     int32_t slot;
 };
 
+// Gaussians of one scene: a view into caller arrays; amplitude channel c of Gaussian i is
+// amplitude[c * amp_stride + i] (amp_stride = total Gaussians of the concatenated batch).
+struct GView {
+    int64_t n;
+    const float *mean_x, *mean_y, *depth, *cov_xx, *cov_xy, *cov_yy, *opacity, *amplitude, *phase;
+    int64_t amp_stride;
+};
+
+struct GradView {
+    float *mean_x, *mean_y, *depth, *cov_xx, *cov_xy, *cov_yy, *opacity, *amplitude, *phase;
+    int64_t amp_stride;
+};
+
+constexpr int MAX_SCENES = 64;
+
+// Per-scene pointers of the forward accumulation.
+struct FwdScene {
+    const GRec *rec;
+    const int32_t *tile_L;
+    const Item *items;
+    const int2 *tile_slots;
+    float2 *partials;
+    float2 *spectrum;
+    long long *counters;
+};
+
+// Per-scene pointers of the adjoint.
+struct BwdScene {
+    const GRec *rec;
+    const float2 *gspec;
+    const BItem *bitems;
+    float *bpartials;
+    long long *counters;
+    int64_t n;
+};
+
+struct FwdTab {
+    int32_t n;
+    int32_t pad;
+    FwdScene s[MAX_SCENES];
+};
+struct BwdTab {
+    int32_t n;
+    int32_t pad;
+    BwdScene s[MAX_SCENES];
+};
+
 // Scalar problem constants passed by value to kernels.
 struct Consts {
     int32_t nx, ny, C, pad0;
@@ -120,12 +167,12 @@ enum Counter {
 };
 
 // ---- kernel launchers (each enqueues on `stream`, returns hipError_t) ----
-hipError_t launch_keys(const gws_gaussians &g, const Consts &k, uint64_t *keys, uint32_t *vals,
+hipError_t launch_keys(const GView &g, const Consts &k, uint64_t *keys, uint32_t *vals,
                        uint32_t *bucket_hist, long long *counters, hipStream_t s);
 hipError_t radix_sort_48(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b,
                          uint32_t *block_hist, int64_t n, int nblocks, hipStream_t s,
                          uint64_t **keys_out, uint32_t **vals_out);
-hipError_t launch_records(const gws_gaussians &g, const Consts &k, const uint64_t *keys,
+hipError_t launch_records(const GView &g, const Consts &k, const uint64_t *keys,
                           const uint32_t *vals, GRec *rec, int64_t n, const long long *counters,
                           hipStream_t s);
 hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32_t *cum, int32_t *tile_L,
@@ -133,19 +180,24 @@ hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32
                               long long *counters, hipStream_t s);
 hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
                                int64_t max_bitems, long long *counters, int64_t n, hipStream_t s);
-hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
-                             const Item *items, float2 *partials, float2 *spectrum, long long *counters,
-                             int grid, hipStream_t s);
-hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const int2 *tile_slots,
-                                  const float2 *partials, float2 *spectrum, hipStream_t s);
+// Writes the scene table and the prefix of per-scene work-item counts, zeroes the queue head.
+hipError_t launch_fwd_table(const FwdTab &tab, FwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s);
+hipError_t launch_bwd_table(const BwdTab &tab, BwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s);
+hipError_t launch_accumulate(const Plan &p, const Consts &k, const FwdScene *scenes, const int32_t *prefix,
+                             int n_scenes, long long *queue, int grid, hipStream_t s);
+hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes,
+                                  hipStream_t s);
 hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
                          hipStream_t s);
-hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
-                           const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
-                           float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s);
-hipError_t launch_grad_final2(const gws_gaussians &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
-                              const float *bpartials, const gws_grads &grads, int64_t n, const long long *counters,
-                              hipStream_t s);
+hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,
+                          long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy, int sx_min,
+                          int sy_min, int grid, hipStream_t s);
+hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
+                             const float *bpartials, const GradView &grads, int64_t n, const long long *counters,
+                             hipStream_t s);
+hipError_t launch_sum_counters(long long *const *src, int n, long long *dst, hipStream_t s);
+int adjoint_occupancy(int C, int F, int depth);
+hipError_t launch_synth(GView g, float *base, int64_t n, uint64_t seed, const Consts &k, hipStream_t s);
 int accumulate_occupancy(int C, int F);
 hipError_t launch_zero_counters(long long *counters, uint32_t *bucket_hist, hipStream_t s);
 hipError_t launch_copy_counters(const long long *src, long long *dst, hipStream_t s);

@@ -59,34 +59,44 @@ struct alignas(16) WEntry {
     float base[4];
 };
 
+// One persistent launch serves every scene of a batch: the queue head walks the
+// concatenation of the scenes' work-item lists (prefix[s] = first item of scene s).
 template <int C, bool EVAN, int F>
-__global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, int32_t tx_lo, const int32_t *__restrict__ tile_xy,
-                                                   const GRec *__restrict__ rec, const int32_t *__restrict__ tile_L,
-                                                   const Item *__restrict__ items, float2 *__restrict__ partials,
-                                                   float2 *__restrict__ spectrum, long long *__restrict__ counters)
+__global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *__restrict__ tile_xy,
+                                                   const FwdScene *__restrict__ scenes, const int32_t *__restrict__ prefix,
+                                                   int n_scenes, long long *__restrict__ queue)
 {
     __shared__ GRec s_rec[WG];
     __shared__ WEntry s_w[WAVES][64];
-    __shared__ int s_item;
+    __shared__ int s_item, s_scene;
     __shared__ int s_cnt[WAVES];
 
     constexpr int SY = sub_h(F), TY = 2 * SY;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nitems = (int)counters[CTR_NITEMS];
-    const int CH = (int)counters[CTR_CHUNK];
+    const int total_items = prefix[n_scenes];
     const int hx = k.nx / 2, hy = k.ny / 2;
     const double Wx = k.nx * k.px, Wy = k.ny * k.py;
     const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
-    (void)tx_lo;
-    long long pairs = 0;
 
     for (;;) {
-        if (tid == 0) s_item = (int)atomicAdd((unsigned long long *)&counters[CTR_WORK], 1ull);
+        if (tid == 0) {
+            const int q = (int)atomicAdd((unsigned long long *)queue, 1ull);
+            int sc = 0;
+            if (q < total_items)
+                while (sc + 1 < n_scenes && prefix[sc + 1] <= q) ++sc;
+            s_item = q;
+            s_scene = sc;
+        }
         __syncthreads();
-        const int item = s_item;
+        const int gitem = s_item, scene = s_scene;
         __syncthreads();
-        if (item >= nitems) break;
-        const Item it = items[item];
+        if (gitem >= total_items) break;
+        const FwdScene S = scenes[scene];
+        const GRec *__restrict__ rec = S.rec;
+        const Item it = S.items[gitem - prefix[scene]];
+        const int CH = (int)S.counters[CTR_CHUNK];
+        const int32_t *__restrict__ tile_L = S.tile_L;
+        long long pairs = 0;
         const int32_t txy = tile_xy[it.tile];
         const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
         const int L = tile_L[it.tile];
@@ -237,24 +247,26 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, int32_t tx_lo, c
                 if (it.slot < 0) {
                     if (valid) {
                         const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
-                        spectrum[((int64_t)c * k.ny + my) * k.nx + mx] = v;
+                        S.spectrum[((int64_t)c * k.ny + my) * k.nx + mx] = v;
                     }
                 } else {
-                    partials[(((int64_t)it.slot * C + c) * F + f) * WG + tid] = v;
+                    S.partials[(((int64_t)it.slot * C + c) * F + f) * WG + tid] = v;
                 }
             }
         }
+        if (lane == 0 && pairs) atomicAdd((unsigned long long *)&S.counters[CTR_PAIRS], (unsigned long long)pairs);
     }
-    if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
 }
 
 template <int C, int F>
 __global__ void __launch_bounds__(WG) k_reduce_partials(Consts k, const int32_t *__restrict__ tile_xy,
-                                                        const int2 *__restrict__ tile_slots,
-                                                        const float2 *__restrict__ partials, float2 *__restrict__ spectrum)
+                                                        const FwdScene *__restrict__ scenes)
 {
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int2 ts = tile_slots[t];
+    const FwdScene S = scenes[blockIdx.y];
+    const float2 *__restrict__ partials = S.partials;
+    float2 *__restrict__ spectrum = S.spectrum;
+    const int2 ts = S.tile_slots[t];
     if (ts.x == 1) return;  // written directly by the accumulation
     const int32_t txy = tile_xy[t];
     const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
@@ -293,63 +305,59 @@ static bool tile_needs_evanescent(const Plan &p, const Consts &k)
 }
 
 template <int C, int F>
-static hipError_t launch_acc_cf(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
-                                const Item *items, float2 *partials, float2 *spectrum, long long *counters, int grid,
-                                hipStream_t s)
+static hipError_t launch_acc_cf(const Plan &p, const Consts &k, const FwdScene *scenes, const int32_t *prefix,
+                                int n_scenes, long long *queue, int grid, hipStream_t s)
 {
     if (tile_needs_evanescent(p, k))
-        hipLaunchKernelGGL((k_accumulate<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
-                           items, partials, spectrum, counters);
+        hipLaunchKernelGGL((k_accumulate<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, scenes, prefix, n_scenes,
+                           queue);
     else
-        hipLaunchKernelGGL((k_accumulate<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tx_min, p.tile_xy, rec, tile_L,
-                           items, partials, spectrum, counters);
+        hipLaunchKernelGGL((k_accumulate<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, scenes, prefix, n_scenes,
+                           queue);
     return hipGetLastError();
 }
 
 template <int C>
-static hipError_t launch_acc_c(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L,
-                               const Item *items, float2 *partials, float2 *spectrum, long long *counters, int grid,
-                               hipStream_t s)
+static hipError_t launch_acc_c(const Plan &p, const Consts &k, const FwdScene *scenes, const int32_t *prefix,
+                               int n_scenes, long long *queue, int grid, hipStream_t s)
 {
     switch (p.F) {
-    case 2: return launch_acc_cf<C, 2>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
-    case 8: return launch_acc_cf<C, 8>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
-    default: return launch_acc_cf<C, 4>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    case 2: return launch_acc_cf<C, 2>(p, k, scenes, prefix, n_scenes, queue, grid, s);
+    case 8: return launch_acc_cf<C, 8>(p, k, scenes, prefix, n_scenes, queue, grid, s);
+    default: return launch_acc_cf<C, 4>(p, k, scenes, prefix, n_scenes, queue, grid, s);
     }
 }
 
-hipError_t launch_accumulate(const Plan &p, const Consts &k, const GRec *rec, const int32_t *tile_L, const Item *items,
-                             float2 *partials, float2 *spectrum, long long *counters, int grid, hipStream_t s)
+hipError_t launch_accumulate(const Plan &p, const Consts &k, const FwdScene *scenes, const int32_t *prefix, int n_scenes,
+                             long long *queue, int grid, hipStream_t s)
 {
     switch (k.C) {
-    case 1: return launch_acc_c<1>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
-    case 2: return launch_acc_c<2>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
-    case 3: return launch_acc_c<3>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
-    case 4: return launch_acc_c<4>(p, k, rec, tile_L, items, partials, spectrum, counters, grid, s);
+    case 1: return launch_acc_c<1>(p, k, scenes, prefix, n_scenes, queue, grid, s);
+    case 2: return launch_acc_c<2>(p, k, scenes, prefix, n_scenes, queue, grid, s);
+    case 3: return launch_acc_c<3>(p, k, scenes, prefix, n_scenes, queue, grid, s);
+    case 4: return launch_acc_c<4>(p, k, scenes, prefix, n_scenes, queue, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int C>
-static void launch_red_c(const Plan &p, const Consts &k, const int2 *tile_slots, const float2 *partials, float2 *spectrum,
-                         hipStream_t s)
+static void launch_red_c(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes, hipStream_t s)
 {
-    const dim3 grid(p.ntiles), block(WG);
+    const dim3 grid(p.ntiles, n_scenes), block(WG);
     switch (p.F) {
-    case 2: hipLaunchKernelGGL((k_reduce_partials<C, 2>), grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
-    case 8: hipLaunchKernelGGL((k_reduce_partials<C, 8>), grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
-    default: hipLaunchKernelGGL((k_reduce_partials<C, 4>), grid, block, 0, s, k, p.tile_xy, tile_slots, partials, spectrum); break;
+    case 2: hipLaunchKernelGGL((k_reduce_partials<C, 2>), grid, block, 0, s, k, p.tile_xy, scenes); break;
+    case 8: hipLaunchKernelGGL((k_reduce_partials<C, 8>), grid, block, 0, s, k, p.tile_xy, scenes); break;
+    default: hipLaunchKernelGGL((k_reduce_partials<C, 4>), grid, block, 0, s, k, p.tile_xy, scenes); break;
     }
 }
 
-hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const int2 *tile_slots, const float2 *partials,
-                                  float2 *spectrum, hipStream_t s)
+hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes, hipStream_t s)
 {
     switch (k.C) {
-    case 1: launch_red_c<1>(p, k, tile_slots, partials, spectrum, s); break;
-    case 2: launch_red_c<2>(p, k, tile_slots, partials, spectrum, s); break;
-    case 3: launch_red_c<3>(p, k, tile_slots, partials, spectrum, s); break;
-    case 4: launch_red_c<4>(p, k, tile_slots, partials, spectrum, s); break;
+    case 1: launch_red_c<1>(p, k, scenes, n_scenes, s); break;
+    case 2: launch_red_c<2>(p, k, scenes, n_scenes, s); break;
+    case 3: launch_red_c<3>(p, k, scenes, n_scenes, s); break;
+    case 4: launch_red_c<4>(p, k, scenes, n_scenes, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

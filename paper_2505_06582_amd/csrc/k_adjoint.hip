@@ -169,12 +169,11 @@ static __device__ __forceinline__ void reduce_transposed(float (&x)[V], int lane
 }
 
 template <int C, bool DEPTH, int F>
-__global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy, const GRec *__restrict__ rec,
-                                                const float2 *__restrict__ gspec, const float *__restrict__ dtab,
-                                                const double *__restrict__ d0tab, int nsx, int nsy, int sx_min,
-                                                int sy_min, const BItem *__restrict__ bitems,
-                                                float *__restrict__ bpartials, long long *__restrict__ counters,
-                                                int64_t n)
+__global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy,
+                                                const BwdScene *__restrict__ scenes, const int32_t *__restrict__ prefix,
+                                                int n_scenes, long long *__restrict__ queue,
+                                                const float *__restrict__ dtab, const double *__restrict__ d0tab,
+                                                int nsx, int nsy, int sx_min, int sy_min)
 {
     // reduced values: Re P_c, Sfx, Sfy, Qxx, Qxy, Qyy, and with depth Im P_c, W_c; without
     // depth the phase gradient's sum_m Im rho rides along as one extra fully reduced value
@@ -187,8 +186,7 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
     __shared__ float s_acc[WAVES][64][NACC];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nitems = (int)counters[CTR_NBITEMS];
-    const int64_t nvalid = n - counters[CTR_NCULLED];
+    const int total_items = prefix[n_scenes];
     const int hx = k.nx / 2, hy = k.ny / 2;
     const int64_t M = (int64_t)k.nx * k.ny;
     const int64_t ns = (int64_t)nsx * nsy;
@@ -197,14 +195,22 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
     constexpr int SY = sub_h(F), TY = 2 * SY;
     const int col = lane & (SUBX - 1), row0 = lane >> 4;
     const float dxf = (float)(col - SUBX / 2);
-    long long pairs = 0;
-
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = (int)atomicAdd((unsigned long long *)&counters[CTR_BWORK], 1ull);
-        item = __shfl(item, 0);
-        if (item >= nitems) break;
-        const BItem bi = bitems[item];
+        int q = 0, sc = 0;
+        if (lane == 0) {
+            q = (int)atomicAdd((unsigned long long *)queue, 1ull);
+            if (q < total_items)
+                while (sc + 1 < n_scenes && prefix[sc + 1] <= q) ++sc;
+        }
+        q = __shfl(q, 0);
+        sc = __shfl(sc, 0);
+        if (q >= total_items) break;
+        const BwdScene S = scenes[sc];
+        const GRec *__restrict__ rec = S.rec;
+        const float2 *__restrict__ gspec = S.gspec;
+        const int64_t nvalid = S.n - S.counters[CTR_NCULLED];
+        const BItem bi = S.bitems[q - prefix[sc]];
+        long long pairs = 0;
         const int64_t gidx = (int64_t)bi.chunk * 64 + lane;
         const bool gvalid = gidx < nvalid;
         GRec r;
@@ -358,56 +364,62 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        float *dst = bpartials + ((int64_t)bi.slot * 64 + lane) * NACC;
+        float *dst = S.bpartials + ((int64_t)bi.slot * 64 + lane) * NACC;
 #pragma unroll
         for (int v = 0; v < NACC; ++v) dst[v] = s_acc[wave][lane][v];
         __builtin_amdgcn_wave_barrier();
+        if (lane == 0 && pairs) atomicAdd((unsigned long long *)&S.counters[CTR_PAIRS], (unsigned long long)pairs);
     }
-    if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
 }
 
 template <int C, int F>
-static hipError_t launch_adj_cf(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
-                                const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
-                                float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
+static hipError_t launch_adj_cf(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix,
+                                int n_scenes, long long *queue, const float *dtab, const double *d0tab, int nsx,
+                                int nsy, int sx_min, int sy_min, int grid, hipStream_t s)
 {
     if (k.depth_grad)
-        hipLaunchKernelGGL((k_adjoint<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, rec, gspec, dtab, d0tab, nsx,
-                           nsy, sx_min, sy_min, bitems, bpartials, counters, n);
+        hipLaunchKernelGGL((k_adjoint<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, scenes, prefix, n_scenes,
+                           queue, dtab, d0tab, nsx, nsy, sx_min, sy_min);
     else
-        hipLaunchKernelGGL((k_adjoint<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, rec, gspec, dtab, d0tab,
-                           nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n);
+        hipLaunchKernelGGL((k_adjoint<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, scenes, prefix, n_scenes,
+                           queue, dtab, d0tab, nsx, nsy, sx_min, sy_min);
     return hipGetLastError();
 }
 
 template <int C>
-static hipError_t launch_adj_c(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
-                               const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
-                               float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
+static hipError_t launch_adj_c(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix,
+                               int n_scenes, long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy,
+                               int sx_min, int sy_min, int grid, hipStream_t s)
 {
     switch (p.F) {
-    case 2: return launch_adj_cf<C, 2>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
-    case 8: return launch_adj_cf<C, 8>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
-    default: return launch_adj_cf<C, 4>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    case 2: return launch_adj_cf<C, 2>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
+    case 8: return launch_adj_cf<C, 8>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
+    default: return launch_adj_cf<C, 4>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
     }
 }
 
-hipError_t launch_adjoint2(const Plan &p, const Consts &k, const GRec *rec, const float2 *gspec, const float *dtab,
-                           const double *d0tab, int nsx, int nsy, int sx_min, int sy_min, const BItem *bitems,
-                           float *bpartials, long long *counters, int64_t n, int grid, hipStream_t s)
+hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,
+                          long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy, int sx_min,
+                          int sy_min, int grid, hipStream_t s)
 {
     switch (k.C) {
-    case 1: return launch_adj_c<1>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
-    case 2: return launch_adj_c<2>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
-    case 3: return launch_adj_c<3>(p, k, rec, gspec, dtab, d0tab, nsx, nsy, sx_min, sy_min, bitems, bpartials, counters, n, grid, s);
+    case 1: return launch_adj_c<1>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
+    case 2: return launch_adj_c<2>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
+    case 3: return launch_adj_c<3>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
     default: return hipErrorInvalidValue;  // 3C + 5 accumulators must fit 16
     }
 }
 
+int adjoint_occupancy(int C, int F, int depth)
+{
+    (void)C; (void)F; (void)depth;
+    return 4;  // __launch_bounds__(WG, 4): at most 128 VGPRs, 32 KB LDS per work-group
+}
+
 // Per Gaussian: sum the item partials of its chunk in order (FP64), then the chain rule.
-__global__ void __launch_bounds__(256) k_grad_final(gws_gaussians g, Consts k, const uint32_t *__restrict__ vals,
+__global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uint32_t *__restrict__ vals,
                                                     const int2 *__restrict__ chunk_items,
-                                                    const float *__restrict__ bpartials, gws_grads grads, int64_t n,
+                                                    const float *__restrict__ bpartials, GradView grads, int64_t n,
                                                     const long long *__restrict__ counters)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,7 +432,7 @@ __global__ void __launch_bounds__(256) k_grad_final(gws_gaussians g, Consts k, c
         if (grads.depth) grads.depth[i] = 0.0f;
         grads.cov_xx[i] = grads.cov_xy[i] = grads.cov_yy[i] = 0.0f;
         grads.opacity[i] = grads.phase[i] = 0.0f;
-        for (int c = 0; c < C; ++c) grads.amplitude[(int64_t)c * g.n + i] = 0.0f;
+        for (int c = 0; c < C; ++c) grads.amplitude[(int64_t)c * grads.amp_stride + i] = 0.0f;
         return;
     }
     const int64_t b = s / 64;
@@ -441,20 +453,20 @@ __global__ void __launch_bounds__(256) k_grad_final(gws_gaussians g, Consts k, c
     const double K = 2.0 * PI * sqrt(det) / (k.px * k.py * (double)k.nx * (double)k.ny);
     double Sre = 0.0, gz = 0.0, go = 0.0;
     for (int c = 0; c < C; ++c) {
-        const double a = g.amplitude[(int64_t)c * g.n + i];
+        const double a = g.amplitude[(int64_t)c * g.amp_stride + i];
         const double A = a * o * K;
         const double Pr = acc[c];
         const double Pi = k.depth_grad ? acc[C + 5 + c] : 0.0, Wc = k.depth_grad ? acc[2 * C + 5 + c] : 0.0;
         Sre += A * Pr;
         gz += A * (k.inv_lambda[c] * Pi + Wc);
         go += a * K * Pr;
-        grads.amplitude[(int64_t)c * g.n + i] = (float)(o * K * Pr);
+        grads.amplitude[(int64_t)c * grads.amp_stride + i] = (float)(o * K * Pr);
     }
     const double Sfx = acc[C], Sfy = acc[C + 1], Qxx = acc[C + 2], Qxy = acc[C + 3], Qyy = acc[C + 4];
     // sum_c A_c Im P_c (= sum_m Im rho): from Im P_c with depth, else the extra reduced slot
     double Sim = 0.0;
     if (k.depth_grad) {
-        for (int c = 0; c < C; ++c) Sim += (double)g.amplitude[(int64_t)c * g.n + i] * o * K * acc[C + 5 + c];
+        for (int c = 0; c < C; ++c) Sim += (double)g.amplitude[(int64_t)c * g.amp_stride + i] * o * K * acc[C + 5 + c];
     } else {
         Sim = acc[8];
     }
@@ -468,9 +480,9 @@ __global__ void __launch_bounds__(256) k_grad_final(gws_gaussians g, Consts k, c
     if (grads.depth) grads.depth[i] = (float)(2.0 * PI * gz);
 }
 
-hipError_t launch_grad_final2(const gws_gaussians &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
-                              const float *bpartials, const gws_grads &grads, int64_t n, const long long *counters,
-                              hipStream_t s)
+hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
+                             const float *bpartials, const GradView &grads, int64_t n, const long long *counters,
+                             hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, k, vals, chunk_items, bpartials,

@@ -21,7 +21,7 @@ static __device__ __forceinline__ bool finite_f(float v) { return (__float_as_ui
 
 static __device__ __forceinline__ double frac_d(double v) { return v - floor(v); }
 
-__global__ void __launch_bounds__(256) k_keys(gws_gaussians g, Consts k, uint64_t *__restrict__ keys,
+__global__ void __launch_bounds__(256) k_keys(GView g, Consts k, uint64_t *__restrict__ keys,
                                                uint32_t *__restrict__ vals, uint32_t *__restrict__ bucket_hist,
                                                long long *__restrict__ counters)
 {
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(256) k_keys(gws_gaussians g, Consts k, uint64_
               finite_f(z) && finite_f(o) && finite_f(ph);
     bool any_amp = false;
     for (int c = 0; c < k.C; ++c) {
-        const float a = g.amplitude[(int64_t)c * g.n + i];
+        const float a = g.amplitude[(int64_t)c * g.amp_stride + i];
         ok = ok && finite_f(a);
         any_amp = any_amp || (a != 0.0f);
     }
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) k_keys(gws_gaussians g, Consts k, uint64_
     vals[i] = (uint32_t)i;
 }
 
-hipError_t launch_keys(const gws_gaussians &g, const Consts &k, uint64_t *keys, uint32_t *vals,
+hipError_t launch_keys(const GView &g, const Consts &k, uint64_t *keys, uint32_t *vals,
                        uint32_t *bucket_hist, long long *counters, hipStream_t s)
 {
     const int64_t blocks = (g.n + 255) / 256;
@@ -192,7 +192,7 @@ hipError_t radix_sort_48(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, u
 // ---------------------------------------------------------------------------------
 // Records, in sorted order.
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_records(gws_gaussians g, Consts k, const uint64_t *__restrict__ keys,
+__global__ void __launch_bounds__(256) k_records(GView g, Consts k, const uint64_t *__restrict__ keys,
                                                   const uint32_t *__restrict__ vals, GRec *__restrict__ rec,
                                                   int64_t n, const long long *__restrict__ counters)
 {
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) k_records(gws_gaussians g, Consts k, cons
     for (int c = 0; c < 4; ++c) {
         if (c < k.C) {
             r.kappa[c] = (float)frac_d(phi_rev - (double)z * k.inv_lambda[c]);
-            r.amp[c] = (float)((double)g.amplitude[(int64_t)c * g.n + i] * o * norm);
+            r.amp[c] = (float)((double)g.amplitude[(int64_t)c * g.amp_stride + i] * o * norm);
         } else {
             r.kappa[c] = 0.0f;
             r.amp[c] = 0.0f;
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(256) k_records(gws_gaussians g, Consts k, cons
     rec[s] = r;
 }
 
-hipError_t launch_records(const gws_gaussians &g, const Consts &k, const uint64_t *keys, const uint32_t *vals,
+hipError_t launch_records(const GView &g, const Consts &k, const uint64_t *keys, const uint32_t *vals,
                           GRec *rec, int64_t n, const long long *counters, hipStream_t s)
 {
     const int64_t blocks = (n + 255) / 256;
@@ -453,6 +453,118 @@ hipError_t launch_zero_counters(long long *counters, uint32_t *bucket_hist, hipS
 hipError_t launch_copy_counters(const long long *src, long long *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy_counters, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
+}
+
+// Scene tables: copy the by-value table to device memory and form the prefix sums of the
+// per-scene work-item counts (so one persistent launch can walk every scene's items).
+__global__ void k_fwd_table(FwdTab tab, FwdScene *__restrict__ dst, int32_t *__restrict__ prefix,
+                            long long *__restrict__ queue)
+{
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < tab.n; ++i) {
+            dst[i] = tab.s[i];
+            prefix[i] = run;
+            run += (int32_t)tab.s[i].counters[CTR_NITEMS];
+        }
+        prefix[tab.n] = run;
+        *queue = 0;
+    }
+}
+
+__global__ void k_bwd_table(BwdTab tab, BwdScene *__restrict__ dst, int32_t *__restrict__ prefix,
+                            long long *__restrict__ queue)
+{
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < tab.n; ++i) {
+            dst[i] = tab.s[i];
+            prefix[i] = run;
+            run += (int32_t)tab.s[i].counters[CTR_NBITEMS];
+        }
+        prefix[tab.n] = run;
+        *queue = 0;
+    }
+}
+
+hipError_t launch_fwd_table(const FwdTab &tab, FwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fwd_table, dim3(1), dim3(64), 0, s, tab, dst, prefix, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_table(const BwdTab &tab, BwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bwd_table, dim3(1), dim3(64), 0, s, tab, dst, prefix, queue);
+    return hipGetLastError();
+}
+
+struct CtrPtrs {
+    int n;
+    long long *p[MAX_SCENES];
+};
+
+// Statistics of a call: counters summed over its scenes.
+__global__ void k_sum_counters(CtrPtrs src, long long *__restrict__ dst)
+{
+    const int t = threadIdx.x;
+    if (t < CTR_COUNT) {
+        long long v = 0;
+        for (int i = 0; i < src.n; ++i) v += src.p[i][t];
+        dst[t] = v;
+    }
+}
+
+hipError_t launch_sum_counters(long long *const *src, int n, long long *dst, hipStream_t s)
+{
+    CtrPtrs c;
+    c.n = n;
+    for (int i = 0; i < n && i < MAX_SCENES; ++i) c.p[i] = src[i];
+    hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(64), 0, s, c, dst);
+    return hipGetLastError();
+}
+
+// Synthetic Gaussians for the autotuner, drawn on the device with a counter-based
+// generator (SplitMix64 of seed, index and draw number): means uniform over the field,
+// depth U(-10, 10) mm, standard deviations U(2, 20) pixels per axis, rotation U(0, pi),
+// opacity U(0.1, 1), amplitudes U(0, 1), phase U(0, 2 pi).
+static __device__ __forceinline__ double u01(uint64_t seed, uint64_t i, uint64_t d)
+{
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (i * 16 + d + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_synth(float *__restrict__ base, int64_t n, uint64_t seed, Consts k)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double PI = 3.14159265358979323846;
+    const double W = k.nx * k.px, H = k.ny * k.py;
+    const double su = (2.0 + 18.0 * u01(seed, i, 3)) * k.px, sv = (2.0 + 18.0 * u01(seed, i, 4)) * k.py;
+    const double th = PI * u01(seed, i, 5);
+    const double c = cos(th), s = sin(th);
+    float *mx = base, *my = base + n, *z = base + 2 * n, *sxx = base + 3 * n, *sxy = base + 4 * n, *syy = base + 5 * n;
+    float *o = base + 6 * n, *ph = base + 7 * n, *amp = base + 8 * n;
+    mx[i] = (float)((u01(seed, i, 0) - 0.5) * W);
+    my[i] = (float)((u01(seed, i, 1) - 0.5) * H);
+    z[i] = (float)((u01(seed, i, 2) - 0.5) * 0.02);
+    sxx[i] = (float)(c * c * su * su + s * s * sv * sv);
+    sxy[i] = (float)(c * s * (su * su - sv * sv));
+    syy[i] = (float)(s * s * su * su + c * c * sv * sv);
+    o[i] = (float)(0.1 + 0.9 * u01(seed, i, 6));
+    ph[i] = (float)(2.0 * PI * u01(seed, i, 7));
+    for (int ch = 0; ch < k.C; ++ch) amp[(int64_t)ch * n + i] = (float)u01(seed, i, 8 + ch);
+}
+
+hipError_t launch_synth(GView g, float *base, int64_t n, uint64_t seed, const Consts &k, hipStream_t s)
+{
+    (void)g;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_synth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n, seed, k);
     return hipGetLastError();
 }
 

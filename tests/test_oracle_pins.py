@@ -275,3 +275,16 @@ def test_p11_evanescent_band_is_zero():
     assert outside.sum() > 100 and (~outside).sum() > 100
     assert np.all(U[outside] == 0)
     assert np.all(np.abs(U[~outside]) > 0)
+
+
+def test_oracle_matches_its_committed_checksums():
+    """Regression of the oracle against values it wrote itself (tests/golden/make_golden.py)."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "small_field_checksums.json")))
+    scene, grid = gwsgen.workload("small")
+    u = oracle.forward(scene, grid)[0]
+    assert abs(np.linalg.norm(u) / ref["norm_l2"] - 1) < 1e-12
+    for k, (re, im) in ref["pixels"].items():
+        iy, ix = map(int, k.split(","))
+        assert abs(u[iy, ix] - complex(re, im)) < 1e-12 * ref["norm_l2"]
