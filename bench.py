@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="fwdbwd100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-config", type=int, default=0, help="0: tuned/default tiling; k: explicit tiling k")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 1 GiB device-to-device 3 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X in this build "
@@ -114,6 +116,10 @@ def main():
     import gwsgen
     import paper_2505_06582_amd as gws
 
+    if args.workload == "batched16":
+        return bench_batched(args)
+    if args.workload == "precision1m":
+        return bench_precision(args)
     log("bench: generating workload %s" % args.workload)
     scene, grid = gwsgen.workload(args.workload)
     target = gwsgen.make_target(grid, 2003)
@@ -219,9 +225,166 @@ def main():
         "kernels": kern,
         "roofline": roofline,
     }
+    tr = traffic_from_profiles(dom)
+    if tr is not None:
+        roofline["traffic"] = tr
+    if args.copy_calibration:
+        copy_calibration()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(scene, grid)
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """Plain device-to-device copies of known size for scaling the HBM byte counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+# Sources whose change invalidates a kernel's stored counter readings: the kernel itself, the
+# binning that orders its work items, and the shared record layouts.
+TRAFFIC_SOURCES = {
+    "adjoint": ("k_adjoint.hip", "k_prep.hip", "gws_internal.h"),
+    "accumulate": ("k_accum.hip", "k_prep.hip", "gws_internal.h"),
+}
+
+
+def source_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2505_06582_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    or None when there is none or a source that shapes the kernel's traffic changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_fwdbwd100k.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_sha256_16") != source_digest(kernel):
+        return None
+    return d["bytes_per_launch"]
+
+
+def bench_batched(args):
+    """16 scenes with log-uniform Gaussian counts in [1e3, 5e5], 1080x1920x3 each, fwd + loss + bwd:
+    one batched call pair (persistent launches, hipGraph replay) against 16 sequential calls."""
+    import numpy as np
+    import torch
+
+    import gwsgen
+    import paper_2505_06582_amd as gws
+    counts = gwsgen.batched_counts(16)
+    grid = gwsgen.Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    log("bench batched16: counts %s (total %d)" % (counts, sum(counts)))
+    scenes = [gwsgen.make_scene(n, grid, 5000 + i, depth_range=(-10e-3, 10e-3)) for i, n in enumerate(counts)]
+    cat = gwsgen.Scene.concat(scenes)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    S, C, M = len(counts), grid.n_lambda, grid.nx * grid.ny
+    ctx = gws.context(0)
+    prob = gws.Problem.from_grid(grid, tile_config=args.tile_config)
+    dev = torch.device("cuda", 0)
+    g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in cat.fields().items()}
+    gs = [{k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in sc.fields().items()} for sc in scenes]
+    target = torch.from_numpy(np.stack([gwsgen.make_target(grid, 6000 + i) for i in range(S)])).to(dev)
+    fields = torch.empty((S, C, grid.ny, grid.nx), dtype=torch.complex64, device=dev)
+    G = torch.empty_like(fields)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in g.items()}
+    stream = torch.cuda.Stream()
+
+    def step_batched():
+        ctx.forward_batched(prob, g, offsets, out=fields)
+        ctx.l2_loss_grad(fields, target, grad=G, loss=loss)
+        ctx.backward_batched(prob, g, offsets, G, want_depth=False, out=grads)
+
+    def step_sequential():
+        for i in range(S):
+            ctx.forward(prob, gs[i], out=fields[i])
+            ctx.l2_loss_grad(fields[i], target[i], grad=G[i], loss=loss)
+            ctx.backward(prob, gs[i], G[i], out=grads, want_depth=False)
+
+    res = {}
+    with torch.cuda.stream(stream):
+        for name, fn in (("batched", step_batched), ("sequential", step_sequential)):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            stream.synchronize()
+            res[name] = e0.elapsed_time(e1) / args.steps
+            log("bench batched16: %s %.2f ms per 16-scene step" % (name, res[name]))
+        replayed = ctx.stats()["graph_replayed"]
+    out = {"metric": "holograms/s, 16 scenes (Gaussians log-uniform in [1e3, 5e5]) at 1080x1920x3 fwd+bwd",
+           "value": 1e3 * S / res["batched"], "unit": "holograms/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["batched"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched16", "scenes": S, "counts": counts, "ny": grid.ny, "nx": grid.nx,
+                      "n_lambda": C},
+           "sequential_ms_per_step": res["sequential"], "sequential_holograms_per_s": 1e3 * S / res["sequential"],
+           "speedup_vs_sequential": res["sequential"] / res["batched"], "graph_replayed": replayed}
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """1M Gaussians at 2160x3840x3 (5% far off-axis at 20-50 mm): forward with the FP32 FFT and
+    with the split-bf16 MFMA DFT; the transform kernels' rooflines."""
+    import numpy as np
+    import torch
+
+    import gwsgen
+    import paper_2505_06582_amd as gws
+    scene, grid = gwsgen.workload("precision1m")
+    ctx = gws.context(0)
+    dev = torch.device("cuda", 0)
+    g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.fields().items()}
+    field = torch.empty((grid.n_lambda, grid.ny, grid.nx), dtype=torch.complex64, device=dev)
+    res = {}
+    for name, xf in (("fft_fp32", gws.XFORM_FFT_FP32), ("dft_bf16x3", gws.XFORM_DFT_BF16X3)):
+        prob = gws.Problem.from_grid(grid, xform=xf, tile_config=args.tile_config)
+        for _ in range(max(1, args.warmup)):
+            ctx.forward(prob, g, out=field)
+        torch.cuda.synchronize()
+        ctx.read_profile()
+        ctx.set_profiling(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            ctx.forward(prob, g, out=field)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.set_profiling(False)
+        prof = ctx.read_profile()
+        res[name] = {"ms_per_forward": e0.elapsed_time(e1) / args.steps,
+                     "stage_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}}
+        log("bench precision1m: %s %.2f ms per forward" % (name, res[name]["ms_per_forward"]))
+    C, M, nx, ny = grid.n_lambda, grid.nx * grid.ny, grid.nx, grid.ny
+    t_fft = res["fft_fp32"]["stage_ms"]["xform_inverse"] * 1e-3
+    t_dft = res["dft_bf16x3"]["stage_ms"]["xform_inverse"] * 1e-3
+    flops = C * 24.0 * (ny * nx * nx + nx * ny * ny)   # two complex GEMMs, 3 bf16 products each
+    out = {"metric": "forward holograms/s, 1M Gaussians at 2160x3840x3 (5% far off-axis at 20-50 mm)",
+           "value": 1e3 / res["fft_fp32"]["ms_per_forward"], "unit": "holograms/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["fft_fp32"]["ms_per_forward"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "precision1m", "gaussians": scene.n, "ny": ny, "nx": nx, "n_lambda": C},
+           "variants": res,
+           "transform_roofline": {
+               "fft_fp32": {"bound": "hbm", "achieved": 4 * C * M * 8 / t_fft / 1e9, "peak": 8000.0, "unit": "GB/s",
+                            "frac": 4 * C * M * 8 / t_fft / 8e12},
+               "dft_bf16x3": {"bound": "mfma", "achieved": flops / t_dft / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                              "frac": flops / t_dft / 2.5e15}}}
     print(json.dumps(out), flush=True)
 
 

@@ -351,6 +351,7 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
     L.off_partials = take(part_bytes);
     L.off_bitems = take(sizeof(BItem) * L.max_bitems);
     L.off_chunk_items = take(sizeof(int2) * (nchunks + 1));
+    L.off_range_base = take(sizeof(int32_t) * (ntiles + 2));
     L.off_bpartials = take(sizeof(float) * (size_t)L.max_bslots * 64 * NACC);
     L.total = o;
     return L;
@@ -527,6 +528,7 @@ struct Bufs {
     GRec *rec;
     int32_t *tile_L;
     int2 *tile_slots, *chunk_items;
+    int32_t *range_base;
     Item *items;
     BItem *bitems;
     float2 *partials;
@@ -551,6 +553,7 @@ static Bufs carve(const Layout &L, char *b)
     r.partials = (float2 *)(b + L.off_partials);
     r.bitems = (BItem *)(b + L.off_bitems);
     r.chunk_items = (int2 *)(b + L.off_chunk_items);
+    r.range_base = (int32_t *)(b + L.off_range_base);
     r.bpartials = (float *)(b + L.off_bpartials);
     return r;
 }
@@ -743,7 +746,9 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
             uint32_t *vals = nullptr;
             st = run_prep(ctx, k, scene_view(g, offsets[i], BL.n[i]), L, B, s, &keys, &vals);
             if (st != GWS_OK) return st;
-            HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, L.max_bitems, B.counters, BL.n[i], s));
+            HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, B.range_base,
+                                               ntiles_for(prob->nx, prob->ny, 2) + 1, L.max_bitems, B.counters, BL.n[i],
+                                               s));
             tab.s[i] = BwdScene{B.rec, gspecs + (int64_t)i * CM, B.bitems, B.bpartials, B.counters, BL.n[i]};
             ctrs[i] = B.counters;
             vals_sorted[i] = vals;
@@ -777,7 +782,8 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
             const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], F);
             const Bufs B = carve(L, base + BL.scene_off[i]);
             HIP_CHECK(ctx, launch_grad_final(scene_view(g, offsets[i], BL.n[i]), k, vals_sorted[i], B.chunk_items,
-                                             B.bpartials, grad_view(grads, offsets[i], g->n), BL.n[i], B.counters, s));
+                                             B.range_base, B.bpartials, grad_view(grads, offsets[i], g->n), BL.n[i],
+                                             B.counters, s));
         }
     }
     HIP_CHECK(ctx, launch_sum_counters(ctrs.data(), S, ctx->d_stats, s));

@@ -138,7 +138,7 @@ struct Plan {
 struct Layout {
     size_t total = 0;
     size_t off_keys_a, off_keys_b, off_vals_a, off_vals_b, off_sort_hist, off_bucket_hist, off_cum;
-    size_t off_counters, off_records, off_tile_L, off_tile_slots, off_items, off_bitems, off_partials, off_bpartials;
+    size_t off_counters, off_records, off_tile_L, off_tile_slots, off_items, off_range_base, off_bitems, off_partials, off_bpartials;
     size_t off_spectrum, off_gspec, off_dtab, off_d0tab, off_chunk_items;
     int32_t nsx = 0, nsy = 0, sx_min = 0, sy_min = 0, F = 4;
     int64_t n = 0;
@@ -179,7 +179,8 @@ hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32
                               int2 *tile_slots, Item *items, int64_t max_items, int64_t max_slots,
                               long long *counters, hipStream_t s);
 hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
-                               int64_t max_bitems, long long *counters, int64_t n, hipStream_t s);
+                               int32_t *range_base, int max_ranges, int64_t max_bitems, long long *counters, int64_t n,
+                               hipStream_t s);
 // Writes the scene table and the prefix of per-scene work-item counts, zeroes the queue head.
 hipError_t launch_fwd_table(const FwdTab &tab, FwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s);
 hipError_t launch_bwd_table(const BwdTab &tab, BwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s);
@@ -193,8 +194,8 @@ hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes
                           long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy, int sx_min,
                           int sy_min, int grid, hipStream_t s);
 hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
-                             const float *bpartials, const GradView &grads, int64_t n, const long long *counters,
-                             hipStream_t s);
+                             const int32_t *range_base, const float *bpartials, const GradView &grads, int64_t n,
+                             const long long *counters, hipStream_t s);
 hipError_t launch_sum_counters(long long *const *src, int n, long long *dst, hipStream_t s);
 int adjoint_occupancy(int C, int F, int depth);
 hipError_t launch_synth(GView g, float *base, int64_t n, uint64_t seed, const Consts &k, hipStream_t s);

@@ -146,10 +146,15 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *_
         for (int base = c0; base < c1; base += WG) {
             const int gi = base + tid;
             bool pred = false;
-            GRec r;
+            // the record as four 16-byte registers (a struct here would be kept in scratch)
+            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, r3 = r0;
             if (gi < c1) {
-                r = rec[gi];
-                pred = ellipse_meets_rect(r.alpha, r.beta2, r.gamma, lim, X0, X1, Y0, Y1);
+                const float4 *src = reinterpret_cast<const float4 *>(rec + gi);
+                r0 = src[0];
+                r1 = src[1];
+                r2 = src[2];
+                r3 = src[3];
+                pred = ellipse_meets_rect(r0.x, r0.y, r0.z, lim, X0, X1, Y0, Y1);
             }
             const uint64_t bal = __ballot(pred);
             const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -162,13 +167,19 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *_
                 off += (w < wave) ? cw : 0;
                 total += cw;
             }
-            if (pred) s_rec[off + __popcll(bal & lt)] = r;
+            if (pred) {
+                float4 *dst = reinterpret_cast<float4 *>(&s_rec[off + __popcll(bal & lt)]);
+                dst[0] = r0;
+                dst[1] = r1;
+                dst[2] = r2;
+                dst[3] = r3;
+            }
             __syncthreads();
             if (wave_live) {
                 for (int j0 = 0; j0 < total; j0 += 64) {
                     const int j = j0 + lane;
                     bool p = false;
-                    WEntry e;
+                    WEntry e = {};
                     if (j < total) {
                         const GRec q = s_rec[j];
                         p = ellipse_meets_rect(q.alpha, q.beta2, q.gamma, lim, x0, x1, y0, y1);

@@ -213,12 +213,18 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
         long long pairs = 0;
         const int64_t gidx = (int64_t)bi.chunk * 64 + lane;
         const bool gvalid = gidx < nvalid;
-        GRec r;
-        if (gvalid) r = rec[gidx];
-        else {
-            r.alpha = r.beta2 = r.gamma = 1.0f; r.z = 0.0f; r.rx = r.ry = 0u; r.rxf = r.ryf = 0.0f;
-            for (int c = 0; c < 4; ++c) { r.kappa[c] = 0.0f; r.amp[c] = 0.0f; }
+        // this lane's record as four 16-byte registers (a struct would be kept in scratch):
+        // r0 = (alpha, beta2, gamma, z), r1 = (rx, ry, rxf, ryf), r2 = kappa[4], r3 = amp[4]
+        float4 r0 = make_float4(1.f, 1.f, 1.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f), r2 = r1, r3 = r1;
+        if (gvalid) {
+            const float4 *src = reinterpret_cast<const float4 *>(rec + gidx);
+            r0 = src[0];
+            r1 = src[1];
+            r2 = src[2];
+            r3 = src[3];
         }
+        const uint32_t rx = __float_as_uint(r1.x), ry = __float_as_uint(r1.y);
+        const float kap[4] = {r2.x, r2.y, r2.z, r2.w};
 #pragma unroll
         for (int v = 0; v < NACC; ++v) s_acc[wave][lane][v] = 0.0f;
 
@@ -233,23 +239,24 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                 const int cx = sx0 + SUBX / 2, cy = sy0 + SY / 2;
                 const int64_t sidx = (int64_t)(sy0 / SY - sy_min) * nsx + (sx0 / SUBX - sx_min);
                 // stage this sub-tile's accepted Gaussians
-                const bool p = gvalid && ellipse_meets_rect_b(r.alpha, r.beta2, r.gamma, lim, x0, x1, y0, y1);
+                const bool p = gvalid && ellipse_meets_rect_b(r0.x, r0.y, r0.z, lim, x0, x1, y0, y1);
                 const uint64_t bal = __ballot(p);
                 const int cnt = __popcll(bal);
                 if (cnt == 0) continue;
                 if (p) {
-                    BEntry e;
-                    e.alpha = r.alpha; e.beta2 = r.beta2; e.gamma = r.gamma; e.z = r.z;
-                    e.rxf = r.rxf; e.ryf = r.ryf; e.owner = lane; e.pad = 0.0f;
-                    const uint32_t ramp = (uint32_t)cx * r.rx + (uint32_t)cy * r.ry;
+                    const uint32_t ramp = (uint32_t)cx * rx + (uint32_t)cy * ry;
                     const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
+                    float4 b4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float bs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        e.amp[c] = r.amp[c];
-                        e.base[c] = c < C ? (float)frac_d((double)r.kappa[c] - ramp_rev - (double)r.z * d0tab[c * ns + sidx])
-                                          : 0.0f;
-                    }
-                    s_w[wave][__popcll(bal & lt)] = e;
+                    for (int c = 0; c < C; ++c)
+                        bs[c] = (float)frac_d((double)kap[c] - ramp_rev - (double)r0.w * d0tab[c * ns + sidx]);
+                    b4 = make_float4(bs[0], bs[1], bs[2], bs[3]);
+                    float4 *dst = reinterpret_cast<float4 *>(&s_w[wave][__popcll(bal & lt)]);
+                    dst[0] = r0;
+                    dst[1] = make_float4(r1.z, r1.w, __int_as_float(lane), 0.f);
+                    dst[2] = r3;
+                    dst[3] = b4;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -419,6 +426,7 @@ int adjoint_occupancy(int C, int F, int depth)
 // Per Gaussian: sum the item partials of its chunk in order (FP64), then the chain rule.
 __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uint32_t *__restrict__ vals,
                                                     const int2 *__restrict__ chunk_items,
+                                                    const int32_t *__restrict__ range_base,
                                                     const float *__restrict__ bpartials, GradView grads, int64_t n,
                                                     const long long *__restrict__ counters)
 {
@@ -441,8 +449,10 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
     const long long nbitems = counters[CTR_NBITEMS];
     double acc[NACC];
     for (int v = 0; v < NACC; ++v) acc[v] = 0.0;
-    for (int j = 0; j < ci.y && (long long)ci.x + j < nbitems; ++j) {
-        const float *src = bpartials + ((int64_t)(ci.x + j) * 64 + lane) * NACC;
+    for (int j = 0; j < ci.y; ++j) {
+        const int64_t it = (int64_t)range_base[j] + b;  // range j of chunk b
+        if (it >= nbitems) break;
+        const float *src = bpartials + (it * 64 + lane) * NACC;
         for (int v = 0; v < NACC; ++v) acc[v] += (double)src[v];
     }
     const double PI = 3.14159265358979323846;
@@ -481,12 +491,12 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
 }
 
 hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
-                             const float *bpartials, const GradView &grads, int64_t n, const long long *counters,
-                             hipStream_t s)
+                             const int32_t *range_base, const float *bpartials, const GradView &grads, int64_t n,
+                             const long long *counters, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, k, vals, chunk_items, bpartials,
-                       grads, n, counters);
+    hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, k, vals, chunk_items,
+                       range_base, bpartials, grads, n, counters);
     return hipGetLastError();
 }
 

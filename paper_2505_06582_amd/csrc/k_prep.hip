@@ -356,23 +356,26 @@ hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32
 // ---------------------------------------------------------------------------------
 // Backward binning: chunk b of BWD_CHUNK sorted Gaussians reaches the first K_b sorted
 // tiles (K_b = tiles whose bucket is at most the chunk's largest bucket).  Those tiles are
-// split into ranges of TRB tiles; TRB grows until the items fit max_bslots.
+// split into ranges of TRB tiles (TRB grows until the items fit max_bitems).  Items are
+// ordered range-major -- range r of every chunk that has one, then range r + 1 -- so the
+// wavefronts in flight at any time read the same tiles of the field gradient (L2 reuse).
+// Because K_b does not increase with b (chunks are sorted by support radius), the chunks
+// that have range r form a prefix [0, P_r) and item (r, b) sits at range_base[r] + b.
 // ---------------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_bin_backward(const int32_t *__restrict__ tile_cum,
                                                        const uint64_t *__restrict__ keys, BItem *__restrict__ bitems,
-                                                       int2 *__restrict__ chunk_items, int64_t max_bitems,
+                                                       int2 *__restrict__ chunk_items, int32_t *__restrict__ range_base,
+                                                       int max_ranges, int64_t max_bitems,
                                                        long long *__restrict__ counters, int64_t n)
 {
     __shared__ uint32_t tmp[1024];
     __shared__ unsigned long long red[1024];
-    __shared__ int32_t trb_sh;
+    __shared__ int32_t trb_sh, nr_sh;
     const int64_t nvalid = n - counters[CTR_NCULLED];
     const int nchunks = (int)((nvalid + BWD_CHUNK - 1) / BWD_CHUNK);
+    auto K_of = [&](int b) { return tile_cum[NBUCKET - 1 - (int)(keys[(int64_t)b * BWD_CHUNK] >> 32)]; };
     unsigned long long sumK = 0;
-    for (int b = threadIdx.x; b < nchunks; b += 1024) {
-        const int bucket = NBUCKET - 1 - (int)(keys[(int64_t)b * BWD_CHUNK] >> 32);
-        sumK += (unsigned long long)tile_cum[bucket];
-    }
+    for (int b = threadIdx.x; b < nchunks; b += 1024) sumK += (unsigned long long)K_of(b);
     red[threadIdx.x] = sumK;
     __syncthreads();
     for (int off = 512; off > 0; off >>= 1) {
@@ -391,31 +394,47 @@ __global__ void __launch_bounds__(1024) k_bin_backward(const int32_t *__restrict
             trb = 1 << 30;
         }
         trb_sh = (int32_t)trb;
+        nr_sh = nchunks > 0 ? (int32_t)((K_of(0) + trb - 1) / trb) : 0;
         counters[CTR_TRB] = trb;
     }
     __syncthreads();
-    const int TRB = trb_sh;
+    const int TRB = trb_sh, NR = min(nr_sh, max_ranges);
+    // P_r = number of chunks with more than r ranges (a prefix, found by bisection)
     uint32_t base = 0;
-    for (int b0 = 0; b0 < nchunks; b0 += 1024) {
-        const int b = b0 + threadIdx.x;
-        int K = 0;
-        if (b < nchunks) K = tile_cum[NBUCKET - 1 - (int)(keys[(int64_t)b * BWD_CHUNK] >> 32)];
-        const uint32_t nk = (uint32_t)((K + TRB - 1) / TRB);
+    for (int r0 = 0; r0 < NR; r0 += 1024) {
+        const int r = r0 + threadIdx.x;
+        uint32_t P = 0;
+        if (r < NR) {
+            int lo = 0, hi = nchunks;  // first b with ceil(K_b / TRB) <= r
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((K_of(mid) + TRB - 1) / TRB > r) lo = mid + 1;
+                else hi = mid;
+            }
+            P = (uint32_t)lo;
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan_1024(nk, tmp, &tot);
-        if (b < nchunks) chunk_items[b] = make_int2((int)(base + ex), (int)nk);
-        for (uint32_t j = 0; j < nk; ++j) {
-            const uint64_t it = (uint64_t)base + ex + j;
-            if (it < (uint64_t)max_bitems) {
+        const uint32_t ex = block_excl_scan_1024(P, tmp, &tot);
+        if (r < NR) range_base[r] = (int32_t)(base + ex);
+        base += tot;
+    }
+    if (threadIdx.x == 0) range_base[NR] = (int32_t)base;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nchunks; b += 1024) {
+        const int K = K_of(b);
+        const int nk = min((K + TRB - 1) / TRB, NR);
+        chunk_items[b] = make_int2(0, nk);
+        for (int r = 0; r < nk; ++r) {
+            const int64_t it = (int64_t)range_base[r] + b;
+            if (it < max_bitems) {
                 BItem e;
                 e.chunk = b;
-                e.k0 = (int32_t)(j * TRB);
-                e.k1 = (int32_t)min((long long)(j + 1) * TRB, (long long)K);
+                e.k0 = r * TRB;
+                e.k1 = min((r + 1) * TRB, K);
                 e.slot = (int32_t)it;
                 bitems[it] = e;
             }
         }
-        base += tot;
     }
     if (threadIdx.x == 0) {
         counters[CTR_NBITEMS] = (long long)(base < max_bitems ? base : max_bitems);
@@ -423,11 +442,12 @@ __global__ void __launch_bounds__(1024) k_bin_backward(const int32_t *__restrict
     }
 }
 
-hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items, int64_t max_bitems,
-                               long long *counters, int64_t n, hipStream_t s)
+hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
+                               int32_t *range_base, int max_ranges, int64_t max_bitems, long long *counters, int64_t n,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin_backward, dim3(1), dim3(1024), 0, s, p.tile_cum, keys, bitems, chunk_items, max_bitems,
-                       counters, n);
+    hipLaunchKernelGGL(k_bin_backward, dim3(1), dim3(1024), 0, s, p.tile_cum, keys, bitems, chunk_items, range_base,
+                       max_ranges, max_bitems, counters, n);
     return hipGetLastError();
 }
 
