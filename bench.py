@@ -175,8 +175,8 @@ def main():
     support = ellipse_support_points(scene, grid)          # (Gaussian, frequency) pairs inside eps-support
     evals_alg = support * C                                # Gaussian.freq-px evaluations per pass
     trans_per_pair = 1 + 2 * C                             # one exp2, a sin and a cos per wavelength
-    fwd_pairs_eval = st_f["n_tile_gaussian"] * 256         # evaluated (sub-tile of 256 frequencies) x Gaussian
-    bwd_pairs_eval = st_b["n_tile_gaussian"] * 256
+    fwd_pairs_eval = st_f["n_pairs_evaluated"]             # (Gaussian, frequency) pairs evaluated
+    bwd_pairs_eval = st_b["n_pairs_evaluated"]
     kern = {}
     t_acc = stage_ms["accumulate"] * 1e-3
     t_adj = stage_ms["adjoint"] * 1e-3

@@ -84,7 +84,7 @@ typedef struct gws_problem {
                                   else the default; k in 1..gws_tile_config_count(): tiling k,
                                   a pair (frequencies per lane of the accumulation, of the
                                   adjoint) from {(4,4),(4,8),(8,8),(8,4),(2,4),(4,2),(2,2),
-                                  (2,8),(8,2)}; the default is 5 = (2,4) */
+                                  (2,8),(8,2)}; the default is 2 = (4,8) */
 } gws_problem;
 
 /* Gaussians as structure-of-arrays float32 device buffers of length n.  amplitude is
@@ -121,7 +121,8 @@ typedef struct gws_stats {
     int64_t n_tiles;          /* frequency tiles of the grid */
     int64_t n_items;          /* accumulation work items launched */
     int64_t chunk;            /* candidate Gaussians per work item */
-    int64_t n_tile_gaussian;  /* (tile, Gaussian) pairs evaluated */
+    int64_t n_pairs_evaluated; /* (Gaussian, frequency) pairs evaluated: accepted Gaussians x the
+                                  frequencies of each wavefront sub-tile they were tested on */
     int64_t n_candidates;     /* (tile, Gaussian) pairs tested */
     int32_t tile_config;      /* tiling used */
     int32_t graph_replayed;   /* batched call replayed a captured graph */

@@ -19,7 +19,8 @@ from typing import Dict, Optional, Sequence
 __all__ = ["LIB_PATH", "GwsError", "Problem", "Context", "load_library", "render", "GaussianWaveSplat",
            "STATUS", "XFORM_FFT_FP32", "XFORM_DFT_BF16X3"]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgws.so")
+# The in-tree build; GWS_LIBRARY names another build of the same library (e.g. to compare two).
+LIB_PATH = os.environ.get("GWS_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgws.so")
 
 XFORM_FFT_FP32 = 0
 XFORM_DFT_BF16X3 = 1
@@ -63,7 +64,7 @@ class _Grads(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("n_input", ctypes.c_int64), ("n_culled", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
-                ("n_items", ctypes.c_int64), ("chunk", ctypes.c_int64), ("n_tile_gaussian", ctypes.c_int64),
+                ("n_items", ctypes.c_int64), ("chunk", ctypes.c_int64), ("n_pairs_evaluated", ctypes.c_int64),
                 ("n_candidates", ctypes.c_int64), ("tile_config", ctypes.c_int32), ("graph_replayed", ctypes.c_int32)]
 
 

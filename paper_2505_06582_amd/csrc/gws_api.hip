@@ -25,7 +25,7 @@ struct gws_ctx {
     int64_t last_n = 0;
     int last_tile_config = 1;
     int last_graph = 0;
-    std::map<int, int> acc_occ;
+    std::map<int, int> acc_occ;  // resident work-groups per CU by kernel variant
     std::map<std::tuple<int, int, int, int>, int> tuned;  // (nx, ny, C, log2 n) -> tile_config
     // batched-graph cache
     struct GraphKey {
@@ -162,10 +162,11 @@ extern "C" gws_status gws_check_problem(const gws_problem *p)
 // work-group tile is 32 x 8F frequencies, the wavefront sub-tile 16 x 4F.
 static const int kTileCfg[][2] = {{4, 4}, {4, 8}, {8, 8}, {8, 4}, {2, 4}, {4, 2}, {2, 2}, {2, 8}, {8, 2}};
 static const int kNumTileCfg = (int)(sizeof(kTileCfg) / sizeof(kTileCfg[0]));
-// Untuned default: F = 2 for the accumulation (finest culling), F = 4 for the adjoint
-// (fewer cross-lane reductions per evaluated term); the fastest pair measured on MI355X
-// for 1e4..1e5 Gaussians at 1080 x 1920.
-static const int kDefaultTileCfg = 5;
+// Untuned default: F = 4 for the accumulation, F = 8 for the adjoint (its cross-lane
+// reductions amortised over twice the rows; row-block culling keeps the evaluated terms
+// those of 16 x 4 blocks); the fastest pair measured on MI355X for 1e5 Gaussians at
+// 1080 x 1920 x 3.
+static const int kDefaultTileCfg = 2;
 
 extern "C" int gws_tile_config_count(void) { return kNumTileCfg; }
 
@@ -484,7 +485,7 @@ extern "C" gws_status gws_get_stats(gws_ctx *ctx, gws_stats *out)
     out->n_culled = h[CTR_NCULLED];
     out->n_items = h[CTR_NITEMS] + h[CTR_NBITEMS];
     out->chunk = h[CTR_CHUNK];
-    out->n_tile_gaussian = h[CTR_PAIRS];
+    out->n_pairs_evaluated = h[CTR_PAIRS];
     out->n_candidates = h[CTR_CAND];
     out->tile_config = ctx->last_tile_config;
     out->graph_replayed = ctx->last_graph;
@@ -608,6 +609,14 @@ static int acc_grid(gws_ctx *ctx, int C, int F)
     const int key = C * 16 + F;
     auto it = ctx->acc_occ.find(key);
     if (it == ctx->acc_occ.end()) it = ctx->acc_occ.emplace(key, accumulate_occupancy(C, F)).first;
+    return ctx->n_cu * it->second;
+}
+
+static int adj_grid(gws_ctx *ctx, int C, int F, int depth)
+{
+    const int key = 256 + (C * 16 + F) * 2 + (depth ? 1 : 0);
+    auto it = ctx->acc_occ.find(key);
+    if (it == ctx->acc_occ.end()) it = ctx->acc_occ.emplace(key, adjoint_occupancy(C, F, depth)).first;
     return ctx->n_cu * it->second;
 }
 
@@ -765,6 +774,7 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     }
     {
         StageScope sc(ctx, s, ST_DTABLE);
+        HIP_CHECK(ctx, launch_polar(gspecs, (int64_t)S * CM, s));
         HIP_CHECK(ctx, launch_dtable(k, dtab, d0tab, L0.nsx, L0.nsy, L0.sx_min, L0.sy_min, sub_h(F), s));
     }
     BwdScene *dscenes = (BwdScene *)(base + BL.off_btab);
@@ -774,7 +784,7 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
         StageScope sc(ctx, s, ST_ADJOINT);
         HIP_CHECK(ctx, launch_bwd_table(tab, dscenes, prefix, queue, s));
         HIP_CHECK(ctx, launch_adjoint(*p, k, dscenes, prefix, S, queue, dtab, d0tab, L0.nsx, L0.nsy, L0.sx_min, L0.sy_min,
-                                      ctx->n_cu * adjoint_occupancy(k.C, F, k.depth_grad), s));
+                                      adj_grid(ctx, k.C, F, k.depth_grad), s));
     }
     {
         StageScope sc(ctx, s, ST_FINAL);

@@ -24,11 +24,86 @@ namespace gws {
 constexpr int SUBX = 16;
 constexpr int TILEX = 2 * SUBX;
 __host__ __device__ constexpr int sub_h(int f) { return 4 * f; }
+// Minimum resident wavefronts per SIMD the evaluation kernels are compiled for: 4 (at most
+// 128 VGPRs) for F <= 4; F = 8 keeps 8 frequencies x C wavelengths of per-lane tables in
+// registers and is compiled for 2 (at most 256 VGPRs) rather than spill.
+__host__ __device__ constexpr int waves_per_simd(int f) { return f >= 8 ? 2 : 4; }
 constexpr int WAVES = 4;             // wavefronts per work-group
 constexpr int WG = 64 * WAVES;       // threads per work-group
 constexpr int NBUCKET = 4096;        // support-radius buckets (index units)
 constexpr int BWD_CHUNK = 64;        // Gaussians per backward work item (one per lane)
 constexpr int NACC = 16;             // per-Gaussian adjoint accumulators (padded)
+
+// ---------------------------------------------------------------------------------
+// Support tests in index units.  The eps-support of a Gaussian's spectrum is the ellipse
+// q(x, y) = a x^2 + b2 x y + g y^2 <= lim centred on DC.  q is convex, so over a
+// rectangle that does not hold the origin its minimum lies on an edge, where q is a 1-D
+// parabola: the test below is exact (up to FP32 rounding).  ia = 1/(2a), ig = 1/(2g).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ bool ellipse_meets_rect_r(float a, float b2, float g, float ia, float ig, float lim,
+                                                     float x0, float x1, float y0, float y1)
+{
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+    float m;
+    float y = fminf(fmaxf(-b2 * x0 * ig, y0), y1);
+    m = x0 * (a * x0 + b2 * y) + g * y * y;
+    y = fminf(fmaxf(-b2 * x1 * ig, y0), y1);
+    m = fminf(m, x1 * (a * x1 + b2 * y) + g * y * y);
+    float x = fminf(fmaxf(-b2 * y0 * ia, x0), x1);
+    m = fminf(m, x * (a * x + b2 * y0) + g * y0 * y0);
+    x = fminf(fmaxf(-b2 * y1 * ia, x0), x1);
+    m = fminf(m, x * (a * x + b2 * y1) + g * y1 * y1);
+    return m <= lim;
+}
+
+// Bit f is set when the support meets the 4-row block f of a sub-tile: columns [x0, x1],
+// rows [sy0 + 4f, sy0 + 4f + 3], rows clipped to the grid [-hy, hy - 1].  Lane rows
+// l / SUBX + 4 f of the tiling are exactly block f, so a wavefront skips block f of a
+// Gaussian whose bit is clear.
+//
+// The rows the support reaches inside the column strip form an interval [ylo, yhi] (the
+// projection of a convex set).  Its top is the ellipse's highest point (x_t, y_t),
+// y_t = sqrt(lim / (g - b2^2 / 4a)), x_t = -b2 y_t / 2a, when x_t lies in the strip, else
+// the upper root of q(x_b, y) = lim on the strip edge x_b nearest x_t; the bottom mirrors
+// it (the ellipse is centred on DC).  The interval is widened by 1e-3 rows so rounding
+// never drops a block the exact test would keep.  Only called for a sub-tile the support
+// meets, so the strip is never empty.
+template <int F>
+__device__ __forceinline__ uint32_t row_block_mask(float a, float b2, float g, float lim, float x0, float x1, int sy0,
+                                                   int hy)
+{
+    const float dg = g - b2 * b2 * (0.25f / a);
+    const float yt = sqrtf(lim / dg), xt = -b2 * yt * (0.5f / a);
+    const float ig2 = 0.5f / g;
+    float yhi = yt, ylo = -yt;
+    if (xt < x0 || xt > x1) {
+        const float xb = fminf(fmaxf(xt, x0), x1);
+        const float d = fmaxf(b2 * b2 * xb * xb - 4.0f * g * (a * xb * xb - lim), 0.0f);
+        yhi = (-b2 * xb + sqrtf(d)) * ig2;
+    }
+    if (-xt < x0 || -xt > x1) {
+        const float xb = fminf(fmaxf(-xt, x0), x1);
+        const float d = fmaxf(b2 * b2 * xb * xb - 4.0f * g * (a * xb * xb - lim), 0.0f);
+        ylo = (-b2 * xb - sqrtf(d)) * ig2;
+    }
+    yhi += 1e-3f * (1.0f + fabsf(yhi));
+    ylo -= 1e-3f * (1.0f + fabsf(ylo));
+    uint32_t m = 0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const int r0 = max(sy0 + 4 * f, -hy), r1 = min(sy0 + 4 * f + 3, hy - 1);
+        if (r0 <= r1 && (float)r0 <= yhi && (float)r1 >= ylo) m |= 1u << f;
+    }
+    return m;
+}
+
+// Sum of a 64-bit counter over the 64 lanes of a wavefront (every lane gets the total).
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
 
 // Per-Gaussian record in sorted order, 64 bytes, written by k_records.
 struct alignas(16) GRec {
@@ -188,6 +263,7 @@ hipError_t launch_accumulate(const Plan &p, const Consts &k, const FwdScene *sce
                              int n_scenes, long long *queue, int grid, hipStream_t s);
 hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes,
                                   hipStream_t s);
+hipError_t launch_polar(float2 *g, int64_t n, hipStream_t s);
 hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
                          hipStream_t s);
 hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,

@@ -29,32 +29,18 @@ static __device__ __forceinline__ double dprop(double nu2, double inv_l)
     return -nu2 / (inv_l + sqrt(w2));
 }
 
-// Does the ellipse q(x, y) = a x^2 + b2 x y + g y^2 <= lim meet the rectangle
-// [x0, x1] x [y0, y1]?  Exact for a convex quadratic: if the rectangle holds the origin
-// the minimum is 0, otherwise it lies on an edge, where q is a 1-D parabola.
 static __device__ __forceinline__ bool ellipse_meets_rect(float a, float b2, float g, float lim, float x0, float x1,
                                                           float y0, float y1)
 {
-    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
-    const float ia = 0.5f / a, ig = 0.5f / g;
-    float m = 3.0e38f;
-    {
-        float y = fminf(fmaxf(-b2 * x0 * ig, y0), y1);
-        m = fminf(m, x0 * (a * x0 + b2 * y) + g * y * y);
-        y = fminf(fmaxf(-b2 * x1 * ig, y0), y1);
-        m = fminf(m, x1 * (a * x1 + b2 * y) + g * y * y);
-        float x = fminf(fmaxf(-b2 * y0 * ia, x0), x1);
-        m = fminf(m, x * (a * x + b2 * y0) + g * y0 * y0);
-        x = fminf(fmaxf(-b2 * y1 * ia, x0), x1);
-        m = fminf(m, x * (a * x + b2 * y1) + g * y1 * y1);
-    }
-    return m <= lim;
+    return ellipse_meets_rect_r(a, b2, g, 0.5f / a, 0.5f / g, lim, x0, x1, y0, y1);
 }
 
 // Compacted per-(sub-tile, Gaussian) entry, 16 floats.
 struct alignas(16) WEntry {
     float alpha, beta2, gamma, z;
-    float rxf, ryf, pad0, pad1;
+    float rxf, ryf;
+    uint32_t rows;   // row_block_mask of this Gaussian on the sub-tile
+    float pad1;
     float amp[4];
     float base[4];
 };
@@ -62,7 +48,7 @@ struct alignas(16) WEntry {
 // One persistent launch serves every scene of a batch: the queue head walks the
 // concatenation of the scenes' work-item lists (prefix[s] = first item of scene s).
 template <int C, bool EVAN, int F>
-__global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *__restrict__ tile_xy,
+__global__ void __launch_bounds__(WG, waves_per_simd(F)) k_accumulate(Consts k, const int32_t *__restrict__ tile_xy,
                                                    const FwdScene *__restrict__ scenes, const int32_t *__restrict__ prefix,
                                                    int n_scenes, long long *__restrict__ queue)
 {
@@ -185,7 +171,9 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *_
                         p = ellipse_meets_rect(q.alpha, q.beta2, q.gamma, lim, x0, x1, y0, y1);
                         if (p) {
                             e.alpha = q.alpha; e.beta2 = q.beta2; e.gamma = q.gamma; e.z = q.z;
-                            e.rxf = q.rxf; e.ryf = q.ryf; e.pad0 = 0.0f; e.pad1 = 0.0f;
+                            e.rxf = q.rxf; e.ryf = q.ryf; e.pad1 = 0.0f;
+                            e.rows = row_block_mask<F>(q.alpha, q.beta2, q.gamma, lim, x0, x1, sy0, hy);
+                            pairs += __popc(e.rows) * (SUBX * 4);
                             // exact ramp at the sub-tile centre: 0.32 fixed point, wraps mod 1
                             const uint32_t ramp = (uint32_t)cx * q.rx + (uint32_t)cy * q.ry;
                             const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
@@ -213,11 +201,11 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *_
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    pairs += cnt;
                     for (int ei = 0; ei < cnt; ++ei) {
                         const WEntry &w = s_w[wave][ei];
                         const float alpha = w.alpha, beta2 = w.beta2, gamma = w.gamma, z = w.z;
                         const float rxf = w.rxf, ryf = w.ryf;
+                        const uint32_t rows = __builtin_amdgcn_readfirstlane(w.rows);
                         float amp[C], bx[C];
                         const float ax = alpha * mxx;
 #pragma unroll
@@ -227,6 +215,7 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *_
                         }
 #pragma unroll
                         for (int f = 0; f < F; ++f) {
+                            if (!(rows & (1u << f))) continue;  // the support misses this 4-row block
                             const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
                             const float E = __builtin_amdgcn_exp2f(-q);
 #pragma unroll
@@ -265,6 +254,7 @@ __global__ void __launch_bounds__(WG, 4) k_accumulate(Consts k, const int32_t *_
                 }
             }
         }
+        pairs = wave_sum_i64(pairs);
         if (lane == 0 && pairs) atomicAdd((unsigned long long *)&S.counters[CTR_PAIRS], (unsigned long long)pairs);
     }
 }

@@ -27,25 +27,14 @@ static __device__ __forceinline__ double frac_d(double v) { return v - floor(v);
 static __device__ __forceinline__ bool ellipse_meets_rect_b(float a, float b2, float g, float lim, float x0, float x1,
                                                             float y0, float y1)
 {
-    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
-    const float ia = 0.5f / a, ig = 0.5f / g;
-    float m = 3.0e38f;
-    float y = fminf(fmaxf(-b2 * x0 * ig, y0), y1);
-    m = fminf(m, x0 * (a * x0 + b2 * y) + g * y * y);
-    y = fminf(fmaxf(-b2 * x1 * ig, y0), y1);
-    m = fminf(m, x1 * (a * x1 + b2 * y) + g * y * y);
-    float x = fminf(fmaxf(-b2 * y0 * ia, x0), x1);
-    m = fminf(m, x * (a * x + b2 * y0) + g * y0 * y0);
-    x = fminf(fmaxf(-b2 * y1 * ia, x0), x1);
-    m = fminf(m, x * (a * x + b2 * y1) + g * y1 * y1);
-    return m <= lim;
+    return ellipse_meets_rect_r(a, b2, g, 0.5f / a, 0.5f / g, lim, x0, x1, y0, y1);
 }
 
 struct alignas(16) BEntry {
     float alpha, beta2, gamma, z;
     float rxf, ryf;
     int32_t owner;   // lane (0..63) that owns this Gaussian
-    float pad;
+    uint32_t rows;   // row_block_mask of this Gaussian on the sub-tile
     float amp[4];
     float base[4];
 };
@@ -96,6 +85,24 @@ hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int ns
     return hipGetLastError();
 }
 
+// Gs in polar form, in place: (Re, Im) -> (|Gs|, arg Gs / 2 pi).  The adjoint then forms
+// conj(Gs) e^{j 2 pi Theta} as |Gs| e^{j 2 pi (Theta - arg Gs / 2 pi)}: one more phase term,
+// two products instead of a complex product.
+__global__ void __launch_bounds__(256) k_polar(float2 *__restrict__ g, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 v = g[i];
+    g[i] = make_float2(hypotf(v.x, v.y), atan2f(v.y, v.x) * 0.15915494309189535f);
+}
+
+hipError_t launch_polar(float2 *g, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_polar, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, n);
+    return hipGetLastError();
+}
+
 // Transposed butterfly reduction of V (8 or 16) per-lane values over the 64 lanes of a
 // wavefront.  Each transposed step pairs value i with value i + h and lane l with lane
 // l ^ d: the lane with the d bit clear keeps and sums the first value of the pair, its
@@ -122,34 +129,34 @@ static __device__ __forceinline__ float dpp_xor1(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
 }
 
-// Sum of one value over all 64 lanes (every lane receives the total).
-static __device__ __forceinline__ float reduce_full(float v)
-{
-    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    v += dpp_ror8(v);
-    v += dpp_half_mirror(v);
-    v += dpp_xor1(v);
-    v += dpp_xor2(v);
-    return v;
-}
-
-template <int V>
-static __device__ __forceinline__ void reduce_transposed(float (&x)[V], int lane)
+// With EXTRA, one more value y is carried along: it is summed over lane bits 5, 4 and 3 on
+// its own, and in the last stage lanes with bit 2 clear keep x while lanes with bit 2 set
+// keep y (the half-row mirror pairs lane i with lane 7 - i, which differ in bit 2), so
+// afterwards lanes with bit 2 set hold the total of y.
+template <int V, bool EXTRA>
+static __device__ __forceinline__ void reduce_transposed(float (&x)[V], float &y, int lane)
 {
     static_assert(V == 8 || V == 16, "8 or 16 values");
+    static_assert(!EXTRA || V == 8, "the extra value rides with 8 values");
     constexpr int H = V / 2;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
         const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i + H]), false, false);
         x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
+    if (EXTRA) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+        y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[i + H / 2]), false, false);
         x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    if (EXTRA) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+        y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        y += dpp_ror8(y);
     }
     const bool b3 = lane & 8;
 #pragma unroll
@@ -158,18 +165,29 @@ static __device__ __forceinline__ void reduce_transposed(float (&x)[V], int lane
         const float send = b3 ? x[i] : x[i + H / 4];
         x[i] = keep + dpp_ror8(send);
     }
-#pragma unroll
-    for (int i = 0; i < V / 8; ++i) {
-        float r = x[i];
-        r += dpp_half_mirror(r);
+    if (EXTRA) {
+        const bool b2 = lane & 4;
+        const float keep = b2 ? y : x[0];
+        const float send = b2 ? x[0] : y;
+        float r = keep + dpp_half_mirror(send);
         r += dpp_xor1(r);
         r += dpp_xor2(r);
-        x[i] = r;
+        x[0] = r;
+        y = r;
+    } else {
+#pragma unroll
+        for (int i = 0; i < V / 8; ++i) {
+            float r = x[i];
+            r += dpp_half_mirror(r);
+            r += dpp_xor1(r);
+            r += dpp_xor2(r);
+            x[i] = r;
+        }
     }
 }
 
 template <int C, bool DEPTH, int F>
-__global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy,
+__global__ void __launch_bounds__(WG, waves_per_simd(F)) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy,
                                                 const BwdScene *__restrict__ scenes, const int32_t *__restrict__ prefix,
                                                 int n_scenes, long long *__restrict__ queue,
                                                 const float *__restrict__ dtab, const double *__restrict__ d0tab,
@@ -207,7 +225,7 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
         if (q >= total_items) break;
         const BwdScene S = scenes[sc];
         const GRec *__restrict__ rec = S.rec;
-        const float2 *__restrict__ gspec = S.gspec;
+        const float2 *__restrict__ gspec = S.gspec;  // polar: (|Gs|, arg Gs / 2 pi)
         const int64_t nvalid = S.n - S.counters[CTR_NCULLED];
         const BItem bi = S.bitems[q - prefix[sc]];
         long long pairs = 0;
@@ -244,6 +262,8 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                 const int cnt = __popcll(bal);
                 if (cnt == 0) continue;
                 if (p) {
+                    const uint32_t rows = row_block_mask<F>(r0.x, r0.y, r0.z, lim, x0, x1, sy0, hy);
+                    pairs += __popc(rows) * (SUBX * 4);
                     const uint32_t ramp = (uint32_t)cx * rx + (uint32_t)cy * ry;
                     const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
                     float4 b4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -254,7 +274,7 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                     b4 = make_float4(bs[0], bs[1], bs[2], bs[3]);
                     float4 *dst = reinterpret_cast<float4 *>(&s_w[wave][__popcll(bal & lt)]);
                     dst[0] = r0;
-                    dst[1] = make_float4(r1.z, r1.w, __int_as_float(lane), 0.f);
+                    dst[1] = make_float4(r1.z, r1.w, __int_as_float(lane), __uint_as_float(rows));
                     dst[2] = r3;
                     dst[3] = b4;
                 }
@@ -267,7 +287,7 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                 const float mxx = fmx * fmx;
                 const int mx = mxp < 0 ? mxp + k.nx : mxp;
                 const bool xin = mxp >= -hx && mxp < hx;
-                float fmy[F], mxy[F], myy[F], dyf[F], dD[F][C], gr[F][C], gi[F][C];
+                float fmy[F], mxy[F], myy[F], dyf[F], dD[F][C], gm[F][C], gp[F][C];
                 float D0f[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) D0f[c] = (float)d0tab[c * ns + sidx];
@@ -285,26 +305,29 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                     for (int c = 0; c < C; ++c) {
                         if (in) {
                             const float2 gv = gspec[c * M + o];
-                            gr[f][c] = gv.x;
-                            gi[f][c] = gv.y;
+                            gm[f][c] = gv.x;
+                            gp[f][c] = gv.y;
                             dD[f][c] = dtab[c * M + o];
                         } else {
-                            gr[f][c] = gi[f][c] = 0.0f;
+                            gm[f][c] = gp[f][c] = 0.0f;
                             dD[f][c] = 0.0f;
                         }
                     }
                 }
-                pairs += cnt;
+                const float4 *sw = reinterpret_cast<const float4 *>(&s_w[wave][0]);
                 for (int ei = 0; ei < cnt; ++ei) {
-                    const BEntry &w = s_w[wave][ei];
-                    const float alpha = w.alpha, beta2 = w.beta2, gamma = w.gamma, z = w.z, rxf = w.rxf, ryf = w.ryf;
-                    const int owner = w.owner;
+                    // e0 = (alpha, beta2, gamma, z), e1 = (rxf, ryf, owner, rows), e2 = amp, e3 = base
+                    const float4 e0 = sw[4 * ei], e1 = sw[4 * ei + 1], e2 = sw[4 * ei + 2], e3 = sw[4 * ei + 3];
+                    const float alpha = e0.x, beta2 = e0.y, gamma = e0.z, z = e0.w, rxf = e1.x, ryf = e1.y;
+                    const int owner = __float_as_int(e1.z);
+                    const uint32_t rows = __builtin_amdgcn_readfirstlane(__float_as_uint(e1.w));
+                    const float ampv[4] = {e2.x, e2.y, e2.z, e2.w}, basev[4] = {e3.x, e3.y, e3.z, e3.w};
                     float amp[C], bx[C];
                     const float ax = alpha * mxx;
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        amp[c] = w.amp[c];
-                        bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, w.base[c]));
+                        amp[c] = ampv[c];
+                        bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, basev[c]));
                     }
                     float Pr[C], Pi[C], Wc[C];
 #pragma unroll
@@ -313,17 +336,18 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                     float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f, I0 = 0.0f, I1 = 0.0f;
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
+                        if (!(rows & (1u << f))) continue;  // the support misses this 4-row block
                         const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
                         const float E = __builtin_amdgcn_exp2f(-q);
                         float ur = 0.0f, ui = 0.0f;
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
-                            const float th = fmaf(-z, dD[f][c], fmaf(-dyf[f], ryf, bx[c]));
+                            // conj(Gs) e^{j 2 pi th} = |Gs| e^{j 2 pi (th - arg Gs / 2 pi)} = h + j k
+                            const float th = fmaf(-z, dD[f][c], fmaf(-dyf[f], ryf, bx[c]) - gp[f][c]);
                             const float sn = __builtin_amdgcn_sinf(th);
                             const float cs = __builtin_amdgcn_cosf(th);
-                            // conj(Gs) e^{j 2 pi th} = h + j k
-                            const float h = fmaf(gr[f][c], cs, gi[f][c] * sn);
-                            const float kk = fmaf(gr[f][c], sn, -gi[f][c] * cs);
+                            const float h = gm[f][c] * cs;
+                            const float kk = gm[f][c] * sn;
                             Pr[c] = fmaf(E, h, Pr[c]);
                             if (DEPTH) Pi[c] = fmaf(E, kk, Pi[c]);
                             ur = fmaf(amp[c], h, ur);
@@ -355,16 +379,16 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
                     }
 #pragma unroll
                     for (int i = NV; i < NR; ++i) x[i] = 0.0f;
-                    reduce_transposed<NR>(x, lane);
-                    float sim = 0.0f;
-                    if (!DEPTH) sim = reduce_full(I0);
+                    // without depth, sum_m Im rho (the phase gradient) rides along as y
+                    float sim = I0;
+                    reduce_transposed<NR, !DEPTH>(x, sim, lane);
                     if ((lane & 7) == 0) {
                         const int v0 = (NR / 8) * (((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1));
 #pragma unroll
                         for (int j = 0; j < NR / 8; ++j)
-                            if (v0 + j < NV) s_acc[wave][owner][v0 + j] += x[j];
+                            if (v0 + j < NV) atomicAdd(&s_acc[wave][owner][v0 + j], x[j]);  // ds_add_f32, no return
                     }
-                    if (!DEPTH && lane == 0) s_acc[wave][owner][EXTRA_SLOT] += sim;
+                    if (!DEPTH && lane == 4) atomicAdd(&s_acc[wave][owner][EXTRA_SLOT], sim);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -375,6 +399,7 @@ __global__ void __launch_bounds__(WG, 4) k_adjoint(Consts k, const int32_t *__re
 #pragma unroll
         for (int v = 0; v < NACC; ++v) dst[v] = s_acc[wave][lane][v];
         __builtin_amdgcn_wave_barrier();
+        pairs = wave_sum_i64(pairs);
         if (lane == 0 && pairs) atomicAdd((unsigned long long *)&S.counters[CTR_PAIRS], (unsigned long long)pairs);
     }
 }
@@ -417,10 +442,27 @@ hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes
     }
 }
 
+template <int C, bool DEPTH>
+static const void *adj_kernel_ptr(int F)
+{
+    switch (F) {
+    case 2: return (const void *)k_adjoint<C, DEPTH, 2>;
+    case 8: return (const void *)k_adjoint<C, DEPTH, 8>;
+    default: return (const void *)k_adjoint<C, DEPTH, 4>;
+    }
+}
+
 int adjoint_occupancy(int C, int F, int depth)
 {
-    (void)C; (void)F; (void)depth;
-    return 4;  // __launch_bounds__(WG, 4): at most 128 VGPRs, 32 KB LDS per work-group
+    const void *kp = nullptr;
+    switch (C) {
+    case 1: kp = depth ? adj_kernel_ptr<1, true>(F) : adj_kernel_ptr<1, false>(F); break;
+    case 2: kp = depth ? adj_kernel_ptr<2, true>(F) : adj_kernel_ptr<2, false>(F); break;
+    default: kp = depth ? adj_kernel_ptr<3, true>(F) : adj_kernel_ptr<3, false>(F); break;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, WG, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
 }
 
 // Per Gaussian: sum the item partials of its chunk in order (FP64), then the chain rule.
