@@ -53,15 +53,16 @@ def ellipse_support_points(scene, grid, eps=1e-7):
     return float(np.minimum(area, grid.nx * grid.ny).sum())
 
 
-def cpu_baseline(scene, grid, seconds_target=20.0):
-    """FP64 oracle on a bounded sample, extrapolated to one fwd+bwd hologram."""
+def cpu_baseline(scene, grid):
+    """FP64 oracle on a bounded sample (about 10-15 s of host time), extrapolated to one
+    fwd+bwd hologram."""
     import numpy as np
     import oracle
     import gwsgen
     rng = np.random.default_rng(4242)
     M = grid.nx * grid.ny
     # forward: Eq. 12 at a sample of frequencies (every Gaussian, every wavelength)
-    S = 1536
+    S = 4096
     mx = rng.integers(0, grid.nx, S).astype(np.int32)
     my = rng.integers(0, grid.ny, S).astype(np.int32)
     t0 = time.perf_counter()
@@ -74,7 +75,7 @@ def cpu_baseline(scene, grid, seconds_target=20.0):
     gs1 = oracle.spectrum_grad_from_field_grad(G1, g1)
     t_xf = time.perf_counter() - t0
     # backward: dense per-Gaussian gradients for a sample of Gaussians
-    nsel = 256
+    nsel = 640
     sel = rng.choice(scene.n, nsel, replace=False)
     gs = np.repeat(gs1, grid.n_lambda, axis=0)
     t0 = time.perf_counter()
@@ -106,8 +107,8 @@ def main():
                     help="after the timed steps, copy 1 GiB device-to-device 3 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the hot path runs on a single MI355X in this build "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path runs on a single MI355X; sharding a hologram "
+              "or a batch across GPUs is not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
