@@ -327,7 +327,8 @@ def bench_batched(args):
             stream.synchronize()
             res[name] = e0.elapsed_time(e1) / args.steps
             log("bench batched16: %s %.2f ms per 16-scene step" % (name, res[name]))
-        replayed = ctx.stats()["graph_replayed"]
+            if name == "batched":
+                replayed = ctx.stats()["graph_replayed"]  # the last batched call replayed its graph
     out = {"metric": "holograms/s, 16 scenes (Gaussians log-uniform in [1e3, 5e5]) at 1080x1920x3 fwd+bwd",
            "value": 1e3 * S / res["batched"], "unit": "holograms/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": res["batched"], "higher_is_better": True, "scaling": "weak",
