@@ -4,7 +4,7 @@
 //   direction +1:  out[n] = sum_m in[m] exp(+j 2 pi m n / N)
 //   direction -1:  out[n] = sum_m in[m] exp(-j 2 pi m n / N)
 // Pass 1 transforms rows (one row per work-group); pass 2 transforms columns, a slab of
-// B adjacent columns per work-group, read and written as contiguous row segments.
+// B adjacent columns per work-group, read and written as whole-cache-line row segments.
 // Twiddles come from per-size FP32 tables computed on the host in FP64.
 #include "gws_internal.h"
 
@@ -170,32 +170,105 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
     for (int i = threadIdx.x; i < pl.n; i += blockDim.x) dst[i] = res[i];
 }
 
-// Column transforms: work-group owns columns [c0, c0 + B) of one image [n][width];
-// LDS holds the B columns transposed (column-major) so each transform is contiguous.
+// Column transforms.  A work-group of FFT_COL_THREADS owns columns [c0, c0 + B) of one image
+// [n][width] (B = 16: 128-byte row segments, whole cache lines) and keeps them in ONE LDS
+// buffer laid out [n][B], so the global reads and writes are contiguous row segments and a
+// butterfly's R inputs of column c sit B apart (consecutive threads take consecutive columns:
+// no bank conflicts).  Each Stockham pass runs in place: every thread first reads the inputs
+// of its (at most KMAX) butterflies into registers, the work-group synchronises, then every
+// thread writes its outputs.  The twiddle table sits in LDS after the data.
+constexpr int FFT_COL_THREADS = 1024;
+constexpr int FFT_COL_MAXELEM = 150 * 1024 / 8;  // complex64 elements of data in LDS (n * B)
+constexpr int FFT_COL_LDSELEM = 160 * 1024 / 8;  // data + twiddle table (n * (B + 1))
+
+template <int R>
+struct ColK {
+    static constexpr int KMAX = (FFT_COL_MAXELEM / R + FFT_COL_THREADS - 1) / FFT_COL_THREADS;
+};
+
+// j / d for j < 2^16 and 2 <= d <= 2^14: with m = floor((2^32 - 1) / d) + 1, umulhi(j, m) = j / d
+// exactly (the error j (m - 2^32/d) / 2^32 < 2^-16 is below the smallest non-zero fraction 1/d).
+// (d = 1 would need m = 2^32; callers handle it.)
+static __device__ __forceinline__ int div_small(int j, uint32_t m) { return (int)__umulhi((uint32_t)j, m); }
+
+template <int R, int S>
+static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n, int lb, int Ns, const float2 *tw,
+                                                             int tid)
+{
+    constexpr int KMAX = ColK<R>::KMAX;
+    const int B = 1 << lb, nb = n / R, total = nb << lb, tstep = n / (Ns * R);
+    const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
+    float2 v[KMAX][R];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        const int idx = tid + q * FFT_COL_THREADS;
+        if (idx < total) {
+            const int j = idx >> lb, c = idx & (B - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[((j + r * nb) << lb) + c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        const int idx = tid + q * FFT_COL_THREADS;
+        if (idx < total) {
+            const int j = idx >> lb, c = idx & (B - 1);
+            const int jq = Ns > 1 ? div_small(j, mNs) : j, k = j - jq * Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[r * k * tstep];
+                if (S < 0) w.y = -w.y;
+                v[q][r] = cmul(v[q][r], w);
+            }
+            if (R == 2) dft2<S>(v[q]);
+            if (R == 3) dft3<S>(v[q]);
+            if (R == 4) dft4<S>(v[q]);
+            if (R == 5) dft5<S>(v[q]);
+            if (R == 8) dft8<S>(v[q]);
+            const int o = jq * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[((o + r * Ns) << lb) + c] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
 template <int S>
-__global__ void __launch_bounds__(FFT_THREADS) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
-                                                          RadixPlan pl, const float2 *__restrict__ tw, int width, int B)
+__global__ void __launch_bounds__(FFT_COL_THREADS) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                              RadixPlan pl, const float2 *__restrict__ tw, int width,
+                                                              int lb)
 {
     extern __shared__ float2 lds[];
-    const int n = pl.n;
-    float2 *a = lds, *b = lds + (size_t)n * B;
+    const int n = pl.n, B = 1 << lb;
+    float2 *tw_s = lds + n * B;  // the twiddle table, read by every pass
+    for (int i = threadIdx.x; i < n; i += FFT_COL_THREADS) tw_s[i] = tw[i];
     const int nslab = (width + B - 1) / B;
     const int64_t img = blockIdx.x / nslab;
     const int c0 = (blockIdx.x - (int)(img * nslab)) * B;
     const int bw = min(B, width - c0);
     const float2 *src = in + img * (int64_t)n * width;
     float2 *dst = out + img * (int64_t)n * width;
-    for (int i = threadIdx.x; i < n * B; i += blockDim.x) {
-        const int r = i / B, c = i - r * B;
-        if (c < bw) a[c * n + r] = src[(int64_t)r * width + c0 + c];
-        else a[c * n + r] = make_float2(0.0f, 0.0f);
+    for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
+        const int r = i >> lb, c = i & (B - 1);
+        lds[i] = c < bw ? src[(int64_t)r * width + c0 + c] : make_float2(0.0f, 0.0f);
     }
     __syncthreads();
-    const int cur = fft_lds<S>(a, b, pl, B, tw);
-    const float2 *res = cur ? b : a;
-    for (int i = threadIdx.x; i < n * B; i += blockDim.x) {
-        const int r = i / B, c = i - r * B;
-        if (c < bw) dst[(int64_t)r * width + c0 + c] = res[c * n + r];
+    int Ns = 1;
+    for (int p = 0; p < pl.nrad; ++p) {
+        const int R = pl.r[p];
+        switch (R) {
+        case 2: stockham_pass_inplace<2, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 3: stockham_pass_inplace<3, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 4: stockham_pass_inplace<4, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 5: stockham_pass_inplace<5, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        default: stockham_pass_inplace<8, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        }
+        Ns *= R;
+    }
+    for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
+        const int r = i >> lb, c = i & (B - 1);
+        if (c < bw) dst[(int64_t)r * width + c0 + c] = lds[i];
     }
 }
 
@@ -210,9 +283,9 @@ static RadixPlan make_radix(int n, const int32_t *r, int nrad)
 
 int fft_col_batch(int n)
 {
-    // largest B (power of two, <= 16) with 2 B n complex64 within 150 KB of LDS
+    // largest B (power of two, <= 16) with B n complex64 of data and the n twiddles in LDS
     int B = 16;
-    while (B > 1 && (size_t)2 * B * n * sizeof(float2) > 150 * 1024) B >>= 1;
+    while (B > 1 && ((int64_t)B * n > FFT_COL_MAXELEM || (int64_t)(B + 1) * n > FFT_COL_LDSELEM)) B >>= 1;
     return B;
 }
 
@@ -236,16 +309,18 @@ hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *i
     const size_t row_lds = 2 * (size_t)p.nx * sizeof(float2);
     const int rows = batch * p.ny;
     const int B = fft_col_batch(p.ny);
-    const size_t col_lds = 2 * (size_t)B * p.ny * sizeof(float2);
+    int lb = 0;
+    while ((1 << lb) < B) ++lb;
+    const size_t col_lds = (size_t)(B + 1) * p.ny * sizeof(float2);
     const int nslab = (p.nx + B - 1) / B;
     if (direction > 0) {
         hipLaunchKernelGGL(k_fft_rows<-1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, in, out, px, p.tw_x);
-        hipLaunchKernelGGL(k_fft_cols<-1>, dim3(batch * nslab), dim3(FFT_THREADS), col_lds, s, out, out, py, p.tw_y,
-                           p.nx, B);
+        hipLaunchKernelGGL(k_fft_cols<-1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, out, out, py, p.tw_y,
+                           p.nx, lb);
     } else {
         hipLaunchKernelGGL(k_fft_rows<1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, in, out, px, p.tw_x);
-        hipLaunchKernelGGL(k_fft_cols<1>, dim3(batch * nslab), dim3(FFT_THREADS), col_lds, s, out, out, py, p.tw_y,
-                           p.nx, B);
+        hipLaunchKernelGGL(k_fft_cols<1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, out, out, py, p.tw_y,
+                           p.nx, lb);
     }
     return hipGetLastError();
 }
