@@ -229,6 +229,20 @@ gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *field, const vo
 gws_status gws_set_profiling(gws_ctx *ctx, int enable);
 gws_status gws_read_profile(gws_ctx *ctx, double *ms, int64_t *count);
 
+/* Roofline denominators measured on the context's device (the derived ones come from unit
+ * counts and clock).  trans_ops_per_s: v_exp_f32, v_sin_f32 and v_cos_f32 in the spectrum
+ * accumulation's 1:3:3 mix, as independent chains at full occupancy; valu_ops_per_s:
+ * independent FP32 FMAs (one op each); hbm_bytes_per_s: a 1 GiB device-to-device copy,
+ * bytes read plus bytes written.  Best of three launches each, timed with HIP events on
+ * `stream`.  Allocates 2 GiB + 64 KiB of device memory for the duration of the call and
+ * synchronises; takes a few tens of milliseconds. */
+typedef struct gws_peaks {
+    double trans_ops_per_s;
+    double valu_ops_per_s;
+    double hbm_bytes_per_s;
+} gws_peaks;
+gws_status gws_measure_peaks(gws_ctx *ctx, gws_peaks *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

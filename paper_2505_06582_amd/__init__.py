@@ -68,6 +68,11 @@ class _Stats(ctypes.Structure):
                 ("n_candidates", ctypes.c_int64), ("tile_config", ctypes.c_int32), ("graph_replayed", ctypes.c_int32)]
 
 
+class _Peaks(ctypes.Structure):
+    _fields_ = [("trans_ops_per_s", ctypes.c_double), ("valu_ops_per_s", ctypes.c_double),
+                ("hbm_bytes_per_s", ctypes.c_double)]
+
+
 PARAMS = ("mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity", "amplitude", "phase")
 
 # exported symbol -> (restype, argtypes)
@@ -103,6 +108,7 @@ _SIGNATURES = {
     "gws_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int64, ctypes.c_char_p,
                                     ctypes.c_void_p]),
     "gws_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Stats)]),
+    "gws_measure_peaks": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Peaks), ctypes.c_void_p]),
     "gws_l2_workspace_size": (ctypes.c_size_t, []),
     "gws_l2_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -377,6 +383,12 @@ class Context:
         s = _Stats()
         _check(self.lib.gws_get_stats(self.handle, ctypes.byref(s)), self.handle)
         return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+    def measure_peaks(self) -> dict:
+        """Measured roofline denominators of this device (gws_measure_peaks)."""
+        p = _Peaks()
+        _check(self.lib.gws_measure_peaks(self.handle, ctypes.byref(p), self._stream()), self.handle)
+        return {f: getattr(p, f) for f, _ in _Peaks._fields_}
 
 
 _ctx_cache: Dict[int, Context] = {}

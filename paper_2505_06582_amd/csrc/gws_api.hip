@@ -1191,3 +1191,12 @@ extern "C" gws_status gws_read_profile(gws_ctx *ctx, double *ms, int64_t *count)
     ctx->recs.clear();
     return GWS_OK;
 }
+
+extern "C" gws_status gws_measure_peaks(gws_ctx *ctx, gws_peaks *out, void *stream)
+{
+    if (!ctx || !out) return fail(ctx, GWS_ERR_INVALID_ARG, "null argument");
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    HIP_CHECK(ctx, run_probes(ctx->n_cu, (hipStream_t)stream, &out->trans_ops_per_s, &out->valu_ops_per_s,
+                              &out->hbm_bytes_per_s));
+    return GWS_OK;
+}

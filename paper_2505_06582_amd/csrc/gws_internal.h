@@ -264,6 +264,7 @@ hipError_t launch_accumulate(const Plan &p, const Consts &k, const FwdScene *sce
 hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes,
                                   hipStream_t s);
 hipError_t launch_polar(float2 *g, int64_t n, hipStream_t s);
+hipError_t run_probes(int n_cu, hipStream_t s, double *trans_ops, double *valu_ops, double *hbm_bytes);
 hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
                          hipStream_t s);
 hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,
