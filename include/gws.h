@@ -48,7 +48,7 @@ typedef enum gws_status {
     GWS_OK = 0,
     GWS_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, bad enum value */
     GWS_ERR_SHAPE = -2,       /* grid not supported: odd, < 16, > 8192, or a prime factor > 5 */
-    GWS_ERR_UNSUPPORTED = -3, /* valid request this build does not implement (exact blending) */
+    GWS_ERR_UNSUPPORTED = -3, /* valid request this build does not implement (see gws_blend) */
     GWS_ERR_WORKSPACE = -4,   /* workspace null, misaligned (256 B) or smaller than required */
     GWS_ERR_NO_DEVICE = -5,   /* no HIP device, or the device is not gfx950 */
     GWS_ERR_HIP = -6,         /* a HIP runtime call failed; see gws_last_error */
@@ -56,8 +56,12 @@ typedef enum gws_status {
 } gws_status;
 
 /* Blending model.  OIT is Eq. 12 (transmittance taken as 1).  EXACT is alpha wave
- * blending with a spatial transmittance map (Eq. 5-6, Alg. 2): not built yet, every
- * call with it returns GWS_ERR_UNSUPPORTED. */
+ * blending with a spatial transmittance map (Eq. 5-6, supplement Alg. 2): Gaussians front to
+ * back (descending depth, ties by index); each splats its own wavefront e^{j phi} g(x)
+ * (profile truncated below eps_support of its peak) masked by the map, propagated by
+ * H(nu, -z) and scaled by a_c o; alpha = o g, dropped unless above 1/255, then updates the
+ * map.  EXACT is supported by gws_forward and gws_workspace_size only; gws_backward, the
+ * batched calls and gws_autotune return GWS_ERR_UNSUPPORTED for it. */
 typedef enum gws_blend { GWS_BLEND_OIT = 0, GWS_BLEND_EXACT = 1 } gws_blend;
 
 /* Inverse transform: mixed-radix FP32 FFT, or the DFT as two dense complex GEMMs on the
@@ -158,7 +162,11 @@ gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *problem, in
 
 /* Forward: the field (and optionally the spectrum) of n Gaussians, Eq. 12 + inverse DFT.
  * Steps on the stream: per-Gaussian preprocessing and keys, depth-within-support-radius
- * radix sort, binning into frequency tiles, spectrum accumulation, inverse 2D transform. */
+ * radix sort, binning into frequency tiles, spectrum accumulation, inverse 2D transform.
+ * With blend = GWS_BLEND_EXACT (Eq. 5-6): depth sort, then per batch of up to 64 Gaussians
+ * the masked wavefronts with the transmittance map, their batched forward FFT and the
+ * propagated splat into the spectrum, then the inverse 2D transform.  The workspace for
+ * EXACT holds one batch of full-grid images (about 1 GiB at 1080 x 1920). */
 gws_status gws_forward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
                        const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
 

@@ -154,7 +154,6 @@ extern "C" gws_status gws_check_problem(const gws_problem *p)
     if (p->tile_config < 0 || p->tile_config > gws_tile_config_count()) return GWS_ERR_INVALID_ARG;
     const gws_status gs = check_grid(p->nx, p->ny);
     if (gs != GWS_OK) return gs;
-    if (p->blend == GWS_BLEND_EXACT) return GWS_ERR_UNSUPPORTED;
     return GWS_OK;
 }
 
@@ -405,6 +404,35 @@ static gws_status check_offsets(int S, const int64_t *offsets, int64_t n)
     return GWS_OK;
 }
 
+// Workspace of the exact-blending forward: sort buffers, records, transmittance map, one
+// batch of full-grid images, the spectrum, and the bf16 DFT's intermediate when used.
+struct ExactLayout {
+    size_t off_keys_a = 0, off_keys_b = 0, off_vals_a = 0, off_vals_b = 0, off_sort_hist = 0, off_rec = 0,
+           off_tmap = 0, off_imgs = 0, off_spec = 0, off_dft = 0, total = 0;
+    int sort_blocks = 1;
+};
+
+static ExactLayout exact_layout(const gws_problem *p, int64_t n)
+{
+    ExactLayout L;
+    const size_t M = (size_t)p->nx * p->ny;
+    L.sort_blocks = (int)std::max<int64_t>(1, (n + 4095) / 4096);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
+    L.off_keys_a = take(sizeof(uint64_t) * n);
+    L.off_keys_b = take(sizeof(uint64_t) * n);
+    L.off_vals_a = take(sizeof(uint32_t) * n);
+    L.off_vals_b = take(sizeof(uint32_t) * n);
+    L.off_sort_hist = take(sizeof(uint32_t) * 256 * L.sort_blocks);
+    L.off_rec = take((size_t)64 * n);
+    L.off_tmap = take(sizeof(float) * M);
+    L.off_imgs = take(sizeof(float2) * M * exact_batch(p->nx, p->ny));
+    L.off_spec = take(sizeof(float2) * M * p->n_lambda);
+    L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? sizeof(float2) * M * p->n_lambda : 1);
+    L.total = o;
+    return L;
+}
+
 extern "C" gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *problem, int64_t n, size_t *bytes)
 {
     (void)ctx;
@@ -412,6 +440,10 @@ extern "C" gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *
     const gws_status st = gws_check_problem(problem);
     if (st != GWS_OK) return st;
     if (n > (int64_t)0x7fffffff) return GWS_ERR_INVALID_ARG;
+    if (problem->blend == GWS_BLEND_EXACT) {
+        *bytes = exact_layout(problem, n).total;
+        return GWS_OK;
+    }
     const int64_t off[2] = {0, n};
     *bytes = make_batch_layout(problem, 1, off).total;
     return GWS_OK;
@@ -424,6 +456,7 @@ extern "C" gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_p
     if (!bytes || !offsets || n_scenes < 1) return GWS_ERR_INVALID_ARG;
     const gws_status st = gws_check_problem(problem);
     if (st != GWS_OK) return st;
+    if (problem->blend == GWS_BLEND_EXACT) return GWS_ERR_UNSUPPORTED;
     if (check_offsets(n_scenes, offsets, offsets[n_scenes]) != GWS_OK) return GWS_ERR_INVALID_ARG;
     *bytes = make_batch_layout(problem, n_scenes, offsets).total;
     return GWS_OK;
@@ -802,6 +835,45 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     return GWS_OK;
 }
 
+static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g,
+                                    const gws_output *out, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    Plan *p = nullptr;
+    gws_status st = get_plan(ctx, prob->nx, prob->ny, 4, &p);  // for its transform tables
+    if (st != GWS_OK) return st;
+    const ExactLayout L = exact_layout(prob, g->n);
+    st = check_ws(ctx, ws, ws_bytes, L.total);
+    if (st != GWS_OK) return st;
+    char *base = (char *)ws;
+    const Consts k = make_consts(prob, 1);
+    ExactBuffers eb;
+    eb.keys_a = (uint64_t *)(base + L.off_keys_a);
+    eb.keys_b = (uint64_t *)(base + L.off_keys_b);
+    eb.vals_a = (uint32_t *)(base + L.off_vals_a);
+    eb.vals_b = (uint32_t *)(base + L.off_vals_b);
+    eb.sort_hist = (uint32_t *)(base + L.off_sort_hist);
+    eb.sort_blocks = L.sort_blocks;
+    eb.rec = (void *)(base + L.off_rec);
+    eb.tmap = (float *)(base + L.off_tmap);
+    eb.imgs = (float2 *)(base + L.off_imgs);
+    float2 *spec = out->spectrum ? (float2 *)out->spectrum : (float2 *)(base + L.off_spec);
+    {
+        StageScope sc(ctx, s, ST_ACCUM);
+        HIP_CHECK(ctx, run_exact_forward(*p, k, scene_view(g, 0, g->n), eb, spec, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_XFORM_INV);
+        if (prob->xform == GWS_XFORM_FFT_FP32)
+            HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spec, (float2 *)out->field, s));
+        else
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)out->field, (void *)(base + L.off_dft), s));
+    }
+    HIP_CHECK(ctx, launch_sum_counters(nullptr, 0, ctx->d_stats, s));
+    ctx->last_n = g->n;
+    ctx->last_tile_config = 0;
+    return GWS_OK;
+}
+
 extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const gws_output *out,
                                   void *ws, size_t ws_bytes, void *stream)
 {
@@ -814,6 +886,7 @@ extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const g
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     const int64_t off[2] = {0, g->n};
     ctx->last_graph = 0;
+    if (prob->blend == GWS_BLEND_EXACT) return exact_forward_run(ctx, prob, g, out, ws, ws_bytes, (hipStream_t)stream);
     return forward_run(ctx, prob, 1, off, g, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -824,6 +897,7 @@ extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const 
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
     if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
+    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "exact blending has no adjoint yet");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     st = check_grads(ctx, grads);
@@ -906,6 +980,7 @@ extern "C" gws_status gws_forward_batched(gws_ctx *ctx, const gws_problem *prob,
     if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "exact blending is not batched");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     if (!out || !out->field) return fail(ctx, GWS_ERR_INVALID_ARG, "output field is NULL");
@@ -935,6 +1010,7 @@ extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *prob
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
     if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
+    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "exact blending is not batched");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     st = check_grads(ctx, grads);
@@ -1064,6 +1140,7 @@ extern "C" gws_status gws_autotune(gws_ctx *ctx, const gws_problem *prob, int64_
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
     if (n_hint < 1 || n_hint > (int64_t)0x7fffffff) return fail(ctx, GWS_ERR_INVALID_ARG, "n_hint out of range");
+    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "the tilings tuned are those of Eq. 12");
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     const int C = prob->n_lambda;

@@ -264,6 +264,19 @@ hipError_t launch_accumulate(const Plan &p, const Consts &k, const FwdScene *sce
 hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes,
                                   hipStream_t s);
 hipError_t launch_polar(float2 *g, int64_t n, hipStream_t s);
+
+// Exact alpha wave blending (k_exact.hip): device buffers of one call.
+struct ExactBuffers {
+    uint64_t *keys_a, *keys_b;
+    uint32_t *vals_a, *vals_b, *sort_hist;
+    int sort_blocks;
+    void *rec;     // 64-byte records, front to back
+    float *tmap;   // transmittance [ny][nx]
+    float2 *imgs;  // masked wavefronts of one batch [B][ny][nx]
+};
+size_t exact_batch(int nx, int ny);
+hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, const ExactBuffers &eb, float2 *spec,
+                             hipStream_t s);
 hipError_t run_probes(int n_cu, hipStream_t s, double *trans_ops, double *valu_ops, double *hbm_bytes);
 hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
                          hipStream_t s);

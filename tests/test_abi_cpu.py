@@ -72,7 +72,8 @@ def test_problem_validation_codes():
     assert _check(gws.Problem(256, 256, lambdas=(-5e-7,))) == -1
     assert _check(gws.Problem(256, 256, eps_support=0.5)) == -1
     assert _check(gws.Problem(256, 256, xform=7)) == -1
-    assert _check(gws.Problem(256, 256, blend=gws.BLEND_EXACT)) == -3
+    assert _check(gws.Problem(256, 256, blend=gws.BLEND_EXACT)) == 0
+    assert _check(gws.Problem(256, 256, blend=5)) == -1
     assert lib.gws_check_problem(None) == -1
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.gws_status_string(code)
@@ -90,6 +91,17 @@ def test_workspace_size_is_host_only_and_grows_with_n():
     sz = ctypes.c_size_t()
     assert lib.gws_workspace_size(None, ctypes.byref(prob), -1, ctypes.byref(sz)) == -1
     assert lib.gws_workspace_size(None, ctypes.byref(prob), 10, None) == -1
+
+
+def test_exact_blending_workspace_and_unsupported_calls():
+    lib = gws.load_library()
+    prob = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9), blend=gws.BLEND_EXACT)._c()
+    sz = ctypes.c_size_t()
+    assert lib.gws_workspace_size(None, ctypes.byref(prob), 1000, ctypes.byref(sz)) == 0
+    # one batch of up to 64 full-grid complex64 images dominates
+    assert sz.value >= 64 * 1920 * 1080 * 8
+    offs = (ctypes.c_int64 * 2)(0, 1000)
+    assert lib.gws_workspace_size_batched(None, ctypes.byref(prob), 1, offs, ctypes.byref(sz)) == -3
 
 
 def test_entry_points_reject_bad_arguments_without_a_device():

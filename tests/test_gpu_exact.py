@@ -1,0 +1,134 @@
+"""GPU parity of exact alpha wave blending (Eq. 5-6, Alg. 2) through the C ABI against the
+FP64 oracle in oracle/exact.py."""
+import sys
+
+import numpy as np
+import pytest
+
+import gwsgen
+import oracle
+import oracle.exact as ex
+from gwsgen import Grid
+from gpu_util import problem, rel_l2, scene_to_torch, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+# FP32 tolerance for exact blending (relative L2 of the field), the same bar as the FP32
+# order-invariant path: the transmittance is a product of FP32 factors and the profile is
+# truncated at eps = 1e-7 of its peak (measured 4e-7 .. 2e-6).  The 1/255 alpha decision is
+# taken in FP32 on the GPU and in FP64 by the oracle; a pixel within rounding of the
+# threshold could flip it, which these seeded scenes do not hit.
+TOL_EXACT = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2505_06582_amd as gws
+    assert torch.cuda.is_available()
+    return gws.context(0)
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def clustered_scene(n, grid, seed, spread=0.3, o_range=(0.2, 1.0), depth_range=(-5e-3, 5e-3)):
+    """Seeded Gaussians with the workloads' shapes, centred in a fraction of the field so that
+    they overlap and occlude one another."""
+    s = gwsgen.make_scene(n, grid, seed, depth_range=depth_range)
+    rng = np.random.default_rng(seed + 1)
+    # standard deviations up to a tenth of the grid, so that one periodic image of each
+    # profile is all that reaches the field (the kernel's window is at most half the grid)
+    smax = min(20.0, min(grid.nx, grid.ny) / 10.0)
+    su, sv = rng.uniform(2.0, smax, n), rng.uniform(2.0, smax, n)
+    th = rng.uniform(0.0, np.pi, n)
+    c, sn = np.cos(th), np.sin(th)
+    p2 = grid.px * grid.py
+    s.cov_xx[:] = ((c * c * su * su + sn * sn * sv * sv) * p2).astype(np.float32)
+    s.cov_xy[:] = ((c * sn * (su * su - sv * sv)) * p2).astype(np.float32)
+    s.cov_yy[:] = ((sn * sn * su * su + c * c * sv * sv) * p2).astype(np.float32)
+    w, h = grid.nx * grid.px, grid.ny * grid.py
+    s.mean_x[:] = (rng.uniform(-spread / 2, spread / 2, n) * w).astype(np.float32)
+    s.mean_y[:] = (rng.uniform(-spread / 2, spread / 2, n) * h).astype(np.float32)
+    s.opacity[:] = rng.uniform(*o_range, n).astype(np.float32)
+    return s
+
+
+def gpu_exact(ctx, scene, grid, **kw):
+    import paper_2505_06582_amd as gws
+    prob = problem(grid, blend=gws.BLEND_EXACT, **kw)
+    return to_numpy(ctx.forward(prob, scene_to_torch(scene)))
+
+
+@pytest.mark.parametrize("n,grid,seed", [
+    (32, Grid(64, 48, 8e-6, 8e-6, (520e-9, 638e-9)), 2101),          # one batch
+    (200, Grid(256, 256, 8e-6, 8e-6, gwsgen.RGB), 2102),              # four batches, 3 wavelengths
+    (65, Grid(240, 200, 8e-6, 8e-6, (450e-9,)), 2103),                # ragged batch, non-square grid
+])
+def test_exact_matches_oracle(ctx, n, grid, seed):
+    log("exact parity n=%d grid=%dx%dx%d seed=%d" % (n, grid.nx, grid.ny, grid.n_lambda, seed))
+    s = clustered_scene(n, grid, seed)
+    u = gpu_exact(ctx, s, grid)
+    ref = ex.exact_forward(s, grid)
+    err = rel_l2(u, ref)
+    log("  rel L2 %.3g" % err)
+    assert err < TOL_EXACT
+    # the occlusion is real: the order-invariant sum differs by far more than the tolerance
+    assert rel_l2(oracle.forward(s, grid), ref) > 100 * TOL_EXACT
+
+
+def test_exact_wraps_around_the_grid_edge(ctx):
+    grid = Grid(128, 96, 8e-6, 8e-6, (520e-9,))
+    s = clustered_scene(24, grid, 2104)
+    # put the cluster on the corner so every window wraps in both axes
+    s.mean_x[:] = (s.mean_x + np.float32(0.5 * grid.nx * grid.px)).astype(np.float32)
+    s.mean_y[:] = (s.mean_y + np.float32(0.5 * grid.ny * grid.py)).astype(np.float32)
+    err = rel_l2(gpu_exact(ctx, s, grid), ex.exact_forward(s, grid))
+    log("exact wrap rel L2 %.3g" % err)
+    assert err < TOL_EXACT
+
+
+def test_exact_below_threshold_equals_gpu_order_invariant(ctx):
+    grid = Grid(192, 160, 8e-6, 8e-6, gwsgen.RGB)
+    s = clustered_scene(40, grid, 2105, o_range=(0.5 / 255, 0.9 / 255))
+    u_exact = gpu_exact(ctx, s, grid)
+    u_oit = to_numpy(ctx.forward(problem(grid), scene_to_torch(s)))
+    err = rel_l2(u_exact, u_oit)
+    log("exact vs OIT below threshold rel L2 %.3g" % err)
+    assert err < 1e-5
+
+
+def test_exact_empty_and_zero_opacity(ctx):
+    grid = Grid(64, 64, 8e-6, 8e-6, (520e-9,))
+    s = clustered_scene(8, grid, 2106)
+    s.opacity[:] = 0.0
+    assert np.all(gpu_exact(ctx, s, grid) == 0)
+    empty = s.subset(np.arange(0))
+    assert np.all(gpu_exact(ctx, empty, grid) == 0)
+
+
+def test_exact_full_size_grid(ctx):
+    grid = gwsgen.Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    s = clustered_scene(40, grid, 2107, spread=0.05, depth_range=(-10e-3, 10e-3))
+    log("exact 1080x1920x3, 40 Gaussians")
+    u = gpu_exact(ctx, s, grid)
+    ref = ex.exact_forward(s, grid)
+    err = rel_l2(u, ref)
+    log("  rel L2 %.3g" % err)
+    assert err < TOL_EXACT
+
+
+def test_exact_backward_and_batched_are_unsupported(ctx):
+    import torch
+    import paper_2505_06582_amd as gws
+    grid = Grid(64, 64, 8e-6, 8e-6, (520e-9,))
+    s = clustered_scene(4, grid, 2108)
+    prob = problem(grid, blend=gws.BLEND_EXACT)
+    g = scene_to_torch(s)
+    G = torch.zeros((1, 64, 64), dtype=torch.complex64, device="cuda")
+    with pytest.raises(gws.GwsError):
+        ctx.backward(prob, g, G)
+    with pytest.raises(gws.GwsError):
+        ctx.forward_batched(prob, g, [0, s.n])
