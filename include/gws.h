@@ -60,8 +60,9 @@ typedef enum gws_status {
  * back (descending depth, ties by index); each splats its own wavefront e^{j phi} g(x)
  * (profile truncated below eps_support of its peak) masked by the map, propagated by
  * H(nu, -z) and scaled by a_c o; alpha = o g, dropped unless above 1/255, then updates the
- * map.  EXACT is supported by gws_forward and gws_workspace_size only; gws_backward, the
- * batched calls and gws_autotune return GWS_ERR_UNSUPPORTED for it. */
+ * map.  EXACT is supported by gws_forward, gws_backward (the map recomputed from per-batch
+ * checkpoints, never divided by 1 - alpha) and gws_workspace_size; the batched calls and
+ * gws_autotune return GWS_ERR_UNSUPPORTED for it. */
 typedef enum gws_blend { GWS_BLEND_OIT = 0, GWS_BLEND_EXACT = 1 } gws_blend;
 
 /* Inverse transform: mixed-radix FP32 FFT, or the DFT as two dense complex GEMMs on the
@@ -173,7 +174,12 @@ gws_status gws_forward(gws_ctx *ctx, const gws_problem *problem, const gws_gauss
 /* Backward: given grad_field = dL/dRe(u) + j dL/dIm(u) (complex64 [n_lambda][ny][nx], the
  * convention torch uses for complex tensors), write dL/d(parameter) for every Gaussian.
  * Recomputes preprocessing, sort and binning (no state is kept from gws_forward) and
- * recomputes every (Gaussian, frequency) term instead of storing it. */
+ * recomputes every (Gaussian, frequency) term instead of storing it.  With
+ * GWS_BLEND_EXACT: a forward sweep checkpoints the transmittance map at every batch start
+ * (about 8 MB per 64 Gaussians at 1080 x 1920), then the batches run back to front,
+ * recomputing the masked wavefronts, the map within the batch and a back-to-front
+ * accumulator instead of storing or dividing them; the 1/255 decision is held fixed (its
+ * derivative is taken as zero). */
 gws_status gws_backward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
                         const void *grad_field, const gws_grads *grads,
                         void *workspace, size_t workspace_bytes, void *stream);

@@ -408,7 +408,8 @@ static gws_status check_offsets(int S, const int64_t *offsets, int64_t n)
 // batch of full-grid images, the spectrum, and the bf16 DFT's intermediate when used.
 struct ExactLayout {
     size_t off_keys_a = 0, off_keys_b = 0, off_vals_a = 0, off_vals_b = 0, off_sort_hist = 0, off_rec = 0,
-           off_tmap = 0, off_imgs = 0, off_spec = 0, off_dft = 0, total = 0;
+           off_tmap = 0, off_imgs = 0, off_spec = 0, off_dft = 0, off_gspec = 0, off_ckpt = 0, off_dmap = 0,
+           off_pspec = 0, off_pspat = 0, total = 0;
     int sort_blocks = 1;
 };
 
@@ -429,6 +430,12 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
     L.off_imgs = take(sizeof(float2) * M * exact_batch(p->nx, p->ny));
     L.off_spec = take(sizeof(float2) * M * p->n_lambda);
     L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? sizeof(float2) * M * p->n_lambda : 1);
+    // adjoint: transformed field gradient, map checkpoints, back-to-front accumulator, partial sums
+    L.off_gspec = take(sizeof(float2) * M * p->n_lambda);
+    L.off_ckpt = take(sizeof(float) * M * (size_t)exact_ckpt_count(n, p->nx, p->ny));
+    L.off_dmap = take(sizeof(float) * M);
+    L.off_pspec = take(sizeof(float) * ((M + 255) / 256) * 64 * 12);
+    L.off_pspat = take(sizeof(float) * (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * 64 * 8);
     L.total = o;
     return L;
 }
@@ -874,6 +881,45 @@ static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const
     return GWS_OK;
 }
 
+static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g,
+                                     const void *grad_field, const gws_grads *grads, void *ws, size_t ws_bytes,
+                                     hipStream_t s)
+{
+    Plan *p = nullptr;
+    gws_status st = get_plan(ctx, prob->nx, prob->ny, 4, &p);
+    if (st != GWS_OK) return st;
+    const ExactLayout L = exact_layout(prob, g->n);
+    st = check_ws(ctx, ws, ws_bytes, L.total);
+    if (st != GWS_OK) return st;
+    char *base = (char *)ws;
+    const Consts k = make_consts(prob, 1);
+    ExactBuffers eb;
+    eb.keys_a = (uint64_t *)(base + L.off_keys_a);
+    eb.keys_b = (uint64_t *)(base + L.off_keys_b);
+    eb.vals_a = (uint32_t *)(base + L.off_vals_a);
+    eb.vals_b = (uint32_t *)(base + L.off_vals_b);
+    eb.sort_hist = (uint32_t *)(base + L.off_sort_hist);
+    eb.sort_blocks = L.sort_blocks;
+    eb.rec = (void *)(base + L.off_rec);
+    eb.tmap = (float *)(base + L.off_tmap);
+    eb.imgs = (float2 *)(base + L.off_imgs);
+    ExactBwdBuffers bb;
+    bb.gspec = (float2 *)(base + L.off_gspec);
+    bb.ckpt = (float *)(base + L.off_ckpt);
+    bb.dmap = (float *)(base + L.off_dmap);
+    bb.pspec = (float *)(base + L.off_pspec);
+    bb.pspat = (float *)(base + L.off_pspat);
+    const GradView gv = grad_view(grads, 0, g->n);
+    {
+        StageScope sc(ctx, s, ST_ADJOINT);
+        HIP_CHECK(ctx, run_exact_backward(*p, k, scene_view(g, 0, g->n), eb, bb, (const float2 *)grad_field, gv, s));
+    }
+    HIP_CHECK(ctx, launch_sum_counters(nullptr, 0, ctx->d_stats, s));
+    ctx->last_n = g->n;
+    ctx->last_tile_config = 0;
+    return GWS_OK;
+}
+
 extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const gws_output *out,
                                   void *ws, size_t ws_bytes, void *stream)
 {
@@ -897,7 +943,6 @@ extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const 
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
     if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
-    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "exact blending has no adjoint yet");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     st = check_grads(ctx, grads);
@@ -906,6 +951,8 @@ extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const 
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     const int64_t off[2] = {0, g->n};
     ctx->last_graph = 0;
+    if (prob->blend == GWS_BLEND_EXACT)
+        return exact_backward_run(ctx, prob, g, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
     return backward_run(ctx, prob, 1, off, g, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
 }
 

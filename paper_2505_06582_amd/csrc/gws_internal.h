@@ -275,6 +275,17 @@ struct ExactBuffers {
     float2 *imgs;  // masked wavefronts of one batch [B][ny][nx]
 };
 size_t exact_batch(int nx, int ny);
+// Extra device buffers of the exact-blending adjoint.
+struct ExactBwdBuffers {
+    float2 *gspec;  // FFT of the field gradient [C][ny][nx]
+    float *ckpt;    // the map at every batch start [nbatch][ny][nx]
+    float *dmap;    // running back-to-front accumulator [ny][nx]
+    float *pspec;   // spectral partial sums [M / 256][64][12]
+    float *pspat;   // spatial partial sums [8 x 8 tiles][64][8]
+};
+int64_t exact_ckpt_count(int64_t n, int nx, int ny);
+hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, const ExactBuffers &eb,
+                              const ExactBwdBuffers &bb, const float2 *grad_field, const GradView &out, hipStream_t s);
 hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, const ExactBuffers &eb, float2 *spec,
                              hipStream_t s);
 hipError_t run_probes(int n_cu, hipStream_t s, double *trans_ops, double *valu_ops, double *hbm_bytes);

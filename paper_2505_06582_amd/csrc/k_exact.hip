@@ -107,9 +107,12 @@ static __device__ __forceinline__ float wrap_d(float d, float n)
     return d - n * rintf(d / n);
 }
 
-// One work-group per 16 x 16 pixel tile; walks Gaussians [b0, b0 + nb) in order.
+// One work-group per 16 x 16 pixel tile; walks Gaussians [b0, b0 + nb) in order.  Reads the
+// map from t_in; writes the map at the batch start to ckpt and at its end to t_out, and the
+// masked wavefronts to imgs (each optional).
 __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec, int b0, int nb, int nx, int ny,
-                                                    float *__restrict__ tmap, float2 *__restrict__ imgs)
+                                                    const float *t_in, float *t_out, float2 *__restrict__ imgs,
+                                                    float *__restrict__ ckpt)
 {
     __shared__ ERec s_rec[64];
     const int tx = blockIdx.x, ty = blockIdx.y;
@@ -120,7 +123,8 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
     __syncthreads();
     const int64_t M = (int64_t)nx * ny;
     const int64_t pix = (int64_t)py * nx + px;
-    float T = in ? tmap[pix] : 1.0f;
+    float T = in ? t_in[pix] : 1.0f;
+    if (ckpt && in) ckpt[pix] = T;
     // tile centre, for the work-group-uniform window test
     const float tcx = tx * EXACT_TILE + 7.5f, tcy = ty * EXACT_TILE + 7.5f;
     for (int b = 0; b < nb; ++b) {
@@ -137,9 +141,9 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
             const float alpha = r.o * gk;
             if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
         }
-        if (in) imgs[(int64_t)b * M + pix] = v;
+        if (imgs && in) imgs[(int64_t)b * M + pix] = v;
     }
-    if (in) tmap[pix] = T;
+    if (t_out && in) t_out[pix] = T;
 }
 
 // One thread per frequency (FFT order): U_c += a_{k,c} o_k H_c(nu, -z_k) FFT(T u_k) / (Nx Ny).
@@ -224,11 +228,307 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
     const dim3 tiles((k.nx + EXACT_TILE - 1) / EXACT_TILE, (k.ny + EXACT_TILE - 1) / EXACT_TILE);
     for (int64_t b0 = 0; b0 < n; b0 += B) {
         const int nb = (int)std::min<int64_t>(B, n - b0);
-        hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.tmap, eb.imgs);
+        hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.tmap, eb.tmap,
+                           eb.imgs, (float *)nullptr);
         e = launch_fft2d(p, nb, -1, eb.imgs, eb.imgs, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_splat, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec, (int)b0, nb, k,
                            eb.imgs, spec);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Adjoint.  With Gs_c = FFT(dL/du_c) (torch's complex-gradient convention) and F_k = FFT(T_k u_k),
+//   dL = Re sum_{c,m} conj(Gs_c) d(A_{k,c} H_{k,c} F_k) / (Nx Ny),
+// which splits into
+//   * the spectral sums P_{k,c} = sum_m conj(Gs_c) H F_k and Q_{k,c} = sum_m W_c conj(Gs_c) H F_k
+//     (W_c = sqrt(1/l^2 - |nu|^2)): dL/da_c = o Re P_c / NxNy, dL/do gains sum_c a_c Re P_c / NxNy,
+//     dL/dz = 2 pi sum_c A_c Im Q_c / NxNy (dH/dz = -j 2 pi W H);
+//   * the spatial part Re sum_x d(T_k u_k) conj(R_k), R_k = IFFT(sum_c A_c Gs_c conj(H_c)) / NxNy.
+//     Through u_k = e^{j phi} g_k it gives the mean, covariance and phase gradients; through the
+//     map, with w_k = Re(u_k conj R_k), dL/d alpha_j(x) = -T_j(x) D_j(x), where
+//     D_j = sum_{k > j} w_k prod_{j < i < k} (1 - alpha_i) is accumulated back to front
+//     (D_{j-1} = w_j + (1 - alpha_j) D_j): the map is recomputed from per-batch checkpoints and
+//     never divided by (1 - alpha).
+// ---------------------------------------------------------------------------------
+constexpr int EXACT_BTILE = 8;          // 8 x 8 pixels: one wavefront per work-group
+constexpr int EXACT_NSPEC = 12;         // Re/Im P_c, Re/Im Q_c for c < 3
+constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, Sphi, So, pad
+
+static __device__ __forceinline__ float wave_sum_f(float v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// One thread per frequency: spectral partial sums per (work-group, Gaussian) and, in place of
+// F_k, V_k = sum_c A_c Gs_c conj(H_c).
+__global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
+                                                      const float2 *__restrict__ gspec, float2 *__restrict__ imgs,
+                                                      float *__restrict__ part)
+{
+    __shared__ float s_red[4][EXACT_NSPEC];
+    const int64_t M = (int64_t)k.nx * k.ny;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = m < M;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double w[3] = {0.0, 0.0, 0.0};
+    bool prop[3] = {false, false, false};
+    float2 gs[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    if (live) {
+        const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
+        const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
+        const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
+        const double nu2 = nux * nux + nuy * nuy;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double w2 = k.inv_lambda[c] * k.inv_lambda[c] - nu2;
+            prop[c] = c < k.C && w2 > 0.0;
+            w[c] = prop[c] ? sqrt(w2) : 0.0;
+            if (c < k.C) gs[c] = gspec[(int64_t)c * M + m];
+        }
+    }
+    for (int b = 0; b < nb; ++b) {
+        const ERec &r = rec[b0 + b];
+        float v[EXACT_NSPEC];
+#pragma unroll
+        for (int i = 0; i < EXACT_NSPEC; ++i) v[i] = 0.0f;
+        float2 V = make_float2(0.0f, 0.0f);
+        if (live && r.valid) {
+            const float2 F = imgs[(int64_t)b * M + m];
+            const double zd = (double)r.z;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!prop[c]) continue;
+                const double ph = -zd * w[c];
+                const float t = (float)(ph - floor(ph));
+                const float hc = __builtin_amdgcn_cosf(t), hs = __builtin_amdgcn_sinf(t);
+                // X = conj(Gs) H F
+                const float hfr = hc * F.x - hs * F.y, hfi = hc * F.y + hs * F.x;
+                const float xr = gs[c].x * hfr + gs[c].y * hfi, xi = gs[c].x * hfi - gs[c].y * hfr;
+                const float wf = (float)w[c];
+                v[4 * c + 0] = xr;
+                v[4 * c + 1] = xi;
+                v[4 * c + 2] = wf * xr;
+                v[4 * c + 3] = wf * xi;
+                // V += A_c Gs conj(H)
+                const float A = r.amp[c];
+                V.x = fmaf(A, gs[c].x * hc + gs[c].y * hs, V.x);
+                V.y = fmaf(A, gs[c].y * hc - gs[c].x * hs, V.y);
+            }
+        }
+        if (live) imgs[(int64_t)b * M + m] = V;
+#pragma unroll
+        for (int i = 0; i < EXACT_NSPEC; ++i) {
+            const float t = wave_sum_f(v[i]);
+            if (lane == 0) s_red[wave][i] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < EXACT_NSPEC) {
+            const float t = s_red[0][threadIdx.x] + s_red[1][threadIdx.x] + s_red[2][threadIdx.x] + s_red[3][threadIdx.x];
+            part[((int64_t)blockIdx.x * 64 + b) * EXACT_NSPEC + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// One wavefront per 8 x 8 pixel tile: replays the map over the batch (kept in LDS), then walks
+// the batch back to front with the running D, and reduces the spatial sums per Gaussian.
+__global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec, int b0, int nb, int nx, int ny,
+                                                   double px_m, double py_m, float rscale,
+                                                   const float *__restrict__ tck, float *__restrict__ dmap,
+                                                   const float2 *__restrict__ R, float *__restrict__ part)
+{
+    __shared__ ERec s_rec[64];
+    __shared__ float s_T[64][64];
+    const int lane = threadIdx.x;
+    const int tx = blockIdx.x, ty = blockIdx.y;
+    const int ntx = gridDim.x;
+    const int px = tx * EXACT_BTILE + (lane & 7), py = ty * EXACT_BTILE + (lane >> 3);
+    const bool in = px < nx && py < ny;
+    for (int i = lane; i < nb * 4; i += 64)
+        reinterpret_cast<float4 *>(s_rec)[i] = reinterpret_cast<const float4 *>(rec + b0)[i];
+    __syncthreads();
+    const int64_t M = (int64_t)nx * ny;
+    const int64_t pix = (int64_t)py * nx + px;
+    const float tcx = tx * EXACT_BTILE + 3.5f, tcy = ty * EXACT_BTILE + 3.5f;
+    const float fx = (float)px, fy = (float)py;
+    // forward replay of the map over the batch
+    float T = in ? tck[pix] : 1.0f;
+    for (int b = 0; b < nb; ++b) {
+        s_T[b][lane] = T;
+        const ERec &r = s_rec[b];
+        const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
+        if (r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f) {
+            const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
+            const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
+            const float alpha = r.o * gk;
+            if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
+        }
+    }
+    // back to front
+    const float ln2x2 = 2.0f * 0.69314718055994531f;
+    float D = in ? dmap[pix] : 0.0f;
+    const int64_t tile = (int64_t)ty * ntx + tx;
+    for (int b = nb - 1; b >= 0; --b) {
+        const ERec &r = s_rec[b];
+        const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
+        const bool hit = r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f;
+        float v[EXACT_NSPAT];
+#pragma unroll
+        for (int i = 0; i < EXACT_NSPAT; ++i) v[i] = 0.0f;
+        if (hit) {
+            if (in) {
+                const float Tb = s_T[b][lane];
+                const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
+                const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
+                // Sigma^-1 d in pixel units (natural-log exponent -1/2 d^T Sigma^-1 d), then metres
+                const float ex = ln2x2 * (r.qa * dx + 0.5f * r.qb * dy) / (float)px_m;
+                const float ey = ln2x2 * (0.5f * r.qb * dx + r.qc * dy) / (float)py_m;
+                const float2 Rv = R[(int64_t)b * M + pix];
+                const float rr = Rv.x * rscale, ri = Rv.y * rscale;
+                // z = e^{j phi} conj(R)
+                const float zr = r.cphi * rr + r.sphi * ri, zi = r.sphi * rr - r.cphi * ri;
+                const float alpha = r.o * gk;
+                const bool kept = alpha > EXACT_T_EPS;
+                const float ga = kept ? -Tb * D : 0.0f;         // dL/d alpha at this pixel
+                const float cg = Tb * zr + r.o * ga;           // coefficient on g
+                const float cgg = cg * gk;
+                v[0] = cgg * ex;
+                v[1] = cgg * ey;
+                v[2] = cgg * ex * ex;
+                v[3] = cgg * ex * ey;
+                v[4] = cgg * ey * ey;
+                v[5] = -Tb * gk * zi;                          // phase
+                v[6] = ga * gk;                                // opacity through alpha
+                D = fmaf(kept ? 1.0f - alpha : 1.0f, D, gk * zr);
+            }
+#pragma unroll
+            for (int i = 0; i < EXACT_NSPAT; ++i) v[i] = wave_sum_f(v[i]);
+        }
+        if (lane < EXACT_NSPAT) {
+            float t = 0.0f;
+#pragma unroll
+            for (int i = 0; i < EXACT_NSPAT; ++i) t = lane == i ? v[i] : t;
+            part[(tile * 64 + b) * EXACT_NSPAT + lane] = t;
+        }
+    }
+    if (in) dmap[pix] = D;
+}
+
+// One work-group per batch Gaussian: fixed-order sums of its partials, then the chain rule.
+__global__ void __launch_bounds__(256) k_exact_gfinal(const ERec *__restrict__ rec, int b0, GView g, Consts k,
+                                                      const uint32_t *__restrict__ order,
+                                                      const float *__restrict__ pspec, int nblk_spec,
+                                                      const float *__restrict__ pspat, int ntile, GradView out)
+{
+    __shared__ double s_red[4][EXACT_NSPEC + EXACT_NSPAT];
+    const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double acc[EXACT_NSPEC + EXACT_NSPAT];
+#pragma unroll
+    for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) acc[i] = 0.0;
+    for (int q = t; q < nblk_spec; q += 256)
+#pragma unroll
+        for (int i = 0; i < EXACT_NSPEC; ++i) acc[i] += (double)pspec[((int64_t)q * 64 + b) * EXACT_NSPEC + i];
+    for (int q = t; q < ntile; q += 256)
+#pragma unroll
+        for (int i = 0; i < EXACT_NSPAT; ++i) acc[EXACT_NSPEC + i] += (double)pspat[((int64_t)q * 64 + b) * EXACT_NSPAT + i];
+#pragma unroll
+    for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) {
+        double v = acc[i];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+        if (lane == 0) s_red[wave][i] = v;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    double S[EXACT_NSPEC + EXACT_NSPAT];
+    for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) S[i] = s_red[0][i] + s_red[1][i] + s_red[2][i] + s_red[3][i];
+    const ERec &r = rec[b0 + b];
+    const int64_t j = order[b0 + b];
+    const double inv = 1.0 / ((double)k.nx * k.ny);
+    double d_o = S[EXACT_NSPEC + 6], d_z = 0.0;
+    const double o = g.opacity[j];
+    for (int c = 0; c < k.C && c < 3; ++c) {
+        const double a = g.amplitude[(int64_t)c * g.amp_stride + j];
+        const double rp = S[4 * c + 0] * inv, iq = S[4 * c + 3] * inv;
+        if (out.amplitude) out.amplitude[(int64_t)c * out.amp_stride + j] = r.valid ? (float)(o * rp) : 0.0f;
+        d_o += a * rp;
+        d_z += 2.0 * M_PI * (double)r.amp[c] * iq;
+    }
+    const double* P = S + EXACT_NSPEC;
+    const bool ok = r.valid != 0;
+    if (out.mean_x) out.mean_x[j] = ok ? (float)P[0] : 0.0f;
+    if (out.mean_y) out.mean_y[j] = ok ? (float)P[1] : 0.0f;
+    if (out.cov_xx) out.cov_xx[j] = ok ? (float)(0.5 * P[2]) : 0.0f;
+    if (out.cov_xy) out.cov_xy[j] = ok ? (float)P[3] : 0.0f;
+    if (out.cov_yy) out.cov_yy[j] = ok ? (float)(0.5 * P[4]) : 0.0f;
+    if (out.phase) out.phase[j] = ok ? (float)P[5] : 0.0f;
+    if (out.opacity) out.opacity[j] = ok ? (float)d_o : 0.0f;
+    if (out.depth) out.depth[j] = ok ? (float)d_z : 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_exact_fill1(float *__restrict__ p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int64_t exact_ckpt_count(int64_t n, int nx, int ny)
+{
+    const int64_t B = (int64_t)exact_batch(nx, ny);
+    return std::max<int64_t>(1, (n + B - 1) / B);
+}
+
+hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, const ExactBuffers &eb,
+                              const ExactBwdBuffers &bb, const float2 *grad_field, const GradView &out, hipStream_t s)
+{
+    const int64_t n = g.n, M = (int64_t)k.nx * k.ny;
+    if (n == 0) return hipSuccess;
+    ERec *rec = (ERec *)eb.rec;
+    const unsigned gn = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_exact_keys, dim3(gn), dim3(256), 0, s, g, eb.keys_a, eb.vals_a);
+    uint64_t *keys = nullptr;
+    uint32_t *order = nullptr;
+    hipError_t e = radix_sort_48(eb.keys_a, eb.vals_a, eb.keys_b, eb.vals_b, eb.sort_hist, n, eb.sort_blocks, s, &keys,
+                                 &order);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_exact_records, dim3(gn), dim3(256), 0, s, g, k, order, rec);
+    // Gs = FFT(dL/du)
+    e = launch_fft2d(p, k.C, -1, grad_field, bb.gspec, s);
+    if (e != hipSuccess) return e;
+    const int B = (int)exact_batch(k.nx, k.ny);
+    const int64_t nbatch = (n + B - 1) / B;
+    const dim3 tiles((k.nx + EXACT_TILE - 1) / EXACT_TILE, (k.ny + EXACT_TILE - 1) / EXACT_TILE);
+    const dim3 btiles((k.nx + EXACT_BTILE - 1) / EXACT_BTILE, (k.ny + EXACT_BTILE - 1) / EXACT_BTILE);
+    const unsigned mblk = (unsigned)((M + 255) / 256);
+    // forward sweep of the map, checkpointed at every batch start
+    hipLaunchKernelGGL(k_exact_fill1, dim3(mblk), dim3(256), 0, s, eb.tmap, M, 1.0f);
+    for (int64_t q = 0; q < nbatch; ++q) {
+        const int64_t b0 = q * B;
+        const int nb = (int)std::min<int64_t>(B, n - b0);
+        hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.tmap, eb.tmap,
+                           (float2 *)nullptr, bb.ckpt + q * M);
+    }
+    hipLaunchKernelGGL(k_exact_fill1, dim3(mblk), dim3(256), 0, s, bb.dmap, M, 0.0f);
+    const float rscale = (float)(1.0 / ((double)k.nx * k.ny));
+    for (int64_t q = nbatch - 1; q >= 0; --q) {
+        const int64_t b0 = q * B;
+        const int nb = (int)std::min<int64_t>(B, n - b0);
+        hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, bb.ckpt + q * M,
+                           (float *)nullptr, eb.imgs, (float *)nullptr);
+        e = launch_fft2d(p, nb, -1, eb.imgs, eb.imgs, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_exact_gsplat, dim3(mblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
+                           bb.pspec);
+        e = launch_fft2d(p, nb, +1, eb.imgs, eb.imgs, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_exact_back, btiles, dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, k.px, k.py, rscale,
+                           bb.ckpt + q * M, bb.dmap, eb.imgs, bb.pspat);
+        hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(256), 0, s, rec, (int)b0, g, k, order, bb.pspec, (int)mblk,
+                           bb.pspat, (int)(btiles.x * btiles.y), out);
     }
     return hipGetLastError();
 }

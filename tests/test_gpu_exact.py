@@ -120,15 +120,64 @@ def test_exact_full_size_grid(ctx):
     assert err < TOL_EXACT
 
 
-def test_exact_backward_and_batched_are_unsupported(ctx):
-    import torch
+def test_exact_batched_is_unsupported(ctx):
     import paper_2505_06582_amd as gws
     grid = Grid(64, 64, 8e-6, 8e-6, (520e-9,))
     s = clustered_scene(4, grid, 2108)
     prob = problem(grid, blend=gws.BLEND_EXACT)
-    g = scene_to_torch(s)
-    G = torch.zeros((1, 64, 64), dtype=torch.complex64, device="cuda")
     with pytest.raises(gws.GwsError):
-        ctx.backward(prob, g, G)
-    with pytest.raises(gws.GwsError):
-        ctx.forward_batched(prob, g, [0, s.n])
+        ctx.forward_batched(prob, scene_to_torch(s), [0, s.n])
+
+
+# Gradients through exact blending: per parameter group, normwise relative L2 against the FP64
+# reverse-mode oracle (itself pinned to central differences), the same bar as the
+# order-invariant adjoint.
+TOL_EXACT_GRAD = 1e-4
+
+
+@pytest.mark.parametrize("n,grid,seed", [
+    (24, Grid(64, 48, 8e-6, 8e-6, (520e-9, 638e-9)), 2201),          # one batch, 2 wavelengths
+    (100, Grid(128, 96, 8e-6, 8e-6, gwsgen.RGB), 2202),               # two batches, 3 wavelengths
+    (65, Grid(96, 80, 8e-6, 8e-6, (450e-9,)), 2203),                  # ragged second batch
+])
+def test_exact_backward_matches_oracle(ctx, n, grid, seed):
+    import torch
+    import paper_2505_06582_amd as gws
+    import oracle.exact_grad as eg
+    log("exact backward n=%d grid=%dx%dx%d" % (n, grid.nx, grid.ny, grid.n_lambda))
+    s = clustered_scene(n, grid, seed)
+    t = gwsgen.make_target(grid, seed + 50) * 0.05
+    _, u, ref = eg.exact_loss_grads(s, grid, t)
+    G = torch.from_numpy((2.0 * (u - t)).astype(np.complex64)).cuda()
+    prob = problem(grid, blend=gws.BLEND_EXACT)
+    got = ctx.backward(prob, scene_to_torch(s), G, want_depth=True)
+    for k in eg.PARAMS:
+        err = rel_l2(to_numpy(got[k]).astype(np.float64), np.asarray(ref[k]))
+        log("  %-10s rel L2 %.3g" % (k, err))
+        assert err < TOL_EXACT_GRAD, k
+
+
+@pytest.mark.parametrize("blend", ["oit", "exact"])
+def test_render_autograd_matches_oracle(ctx, blend):
+    """The torch.autograd.Function path (render + loss.backward) for both blending models."""
+    import torch
+    import paper_2505_06582_amd as gws
+    import oracle.exact_grad as eg
+    grid = Grid(64, 48, 8e-6, 8e-6, (520e-9, 638e-9))
+    s = clustered_scene(20, grid, 2301)
+    t = gwsgen.make_target(grid, 2302) * 0.05
+    prob = problem(grid, blend=gws.BLEND_EXACT if blend == "exact" else gws.BLEND_OIT)
+    params = {k: v.clone().requires_grad_(True) for k, v in scene_to_torch(s).items()}
+    u = gws.render(prob, *[params[k] for k in eg.PARAMS])
+    loss = torch.sum(torch.abs(u - torch.from_numpy(t.astype(np.complex64)).cuda()) ** 2)
+    loss.backward()
+    if blend == "exact":
+        _, _, ref = eg.exact_loss_grads(s, grid, t)
+    else:
+        uo = oracle.forward(s, grid)
+        _, G = oracle.loss_and_field_grad(uo, t)
+        ref = oracle.backward(s, grid, G)
+    for k in eg.PARAMS:
+        err = rel_l2(to_numpy(params[k].grad).astype(np.float64), np.asarray(ref[k]))
+        log("  render/%s %-10s rel L2 %.3g" % (blend, k, err))
+        assert err < TOL_EXACT_GRAD, k
