@@ -388,6 +388,29 @@ def bench_exact(args):
         res[name] = {"ms_per_forward": e0.elapsed_time(e1) / args.steps,
                      "stage_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}}
         log("bench exact1k: %s %.2f ms per forward" % (name, res[name]["ms_per_forward"]))
+    # the training step: exact forward, L2 loss and its gradient, exact backward
+    prob = gws.Problem.from_grid(grid, blend=gws.BLEND_EXACT)
+    target = torch.from_numpy(gwsgen.make_target(grid, 1006)).to(dev)
+    G = torch.empty_like(field)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in g.items()}
+
+    def step():
+        ctx.forward(prob, g, out=field)
+        ctx.l2_loss_grad(field, target, grad=G, loss=loss)
+        ctx.backward(prob, g, G, out=grads, want_depth=False)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    res["exact_fwd_bwd_ms"] = e0.elapsed_time(e1) / args.steps
+    log("bench exact1k: exact forward + loss + backward %.2f ms per step" % res["exact_fwd_bwd_ms"])
     M, C = grid.nx * grid.ny, grid.n_lambda
     t = res["exact"]["stage_ms"]["accumulate"] * 1e-3
     # per Gaussian: the masked image written (8M), its 2D FFT (two passes, each 8M read + 8M

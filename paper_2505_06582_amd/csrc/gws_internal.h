@@ -273,6 +273,7 @@ struct ExactBuffers {
     void *rec;     // 64-byte records, front to back
     float *tmap;   // transmittance [ny][nx]
     float2 *imgs;  // masked wavefronts of one batch [B][ny][nx]
+    int2 *colwin, *rowwin;  // per batch image: window columns / rows as (first, count)
 };
 size_t exact_batch(int nx, int ny);
 // Extra device buffers of the exact-blending adjoint.
@@ -314,6 +315,8 @@ enum Stage {
 };
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                         hipStream_t s);
+hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
+                            const int2 *colwin, const int2 *rowwin, hipStream_t s);
 hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in, float2 *out,
                              void *ws, hipStream_t s);
 size_t dft_bf16x3_workspace(int nx, int ny, int batch);

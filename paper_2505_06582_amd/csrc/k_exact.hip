@@ -134,12 +134,14 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
         float2 v = make_float2(0.0f, 0.0f);
         if (hit) {
             const float dx = wrap_d((float)px - r.cx, (float)nx), dy = wrap_d((float)py - r.cy, (float)ny);
-            const float q = fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy));
-            const float gk = __builtin_amdgcn_exp2f(-q);
-            const float m = T * gk;
-            v = make_float2(m * r.cphi, m * r.sphi);
-            const float alpha = r.o * gk;
-            if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
+            if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {  // the profile's window
+                const float q = fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy));
+                const float gk = __builtin_amdgcn_exp2f(-q);
+                const float m = T * gk;
+                v = make_float2(m * r.cphi, m * r.sphi);
+                const float alpha = r.o * gk;
+                if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
+            }
         }
         if (imgs && in) imgs[(int64_t)b * M + pix] = v;
     }
@@ -190,6 +192,25 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
         if (c < k.C) spec[(int64_t)c * M + m] = acc[c];
 }
 
+// Per batch image: the columns and rows of the profile's window, as (first, count) on the
+// periodic axes (count 0 for a Gaussian that contributes nothing).
+__global__ void __launch_bounds__(64) k_exact_windows(const ERec *__restrict__ rec, int b0, int nb, int nx, int ny,
+                                                      int2 *__restrict__ colwin, int2 *__restrict__ rowwin)
+{
+    const int b = threadIdx.x;
+    if (b >= nb) return;
+    const ERec &r = rec[b0 + b];
+    if (r.hwx < 0) {
+        colwin[b] = make_int2(0, 0);
+        rowwin[b] = make_int2(0, 0);
+        return;
+    }
+    const int x0 = (int)ceilf(r.cx - (float)r.hwx), x1 = (int)floorf(r.cx + (float)r.hwx);
+    const int y0 = (int)ceilf(r.cy - (float)r.hwy), y1 = (int)floorf(r.cy + (float)r.hwy);
+    colwin[b] = make_int2(((x0 % nx) + nx) % nx, min(x1 - x0 + 1, nx));
+    rowwin[b] = make_int2(((y0 % ny) + ny) % ny, min(y1 - y0 + 1, ny));
+}
+
 __global__ void __launch_bounds__(256) k_exact_fill(float *__restrict__ tmap, float2 *__restrict__ spec, int64_t M,
                                                     int C)
 {
@@ -230,7 +251,9 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
         const int nb = (int)std::min<int64_t>(B, n - b0);
         hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.tmap, eb.tmap,
                            eb.imgs, (float *)nullptr);
-        e = launch_fft2d(p, nb, -1, eb.imgs, eb.imgs, s);
+        hipLaunchKernelGGL(k_exact_windows, dim3(1), dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.colwin,
+                           eb.rowwin);
+        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, (const int2 *)nullptr, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_splat, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec, (int)b0, nb, k,
                            eb.imgs, spec);
@@ -363,9 +386,11 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
         const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
         if (r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f) {
             const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
-            const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
-            const float alpha = r.o * gk;
-            if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
+            if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {
+                const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
+                const float alpha = r.o * gk;
+                if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
+            }
         }
     }
     // back to front
@@ -380,9 +405,9 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
 #pragma unroll
         for (int i = 0; i < EXACT_NSPAT; ++i) v[i] = 0.0f;
         if (hit) {
-            if (in) {
+            const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
+            if (in && fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {
                 const float Tb = s_T[b][lane];
-                const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
                 const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
                 // Sigma^-1 d in pixel units (natural-log exponent -1/2 d^T Sigma^-1 d), then metres
                 const float ex = ln2x2 * (r.qa * dx + 0.5f * r.qb * dy) / (float)px_m;
@@ -519,11 +544,14 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
         const int nb = (int)std::min<int64_t>(B, n - b0);
         hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, bb.ckpt + q * M,
                            (float *)nullptr, eb.imgs, (float *)nullptr);
-        e = launch_fft2d(p, nb, -1, eb.imgs, eb.imgs, s);
+        hipLaunchKernelGGL(k_exact_windows, dim3(1), dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.colwin,
+                           eb.rowwin);
+        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, (const int2 *)nullptr, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_gsplat, dim3(mblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
                            bb.pspec);
-        e = launch_fft2d(p, nb, +1, eb.imgs, eb.imgs, s);
+        // R is read only inside each window: full column pass, rows of the window only
+        e = launch_fft2d_win(p, nb, +1, eb.imgs, eb.imgs, (const int2 *)nullptr, eb.rowwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_back, btiles, dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, k.px, k.py, rscale,
                            bb.ckpt + q * M, bb.dmap, eb.imgs, bb.pspat);

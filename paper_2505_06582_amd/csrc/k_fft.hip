@@ -156,11 +156,18 @@ static __device__ int fft_lds(float2 *a, float2 *b, const RadixPlan &pl, int bat
 // Row transforms: one row per work-group.  in/out: [rows][n].
 template <int S>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restrict__ in, float2 *__restrict__ out,
-                                                          RadixPlan pl, const float2 *__restrict__ tw)
+                                                          RadixPlan pl, const float2 *__restrict__ tw,
+                                                          const int2 *__restrict__ rowwin, int rows_per_img)
 {
     extern __shared__ float2 lds[];
     float2 *a = lds, *b = lds + pl.n;
     const int64_t row = blockIdx.x;
+    if (rowwin) {  // only rows (start + i) mod rows_per_img, i < len, of each image are wanted
+        const int img = (int)(row / rows_per_img), r = (int)(row - (int64_t)img * rows_per_img);
+        const int2 w = rowwin[img];
+        const int d = ((r - w.x) % rows_per_img + rows_per_img) % rows_per_img;
+        if (d >= w.y) return;
+    }
     const float2 *src = in + row * pl.n;
     for (int i = threadIdx.x; i < pl.n; i += blockDim.x) a[i] = src[i];
     __syncthreads();
@@ -237,10 +244,17 @@ static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n,
 template <int S>
 __global__ void __launch_bounds__(FFT_COL_THREADS) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                               RadixPlan pl, const float2 *__restrict__ tw, int width,
-                                                              int lb)
+                                                              int lb, const int2 *__restrict__ colwin)
 {
     extern __shared__ float2 lds[];
     const int n = pl.n, B = 1 << lb;
+    if (colwin) {  // only columns (start + i) mod width, i < len, of each image are nonzero
+        const int ns = (width + B - 1) / B;
+        const int im = blockIdx.x / ns, c0s = (blockIdx.x - im * ns) * B;
+        const int2 w = colwin[im];
+        const int d = ((c0s - w.x) % width + width) % width;
+        if (!(d < w.y || d + B > width)) return;
+    }
     float2 *tw_s = lds + n * B;  // the twiddle table, read by every pass
     for (int i = threadIdx.x; i < n; i += FFT_COL_THREADS) tw_s[i] = tw[i];
     const int nslab = (width + B - 1) / B;
@@ -303,6 +317,14 @@ static void allow_big_lds()
 
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out, hipStream_t s)
 {
+    return launch_fft2d_win(p, batch, direction, in, out, nullptr, nullptr, s);
+}
+
+// Rows then columns; with windows, columns first (only the slabs meeting colwin, the rest
+// being zero) and then the rows (only those in rowwin; the others are left unfinished).
+hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
+                            const int2 *colwin, const int2 *rowwin, hipStream_t s)
+{
     allow_big_lds();
     const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
     const RadixPlan py = make_radix(p.ny, p.radix_y, p.nrad_y);
@@ -313,14 +335,30 @@ hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *i
     while ((1 << lb) < B) ++lb;
     const size_t col_lds = (size_t)(B + 1) * p.ny * sizeof(float2);
     const int nslab = (p.nx + B - 1) / B;
-    if (direction > 0) {
-        hipLaunchKernelGGL(k_fft_rows<-1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, in, out, px, p.tw_x);
-        hipLaunchKernelGGL(k_fft_cols<-1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, out, out, py, p.tw_y,
-                           p.nx, lb);
+    const bool cols_first = colwin != nullptr || rowwin != nullptr;
+    if (cols_first && in != out) return hipErrorInvalidValue;  // the windowed form works in place
+    auto rows_pass = [&](const float2 *src, float2 *dst) {
+        if (direction > 0)
+            hipLaunchKernelGGL(k_fft_rows<-1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, src, dst, px, p.tw_x, rowwin,
+                               p.ny);
+        else
+            hipLaunchKernelGGL(k_fft_rows<1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, src, dst, px, p.tw_x, rowwin,
+                               p.ny);
+    };
+    auto cols_pass = [&](float2 *buf) {
+        if (direction > 0)
+            hipLaunchKernelGGL(k_fft_cols<-1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, buf, buf, py,
+                               p.tw_y, p.nx, lb, colwin);
+        else
+            hipLaunchKernelGGL(k_fft_cols<1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, buf, buf, py,
+                               p.tw_y, p.nx, lb, colwin);
+    };
+    if (cols_first) {
+        cols_pass(out);
+        rows_pass(out, out);
     } else {
-        hipLaunchKernelGGL(k_fft_rows<1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, in, out, px, p.tw_x);
-        hipLaunchKernelGGL(k_fft_cols<1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, out, out, py, p.tw_y,
-                           p.nx, lb);
+        rows_pass(in, out);
+        cols_pass(out);
     }
     return hipGetLastError();
 }
