@@ -286,31 +286,40 @@ static __device__ __forceinline__ float wave_sum_f(float v)
     return v;
 }
 
-// One thread per frequency: spectral partial sums per (work-group, Gaussian) and, in place of
-// F_k, V_k = sum_c A_c Gs_c conj(H_c).
+// Four frequencies per thread (strided by the work-group size): spectral partial sums per
+// (work-group, Gaussian) and, in place of F_k, V_k = sum_c A_c Gs_c conj(H_c).
+constexpr int EXACT_GS_PER = 4;
+
 __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
                                                       const float2 *__restrict__ gspec, float2 *__restrict__ imgs,
                                                       float *__restrict__ part)
 {
     __shared__ float s_red[4][EXACT_NSPEC];
     const int64_t M = (int64_t)k.nx * k.ny;
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = m < M;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double w[3] = {0.0, 0.0, 0.0};
-    bool prop[3] = {false, false, false};
-    float2 gs[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-    if (live) {
-        const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
-        const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
-        const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
-        const double nu2 = nux * nux + nuy * nuy;
+    int64_t mi[EXACT_GS_PER];
+    bool live[EXACT_GS_PER];
+    double w[EXACT_GS_PER][3];
+    bool prop[EXACT_GS_PER][3];
+    float2 gs[EXACT_GS_PER][3];
+#pragma unroll
+    for (int q = 0; q < EXACT_GS_PER; ++q) {
+        const int64_t m = ((int64_t)blockIdx.x * EXACT_GS_PER + q) * blockDim.x + threadIdx.x;
+        mi[q] = m;
+        live[q] = m < M;
+        double nu2 = 0.0;
+        if (live[q]) {
+            const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
+            const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
+            const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
+            nu2 = nux * nux + nuy * nuy;
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double w2 = k.inv_lambda[c] * k.inv_lambda[c] - nu2;
-            prop[c] = c < k.C && w2 > 0.0;
-            w[c] = prop[c] ? sqrt(w2) : 0.0;
-            if (c < k.C) gs[c] = gspec[(int64_t)c * M + m];
+            prop[q][c] = live[q] && c < k.C && w2 > 0.0;
+            w[q][c] = prop[q][c] ? sqrt(w2) : 0.0;
+            gs[q][c] = (live[q] && c < k.C) ? gspec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
         }
     }
     for (int b = 0; b < nb; ++b) {
@@ -318,31 +327,34 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
         float v[EXACT_NSPEC];
 #pragma unroll
         for (int i = 0; i < EXACT_NSPEC; ++i) v[i] = 0.0f;
-        float2 V = make_float2(0.0f, 0.0f);
-        if (live && r.valid) {
-            const float2 F = imgs[(int64_t)b * M + m];
-            const double zd = (double)r.z;
+        const double zd = (double)r.z;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (!prop[c]) continue;
-                const double ph = -zd * w[c];
-                const float t = (float)(ph - floor(ph));
-                const float hc = __builtin_amdgcn_cosf(t), hs = __builtin_amdgcn_sinf(t);
-                // X = conj(Gs) H F
-                const float hfr = hc * F.x - hs * F.y, hfi = hc * F.y + hs * F.x;
-                const float xr = gs[c].x * hfr + gs[c].y * hfi, xi = gs[c].x * hfi - gs[c].y * hfr;
-                const float wf = (float)w[c];
-                v[4 * c + 0] = xr;
-                v[4 * c + 1] = xi;
-                v[4 * c + 2] = wf * xr;
-                v[4 * c + 3] = wf * xi;
-                // V += A_c Gs conj(H)
-                const float A = r.amp[c];
-                V.x = fmaf(A, gs[c].x * hc + gs[c].y * hs, V.x);
-                V.y = fmaf(A, gs[c].y * hc - gs[c].x * hs, V.y);
+        for (int q = 0; q < EXACT_GS_PER; ++q) {
+            float2 V = make_float2(0.0f, 0.0f);
+            if (live[q] && r.valid) {
+                const float2 F = imgs[(int64_t)b * M + mi[q]];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!prop[q][c]) continue;
+                    const double ph = -zd * w[q][c];
+                    const float t = (float)(ph - floor(ph));
+                    const float hc = __builtin_amdgcn_cosf(t), hs = __builtin_amdgcn_sinf(t);
+                    // X = conj(Gs) H F
+                    const float hfr = hc * F.x - hs * F.y, hfi = hc * F.y + hs * F.x;
+                    const float xr = gs[q][c].x * hfr + gs[q][c].y * hfi, xi = gs[q][c].x * hfi - gs[q][c].y * hfr;
+                    const float wf = (float)w[q][c];
+                    v[4 * c + 0] += xr;
+                    v[4 * c + 1] += xi;
+                    v[4 * c + 2] = fmaf(wf, xr, v[4 * c + 2]);
+                    v[4 * c + 3] = fmaf(wf, xi, v[4 * c + 3]);
+                    // V += A_c Gs conj(H)
+                    const float A = r.amp[c];
+                    V.x = fmaf(A, gs[q][c].x * hc + gs[q][c].y * hs, V.x);
+                    V.y = fmaf(A, gs[q][c].y * hc - gs[q][c].x * hs, V.y);
+                }
             }
+            if (live[q]) imgs[(int64_t)b * M + mi[q]] = V;
         }
-        if (live) imgs[(int64_t)b * M + m] = V;
 #pragma unroll
         for (int i = 0; i < EXACT_NSPEC; ++i) {
             const float t = wave_sum_f(v[i]);
@@ -529,6 +541,7 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
     const dim3 tiles((k.nx + EXACT_TILE - 1) / EXACT_TILE, (k.ny + EXACT_TILE - 1) / EXACT_TILE);
     const dim3 btiles((k.nx + EXACT_BTILE - 1) / EXACT_BTILE, (k.ny + EXACT_BTILE - 1) / EXACT_BTILE);
     const unsigned mblk = (unsigned)((M + 255) / 256);
+    const unsigned gsblk = (unsigned)((M + 256 * EXACT_GS_PER - 1) / (256 * EXACT_GS_PER));
     // forward sweep of the map, checkpointed at every batch start
     hipLaunchKernelGGL(k_exact_fill1, dim3(mblk), dim3(256), 0, s, eb.tmap, M, 1.0f);
     for (int64_t q = 0; q < nbatch; ++q) {
@@ -548,14 +561,14 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
                            eb.rowwin);
         e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, (const int2 *)nullptr, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_exact_gsplat, dim3(mblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
+        hipLaunchKernelGGL(k_exact_gsplat, dim3(gsblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
                            bb.pspec);
         // R is read only inside each window: full column pass, rows of the window only
         e = launch_fft2d_win(p, nb, +1, eb.imgs, eb.imgs, (const int2 *)nullptr, eb.rowwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_back, btiles, dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, k.px, k.py, rscale,
                            bb.ckpt + q * M, bb.dmap, eb.imgs, bb.pspat);
-        hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(256), 0, s, rec, (int)b0, g, k, order, bb.pspec, (int)mblk,
+        hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(256), 0, s, rec, (int)b0, g, k, order, bb.pspec, (int)gsblk,
                            bb.pspat, (int)(btiles.x * btiles.y), out);
     }
     return hipGetLastError();
