@@ -332,35 +332,38 @@ __global__ void __launch_bounds__(WG, waves_per_simd(F)) k_adjoint(Consts k, con
                     float Pr[C], Pi[C], Wc[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) Pr[c] = Pi[c] = Wc[c] = 0.0f;
-                    // R0 = sum Re rho, R1 = sum m_y' Re rho, R2 = sum m_y'^2 Re rho, I0 = sum Im rho, I1 = sum m_y' Im rho
-                    float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f, I0 = 0.0f, I1 = 0.0f;
+                    // rho = sum_c amp_c E conj(Gs_c) e^{j 2 pi th_c} at one frequency;
+                    // R1 = sum m_y' Re rho, R2 = sum m_y'^2 Re rho, I0 = sum Im rho, I1 = sum m_y' Im rho,
+                    // and sum Re rho = sum_c amp_c Re P_c is formed once after the loop
+                    float R1 = 0.0f, R2 = 0.0f, I0 = 0.0f, I1 = 0.0f;
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
                         if (!(rows & (1u << f))) continue;  // the support misses this 4-row block
                         const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
                         const float E = __builtin_amdgcn_exp2f(-q);
-                        float ur = 0.0f, ui = 0.0f;
+                        float rr = 0.0f, ri = 0.0f;
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
-                            // conj(Gs) e^{j 2 pi th} = |Gs| e^{j 2 pi (th - arg Gs / 2 pi)} = h + j k
+                            // E conj(Gs) e^{j 2 pi th} = E |Gs| e^{j 2 pi (th - arg Gs / 2 pi)}
                             const float th = fmaf(-z, dD[f][c], fmaf(-dyf[f], ryf, bx[c]) - gp[f][c]);
                             const float sn = __builtin_amdgcn_sinf(th);
                             const float cs = __builtin_amdgcn_cosf(th);
-                            const float h = gm[f][c] * cs;
-                            const float kk = gm[f][c] * sn;
-                            Pr[c] = fmaf(E, h, Pr[c]);
-                            if (DEPTH) Pi[c] = fmaf(E, kk, Pi[c]);
-                            ur = fmaf(amp[c], h, ur);
-                            ui = fmaf(amp[c], kk, ui);
-                            if (DEPTH) Wc[c] = fmaf(dD[f][c] * E, kk, Wc[c]);
+                            const float eg = E * gm[f][c];
+                            Pr[c] = fmaf(eg, cs, Pr[c]);
+                            if (DEPTH) Pi[c] = fmaf(eg, sn, Pi[c]);
+                            if (DEPTH) Wc[c] = fmaf(dD[f][c] * eg, sn, Wc[c]);
+                            const float ae = amp[c] * eg;
+                            rr = fmaf(ae, cs, rr);
+                            ri = fmaf(ae, sn, ri);
                         }
-                        const float rr = E * ur, ri = E * ui;
-                        R0 += rr;
                         R1 = fmaf(fmy[f], rr, R1);
                         R2 = fmaf(myy[f], rr, R2);
                         I0 += ri;
                         I1 = fmaf(fmy[f], ri, I1);
                     }
+                    float R0 = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) R0 = fmaf(amp[c], Pr[c], R0);
                     // value layout: Re P_c (C), Sfx, Sfy, Qxx, Qxy, Qyy, then with depth Im P_c (C), W_c (C)
                     float x[NR];
 #pragma unroll
