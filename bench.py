@@ -122,6 +122,8 @@ def main():
         return bench_batched(args)
     if args.workload == "exact1k":
         return bench_exact(args)
+    if args.workload == "focal8":
+        return bench_focal(args)
     if args.workload == "precision1m":
         return bench_precision(args)
     log("bench: generating workload %s" % args.workload)
@@ -425,6 +427,66 @@ def bench_exact(args):
            "roofline": {"bound": "hbm", "achieved": bytes_alg / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                         "frac": bytes_alg / t / PEAK_HBM, "traffic": None, "kernel": "exact mask + FFT + splat",
                         "work_per_launch": "6 x 8 x M bytes per Gaussian"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_focal(args):
+    """Display chain at 1080x1920x3: double-phase coding of a hologram-sized field, then the
+    half-band-filtered focal stack of the phase-only pattern at 8 planes (-10 .. 10 mm)."""
+    import numpy as np
+    import torch
+
+    import gwsgen
+    import paper_2505_06582_amd as gws
+    grid = gwsgen.Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    K = 8
+    depths = [float(d) for d in np.linspace(-10e-3, 10e-3, K)]
+    ctx = gws.context(0)
+    dev = torch.device("cuda", 0)
+    prob = gws.Problem.from_grid(grid)
+    u = torch.from_numpy(gwsgen.make_target(grid, 1007)).to(dev)
+    C, M = grid.n_lambda, grid.nx * grid.ny
+    P = torch.empty((C, grid.ny, grid.nx), dtype=torch.float32, device=dev)
+    stack = torch.empty((K, C, grid.ny, grid.nx), dtype=torch.float32, device=dev)
+
+    def step():
+        ctx.dpac_encode(u, out=P)
+        ctx.focal_stack(prob, P, depths, phase_input=True, half_band=True, out=stack)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ctx.read_profile()
+    ctx.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    prof = ctx.read_profile()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
+    log("bench focal8: %.3f ms per step; stages %s" % (ms, {k: round(v, 4) for k, v in st.items()}))
+    # algorithmic bytes: the coding reads the field (8 B) and writes the pattern (4 B); the
+    # stack reads the pattern once (4 B) and writes K intensity planes (4 B each)
+    b_dpac, b_focal = 12.0 * C * M, (4.0 + 4.0 * K) * C * M
+    t_focal = st["focal_stack"] * 1e-3
+    out = {"metric": "display chain (double-phase coding + 8-plane filtered focal stack) per second, 1080x1920x3",
+           "value": 1e3 / ms, "unit": "stacks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "focal8", "planes": K, "depths_m": depths, "ny": grid.ny, "nx": grid.nx,
+                      "n_lambda": C},
+           "stage_ms": st,
+           "dpac_roofline": {"bound": "hbm", "achieved": b_dpac / (st["dpac"] * 1e-3) / 1e9,
+                             "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                             "frac": b_dpac / (st["dpac"] * 1e-3) / PEAK_HBM},
+           "roofline": {"bound": "hbm", "achieved": b_focal / t_focal / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                        "frac": b_focal / t_focal / PEAK_HBM, "traffic": None,
+                        "kernel": "focal stack (e^{jP}, forward FFT, per-plane transfer + inverse FFT, |u|^2)",
+                        "work_per_launch": "(4 + 4 K) bytes per pixel and wavelength"}}
     print(json.dumps(out), flush=True)
 
 

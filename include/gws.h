@@ -236,10 +236,11 @@ gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *field, const vo
 /* Stage timing with HIP events on the caller's stream.  While enabled, every library call
  * records an event pair around each of its stages (0 preprocess+sort+records, 1 binning,
  * 2 spectrum accumulation, 3 partial-sum reduction, 4 inverse transform, 5 forward
- * transform, 6 propagation table, 7 adjoint accumulation, 8 gradient chain rule, 9 loss).
+ * transform, 6 propagation table, 7 adjoint accumulation, 8 gradient chain rule, 9 loss,
+ * 10 double-phase coding, 11 focal stack).
  * gws_read_profile synchronises, returns per stage the summed milliseconds and the number
  * of launches since the last read (host arrays of GWS_N_STAGES entries), and clears them. */
-#define GWS_N_STAGES 10
+#define GWS_N_STAGES 12
 gws_status gws_set_profiling(gws_ctx *ctx, int enable);
 gws_status gws_read_profile(gws_ctx *ctx, double *ms, int64_t *count);
 
@@ -256,6 +257,44 @@ typedef struct gws_peaks {
     double hbm_bytes_per_s;
 } gws_peaks;
 gws_status gws_measure_peaks(gws_ctx *ctx, gws_peaks *out, void *stream);
+
+/* ---- Display side: phase-only encoding and focal stacks of a hologram ---- */
+
+/* Double-phase amplitude coding (Sec. 5, phase-only encoding; supplement, display
+ * section, read in the standard double-phase form of the works it cites, since the printed
+ * pair of phases is garbled).  field: complex64 [n_lambda][ny][nx] (device); phase: float32
+ * radians, same shape (device, overwritten).  With r = min(|u| / a_max, 1) (r = 0 when
+ * a_max = 0), phase = arg u - arccos r where n_x + n_y is even and arg u + arccos r where it
+ * is odd, so that a_max (e^{jP-} + e^{jP+}) / 2 = u at every pixel.  Phases are not
+ * wrapped: they lie in (-2 pi, 2 pi].  a_max > 0 is used for every channel; a_max <= 0
+ * takes each channel's largest |u|, computed on the device into the workspace
+ * (gws_dpac_workspace_size bytes, 256-byte aligned; may be NULL when a_max > 0).
+ * nx, ny >= 1 and n_lambda in [1, GWS_MAX_LAMBDA] (GWS_ERR_INVALID_ARG otherwise), and
+ * n_lambda * ny <= 65535 (GWS_ERR_SHAPE otherwise). */
+size_t gws_dpac_workspace_size(int32_t n_lambda);
+gws_status gws_dpac_encode(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t n_lambda, const void *field, float a_max,
+                           float *phase, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Focal stack by the angular-spectrum method (Eq. 3-4) on the hologram's periodic grid:
+ * plane k holds P(u; d_k) = IDFT(DFT(u) H(nu, d_k)), H = exp(j 2 pi d sqrt(1/lambda^2 -
+ * |nu|^2)) inside the propagating band and 0 outside, for every wavelength of the problem
+ * (its nx, ny, pitches and lambdas are used; blend and xform are ignored).  A Gaussian whose
+ * hologram term carries H(nu, -z) (Eq. 5, 12) is in focus in plane d = z.
+ * input: complex64 field [n_lambda][ny][nx], or with GWS_FS_PHASE_INPUT a float32 phase-only
+ * pattern P of that shape (u = e^{jP}).  GWS_FS_HALF_BAND keeps only |m'_x| < nx/4 and
+ * |m'_y| < ny/4 (signed FFT indices), the Fourier filter of double-phase coding.
+ * depths: host array of n_planes distances in metres.  out (device, overwritten): float32
+ * intensities |P(u; d_k)|^2 [n_planes][n_lambda][ny][nx], or with GWS_FS_COMPLEX_OUTPUT the
+ * complex64 fields.  The phase of each plane is reduced in FP64.  nx <= 4096 (GWS_ERR_SHAPE
+ * otherwise); n_planes = 0 does nothing.  workspace: gws_focal_stack_workspace_size bytes. */
+#define GWS_FS_PHASE_INPUT 1
+#define GWS_FS_HALF_BAND 2
+#define GWS_FS_COMPLEX_OUTPUT 4
+gws_status gws_focal_stack_workspace_size(const gws_ctx *ctx, const gws_problem *problem, int32_t n_planes,
+                                          int32_t flags, size_t *bytes);
+gws_status gws_focal_stack(gws_ctx *ctx, const gws_problem *problem, const void *input, int32_t n_planes,
+                           const double *depths, int32_t flags, void *out, void *workspace, size_t workspace_bytes,
+                           void *stream);
 
 #ifdef __cplusplus
 }

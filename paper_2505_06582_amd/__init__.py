@@ -27,6 +27,9 @@ XFORM_DFT_BF16X3 = 1
 BLEND_OIT = 0
 BLEND_EXACT = 1
 MAX_LAMBDA = 4
+FS_PHASE_INPUT = 1
+FS_HALF_BAND = 2
+FS_COMPLEX_OUTPUT = 4
 
 STATUS = {0: "GWS_OK", -1: "GWS_ERR_INVALID_ARG", -2: "GWS_ERR_SHAPE", -3: "GWS_ERR_UNSUPPORTED",
           -4: "GWS_ERR_WORKSPACE", -5: "GWS_ERR_NO_DEVICE", -6: "GWS_ERR_HIP", -7: "GWS_ERR_OOM"}
@@ -113,13 +116,22 @@ _SIGNATURES = {
     "gws_l2_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "gws_dpac_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
+    "gws_dpac_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p]),
+    "gws_focal_stack_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gws_focal_stack": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gws_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "gws_read_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]),
 }
 
 STAGES = ("prep_sort", "bin", "accumulate", "reduce", "xform_inverse", "xform_forward", "dtable", "adjoint",
-          "grad_final", "loss")
+          "grad_final", "loss", "dpac", "focal_stack")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -369,6 +381,44 @@ class Context:
                                          ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(self._l2ws.data_ptr()),
                                          self._l2ws.numel(), self._stream()), self.handle)
         return loss, grad
+
+    def dpac_encode(self, field, a_max: Optional[float] = None, out=None):
+        """Double-phase coding of a (C, ny, nx) complex64 field into a float32 phase-only
+        pattern of the same shape; a_max None takes each channel's largest |u|."""
+        torch = _torch()
+        C, ny, nx = field.shape
+        out = out if out is not None else torch.empty((C, ny, nx), dtype=torch.float32, device=field.device)
+        am = 0.0 if a_max is None else float(a_max)
+        if getattr(self, "_dpacws", None) is None:
+            self._dpacws = torch.empty(int(self.lib.gws_dpac_workspace_size(4)), dtype=torch.uint8,
+                                       device=self.torch_device)
+        _check(self.lib.gws_dpac_encode(self.handle, nx, ny, C, ctypes.c_void_p(field.data_ptr()), am,
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._dpacws.data_ptr()),
+                                        self._dpacws.numel(), self._stream()), self.handle)
+        return out
+
+    def focal_stack(self, prob: Problem, inp, depths, phase_input: bool = False, half_band: bool = False,
+                    complex_output: bool = False, out=None):
+        """(K, C, ny, nx) intensities |P(u; d_k)|^2 (float32) or fields (complex64) of a
+        (C, ny, nx) field, or of the phase-only pattern e^{jP} with phase_input."""
+        torch = _torch()
+        flags = (FS_PHASE_INPUT if phase_input else 0) | (FS_HALF_BAND if half_band else 0) | \
+            (FS_COMPLEX_OUTPUT if complex_output else 0)
+        K = len(depths)
+        dep = (ctypes.c_double * max(K, 1))(*[float(d) for d in depths])
+        pc = prob._c()
+        sz = ctypes.c_size_t()
+        _check(self.lib.gws_focal_stack_workspace_size(self.handle, ctypes.byref(pc), K, flags, ctypes.byref(sz)),
+               self.handle)
+        shape = (K, prob.n_lambda, prob.ny, prob.nx)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64 if complex_output else torch.float32,
+                              device=inp.device)
+        ws = self.workspace(sz.value)
+        _check(self.lib.gws_focal_stack(self.handle, ctypes.byref(pc), ctypes.c_void_p(inp.data_ptr()), K, dep,
+                                        flags, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel(), self._stream()), self.handle)
+        return out
 
     def set_profiling(self, on: bool):
         _check(self.lib.gws_set_profiling(self.handle, 1 if on else 0), self.handle)

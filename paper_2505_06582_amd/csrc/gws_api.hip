@@ -1,6 +1,7 @@
 // Host side of libgws: the C ABI of include/gws.h, argument validation, per-shape plans,
 // workspace layout and the launch sequence of the forward and backward hot path.
 #include <math.h>
+#include <cmath>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1288,6 +1289,123 @@ extern "C" gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *fiel
     StageScope sc(ctx, (hipStream_t)stream, ST_LOSS);
     HIP_CHECK(ctx, launch_l2_grad((const float2 *)field, (const float2 *)target, (float2 *)grad, loss, ws, n,
                                   (hipStream_t)stream));
+    return GWS_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Display side: double-phase coding and focal stacks
+// ---------------------------------------------------------------------------------
+extern "C" size_t gws_dpac_workspace_size(int32_t n_lambda)
+{
+    return align256(sizeof(uint32_t) * (size_t)std::max<int32_t>(n_lambda, 1));
+}
+
+extern "C" gws_status gws_dpac_encode(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t n_lambda, const void *field,
+                                      float a_max, float *phase, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    if (nx < 1 || ny < 1 || n_lambda < 1 || n_lambda > GWS_MAX_LAMBDA || !field || !phase || !(a_max == a_max))
+        return fail(ctx, GWS_ERR_INVALID_ARG, "bad double-phase arguments");
+    if ((int64_t)n_lambda * ny > 65535) return fail(ctx, GWS_ERR_SHAPE, "double-phase coding needs n_lambda * ny <= 65535");
+    const bool auto_max = !(a_max > 0.0f);
+    if (auto_max) {
+        const gws_status st = check_ws(ctx, ws, ws_bytes, gws_dpac_workspace_size(n_lambda));
+        if (st != GWS_OK) return st;
+    }
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const hipStream_t s = (hipStream_t)stream;
+    StageScope sc(ctx, s, ST_DPAC);
+    const int64_t m = (int64_t)nx * ny;
+    uint32_t *bits = auto_max ? (uint32_t *)ws : nullptr;
+    if (auto_max) HIP_CHECK(ctx, launch_amax((const float2 *)field, m, n_lambda, bits, s));
+    HIP_CHECK(ctx, launch_dpac((const float2 *)field, nx, ny, n_lambda, bits, auto_max ? 0.0f : a_max, phase, s));
+    return GWS_OK;
+}
+
+static size_t focal_stack_bytes(const gws_problem *p, int32_t n_planes, int32_t flags)
+{
+    const size_t img = (size_t)p->nx * p->ny * p->n_lambda * sizeof(float2);
+    size_t bytes = align256(img);  // the spectrum DFT(u)
+    if (!(flags & GWS_FS_COMPLEX_OUTPUT))
+        bytes += align256(img * (size_t)std::min<int32_t>(std::max<int32_t>(n_planes, 1), STACK_MAXK));
+    return bytes;
+}
+
+static gws_status check_focal(gws_ctx *ctx, const gws_problem *p, int32_t n_planes, int32_t flags)
+{
+    const gws_status st = gws_check_problem(p);
+    if (st != GWS_OK) return fail(ctx, st, "invalid problem");
+    if (!focal_stack_fits(p->nx)) return fail(ctx, GWS_ERR_SHAPE, "focal stacks need nx <= 4096");
+    if (n_planes < 0 || (flags & ~(GWS_FS_PHASE_INPUT | GWS_FS_HALF_BAND | GWS_FS_COMPLEX_OUTPUT)))
+        return fail(ctx, GWS_ERR_INVALID_ARG, "bad focal-stack arguments");
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_focal_stack_workspace_size(const gws_ctx *ctx, const gws_problem *problem, int32_t n_planes,
+                                                     int32_t flags, size_t *bytes)
+{
+    if (!bytes) return GWS_ERR_INVALID_ARG;
+    const gws_status st = check_focal(const_cast<gws_ctx *>(ctx), problem, n_planes, flags);
+    if (st != GWS_OK) return st;
+    *bytes = focal_stack_bytes(problem, n_planes, flags);
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_focal_stack(gws_ctx *ctx, const gws_problem *prob, const void *input, int32_t n_planes,
+                                      const double *depths, int32_t flags, void *out, void *ws, size_t ws_bytes,
+                                      void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = check_focal(ctx, prob, n_planes, flags);
+    if (st != GWS_OK) return st;
+    if (n_planes == 0) return GWS_OK;
+    if (!input || !out || !depths) return fail(ctx, GWS_ERR_INVALID_ARG, "input, depths and out are required");
+    for (int k = 0; k < n_planes; ++k)
+        if (!std::isfinite(depths[k])) return fail(ctx, GWS_ERR_INVALID_ARG, "depths must be finite");
+    st = check_ws(ctx, ws, ws_bytes, focal_stack_bytes(prob, n_planes, flags));
+    if (st != GWS_OK) return st;
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    Plan *p = nullptr;
+    st = get_plan(ctx, prob->nx, prob->ny, 4, &p);
+    if (st != GWS_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    StageScope sc(ctx, s, ST_FOCAL);
+    const int C = prob->n_lambda;
+    const int64_t m = (int64_t)prob->nx * prob->ny;
+    float2 *spec = (float2 *)ws;
+    float2 *planes = (float2 *)((char *)ws + align256((size_t)m * C * sizeof(float2)));
+    if (flags & GWS_FS_PHASE_INPUT) {
+        HIP_CHECK(ctx, launch_phase_field((const float *)input, m * C, spec, s));
+        HIP_CHECK(ctx, launch_fft2d(*p, C, -1, spec, spec, s));
+    } else {
+        HIP_CHECK(ctx, launch_fft2d(*p, C, -1, (const float2 *)input, spec, s));
+    }
+    StackArgs sa{};
+    sa.C = C;
+    sa.ny = prob->ny;
+    sa.half_band = (flags & GWS_FS_HALF_BAND) ? 1 : 0;
+    sa.scale = (float)(1.0 / ((double)prob->nx * prob->ny));
+    sa.dnux = 1.0 / (prob->nx * prob->pitch_x);
+    sa.dnuy = 1.0 / (prob->ny * prob->pitch_y);
+    for (int c = 0; c < C; ++c) sa.inv_l[c] = 1.0 / prob->lambdas[c];
+    for (int k0 = 0; k0 < n_planes; k0 += STACK_MAXK) {
+        sa.K = std::min(STACK_MAXK, n_planes - k0);
+        for (int k = 0; k < sa.K; ++k) {
+            const double z = depths[k0 + k];
+            sa.z[k] = z;
+            for (int c = 0; c < C; ++c) {
+                const double t = z * sa.inv_l[c];  // z / lambda to FP64 rounding (|z / lambda| << 2^52)
+                sa.piston[k * STACK_MAXC + c] = t - std::floor(t);
+            }
+        }
+        if (flags & GWS_FS_COMPLEX_OUTPUT) {
+            float2 *dst = (float2 *)out + (int64_t)k0 * C * m;
+            HIP_CHECK(ctx, launch_focal_stack(*p, spec, dst, nullptr, sa, s));
+        } else {
+            float *dst = (float *)out + (int64_t)k0 * C * m;
+            HIP_CHECK(ctx, launch_focal_stack(*p, spec, planes, dst, sa, s));
+        }
+    }
     return GWS_OK;
 }
 

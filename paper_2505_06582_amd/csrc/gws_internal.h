@@ -311,10 +311,32 @@ hipError_t launch_l2_grad(const float2 *u, const float2 *t, float2 *g, double *l
 // Stages timed with HIP events when profiling is on (gws_set_profiling).
 enum Stage {
     ST_PREP = 0, ST_BIN, ST_ACCUM, ST_REDUCE, ST_XFORM_INV, ST_XFORM_FWD, ST_DTABLE, ST_ADJOINT, ST_FINAL, ST_LOSS,
-    ST_COUNT
+    ST_DPAC, ST_FOCAL, ST_COUNT
 };
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                         hipStream_t s);
+// Focal stack (angular-spectrum propagation of one field to up to STACK_MAXK planes per launch).
+constexpr int STACK_MAXK = 32, STACK_MAXC = 4;
+struct StackArgs {
+    int32_t K, C, ny, half_band;
+    float scale;                         // 1 / (N_x N_y), the inverse transform's normalisation
+    float pad0;
+    double dnux, dnuy;                   // frequency steps 1 / (N p)
+    double inv_l[STACK_MAXC];            // 1 / lambda_c
+    double z[STACK_MAXK];                // plane distances (m)
+    double piston[STACK_MAXK * STACK_MAXC];  // frac(z_k / lambda_c), reduced on the host in FP64
+};
+bool focal_stack_fits(int nx);
+hipError_t launch_focal_stack(const Plan &p, const float2 *spec, float2 *planes, float *intensity,
+                              const StackArgs &sa, hipStream_t s);
+// Display kernels: per-channel max |u| (as float bits), double-phase coding, e^{jP}.
+hipError_t launch_amax(const float2 *u, int64_t m, int C, uint32_t *amax_bits, hipStream_t s);
+hipError_t launch_dpac(const float2 *u, int nx, int ny, int C, const uint32_t *amax_bits, float amax_fixed,
+                       float *phase, hipStream_t s);
+hipError_t launch_phase_field(const float *phase, int64_t n, float2 *u, hipStream_t s);
+
+hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int2 *colwin,
+                                 hipStream_t s);
 hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                             const int2 *colwin, const int2 *rowwin, hipStream_t s);
 hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in, float2 *out,

@@ -563,8 +563,8 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_gsplat, dim3(gsblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
                            bb.pspec);
-        // R is read only inside each window: full column pass, rows of the window only
-        e = launch_fft2d_win(p, nb, +1, eb.imgs, eb.imgs, (const int2 *)nullptr, eb.rowwin, s);
+        // R is read only inside each window: full row pass, columns of the window only
+        e = launch_fft2d_cols_out(p, nb, +1, eb.imgs, eb.colwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_back, btiles, dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, k.px, k.py, rscale,
                            bb.ckpt + q * M, bb.dmap, eb.imgs, bb.pspat);

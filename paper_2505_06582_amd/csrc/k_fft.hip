@@ -97,70 +97,90 @@ static __device__ __forceinline__ void dft8(float2 *v)
     v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
 }
 
-// One Stockham pass of radix R over `nb = n/R` butterflies for each of `batch` transforms
-// stored contiguously (stride n) in src; result into dst.
-template <int R, int S>
-static __device__ __forceinline__ void stockham_pass(const float2 *src, float2 *dst, int n, int batch, int Ns,
-                                                     const float2 *__restrict__ tw, int tid, int nthr)
+// j / d for j < 2^16 and 2 <= d <= 2^14: with m = floor((2^32 - 1) / d) + 1, umulhi(j, m) = j / d
+// exactly (the error j (m - 2^32/d) / 2^32 < 2^-16 is below the smallest non-zero fraction 1/d).
+// (d = 1 would need m = 2^32; callers handle it.)
+static __device__ __forceinline__ int div_small(int j, uint32_t m) { return (int)__umulhi((uint32_t)j, m); }
+
+// Row transforms keep one row in ONE padded LDS buffer (element i at lds_pad(i): one element
+// of padding every 16 spreads the early passes' strided stores over the banks) and run each
+// Stockham pass in place: every thread reads the inputs of its butterflies into registers,
+// the work-group synchronises, then every thread writes its outputs.  NPT bounds the row
+// elements per thread (n <= NPT * FFT_THREADS), so a radix-R pass holds at most
+// ceil(NPT / R) butterflies per thread; one buffer and few registers let eight work-groups
+// share a CU.
+static __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+static __host__ __device__ constexpr int lds_padded_len(int n) { return n + (n >> 4) + 1; }
+
+template <int R, int S, int NPT>
+static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int Ns, const float2 *__restrict__ tw,
+                                                        int tid)
 {
-    const int nb = n / R;
-    const int total = nb * batch;
-    const int tstep = n / (Ns * R);
-    for (int idx = tid; idx < total; idx += nthr) {
-        const int b = idx / nb, j = idx - b * nb;
-        const float2 *s = src + b * n;
-        float2 *d = dst + b * n;
-        const int k = j % Ns;
-        float2 v[R];
+    constexpr int KB = (NPT + R - 1) / R;
+    const int nb = n / R, tstep = n / (Ns * R);
+    const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
+    float2 v[KB][R], w[KB][R - 1];
+    // the twiddles are fetched from memory before the barrier, so their latency overlaps it
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
+    for (int q = 0; q < KB; ++q) {
+        const int j = tid + q * FFT_THREADS;
+        if (j < nb) {
+            const int jq = Ns > 1 ? div_small(j, mNs) : j, k = j - jq * Ns;
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-            float2 w = tw[r * k * tstep];
-            if (S < 0) w.y = -w.y;
-            v[r] = cmul(v[r], w);
+            for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r * k * tstep];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[lds_pad(j + r * nb)];
         }
-        if (R == 2) dft2<S>(v);
-        if (R == 3) dft3<S>(v);
-        if (R == 4) dft4<S>(v);
-        if (R == 5) dft5<S>(v);
-        if (R == 8) dft8<S>(v);
-        const int o = (j / Ns) * Ns * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r) d[o + r * Ns] = v[r];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+        const int j = tid + q * FFT_THREADS;
+        if (j < nb) {
+            const int jq = Ns > 1 ? div_small(j, mNs) : j, k = j - jq * Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 t = w[q][r - 1];
+                if (S < 0) t.y = -t.y;
+                v[q][r] = cmul(v[q][r], t);
+            }
+            if (R == 2) dft2<S>(v[q]);
+            if (R == 3) dft3<S>(v[q]);
+            if (R == 4) dft4<S>(v[q]);
+            if (R == 5) dft5<S>(v[q]);
+            if (R == 8) dft8<S>(v[q]);
+            const int o = jq * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lds_pad(o + r * Ns)] = v[q][r];
+        }
+    }
+    __syncthreads();
 }
 
-// Runs all passes; returns which buffer (0: a, 1: b) holds the result.
-template <int S>
-static __device__ int fft_lds(float2 *a, float2 *b, const RadixPlan &pl, int batch, const float2 *__restrict__ tw)
+template <int S, int NPT>
+static __device__ void fft_row_lds(float2 *buf, const RadixPlan &pl, const float2 *__restrict__ tw)
 {
-    int Ns = 1, cur = 0;
+    int Ns = 1;
     for (int p = 0; p < pl.nrad; ++p) {
         const int R = pl.r[p];
-        float2 *src = cur ? b : a, *dst = cur ? a : b;
         switch (R) {
-        case 2: stockham_pass<2, S>(src, dst, pl.n, batch, Ns, tw, threadIdx.x, blockDim.x); break;
-        case 3: stockham_pass<3, S>(src, dst, pl.n, batch, Ns, tw, threadIdx.x, blockDim.x); break;
-        case 4: stockham_pass<4, S>(src, dst, pl.n, batch, Ns, tw, threadIdx.x, blockDim.x); break;
-        case 5: stockham_pass<5, S>(src, dst, pl.n, batch, Ns, tw, threadIdx.x, blockDim.x); break;
-        default: stockham_pass<8, S>(src, dst, pl.n, batch, Ns, tw, threadIdx.x, blockDim.x); break;
+        case 2: row_pass_inplace<2, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 3: row_pass_inplace<3, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 4: row_pass_inplace<4, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 5: row_pass_inplace<5, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        default: row_pass_inplace<8, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
         }
-        __syncthreads();
         Ns *= R;
-        cur ^= 1;
     }
-    return cur;
 }
 
 // Row transforms: one row per work-group.  in/out: [rows][n].
-template <int S>
+template <int S, int NPT>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                           RadixPlan pl, const float2 *__restrict__ tw,
                                                           const int2 *__restrict__ rowwin, int rows_per_img)
 {
     extern __shared__ float2 lds[];
-    float2 *a = lds, *b = lds + pl.n;
     const int64_t row = blockIdx.x;
     if (rowwin) {  // only rows (start + i) mod rows_per_img, i < len, of each image are wanted
         const int img = (int)(row / rows_per_img), r = (int)(row - (int64_t)img * rows_per_img);
@@ -169,40 +189,35 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
         if (d >= w.y) return;
     }
     const float2 *src = in + row * pl.n;
-    for (int i = threadIdx.x; i < pl.n; i += blockDim.x) a[i] = src[i];
+    for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) lds[lds_pad(i)] = src[i];
     __syncthreads();
-    const int cur = fft_lds<S>(a, b, pl, 1, tw);
-    const float2 *res = cur ? b : a;
+    fft_row_lds<S, NPT>(lds, pl, tw);
     float2 *dst = out + row * pl.n;
-    for (int i = threadIdx.x; i < pl.n; i += blockDim.x) dst[i] = res[i];
+    for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) dst[i] = lds[lds_pad(i)];
 }
 
 // Column transforms.  A work-group of FFT_COL_THREADS owns columns [c0, c0 + B) of one image
-// [n][width] (B = 16: 128-byte row segments, whole cache lines) and keeps them in ONE LDS
-// buffer laid out [n][B], so the global reads and writes are contiguous row segments and a
-// butterfly's R inputs of column c sit B apart (consecutive threads take consecutive columns:
-// no bank conflicts).  Each Stockham pass runs in place: every thread first reads the inputs
-// of its (at most KMAX) butterflies into registers, the work-group synchronises, then every
-// thread writes its outputs.  The twiddle table sits in LDS after the data.
-constexpr int FFT_COL_THREADS = 1024;
-constexpr int FFT_COL_MAXELEM = 150 * 1024 / 8;  // complex64 elements of data in LDS (n * B)
-constexpr int FFT_COL_LDSELEM = 160 * 1024 / 8;  // data + twiddle table (n * (B + 1))
+// [n][width] and keeps them in ONE LDS buffer laid out [n][B], so the global reads and writes
+// are contiguous row segments and a butterfly's R inputs of column c sit B apart (consecutive
+// threads take consecutive columns: no bank conflicts).  Each Stockham pass runs in place:
+// every thread first reads the inputs of its (at most KMAX) butterflies into registers, the
+// work-group synchronises, then every thread writes its outputs.  The twiddle table sits in
+// LDS after the data.  Two LDS budgets: 80 KB (B <= 8 columns, two work-groups per CU, so
+// one's loads and stores overlap the other's passes) where B >= 4 fits, else 160 KB.
+constexpr int FFT_COL_THREADS = 512;
+constexpr int FFT_COL_LDS_SMALL = 80 * 1024, FFT_COL_LDS_BIG = 160 * 1024;
 
-template <int R>
+template <int R, int LDSB>
 struct ColK {
-    static constexpr int KMAX = (FFT_COL_MAXELEM / R + FFT_COL_THREADS - 1) / FFT_COL_THREADS;
+    static constexpr int KMAX = (LDSB / 8 / R + FFT_COL_THREADS - 1) / FFT_COL_THREADS;
 };
 
-// j / d for j < 2^16 and 2 <= d <= 2^14: with m = floor((2^32 - 1) / d) + 1, umulhi(j, m) = j / d
-// exactly (the error j (m - 2^32/d) / 2^32 < 2^-16 is below the smallest non-zero fraction 1/d).
-// (d = 1 would need m = 2^32; callers handle it.)
-static __device__ __forceinline__ int div_small(int j, uint32_t m) { return (int)__umulhi((uint32_t)j, m); }
 
-template <int R, int S>
+template <int R, int S, int LDSB>
 static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n, int lb, int Ns, const float2 *tw,
                                                              int tid)
 {
-    constexpr int KMAX = ColK<R>::KMAX;
+    constexpr int KMAX = ColK<R, LDSB>::KMAX;
     const int B = 1 << lb, nb = n / R, total = nb << lb, tstep = n / (Ns * R);
     const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
     float2 v[KMAX][R];
@@ -241,25 +256,35 @@ static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n,
     __syncthreads();
 }
 
-template <int S>
-__global__ void __launch_bounds__(FFT_COL_THREADS) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
+// Work-groups are dispatched to the 8 XCDs round robin (block i to XCD i mod 8).  Renumber them
+// so that each XCD takes one contiguous range of slabs: neighbouring slabs, which share cache
+// lines when B < 16, then meet in the same L2.
+static __device__ __forceinline__ int xcd_contiguous(int i, int G)
+{
+    const int x = i & 7, j = i >> 3, q = G >> 3, r = G & 7;
+    return x * q + min(x, r) + j;
+}
+
+// With INTENSITY the results are not stored: |x|^2 goes to outf (float, same indexing).
+template <int S, bool INTENSITY, int LDSB>
+__global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4 : 2) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                               RadixPlan pl, const float2 *__restrict__ tw, int width,
-                                                              int lb, const int2 *__restrict__ colwin)
+                                                              int lb, const int2 *__restrict__ colwin,
+                                                              float *__restrict__ outf)
 {
     extern __shared__ float2 lds[];
     const int n = pl.n, B = 1 << lb;
+    const int blk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int nslab = (width + B - 1) / B;
+    const int64_t img = blk / nslab;
+    const int c0 = (blk - (int)(img * nslab)) * B;
     if (colwin) {  // only columns (start + i) mod width, i < len, of each image are nonzero
-        const int ns = (width + B - 1) / B;
-        const int im = blockIdx.x / ns, c0s = (blockIdx.x - im * ns) * B;
-        const int2 w = colwin[im];
-        const int d = ((c0s - w.x) % width + width) % width;
+        const int2 w = colwin[img];
+        const int d = ((c0 - w.x) % width + width) % width;
         if (!(d < w.y || d + B > width)) return;
     }
     float2 *tw_s = lds + n * B;  // the twiddle table, read by every pass
     for (int i = threadIdx.x; i < n; i += FFT_COL_THREADS) tw_s[i] = tw[i];
-    const int nslab = (width + B - 1) / B;
-    const int64_t img = blockIdx.x / nslab;
-    const int c0 = (blockIdx.x - (int)(img * nslab)) * B;
     const int bw = min(B, width - c0);
     const float2 *src = in + img * (int64_t)n * width;
     float2 *dst = out + img * (int64_t)n * width;
@@ -272,17 +297,91 @@ __global__ void __launch_bounds__(FFT_COL_THREADS) k_fft_cols(const float2 *__re
     for (int p = 0; p < pl.nrad; ++p) {
         const int R = pl.r[p];
         switch (R) {
-        case 2: stockham_pass_inplace<2, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
-        case 3: stockham_pass_inplace<3, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
-        case 4: stockham_pass_inplace<4, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
-        case 5: stockham_pass_inplace<5, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
-        default: stockham_pass_inplace<8, S>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 2: stockham_pass_inplace<2, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 3: stockham_pass_inplace<3, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 4: stockham_pass_inplace<4, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 5: stockham_pass_inplace<5, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        default: stockham_pass_inplace<8, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
         }
         Ns *= R;
     }
-    for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
-        const int r = i >> lb, c = i & (B - 1);
-        if (c < bw) dst[(int64_t)r * width + c0 + c] = lds[i];
+    if (INTENSITY) {
+        float *dstf = outf + img * (int64_t)n * width;
+        for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
+            const int r = i >> lb, c = i & (B - 1);
+            const float2 v = lds[i];
+            if (c < bw) dstf[(int64_t)r * width + c0 + c] = fmaf(v.x, v.x, v.y * v.y);
+        }
+    } else {
+        for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
+            const int r = i >> lb, c = i & (B - 1);
+            if (c < bw) dst[(int64_t)r * width + c0 + c] = lds[i];
+        }
+    }
+}
+
+// Focal stack, row pass.  One work-group per (wavelength c, spectrum row y) reads the row of
+// the forward spectrum DFT(u) once, forms per element the angular-spectrum phase
+// d_c(nu) = sqrt(1/lambda_c^2 - |nu|^2) - 1/lambda_c = -|nu|^2 / (1/lambda_c + sqrt(...))
+// in FP64 (Eq. 4 without cancellation), and then for every plane k multiplies the row by
+// H(nu, z_k) = exp(j 2 pi (frac(z_k / lambda_c) + z_k d_c(nu))) (zero outside the propagating
+// band and, with the half-band filter, outside |m'_x| < N_x / 4, |m'_y| < N_y / 4), times the
+// 1 / (N_x N_y) of the inverse, transforms it and stores it to plane k.
+constexpr int STACK_MAXPT = 16;  // row elements per thread: N_x <= 16 * FFT_THREADS
+template <int S, int NPT>
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_rows_stack(const float2 *__restrict__ spec,
+                                                                float2 *__restrict__ planes, RadixPlan pl,
+                                                                const float2 *__restrict__ tw, StackArgs sa)
+{
+    extern __shared__ float2 lds[];
+    const int nx = pl.n, ny = sa.ny;
+    const int row = blockIdx.x, c = row / ny, y = row - c * ny;
+    const int myp = y < ny / 2 ? y : y - ny;
+    const double nuy = (double)myp * sa.dnuy, il = sa.inv_l[c];
+    const bool yin = !sa.half_band || 4 * abs(myp) < ny;
+    float2 sv[NPT];
+    double dv[NPT];
+    bool keep[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int i = threadIdx.x + j * FFT_THREADS;
+        sv[j] = make_float2(0.0f, 0.0f);
+        dv[j] = 0.0;
+        keep[j] = false;
+        if (i < nx) {
+            const int mxp = i < nx / 2 ? i : i - nx;
+            const double nux = (double)mxp * sa.dnux;
+            const double nu2 = fma(nux, nux, nuy * nuy);
+            const double w2 = fma(il, il, -nu2);
+            keep[j] = w2 > 0.0 && yin && (!sa.half_band || 4 * abs(mxp) < nx);
+            if (keep[j]) {
+                dv[j] = -nu2 / (il + sqrt(w2));
+                sv[j] = spec[(int64_t)row * nx + i];
+            }
+        }
+    }
+    for (int k = 0; k < sa.K; ++k) {
+        const double zk = sa.z[k], pk = sa.piston[k * STACK_MAXC + c];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int i = threadIdx.x + j * FFT_THREADS;
+            if (i < nx) {
+                float2 v = make_float2(0.0f, 0.0f);
+                if (keep[j]) {
+                    double t = fma(zk, dv[j], pk);
+                    t -= floor(t);
+                    const float th = (float)t;
+                    const float cs = __builtin_amdgcn_cosf(th) * sa.scale, sn = __builtin_amdgcn_sinf(th) * sa.scale;
+                    v = make_float2(sv[j].x * cs - sv[j].y * sn, sv[j].x * sn + sv[j].y * cs);
+                }
+                lds[lds_pad(i)] = v;
+            }
+        }
+        __syncthreads();
+        fft_row_lds<S, NPT>(lds, pl, tw);
+        float2 *dst = planes + ((int64_t)(k * sa.C + c) * ny + y) * nx;
+        for (int i = threadIdx.x; i < nx; i += FFT_THREADS) dst[i] = lds[lds_pad(i)];
+        __syncthreads();
     }
 }
 
@@ -295,12 +394,34 @@ static RadixPlan make_radix(int n, const int32_t *r, int nrad)
     return p;
 }
 
-int fft_col_batch(int n)
+// Columns per work-group and LDS budget for columns of length n: the largest B <= 8 with the
+// B n data and the n twiddles in 80 KB if that B is at least 4, else the largest B <= 16 in
+// 160 KB (B = 1 fits up to n = 8192).
+struct ColCfg {
+    int B, lb, ldsb;
+};
+static ColCfg col_config(int n)
 {
-    // largest B (power of two, <= 16) with B n complex64 of data and the n twiddles in LDS
-    int B = 16;
-    while (B > 1 && ((int64_t)B * n > FFT_COL_MAXELEM || (int64_t)(B + 1) * n > FFT_COL_LDSELEM)) B >>= 1;
-    return B;
+    ColCfg c{8, 0, FFT_COL_LDS_SMALL};
+    while (c.B > 1 && (int64_t)(c.B + 1) * n * 8 > FFT_COL_LDS_SMALL) c.B >>= 1;
+    if (c.B < 4) {
+        c.B = 16;
+        c.ldsb = FFT_COL_LDS_BIG;
+        while (c.B > 1 && (int64_t)(c.B + 1) * n * 8 > FFT_COL_LDS_BIG) c.B >>= 1;
+    }
+    while ((1 << c.lb) < c.B) ++c.lb;
+    return c;
+}
+
+int fft_col_batch(int n) { return col_config(n).B; }
+
+template <int S, bool INTENSITY>
+static void set_col_lds()
+{
+    hipFuncSetAttribute((const void *)k_fft_cols<S, INTENSITY, FFT_COL_LDS_SMALL>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, FFT_COL_LDS_SMALL);
+    hipFuncSetAttribute((const void *)k_fft_cols<S, INTENSITY, FFT_COL_LDS_BIG>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, FFT_COL_LDS_BIG);
 }
 
 static void allow_big_lds()
@@ -308,11 +429,49 @@ static void allow_big_lds()
     static bool done = false;
     if (done) return;
     const int lim = 160 * 1024;
-    hipFuncSetAttribute((const void *)k_fft_cols<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_fft_cols<-1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_fft_rows<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_fft_rows<-1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    set_col_lds<1, false>();
+    set_col_lds<-1, false>();
+    set_col_lds<-1, true>();
+    hipFuncSetAttribute((const void *)k_fft_rows<1, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_fft_rows<-1, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     done = true;
+}
+
+// Row passes: the smallest elements-per-thread bound that covers n.
+template <int S>
+static void rows_launch(const Plan &p, const RadixPlan &px, int rows, const float2 *src, float2 *dst,
+                        const int2 *rowwin, hipStream_t s)
+{
+    const size_t lds = (size_t)lds_padded_len(p.nx) * sizeof(float2);
+    const int npt = (p.nx + FFT_THREADS - 1) / FFT_THREADS;
+    const dim3 g(rows), b(FFT_THREADS);
+    if (npt <= 2)
+        hipLaunchKernelGGL((k_fft_rows<S, 2>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+    else if (npt <= 4)
+        hipLaunchKernelGGL((k_fft_rows<S, 4>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+    else if (npt <= 8)
+        hipLaunchKernelGGL((k_fft_rows<S, 8>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+    else if (npt <= 16)
+        hipLaunchKernelGGL((k_fft_rows<S, 16>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+    else
+        hipLaunchKernelGGL((k_fft_rows<S, 32>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+}
+
+// One column pass over nimg images [ny][nx] in place (or, with intensity, |x|^2 to it).
+template <int S, bool INTENSITY>
+static void cols_launch(const Plan &p, const RadixPlan &py, int nimg, float2 *buf, const int2 *colwin, float *outf,
+                        hipStream_t s)
+{
+    const ColCfg c = col_config(p.ny);
+    const size_t lds = (size_t)(c.B + 1) * p.ny * sizeof(float2);
+    const int nslab = (p.nx + c.B - 1) / c.B;
+    const dim3 grid(nimg * nslab), block(FFT_COL_THREADS);
+    if (c.ldsb == FFT_COL_LDS_SMALL)
+        hipLaunchKernelGGL((k_fft_cols<S, INTENSITY, FFT_COL_LDS_SMALL>), grid, block, lds, s, buf, buf, py, p.tw_y,
+                           p.nx, c.lb, colwin, outf);
+    else
+        hipLaunchKernelGGL((k_fft_cols<S, INTENSITY, FFT_COL_LDS_BIG>), grid, block, lds, s, buf, buf, py, p.tw_y,
+                           p.nx, c.lb, colwin, outf);
 }
 
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out, hipStream_t s)
@@ -328,30 +487,20 @@ hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float
     allow_big_lds();
     const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
     const RadixPlan py = make_radix(p.ny, p.radix_y, p.nrad_y);
-    const size_t row_lds = 2 * (size_t)p.nx * sizeof(float2);
     const int rows = batch * p.ny;
-    const int B = fft_col_batch(p.ny);
-    int lb = 0;
-    while ((1 << lb) < B) ++lb;
-    const size_t col_lds = (size_t)(B + 1) * p.ny * sizeof(float2);
-    const int nslab = (p.nx + B - 1) / B;
     const bool cols_first = colwin != nullptr || rowwin != nullptr;
     if (cols_first && in != out) return hipErrorInvalidValue;  // the windowed form works in place
     auto rows_pass = [&](const float2 *src, float2 *dst) {
         if (direction > 0)
-            hipLaunchKernelGGL(k_fft_rows<-1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, src, dst, px, p.tw_x, rowwin,
-                               p.ny);
+            rows_launch<-1>(p, px, rows, src, dst, rowwin, s);
         else
-            hipLaunchKernelGGL(k_fft_rows<1>, dim3(rows), dim3(FFT_THREADS), row_lds, s, src, dst, px, p.tw_x, rowwin,
-                               p.ny);
+            rows_launch<1>(p, px, rows, src, dst, rowwin, s);
     };
     auto cols_pass = [&](float2 *buf) {
         if (direction > 0)
-            hipLaunchKernelGGL(k_fft_cols<-1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, buf, buf, py,
-                               p.tw_y, p.nx, lb, colwin);
+            cols_launch<-1, false>(p, py, batch, buf, colwin, nullptr, s);
         else
-            hipLaunchKernelGGL(k_fft_cols<1>, dim3(batch * nslab), dim3(FFT_COL_THREADS), col_lds, s, buf, buf, py,
-                               p.tw_y, p.nx, lb, colwin);
+            cols_launch<1, false>(p, py, batch, buf, colwin, nullptr, s);
     };
     if (cols_first) {
         cols_pass(out);
@@ -360,6 +509,55 @@ hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float
         rows_pass(in, out);
         cols_pass(out);
     }
+    return hipGetLastError();
+}
+
+// Rows first over every row, then only the column slabs that meet colwin (the output is
+// wanted only in those columns; the others are left unfinished).  In place.
+hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int2 *colwin,
+                                 hipStream_t s)
+{
+    allow_big_lds();
+    const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
+    const RadixPlan py = make_radix(p.ny, p.radix_y, p.nrad_y);
+    if (direction > 0) {
+        rows_launch<-1>(p, px, batch * p.ny, buf, buf, nullptr, s);
+        cols_launch<-1, false>(p, py, batch, buf, colwin, nullptr, s);
+    } else {
+        rows_launch<1>(p, px, batch * p.ny, buf, buf, nullptr, s);
+        cols_launch<1, false>(p, py, batch, buf, colwin, nullptr, s);
+    }
+    return hipGetLastError();
+}
+
+bool focal_stack_fits(int nx) { return nx <= STACK_MAXPT * FFT_THREADS; }
+
+// The inverse transforms of sa.K planes: the row pass forms and transforms every plane from
+// the spectrum, then the column pass either finishes them in place (intensity == nullptr)
+// or writes |u|^2 of each to `intensity`.
+hipError_t launch_focal_stack(const Plan &p, const float2 *spec, float2 *planes, float *intensity,
+                              const StackArgs &sa, hipStream_t s)
+{
+    if (sa.K <= 0) return hipSuccess;
+    if (!focal_stack_fits(p.nx) || sa.K > STACK_MAXK || sa.C > STACK_MAXC) return hipErrorInvalidValue;
+    allow_big_lds();
+    const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
+    const RadixPlan py = make_radix(p.ny, p.radix_y, p.nrad_y);
+    const size_t row_lds = (size_t)lds_padded_len(p.nx) * sizeof(float2);
+    const int npt = (p.nx + FFT_THREADS - 1) / FFT_THREADS;
+    const dim3 g(sa.C * p.ny), b(FFT_THREADS);
+    if (npt <= 2)
+        hipLaunchKernelGGL((k_fft_rows_stack<-1, 2>), g, b, row_lds, s, spec, planes, px, p.tw_x, sa);
+    else if (npt <= 4)
+        hipLaunchKernelGGL((k_fft_rows_stack<-1, 4>), g, b, row_lds, s, spec, planes, px, p.tw_x, sa);
+    else if (npt <= 8)
+        hipLaunchKernelGGL((k_fft_rows_stack<-1, 8>), g, b, row_lds, s, spec, planes, px, p.tw_x, sa);
+    else
+        hipLaunchKernelGGL((k_fft_rows_stack<-1, STACK_MAXPT>), g, b, row_lds, s, spec, planes, px, p.tw_x, sa);
+    if (intensity)
+        cols_launch<-1, true>(p, py, sa.K * sa.C, planes, nullptr, intensity, s);
+    else
+        cols_launch<-1, false>(p, py, sa.K * sa.C, planes, nullptr, nullptr, s);
     return hipGetLastError();
 }
 

@@ -119,3 +119,26 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert lib.gws_backward(None, ctypes.byref(prob), None, None, None, None, 0, None) == -1
     assert lib.gws_dft2d(None, 256, 256, 1, 1, 0, None, None, None, 0, None) == -1
     assert lib.gws_destroy(None) == 0
+
+
+def test_display_entry_points_validate_on_the_host():
+    lib = gws.load_library()
+    assert lib.gws_dpac_workspace_size(3) >= 3 * 4 and lib.gws_dpac_workspace_size(3) % 256 == 0
+    prob = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9))._c()
+    sz = ctypes.c_size_t()
+    img = 1920 * 1080 * 3 * 8
+    # intensity output: the spectrum plus one complex plane buffer per plane (up to 32 per launch)
+    assert lib.gws_focal_stack_workspace_size(None, ctypes.byref(prob), 8, 0, ctypes.byref(sz)) == 0
+    assert sz.value >= 9 * img
+    assert lib.gws_focal_stack_workspace_size(None, ctypes.byref(prob), 100, 0, ctypes.byref(sz)) == 0
+    assert img * 33 <= sz.value < img * 34
+    # complex output: the planes are the output itself
+    assert lib.gws_focal_stack_workspace_size(None, ctypes.byref(prob), 8, gws.FS_COMPLEX_OUTPUT,
+                                              ctypes.byref(sz)) == 0
+    assert img <= sz.value < 2 * img
+    assert lib.gws_focal_stack_workspace_size(None, ctypes.byref(prob), -1, 0, ctypes.byref(sz)) == -1
+    assert lib.gws_focal_stack_workspace_size(None, ctypes.byref(prob), 1, 64, ctypes.byref(sz)) == -1
+    wide = gws.Problem(8000, 64, lambdas=(520e-9,))._c()
+    assert lib.gws_focal_stack_workspace_size(None, ctypes.byref(wide), 1, 0, ctypes.byref(sz)) == -2
+    assert lib.gws_dpac_encode(None, 64, 64, 1, None, 0.0, None, None, 0, None) == -1
+    assert lib.gws_focal_stack(None, ctypes.byref(prob), None, 1, None, 0, None, None, 0, None) == -1
