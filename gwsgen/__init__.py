@@ -155,3 +155,56 @@ def batched_counts(n_scenes: int = 16, seed: int = 5000, lo: float = 1e3, hi: fl
     """Gaussian counts log-uniform in [lo, hi] for the multi-scene batched workload."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return [int(round(math.exp(v))) for v in rng.uniform(math.log(lo), math.log(hi), n_scenes)]
+
+
+# ---- world-space scenes for the holographics transform ----------------------------------
+
+def make_camera(seed: int, nx: int = 1920, ny: int = 1080, pitch: float = 8e-6, sh_degree: int = 3,
+                depth_range=(-10e-3, 10e-3), near_far=(1.0, 3.0)) -> dict:
+    """A pinhole camera with a random pose (world_to_view = [R | t], rows, R from a random
+    rotation vector of ~0.3 rad, t ~ N(0, 0.5 m)), focal lengths 1000 / 1000 px and the
+    principal point at the image centre; ray-space pixels map to SLM metres with the principal
+    point at the SLM centre, and view distances near_far map linearly onto depth_range (the
+    nearest to the largest depth, i.e. closest to the viewer)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rv = rng.normal(0.0, 0.3, 3)
+    t = rng.normal(0.0, 0.5, 3)
+    ang = float(np.linalg.norm(rv))
+    k = rv / ang
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    R = np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * (K @ K)
+    d0, d1 = near_far
+    z0, z1 = depth_range
+    # z_h = a * z_view + b with z_view = -d1 -> z0 and z_view = -d0 -> z1
+    a = (z1 - z0) / (d1 - d0)
+    b = z1 + a * d0
+    return dict(world_to_view=np.concatenate([R, t[:, None]], axis=1).ravel().tolist(), fx=1000.0, fy=1000.0,
+                cx=nx / 2.0, cy=ny / 2.0, near=0.1,
+                ray_to_holo=[pitch, 0.0, -nx / 2.0 * pitch, 0.0, pitch, -ny / 2.0 * pitch],
+                depth_scale=a, depth_offset=b, sh_degree=sh_degree)
+
+
+def make_world_scene(n: int, cam: dict, seed: int, nx: int = 1920, ny: int = 1080, near_far=(1.0, 3.0),
+                     sigma_px=(2.0, 20.0), sh_degree: int = 3, flat: bool = True) -> dict:
+    """n world-space Gaussians inside the camera's view: view-space positions uniform over
+    the image and over the distance range, taken back to world space through the camera pose;
+    random unnormalised quaternions (w, x, y, z); scales giving 2-20 px on the image (third
+    scale 0 for flat 2D Gaussians); opacity SH coefficients with the degree-0 term giving
+    0.1-1 and small higher-order terms.  Draw order: u, v, distance, quaternion, scales, SH."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    V = np.asarray(cam["world_to_view"], dtype=np.float64).reshape(3, 4)
+    R, t = V[:, :3], V[:, 3]
+    u = rng.uniform(0, nx, n)
+    v = rng.uniform(0, ny, n)
+    dist = rng.uniform(near_far[0], near_far[1], n)
+    p = np.stack([(u - cam["cx"]) / cam["fx"] * dist, (v - cam["cy"]) / cam["fy"] * dist, -dist], axis=1)
+    mean = (p - t[None, :]) @ R            # R^T (p - t), row-wise
+    quat = rng.normal(size=(n, 4))
+    s = rng.uniform(sigma_px[0], sigma_px[1], (n, 3)) * (dist / cam["fx"])[:, None]
+    if flat:
+        s[:, 2] = 0.0
+    K = (sh_degree + 1) ** 2
+    sh = rng.normal(0.0, 0.05, (n, K))
+    sh[:, 0] = rng.uniform(0.1, 1.0, n) / 0.28209479177387814
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return dict(mean=f32(mean), quat=f32(quat), scale=f32(s), opacity_sh=f32(sh))
