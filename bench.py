@@ -122,6 +122,8 @@ def main():
         return bench_batched(args)
     if args.workload == "exact1k":
         return bench_exact(args)
+    if args.workload == "holo100k":
+        return bench_holo(args)
     if args.workload == "focal8":
         return bench_focal(args)
     if args.workload == "precision1m":
@@ -427,6 +429,67 @@ def bench_exact(args):
            "roofline": {"bound": "hbm", "achieved": bytes_alg / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                         "frac": bytes_alg / t / PEAK_HBM, "traffic": None, "kernel": "exact mask + FFT + splat",
                         "work_per_launch": "6 x 8 x M bytes per Gaussian"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_holo(args):
+    """World space to hologram: 100k flat world-space Gaussians with degree-3 opacity seen by
+    a random camera, the holographics transform, then the order-invariant forward at
+    1080x1920x3."""
+    import numpy as np
+    import torch
+
+    import gwsgen
+    import paper_2505_06582_amd as gws
+    grid = gwsgen.Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    n = 100_000
+    cam = gwsgen.make_camera(1008)
+    w = gwsgen.make_world_scene(n, cam, 1009)
+    ctx = gws.context(0)
+    dev = torch.device("cuda", 0)
+    wt = {k: torch.from_numpy(v).to(dev) for k, v in w.items()}
+    rng = np.random.Generator(np.random.PCG64(1010))
+    g = {"amplitude": torch.from_numpy(rng.uniform(0, 1, (3, n)).astype(np.float32)).to(dev),
+         "phase": torch.from_numpy(rng.uniform(0, 2 * np.pi, n).astype(np.float32)).to(dev)}
+    plane = ctx.holographics(cam, wt)
+    g.update(plane)
+    prob = gws.Problem.from_grid(grid)
+    field = torch.empty((3, grid.ny, grid.nx), dtype=torch.complex64, device=dev)
+
+    def step():
+        ctx.holographics(cam, wt, out=plane)
+        ctx.forward(prob, g, out=field)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ctx.read_profile()
+    ctx.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    prof = ctx.read_profile()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
+    log("bench holo100k: %.3f ms per step; stages %s" % (ms, {k: round(v, 4) for k, v in st.items()}))
+    # per Gaussian: mean 12 B, quaternion 16 B, scales 12 B, 16 SH coefficients 64 B read,
+    # seven 4-byte outputs written
+    b_holo = n * (12.0 + 16.0 + 12.0 + 64.0 + 28.0)
+    t_holo = st["holographics"] * 1e-3
+    out = {"metric": "world-space scene to hologram (holographics transform + order-invariant forward) per second, "
+                     "100k Gaussians at 1080x1920x3",
+           "value": 1e3 / ms, "unit": "holograms/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "holo100k", "gaussians": n, "ny": grid.ny, "nx": grid.nx,
+                                           "n_lambda": 3, "sh_degree": 3},
+           "stage_ms": st,
+           "holographics_roofline": {"bound": "hbm", "achieved": b_holo / t_holo / 1e9, "peak": PEAK_HBM / 1e9,
+                                     "unit": "GB/s", "frac": b_holo / t_holo / PEAK_HBM,
+                                     "work_per_launch": "132 bytes per Gaussian"}}
     print(json.dumps(out), flush=True)
 
 

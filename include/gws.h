@@ -237,10 +237,10 @@ gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *field, const vo
  * records an event pair around each of its stages (0 preprocess+sort+records, 1 binning,
  * 2 spectrum accumulation, 3 partial-sum reduction, 4 inverse transform, 5 forward
  * transform, 6 propagation table, 7 adjoint accumulation, 8 gradient chain rule, 9 loss,
- * 10 double-phase coding, 11 focal stack).
+ * 10 double-phase coding, 11 focal stack, 12 holographics transform).
  * gws_read_profile synchronises, returns per stage the summed milliseconds and the number
  * of launches since the last read (host arrays of GWS_N_STAGES entries), and clears them. */
-#define GWS_N_STAGES 12
+#define GWS_N_STAGES 13
 gws_status gws_set_profiling(gws_ctx *ctx, int enable);
 gws_status gws_read_profile(gws_ctx *ctx, double *ms, int64_t *count);
 
@@ -257,6 +257,52 @@ typedef struct gws_peaks {
     double hbm_bytes_per_s;
 } gws_peaks;
 gws_status gws_measure_peaks(gws_ctx *ctx, gws_peaks *out, void *stream);
+
+/* ---- Holographics: world-space Gaussians to hologram-space in-plane Gaussians ---- */
+
+/* Camera and display of the holographics transform (supplement, Holographics pipeline). */
+typedef struct gws_view {
+    double world_to_view[12]; /* [R | t], 3 x 4 row-major: p = R mu + t; the camera looks along -z */
+    double fx, fy;            /* pinhole focal lengths, ray-space units (e.g. pixels); > 0 */
+    double cx, cy;            /* principal point, ray-space units */
+    double near;              /* Gaussians with view distance -p_z < near are culled; >= 0 */
+    double ray_to_holo[6];    /* 2 x 3 row-major: (x_h, y_h) = A (u, v) + b, metres on the SLM */
+    double depth_scale;       /* hologram depth z_h = depth_scale * p_z + depth_offset (metres) */
+    double depth_offset;
+    int32_t sh_degree;        /* 0..3: (sh_degree + 1)^2 opacity coefficients per Gaussian */
+    int32_t pad;
+} gws_view;
+
+/* World-space Gaussians, float32 rows (device pointers). */
+typedef struct gws_world_gaussians {
+    int64_t n;
+    const float *mean;        /* [n][3] */
+    const float *quat;        /* [n][4] rotation quaternion (w, x, y, z); normalised here */
+    const float *scale;       /* [n][3] standard deviations along the rotated axes (flat 2D
+                                 Gaussians: third scale 0) */
+    const float *opacity_sh;  /* [n][(sh_degree + 1)^2] view-dependent opacity coefficients */
+} gws_world_gaussians;
+
+/* In-plane hologram-space Gaussians written by gws_holographics (device, float32 [n] each;
+ * overwritten).  They are the mean_x .. opacity fields of gws_gaussians; amplitude and phase
+ * are not part of the transform and pass through unchanged. */
+typedef struct gws_plane_gaussians {
+    float *mean_x, *mean_y, *depth, *cov_xx, *cov_xy, *cov_yy, *opacity;
+} gws_plane_gaussians;
+
+/* The holographics transform (supplement, Holographics pipeline; Sec. 4 view-dependent
+ * opacity), in FP64 per Gaussian: model transform Sigma_w = R_w S_w S_w^T R_w^T; view transform;
+ * pinhole projection Pi(p) = (fx p_x / -p_z + cx, fy p_y / -p_z + cy) with the local affine
+ * (EWA) approximation Sigma_r = J R Sigma_w R^T J^T, J = dPi/dp; lift with the view depth p_z
+ * and zero z-scale; the hologram transform (an in-plane 2 x 2 map with offset and an affine
+ * depth map, which keep every Gaussian in-plane); opacity = sum_k o_k Y_k(d) clamped to [0, 1],
+ * Y_k the real spherical harmonics (Condon-Shortley phase, k = l^2 + l + m) of the unit
+ * direction d from the camera centre -R^T t to the mean.  Gaussians closer than `near` in
+ * front of the camera get opacity 0 and a zero covariance (culled by gws_forward).  n = 0
+ * does nothing.  GWS_ERR_INVALID_ARG for NULL pointers, fx or fy <= 0, near < 0 or a
+ * sh_degree outside 0..3. */
+gws_status gws_holographics(gws_ctx *ctx, const gws_view *view, const gws_world_gaussians *in,
+                            const gws_plane_gaussians *out, void *stream);
 
 /* ---- Display side: phase-only encoding and focal stacks of a hologram ---- */
 

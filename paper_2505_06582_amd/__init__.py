@@ -71,6 +71,24 @@ class _Stats(ctypes.Structure):
                 ("n_candidates", ctypes.c_int64), ("tile_config", ctypes.c_int32), ("graph_replayed", ctypes.c_int32)]
 
 
+class _View(ctypes.Structure):
+    _fields_ = [("world_to_view", ctypes.c_double * 12), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("near", ctypes.c_double),
+                ("ray_to_holo", ctypes.c_double * 6), ("depth_scale", ctypes.c_double),
+                ("depth_offset", ctypes.c_double), ("sh_degree", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _WorldGaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in ("mean", "quat", "scale", "opacity_sh")]
+
+
+PLANE_FIELDS = ("mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity")
+
+
+class _PlaneGaussians(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in PLANE_FIELDS]
+
+
 class _Peaks(ctypes.Structure):
     _fields_ = [("trans_ops_per_s", ctypes.c_double), ("valu_ops_per_s", ctypes.c_double),
                 ("hbm_bytes_per_s", ctypes.c_double)]
@@ -116,6 +134,8 @@ _SIGNATURES = {
     "gws_l2_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "gws_holographics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_View), ctypes.POINTER(_WorldGaussians),
+                                        ctypes.POINTER(_PlaneGaussians), ctypes.c_void_p]),
     "gws_dpac_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
     "gws_dpac_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
@@ -131,7 +151,7 @@ _SIGNATURES = {
 }
 
 STAGES = ("prep_sort", "bin", "accumulate", "reduce", "xform_inverse", "xform_forward", "dtable", "adjoint",
-          "grad_final", "loss", "dpac", "focal_stack")
+          "grad_final", "loss", "dpac", "focal_stack", "holographics")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -381,6 +401,27 @@ class Context:
                                          ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(self._l2ws.data_ptr()),
                                          self._l2ws.numel(), self._stream()), self.handle)
         return loss, grad
+
+    def holographics(self, view: dict, world: Dict[str, "object"], out=None) -> dict:
+        """World-space Gaussians (mean [n, 3], quat [n, 4], scale [n, 3], opacity_sh [n, K]
+        float32 device tensors) to hologram-space in-plane Gaussians (dict of [n] tensors)."""
+        torch = _torch()
+        n = int(world["mean"].shape[0])
+        v = _View()
+        for i, x in enumerate(view["world_to_view"]):
+            v.world_to_view[i] = float(x)
+        for i, x in enumerate(view["ray_to_holo"]):
+            v.ray_to_holo[i] = float(x)
+        for k in ("fx", "fy", "cx", "cy", "near", "depth_scale", "depth_offset"):
+            setattr(v, k, float(view[k]))
+        v.sh_degree = int(view["sh_degree"])
+        w = _WorldGaussians(n, *[ctypes.c_void_p(world[k].data_ptr()) for k in ("mean", "quat", "scale", "opacity_sh")])
+        if out is None:
+            out = {k: torch.empty(n, dtype=torch.float32, device=world["mean"].device) for k in PLANE_FIELDS}
+        pg = _PlaneGaussians(*[ctypes.c_void_p(out[k].data_ptr()) for k in PLANE_FIELDS])
+        _check(self.lib.gws_holographics(self.handle, ctypes.byref(v), ctypes.byref(w), ctypes.byref(pg),
+                                         self._stream()), self.handle)
+        return out
 
     def dpac_encode(self, field, a_max: Optional[float] = None, out=None):
         """Double-phase coding of a (C, ny, nx) complex64 field into a float32 phase-only

@@ -1293,6 +1293,50 @@ extern "C" gws_status gws_l2_loss_grad(gws_ctx *ctx, int64_t n, const void *fiel
 }
 
 // ---------------------------------------------------------------------------------
+// Holographics transform
+// ---------------------------------------------------------------------------------
+extern "C" gws_status gws_holographics(gws_ctx *ctx, const gws_view *view, const gws_world_gaussians *in,
+                                       const gws_plane_gaussians *out, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    if (!view || !in || !out || in->n < 0) return fail(ctx, GWS_ERR_INVALID_ARG, "bad holographics arguments");
+    if (!(view->fx > 0.0) || !(view->fy > 0.0) || !(view->near >= 0.0) || view->sh_degree < 0 || view->sh_degree > 3)
+        return fail(ctx, GWS_ERR_INVALID_ARG, "bad camera: fx, fy > 0, near >= 0, sh_degree 0..3");
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(view->world_to_view[i])) return fail(ctx, GWS_ERR_INVALID_ARG, "non-finite view matrix");
+    if (in->n == 0) return GWS_OK;
+    if (!in->mean || !in->quat || !in->scale || !in->opacity_sh || !out->mean_x || !out->mean_y || !out->depth ||
+        !out->cov_xx || !out->cov_xy || !out->cov_yy || !out->opacity)
+        return fail(ctx, GWS_ERR_INVALID_ARG, "a Gaussian array is NULL");
+    HoloArgs a{};
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) a.R[3 * r + c] = view->world_to_view[4 * r + c];
+        a.t[r] = view->world_to_view[4 * r + 3];
+    }
+    for (int c = 0; c < 3; ++c) a.centre[c] = -(a.R[c] * a.t[0] + a.R[3 + c] * a.t[1] + a.R[6 + c] * a.t[2]);
+    a.fx = view->fx;
+    a.fy = view->fy;
+    a.cx = view->cx;
+    a.cy = view->cy;
+    a.near = view->near;
+    a.A[0] = view->ray_to_holo[0];
+    a.A[1] = view->ray_to_holo[1];
+    a.b[0] = view->ray_to_holo[2];
+    a.A[2] = view->ray_to_holo[3];
+    a.A[3] = view->ray_to_holo[4];
+    a.b[1] = view->ray_to_holo[5];
+    a.depth_scale = view->depth_scale;
+    a.depth_offset = view->depth_offset;
+    a.sh_degree = view->sh_degree;
+    const PlaneOut po{out->mean_x, out->mean_y, out->depth, out->cov_xx, out->cov_xy, out->cov_yy, out->opacity};
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const hipStream_t s = (hipStream_t)stream;
+    StageScope sc(ctx, s, ST_HOLO);
+    HIP_CHECK(ctx, launch_holographics(a, in->n, in->mean, in->quat, in->scale, in->opacity_sh, po, s));
+    return GWS_OK;
+}
+
+// ---------------------------------------------------------------------------------
 // Display side: double-phase coding and focal stacks
 // ---------------------------------------------------------------------------------
 extern "C" size_t gws_dpac_workspace_size(int32_t n_lambda)

@@ -311,7 +311,7 @@ hipError_t launch_l2_grad(const float2 *u, const float2 *t, float2 *g, double *l
 // Stages timed with HIP events when profiling is on (gws_set_profiling).
 enum Stage {
     ST_PREP = 0, ST_BIN, ST_ACCUM, ST_REDUCE, ST_XFORM_INV, ST_XFORM_FWD, ST_DTABLE, ST_ADJOINT, ST_FINAL, ST_LOSS,
-    ST_DPAC, ST_FOCAL, ST_COUNT
+    ST_DPAC, ST_FOCAL, ST_HOLO, ST_COUNT
 };
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                         hipStream_t s);
@@ -329,6 +329,21 @@ struct StackArgs {
 bool focal_stack_fits(int nx);
 hipError_t launch_focal_stack(const Plan &p, const float2 *spec, float2 *planes, float *intensity,
                               const StackArgs &sa, hipStream_t s);
+// Holographics transform: camera and display parameters (FP64), and the in-plane outputs.
+struct HoloArgs {
+    double R[9], t[3];            // world to view: p = R mu + t (row-major R)
+    double centre[3];             // camera centre in world space, -R^T t
+    double fx, fy, cx, cy, near;
+    double A[4], b[2];            // ray space to hologram plane (row-major 2 x 2, offset)
+    double depth_scale, depth_offset;
+    int32_t sh_degree, pad;
+};
+struct PlaneOut {
+    float *mean_x, *mean_y, *depth, *cov_xx, *cov_xy, *cov_yy, *opacity;
+};
+hipError_t launch_holographics(const HoloArgs &a, int64_t n, const float *mean, const float *quat, const float *scale,
+                               const float *sh, const PlaneOut &out, hipStream_t s);
+
 // Display kernels: per-channel max |u| (as float bits), double-phase coding, e^{jP}.
 hipError_t launch_amax(const float2 *u, int64_t m, int C, uint32_t *amax_bits, hipStream_t s);
 hipError_t launch_dpac(const float2 *u, int nx, int ny, int C, const uint32_t *amax_bits, float amax_fixed,

@@ -28,8 +28,15 @@ __global__ void __launch_bounds__(DISP_THREADS) k_amax(const float2 *__restrict_
     const int c = blockIdx.y;
     const float2 *src = u + (int64_t)c * m;
     float mx = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * DISP_THREADS + threadIdx.x; i < m; i += (int64_t)gridDim.x * DISP_THREADS)
-        mx = fmaxf(mx, magnitude(src[i]));
+    const int64_t stride = (int64_t)gridDim.x * DISP_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * DISP_THREADS + threadIdx.x; i < m; i += 4 * stride) {
+        // four independent loads in flight per thread
+        float2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = i + q * stride < m ? src[i + q * stride] : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mx = fmaxf(mx, magnitude(v[q]));
+    }
     for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
     if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -44,8 +51,9 @@ hipError_t launch_amax(const float2 *u, int64_t m, int C, uint32_t *amax_bits, h
 {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, amax_bits, C);
     if (m <= 0) return hipGetLastError();
-    const int64_t want = (m + DISP_THREADS * 8 - 1) / (DISP_THREADS * 8);
-    const int nb = (int)(want < 1024 ? want : 1024);
+    // few work-groups per channel: each ends with one atomic on the channel's word
+    const int64_t want = (m + DISP_THREADS * 16 - 1) / (DISP_THREADS * 16);
+    const int nb = (int)(want < 128 ? want : 128);
     hipLaunchKernelGGL(k_amax, dim3(nb, C), dim3(DISP_THREADS), 0, s, u, m, amax_bits);
     return hipGetLastError();
 }

@@ -53,6 +53,29 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert got == want
 
 
+def test_holographics_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "szh.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gws.h"\nint main(void){printf("%zu %zu %zu %zu %zu\\n",'
+                   ' sizeof(gws_view), offsetof(gws_view, ray_to_holo), offsetof(gws_view, sh_degree),'
+                   ' sizeof(gws_world_gaussians), sizeof(gws_plane_gaussians)); return 0;}\n')
+    exe = tmp_path / "szh"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
+    want = [ctypes.sizeof(gws._View), gws._View.ray_to_holo.offset, gws._View.sh_degree.offset,
+            ctypes.sizeof(gws._WorldGaussians), ctypes.sizeof(gws._PlaneGaussians)]
+    assert got == want
+
+
+def test_holographics_validates_on_the_host():
+    lib = gws.load_library()
+    v = gws._View()
+    v.fx = v.fy = 1000.0
+    v.sh_degree = 3
+    w = gws._WorldGaussians(0)
+    pg = gws._PlaneGaussians()
+    assert lib.gws_holographics(None, ctypes.byref(v), ctypes.byref(w), ctypes.byref(pg), None) == -1
+
+
 def _check(prob):
     lib = gws.load_library()
     return lib.gws_check_problem(ctypes.byref(prob._c()))
