@@ -118,6 +118,8 @@ def main():
     import gwsgen
     import paper_2505_06582_amd as gws
 
+    if args.copy_calibration and args.workload != "fwdbwd100k":
+        copy_calibration()
     if args.workload == "batched16":
         return bench_batched(args)
     if args.workload == "exact1k":

@@ -117,6 +117,7 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
                                                         int tid)
 {
     constexpr int KB = (NPT + R - 1) / R;
+    asm volatile("" : "+v"(tid));  // addresses formed per pass, not hoisted out of the pass loop
     const int nb = n / R, tstep = n / (Ns * R);
     const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
     float2 v[KB][R], w[KB][R - 1];
@@ -218,6 +219,9 @@ static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n,
                                                              int tid)
 {
     constexpr int KMAX = ColK<R, LDSB>::KMAX;
+    // an opaque copy of the thread index: the addresses below are then formed in each pass
+    // instead of being hoisted out of the pass loop for every radix (which spills them)
+    asm volatile("" : "+v"(tid));
     const int B = 1 << lb, nb = n / R, total = nb << lb, tstep = n / (Ns * R);
     const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
     float2 v[KMAX][R];

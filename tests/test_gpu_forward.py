@@ -29,7 +29,11 @@ def log(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("ny,nx,batch", [(256, 256, 1), (40, 48, 2), (1080, 1920, 3), (90, 160, 1)])
+# Row lengths cover every elements-per-thread bound of the row pass (<= 512, 1024, 2048, 4096,
+# 8192) and column lengths both LDS budgets of the column pass (80 KB slabs of 8..4 columns,
+# 160 KB slabs down to one column at 8000).
+@pytest.mark.parametrize("ny,nx,batch", [(256, 256, 1), (40, 48, 2), (1080, 1920, 3), (90, 160, 1), (1000, 1000, 1),
+                                         (2160, 3840, 1), (16, 8000, 2), (8000, 16, 1)])
 def test_fft_matches_numpy_both_directions(ctx, ny, nx, batch):
     import torch
     log("fft %dx%d batch %d" % (ny, nx, batch))
