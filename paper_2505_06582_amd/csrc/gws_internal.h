@@ -98,6 +98,89 @@ __device__ __forceinline__ uint32_t row_block_mask(float a, float b2, float g, f
 }
 
 // Sum of a 64-bit counter over the 64 lanes of a wavefront (every lane gets the total).
+// Transposed butterfly reduction of V (8 or 16) per-lane values over the 64 lanes of a
+// wavefront.  Each transposed step pairs value i with value i + h and lane l with lane
+// l ^ d: the lane with the d bit clear keeps and sums the first value of the pair, its
+// partner the second, so a step halves the values per lane with one exchange and one add
+// per pair.  Steps d = 32 and d = 16 use the gfx950 cross-row swaps (v_permlane32_swap,
+// v_permlane16_swap), d = 8 a DPP rotate inside the 16-lane row.  What remains (V / 8
+// values per lane) is summed over the 8 lanes of each half-row with three DPP adds
+// (half-row mirror, then the two quad swaps).  On return register j of lane l holds the
+// total of value (V / 8) (4 b5 + 2 b4 + b3) + j (b_k = bit k of l); no LDS is involved.
+static __device__ __forceinline__ float dpp_ror8(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+}
+static __device__ __forceinline__ float dpp_half_mirror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, false));
+}
+static __device__ __forceinline__ float dpp_xor2(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xf, 0xf, false));
+}
+static __device__ __forceinline__ float dpp_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+
+// With EXTRA, one more value y is carried along: it is summed over lane bits 5, 4 and 3 on
+// its own, and in the last stage lanes with bit 2 clear keep x while lanes with bit 2 set
+// keep y (the half-row mirror pairs lane i with lane 7 - i, which differ in bit 2), so
+// afterwards lanes with bit 2 set hold the total of y.
+template <int V, bool EXTRA>
+static __device__ __forceinline__ void reduce_transposed(float (&x)[V], float &y, int lane)
+{
+    static_assert(V == 8 || V == 16, "8 or 16 values");
+    static_assert(!EXTRA || V == 8, "the extra value rides with 8 values");
+    constexpr int H = V / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i + H]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    if (EXTRA) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+        y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[i + H / 2]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    if (EXTRA) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+        y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        y += dpp_ror8(y);
+    }
+    const bool b3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < H / 4; ++i) {
+        const float keep = b3 ? x[i + H / 4] : x[i];
+        const float send = b3 ? x[i] : x[i + H / 4];
+        x[i] = keep + dpp_ror8(send);
+    }
+    if (EXTRA) {
+        const bool b2 = lane & 4;
+        const float keep = b2 ? y : x[0];
+        const float send = b2 ? x[0] : y;
+        float r = keep + dpp_half_mirror(send);
+        r += dpp_xor1(r);
+        r += dpp_xor2(r);
+        x[0] = r;
+        y = r;
+    } else {
+#pragma unroll
+        for (int i = 0; i < V / 8; ++i) {
+            float r = x[i];
+            r += dpp_half_mirror(r);
+            r += dpp_xor1(r);
+            r += dpp_xor2(r);
+            x[i] = r;
+        }
+    }
+}
+
 __device__ __forceinline__ long long wave_sum_i64(long long v)
 {
 #pragma unroll

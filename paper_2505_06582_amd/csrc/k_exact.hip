@@ -279,13 +279,6 @@ constexpr int EXACT_BTILE = 8;          // 8 x 8 pixels: one wavefront per work-
 constexpr int EXACT_NSPEC = 12;         // Re/Im P_c, Re/Im Q_c for c < 3
 constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, Sphi, So, pad
 
-static __device__ __forceinline__ float wave_sum_f(float v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
-}
-
 // Four frequencies per thread (strided by the work-group size): spectral partial sums per
 // (work-group, Gaussian) and, in place of F_k, V_k = sum_c A_c Gs_c conj(H_c).
 constexpr int EXACT_GS_PER = 4;
@@ -294,7 +287,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
                                                       const float2 *__restrict__ gspec, float2 *__restrict__ imgs,
                                                       float *__restrict__ part)
 {
-    __shared__ float s_red[4][EXACT_NSPEC];
+    __shared__ float s_red[4][16];
     const int64_t M = (int64_t)k.nx * k.ny;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t mi[EXACT_GS_PER];
@@ -355,10 +348,17 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
             }
             if (live[q]) imgs[(int64_t)b * M + mi[q]] = V;
         }
+        // one transposed butterfly over the 12 sums (padded to 16): afterwards lane l with
+        // bits 0-2 clear holds sums 2 (4 b5 + 2 b4 + b3) and that + 1
+        float x[16];
 #pragma unroll
-        for (int i = 0; i < EXACT_NSPEC; ++i) {
-            const float t = wave_sum_f(v[i]);
-            if (lane == 0) s_red[wave][i] = t;
+        for (int i = 0; i < 16; ++i) x[i] = i < EXACT_NSPEC ? v[i] : 0.0f;
+        float unused = 0.0f;
+        reduce_transposed<16, false>(x, unused, lane);
+        if ((lane & 7) == 0) {
+            const int v0 = 2 * (((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1));
+            s_red[wave][v0] = x[0];
+            s_red[wave][v0 + 1] = x[1];
         }
         __syncthreads();
         if (threadIdx.x < EXACT_NSPEC) {
@@ -442,14 +442,14 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
                 v[6] = ga * gk;                                // opacity through alpha
                 D = fmaf(kept ? 1.0f - alpha : 1.0f, D, gk * zr);
             }
-#pragma unroll
-            for (int i = 0; i < EXACT_NSPAT; ++i) v[i] = wave_sum_f(v[i]);
+            // one transposed butterfly over the 8 sums: afterwards lane l with bits 0-2 clear
+            // holds sum 4 b5 + 2 b4 + b3
+            float unused = 0.0f;
+            reduce_transposed<EXACT_NSPAT, false>(v, unused, lane);
         }
-        if (lane < EXACT_NSPAT) {
-            float t = 0.0f;
-#pragma unroll
-            for (int i = 0; i < EXACT_NSPAT; ++i) t = lane == i ? v[i] : t;
-            part[(tile * 64 + b) * EXACT_NSPAT + lane] = t;
+        if ((lane & 7) == 0) {
+            const int i = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+            part[(tile * 64 + b) * EXACT_NSPAT + i] = v[0];
         }
     }
     if (in) dmap[pix] = D;
