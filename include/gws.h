@@ -61,8 +61,8 @@ typedef enum gws_status {
  * (profile truncated below eps_support of its peak) masked by the map, propagated by
  * H(nu, -z) and scaled by a_c o; alpha = o g, dropped unless above 1/255, then updates the
  * map.  EXACT is supported by gws_forward, gws_backward (the map recomputed from per-batch
- * checkpoints, never divided by 1 - alpha) and gws_workspace_size; the batched calls and
- * gws_autotune return GWS_ERR_UNSUPPORTED for it. */
+ * checkpoints, never divided by 1 - alpha), the batched calls (scene after scene) and the
+ * workspace queries; gws_autotune returns GWS_ERR_UNSUPPORTED for it (it has no tiling). */
 typedef enum gws_blend { GWS_BLEND_OIT = 0, GWS_BLEND_EXACT = 1 } gws_blend;
 
 /* Inverse transform: mixed-radix FP32 FFT, or the DFT as two dense complex GEMMs on the
@@ -189,7 +189,9 @@ gws_status gws_backward(gws_ctx *ctx, const gws_problem *problem, const gws_gaus
  * offsets[0] = 0, non-decreasing, offsets[n_scenes] = g->n).  Fields are written to
  * out->field + s * n_lambda*ny*nx complex64 (spectrum likewise if non-NULL).  All scenes
  * run through one persistent accumulation launch; the whole sequence is captured into a
- * hipGraph on first use for a given (problem, offsets, pointers) and replayed after. */
+ * hipGraph on first use for a given (problem, offsets, pointers) and replayed after.  With
+ * GWS_BLEND_EXACT the scenes run one after another on the stream, sharing a workspace sized
+ * for the largest, without graph capture. */
 gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,
                                       const int64_t *offsets, size_t *bytes);
 gws_status gws_forward_batched(gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,

@@ -458,6 +458,15 @@ extern "C" gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *
     return GWS_OK;
 }
 
+// Exact blending over several scenes: one scene after another on the stream, sharing the
+// workspace (sized for the largest scene).
+static size_t exact_batched_bytes(const gws_problem *prob, int S, const int64_t *offsets)
+{
+    size_t b = 0;
+    for (int i = 0; i < S; ++i) b = std::max(b, exact_layout(prob, offsets[i + 1] - offsets[i]).total);
+    return b;
+}
+
 extern "C" gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_problem *problem, int32_t n_scenes,
                                                  const int64_t *offsets, size_t *bytes)
 {
@@ -465,9 +474,9 @@ extern "C" gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_p
     if (!bytes || !offsets || n_scenes < 1) return GWS_ERR_INVALID_ARG;
     const gws_status st = gws_check_problem(problem);
     if (st != GWS_OK) return st;
-    if (problem->blend == GWS_BLEND_EXACT) return GWS_ERR_UNSUPPORTED;
     if (check_offsets(n_scenes, offsets, offsets[n_scenes]) != GWS_OK) return GWS_ERR_INVALID_ARG;
-    *bytes = make_batch_layout(problem, n_scenes, offsets).total;
+    *bytes = problem->blend == GWS_BLEND_EXACT ? exact_batched_bytes(problem, n_scenes, offsets)
+                                               : make_batch_layout(problem, n_scenes, offsets).total;
     return GWS_OK;
 }
 
@@ -844,13 +853,14 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     return GWS_OK;
 }
 
-static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g,
-                                    const gws_output *out, void *ws, size_t ws_bytes, hipStream_t s)
+// Gaussians [off, off + n) of g, one scene; field (and optionally spectrum) of that scene.
+static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, int64_t off,
+                                    int64_t n, void *field, void *spectrum, void *ws, size_t ws_bytes, hipStream_t s)
 {
     Plan *p = nullptr;
     gws_status st = get_plan(ctx, prob->nx, prob->ny, 4, &p);  // for its transform tables
     if (st != GWS_OK) return st;
-    const ExactLayout L = exact_layout(prob, g->n);
+    const ExactLayout L = exact_layout(prob, n);
     st = check_ws(ctx, ws, ws_bytes, L.total);
     if (st != GWS_OK) return st;
     char *base = (char *)ws;
@@ -867,32 +877,32 @@ static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const
     eb.imgs = (float2 *)(base + L.off_imgs);
     eb.colwin = (int2 *)(base + L.off_win);
     eb.rowwin = eb.colwin + 64;
-    float2 *spec = out->spectrum ? (float2 *)out->spectrum : (float2 *)(base + L.off_spec);
+    float2 *spec = spectrum ? (float2 *)spectrum : (float2 *)(base + L.off_spec);
     {
         StageScope sc(ctx, s, ST_ACCUM);
-        HIP_CHECK(ctx, run_exact_forward(*p, k, scene_view(g, 0, g->n), eb, spec, s));
+        HIP_CHECK(ctx, run_exact_forward(*p, k, scene_view(g, off, n), eb, spec, s));
     }
     {
         StageScope sc(ctx, s, ST_XFORM_INV);
         if (prob->xform == GWS_XFORM_FFT_FP32)
-            HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spec, (float2 *)out->field, s));
+            HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spec, (float2 *)field, s));
         else
-            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)out->field, (void *)(base + L.off_dft), s));
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)field, (void *)(base + L.off_dft), s));
     }
     HIP_CHECK(ctx, launch_sum_counters(nullptr, 0, ctx->d_stats, s));
-    ctx->last_n = g->n;
     ctx->last_tile_config = 0;
     return GWS_OK;
 }
 
-static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g,
-                                     const void *grad_field, const gws_grads *grads, void *ws, size_t ws_bytes,
-                                     hipStream_t s)
+// Gaussians [off, off + n) of g, one scene with its field gradient; their gradients.
+static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, int64_t off,
+                                     int64_t n, const void *grad_field, const gws_grads *grads, void *ws,
+                                     size_t ws_bytes, hipStream_t s)
 {
     Plan *p = nullptr;
     gws_status st = get_plan(ctx, prob->nx, prob->ny, 4, &p);
     if (st != GWS_OK) return st;
-    const ExactLayout L = exact_layout(prob, g->n);
+    const ExactLayout L = exact_layout(prob, n);
     st = check_ws(ctx, ws, ws_bytes, L.total);
     if (st != GWS_OK) return st;
     char *base = (char *)ws;
@@ -915,16 +925,16 @@ static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, cons
     bb.dmap = (float *)(base + L.off_dmap);
     bb.pspec = (float *)(base + L.off_pspec);
     bb.pspat = (float *)(base + L.off_pspat);
-    const GradView gv = grad_view(grads, 0, g->n);
+    const GradView gv = grad_view(grads, off, g->n);  // amplitude rows are strided by the whole batch
     {
         StageScope sc(ctx, s, ST_ADJOINT);
-        HIP_CHECK(ctx, run_exact_backward(*p, k, scene_view(g, 0, g->n), eb, bb, (const float2 *)grad_field, gv, s));
+        HIP_CHECK(ctx, run_exact_backward(*p, k, scene_view(g, off, n), eb, bb, (const float2 *)grad_field, gv, s));
     }
     HIP_CHECK(ctx, launch_sum_counters(nullptr, 0, ctx->d_stats, s));
-    ctx->last_n = g->n;
     ctx->last_tile_config = 0;
     return GWS_OK;
 }
+
 
 extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const gws_output *out,
                                   void *ws, size_t ws_bytes, void *stream)
@@ -938,7 +948,10 @@ extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const g
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     const int64_t off[2] = {0, g->n};
     ctx->last_graph = 0;
-    if (prob->blend == GWS_BLEND_EXACT) return exact_forward_run(ctx, prob, g, out, ws, ws_bytes, (hipStream_t)stream);
+    if (prob->blend == GWS_BLEND_EXACT) {
+        ctx->last_n = g->n;
+        return exact_forward_run(ctx, prob, g, 0, g->n, out->field, out->spectrum, ws, ws_bytes, (hipStream_t)stream);
+    }
     return forward_run(ctx, prob, 1, off, g, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -957,8 +970,10 @@ extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const 
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     const int64_t off[2] = {0, g->n};
     ctx->last_graph = 0;
-    if (prob->blend == GWS_BLEND_EXACT)
-        return exact_backward_run(ctx, prob, g, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
+    if (prob->blend == GWS_BLEND_EXACT) {
+        ctx->last_n = g->n;
+        return exact_backward_run(ctx, prob, g, 0, g->n, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
+    }
     return backward_run(ctx, prob, 1, off, g, grad_field, grads, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -1033,13 +1048,26 @@ extern "C" gws_status gws_forward_batched(gws_ctx *ctx, const gws_problem *prob,
     if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
-    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "exact blending is not batched");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     if (!out || !out->field) return fail(ctx, GWS_ERR_INVALID_ARG, "output field is NULL");
     if (check_offsets(n_scenes, offsets, g->n) != GWS_OK)
         return fail(ctx, GWS_ERR_INVALID_ARG, "offsets must be a CSR array of n_scenes + 1 entries (1..64 scenes)");
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    if (prob->blend == GWS_BLEND_EXACT) {
+        st = check_ws(ctx, ws, ws_bytes, exact_batched_bytes(prob, n_scenes, offsets));
+        if (st != GWS_OK) return st;
+        const size_t img = (size_t)prob->n_lambda * prob->nx * prob->ny * sizeof(float2);
+        ctx->last_graph = 0;
+        ctx->last_n = g->n;
+        for (int i = 0; i < n_scenes; ++i) {
+            st = exact_forward_run(ctx, prob, g, offsets[i], offsets[i + 1] - offsets[i], (char *)out->field + i * img,
+                                   out->spectrum ? (char *)out->spectrum + i * img : nullptr, ws, ws_bytes,
+                                   (hipStream_t)stream);
+            if (st != GWS_OK) return st;
+        }
+        return GWS_OK;
+    }
     st = prepare_plans(ctx, prob, n_scenes, offsets);
     if (st != GWS_OK) return st;
     gws_ctx::GraphKey key;
@@ -1063,7 +1091,6 @@ extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *prob
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
     if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
-    if (prob->blend == GWS_BLEND_EXACT) return fail(ctx, GWS_ERR_UNSUPPORTED, "exact blending is not batched");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     st = check_grads(ctx, grads);
@@ -1072,6 +1099,19 @@ extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *prob
     if (check_offsets(n_scenes, offsets, g->n) != GWS_OK)
         return fail(ctx, GWS_ERR_INVALID_ARG, "offsets must be a CSR array of n_scenes + 1 entries (1..64 scenes)");
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    if (prob->blend == GWS_BLEND_EXACT) {
+        st = check_ws(ctx, ws, ws_bytes, exact_batched_bytes(prob, n_scenes, offsets));
+        if (st != GWS_OK) return st;
+        const size_t img = (size_t)prob->n_lambda * prob->nx * prob->ny * sizeof(float2);
+        ctx->last_graph = 0;
+        ctx->last_n = g->n;
+        for (int i = 0; i < n_scenes; ++i) {
+            st = exact_backward_run(ctx, prob, g, offsets[i], offsets[i + 1] - offsets[i],
+                                    (const char *)grad_field + i * img, grads, ws, ws_bytes, (hipStream_t)stream);
+            if (st != GWS_OK) return st;
+        }
+        return GWS_OK;
+    }
     st = prepare_plans(ctx, prob, n_scenes, offsets);
     if (st != GWS_OK) return st;
     gws_ctx::GraphKey key;

@@ -116,15 +116,18 @@ def test_workspace_size_is_host_only_and_grows_with_n():
     assert lib.gws_workspace_size(None, ctypes.byref(prob), 10, None) == -1
 
 
-def test_exact_blending_workspace_and_unsupported_calls():
+def test_exact_blending_workspace_sizes():
     lib = gws.load_library()
     prob = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9), blend=gws.BLEND_EXACT)._c()
     sz = ctypes.c_size_t()
     assert lib.gws_workspace_size(None, ctypes.byref(prob), 1000, ctypes.byref(sz)) == 0
     # one batch of up to 64 full-grid complex64 images dominates
     assert sz.value >= 64 * 1920 * 1080 * 8
-    offs = (ctypes.c_int64 * 2)(0, 1000)
-    assert lib.gws_workspace_size_batched(None, ctypes.byref(prob), 1, offs, ctypes.byref(sz)) == -3
+    single = sz.value
+    # batched exact blending runs scene after scene: the workspace of the largest scene
+    offs = (ctypes.c_int64 * 4)(0, 1000, 1000, 1600)
+    assert lib.gws_workspace_size_batched(None, ctypes.byref(prob), 3, offs, ctypes.byref(sz)) == 0
+    assert sz.value == single
 
 
 def test_entry_points_reject_bad_arguments_without_a_device():

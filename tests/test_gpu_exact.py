@@ -120,13 +120,35 @@ def test_exact_full_size_grid(ctx):
     assert err < TOL_EXACT
 
 
-def test_exact_batched_is_unsupported(ctx):
+def test_exact_batched_equals_one_call_per_scene(ctx):
+    """Batched exact blending (scenes of 30, 0, 70 and 5 Gaussians) gives each scene's own
+    exact forward and backward, and the forward matches the oracle per scene."""
+    import torch
     import paper_2505_06582_amd as gws
-    grid = Grid(64, 64, 8e-6, 8e-6, (520e-9,))
-    s = clustered_scene(4, grid, 2108)
+    grid = Grid(96, 80, 8e-6, 8e-6, (638e-9, 520e-9))
+    parts = [clustered_scene(n, grid, 2108 + i) for i, n in enumerate((30, 0, 70, 5))]
+    offs = np.cumsum([0] + [p.n for p in parts]).tolist()
+    allg = gwsgen.Scene.concat(parts)
     prob = problem(grid, blend=gws.BLEND_EXACT)
-    with pytest.raises(gws.GwsError):
-        ctx.forward_batched(prob, scene_to_torch(s), [0, s.n])
+    tg = scene_to_torch(allg)
+    fb = to_numpy(ctx.forward_batched(prob, tg, offs))
+    M = grid.n_lambda * grid.ny * grid.nx
+    G = np.stack([gwsgen.make_target(grid, 2120 + i) * 0.05 for i in range(len(parts))])
+    gb = ctx.backward_batched(prob, tg, offs, torch.from_numpy(G.astype(np.complex64)).cuda(), want_depth=True)
+    for i, p in enumerate(parts):
+        one = to_numpy(ctx.forward(prob, scene_to_torch(p)))
+        assert np.array_equal(fb[i], one), i
+        assert rel_l2(fb[i], ex.exact_forward(p, grid)) < TOL_EXACT or p.n == 0
+        if p.n == 0:
+            assert np.all(fb[i] == 0)
+            continue
+        g1 = ctx.backward(prob, scene_to_torch(p), torch.from_numpy(G[i].astype(np.complex64)).cuda(),
+                          want_depth=True)
+        for k in g1:
+            a = to_numpy(gb[k])
+            a = a[:, offs[i]:offs[i + 1]] if a.ndim == 2 else a[offs[i]:offs[i + 1]]
+            assert np.array_equal(a, to_numpy(g1[k])), (i, k)
+    log("batched exact == per-scene calls (forward and backward), %d scenes" % len(parts))
 
 
 # Gradients through exact blending: per parameter group, normwise relative L2 against the FP64
