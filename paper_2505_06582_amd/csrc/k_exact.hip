@@ -107,9 +107,25 @@ static __device__ __forceinline__ float wrap_d(float d, float n)
     return d - n * rintf(d / n);
 }
 
+// The window rectangle of a record on the periodic grid, as (first, count) per axis: the
+// columns ceil(cx - hwx) .. floor(cx + hwx) and the rows likewise (count 0 when the record
+// contributes nothing).  The transforms of the masked images read exactly this rectangle.
+static __device__ __forceinline__ void window_rect(const ERec &r, int nx, int ny, int2 &cw, int2 &rw)
+{
+    if (r.hwx < 0) {
+        cw = rw = make_int2(0, 0);
+        return;
+    }
+    const int x0 = (int)ceilf(r.cx - (float)r.hwx), x1 = (int)floorf(r.cx + (float)r.hwx);
+    const int y0 = (int)ceilf(r.cy - (float)r.hwy), y1 = (int)floorf(r.cy + (float)r.hwy);
+    cw = make_int2(((x0 % nx) + nx) % nx, min(x1 - x0 + 1, nx));
+    rw = make_int2(((y0 % ny) + ny) % ny, min(y1 - y0 + 1, ny));
+}
+
 // One work-group per 16 x 16 pixel tile; walks Gaussians [b0, b0 + nb) in order.  Reads the
 // map from t_in; writes the map at the batch start to ckpt and at its end to t_out, and the
-// masked wavefronts to imgs (each optional).
+// masked wavefronts to imgs (each optional) -- only inside each Gaussian's window rectangle
+// (zeros included); the rest of an image is never written and never read.
 __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec, int b0, int nb, int nx, int ny,
                                                     const float *t_in, float *t_out, float2 *__restrict__ imgs,
                                                     float *__restrict__ ckpt)
@@ -131,8 +147,8 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
         const ERec &r = s_rec[b];
         const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
         const bool hit = r.hwx >= 0 && dcx <= (float)r.hwx + 8.5f && dcy <= (float)r.hwy + 8.5f;
-        float2 v = make_float2(0.0f, 0.0f);
         if (hit) {
+            float2 v = make_float2(0.0f, 0.0f);
             const float dx = wrap_d((float)px - r.cx, (float)nx), dy = wrap_d((float)py - r.cy, (float)ny);
             if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {  // the profile's window
                 const float q = fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy));
@@ -142,8 +158,13 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
                 const float alpha = r.o * gk;
                 if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
             }
+            if (imgs && in) {
+                int2 cw, rw;
+                window_rect(r, nx, ny, cw, rw);
+                const int ex = ((px - cw.x) % nx + nx) % nx, ey = ((py - rw.x) % ny + ny) % ny;
+                if (ex < cw.y && ey < rw.y) imgs[(int64_t)b * M + pix] = v;
+            }
         }
-        if (imgs && in) imgs[(int64_t)b * M + pix] = v;
     }
     if (t_out && in) t_out[pix] = T;
 }
@@ -199,16 +220,10 @@ __global__ void __launch_bounds__(64) k_exact_windows(const ERec *__restrict__ r
 {
     const int b = threadIdx.x;
     if (b >= nb) return;
-    const ERec &r = rec[b0 + b];
-    if (r.hwx < 0) {
-        colwin[b] = make_int2(0, 0);
-        rowwin[b] = make_int2(0, 0);
-        return;
-    }
-    const int x0 = (int)ceilf(r.cx - (float)r.hwx), x1 = (int)floorf(r.cx + (float)r.hwx);
-    const int y0 = (int)ceilf(r.cy - (float)r.hwy), y1 = (int)floorf(r.cy + (float)r.hwy);
-    colwin[b] = make_int2(((x0 % nx) + nx) % nx, min(x1 - x0 + 1, nx));
-    rowwin[b] = make_int2(((y0 % ny) + ny) % ny, min(y1 - y0 + 1, ny));
+    int2 cw, rw;
+    window_rect(rec[b0 + b], nx, ny, cw, rw);
+    colwin[b] = cw;
+    rowwin[b] = rw;
 }
 
 __global__ void __launch_bounds__(256) k_exact_fill(float *__restrict__ tmap, float2 *__restrict__ spec, int64_t M,
@@ -253,7 +268,7 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
                            eb.imgs, (float *)nullptr);
         hipLaunchKernelGGL(k_exact_windows, dim3(1), dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.colwin,
                            eb.rowwin);
-        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, (const int2 *)nullptr, s);
+        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, eb.rowwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_splat, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec, (int)b0, nb, k,
                            eb.imgs, spec);
@@ -559,7 +574,7 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
                            (float *)nullptr, eb.imgs, (float *)nullptr);
         hipLaunchKernelGGL(k_exact_windows, dim3(1), dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.colwin,
                            eb.rowwin);
-        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, (const int2 *)nullptr, s);
+        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, eb.rowwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_gsplat, dim3(gsblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
                            bb.pspec);

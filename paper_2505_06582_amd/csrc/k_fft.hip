@@ -175,22 +175,27 @@ static __device__ void fft_row_lds(float2 *buf, const RadixPlan &pl, const float
     }
 }
 
-// Row transforms: one row per work-group.  in/out: [rows][n].
+// Position d of index v inside the periodic window w = (start, len) of an axis of length n;
+// inside when d < len.
+static __device__ __forceinline__ int win_pos(int v, int2 w, int n) { return ((v - w.x) % n + n) % n; }
+
+// Row transforms: one row per work-group.  in/out: [rows][n].  With colin, each image's
+// input is nonzero only in its window of columns: the others are read as zero, not loaded.
 template <int S, int NPT>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                           RadixPlan pl, const float2 *__restrict__ tw,
-                                                          const int2 *__restrict__ rowwin, int rows_per_img)
+                                                          const int2 *__restrict__ colin, int rows_per_img)
 {
     extern __shared__ float2 lds[];
     const int64_t row = blockIdx.x;
-    if (rowwin) {  // only rows (start + i) mod rows_per_img, i < len, of each image are wanted
-        const int img = (int)(row / rows_per_img), r = (int)(row - (int64_t)img * rows_per_img);
-        const int2 w = rowwin[img];
-        const int d = ((r - w.x) % rows_per_img + rows_per_img) % rows_per_img;
-        if (d >= w.y) return;
-    }
     const float2 *src = in + row * pl.n;
-    for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) lds[lds_pad(i)] = src[i];
+    if (colin) {
+        const int2 w = colin[row / rows_per_img];
+        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS)
+            lds[lds_pad(i)] = win_pos(i, w, pl.n) < w.y ? src[i] : make_float2(0.0f, 0.0f);
+    } else {
+        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) lds[lds_pad(i)] = src[i];
+    }
     __syncthreads();
     fft_row_lds<S, NPT>(lds, pl, tw);
     float2 *dst = out + row * pl.n;
@@ -274,7 +279,8 @@ template <int S, bool INTENSITY, int LDSB>
 __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4 : 2) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                               RadixPlan pl, const float2 *__restrict__ tw, int width,
                                                               int lb, const int2 *__restrict__ colwin,
-                                                              float *__restrict__ outf)
+                                                              float *__restrict__ outf,
+                                                              const int2 *__restrict__ rowin)
 {
     extern __shared__ float2 lds[];
     const int n = pl.n, B = 1 << lb;
@@ -282,7 +288,10 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
     const int nslab = (width + B - 1) / B;
     const int64_t img = blk / nslab;
     const int c0 = (blk - (int)(img * nslab)) * B;
-    if (colwin) {  // only columns (start + i) mod width, i < len, of each image are nonzero
+    // colwin: only the slabs meeting each image's window of columns are transformed.  rowin
+    // (input support): the image is nonzero only inside colwin x rowin; what lies outside is
+    // read as zero, not loaded.
+    if (colwin) {
         const int2 w = colwin[img];
         const int d = ((c0 - w.x) % width + width) % width;
         if (!(d < w.y || d + B > width)) return;
@@ -292,9 +301,18 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
     const int bw = min(B, width - c0);
     const float2 *src = in + img * (int64_t)n * width;
     float2 *dst = out + img * (int64_t)n * width;
-    for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
-        const int r = i >> lb, c = i & (B - 1);
-        lds[i] = c < bw ? src[(int64_t)r * width + c0 + c] : make_float2(0.0f, 0.0f);
+    if (rowin) {
+        const int2 wc = colwin[img], wr = rowin[img];
+        for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
+            const int r = i >> lb, c = i & (B - 1);
+            const bool live = c < bw && win_pos(c0 + c, wc, width) < wc.y && win_pos(r, wr, n) < wr.y;
+            lds[i] = live ? src[(int64_t)r * width + c0 + c] : make_float2(0.0f, 0.0f);
+        }
+    } else {
+        for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
+            const int r = i >> lb, c = i & (B - 1);
+            lds[i] = c < bw ? src[(int64_t)r * width + c0 + c] : make_float2(0.0f, 0.0f);
+        }
     }
     __syncthreads();
     int Ns = 1;
@@ -444,27 +462,27 @@ static void allow_big_lds()
 // Row passes: the smallest elements-per-thread bound that covers n.
 template <int S>
 static void rows_launch(const Plan &p, const RadixPlan &px, int rows, const float2 *src, float2 *dst,
-                        const int2 *rowwin, hipStream_t s)
+                        const int2 *colin, hipStream_t s)
 {
     const size_t lds = (size_t)lds_padded_len(p.nx) * sizeof(float2);
     const int npt = (p.nx + FFT_THREADS - 1) / FFT_THREADS;
     const dim3 g(rows), b(FFT_THREADS);
     if (npt <= 2)
-        hipLaunchKernelGGL((k_fft_rows<S, 2>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 2>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
     else if (npt <= 4)
-        hipLaunchKernelGGL((k_fft_rows<S, 4>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 4>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
     else if (npt <= 8)
-        hipLaunchKernelGGL((k_fft_rows<S, 8>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 8>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
     else if (npt <= 16)
-        hipLaunchKernelGGL((k_fft_rows<S, 16>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 16>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
     else
-        hipLaunchKernelGGL((k_fft_rows<S, 32>), g, b, lds, s, src, dst, px, p.tw_x, rowwin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 32>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
 }
 
 // One column pass over nimg images [ny][nx] in place (or, with intensity, |x|^2 to it).
 template <int S, bool INTENSITY>
 static void cols_launch(const Plan &p, const RadixPlan &py, int nimg, float2 *buf, const int2 *colwin, float *outf,
-                        hipStream_t s)
+                        hipStream_t s, const int2 *rowin = nullptr)
 {
     const ColCfg c = col_config(p.ny);
     const size_t lds = (size_t)(c.B + 1) * p.ny * sizeof(float2);
@@ -472,10 +490,10 @@ static void cols_launch(const Plan &p, const RadixPlan &py, int nimg, float2 *bu
     const dim3 grid(nimg * nslab), block(FFT_COL_THREADS);
     if (c.ldsb == FFT_COL_LDS_SMALL)
         hipLaunchKernelGGL((k_fft_cols<S, INTENSITY, FFT_COL_LDS_SMALL>), grid, block, lds, s, buf, buf, py, p.tw_y,
-                           p.nx, c.lb, colwin, outf);
+                           p.nx, c.lb, colwin, outf, rowin);
     else
         hipLaunchKernelGGL((k_fft_cols<S, INTENSITY, FFT_COL_LDS_BIG>), grid, block, lds, s, buf, buf, py, p.tw_y,
-                           p.nx, c.lb, colwin, outf);
+                           p.nx, c.lb, colwin, outf, rowin);
 }
 
 hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *in, float2 *out, hipStream_t s)
@@ -483,8 +501,10 @@ hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *i
     return launch_fft2d_win(p, batch, direction, in, out, nullptr, nullptr, s);
 }
 
-// Rows then columns; with windows, columns first (only the slabs meeting colwin, the rest
-// being zero) and then the rows (only those in rowwin; the others are left unfinished).
+// Rows then columns.  With windows, the input of each image is nonzero only inside its
+// rectangle colwin x rowwin (rowwin may be NULL: all rows): columns first, only the slabs
+// meeting colwin, loading only the rectangle; then every row, loading only colwin's columns
+// (what lies outside the rectangle is never read, so it need not be zero).  In place.
 hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                             const int2 *colwin, const int2 *rowwin, hipStream_t s)
 {
@@ -492,26 +512,22 @@ hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float
     const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
     const RadixPlan py = make_radix(p.ny, p.radix_y, p.nrad_y);
     const int rows = batch * p.ny;
-    const bool cols_first = colwin != nullptr || rowwin != nullptr;
-    if (cols_first && in != out) return hipErrorInvalidValue;  // the windowed form works in place
-    auto rows_pass = [&](const float2 *src, float2 *dst) {
-        if (direction > 0)
-            rows_launch<-1>(p, px, rows, src, dst, rowwin, s);
-        else
-            rows_launch<1>(p, px, rows, src, dst, rowwin, s);
-    };
-    auto cols_pass = [&](float2 *buf) {
-        if (direction > 0)
-            cols_launch<-1, false>(p, py, batch, buf, colwin, nullptr, s);
-        else
-            cols_launch<1, false>(p, py, batch, buf, colwin, nullptr, s);
-    };
-    if (cols_first) {
-        cols_pass(out);
-        rows_pass(out, out);
+    if (!colwin && rowwin) return hipErrorInvalidValue;
+    if (colwin && in != out) return hipErrorInvalidValue;  // the windowed form works in place
+    if (colwin) {
+        if (direction > 0) {
+            cols_launch<-1, false>(p, py, batch, out, colwin, nullptr, s, rowwin);
+            rows_launch<-1>(p, px, rows, out, out, colwin, s);
+        } else {
+            cols_launch<1, false>(p, py, batch, out, colwin, nullptr, s, rowwin);
+            rows_launch<1>(p, px, rows, out, out, colwin, s);
+        }
+    } else if (direction > 0) {
+        rows_launch<-1>(p, px, rows, in, out, nullptr, s);
+        cols_launch<-1, false>(p, py, batch, out, nullptr, nullptr, s);
     } else {
-        rows_pass(in, out);
-        cols_pass(out);
+        rows_launch<1>(p, px, rows, in, out, nullptr, s);
+        cols_launch<1, false>(p, py, batch, out, nullptr, nullptr, s);
     }
     return hipGetLastError();
 }
