@@ -162,3 +162,18 @@ def test_focal_stack_no_planes_and_bad_width(ctx):
     wide = Grid(5000, 16, 8e-6, 8e-6, (520e-9,))
     with pytest.raises(gws.GwsError):
         ctx.focal_stack(problem(wide), u, [0.0])
+
+
+def test_four_wavelengths(ctx):
+    """The display calls take up to four wavelengths (the problem's maximum)."""
+    lams = (638e-9, 560e-9, 520e-9, 450e-9)
+    g = Grid(80, 64, 8e-6, 8e-6, lams)
+    u = gwsgen.make_target(g, 3701)
+    got = to_numpy(ctx.dpac_encode(cuda(u))).astype(np.float64)
+    assert np.all(dp.phase_distance(got, dp.dpac_encode(u.astype(np.complex128))) <= phase_bound(u))
+    depths = (3e-3, -6e-3)
+    st = to_numpy(ctx.focal_stack(problem(g), cuda(u), depths))
+    ref = dp.focal_stack(u, g, depths)
+    worst = max(rel_l2(st[k], ref[k]) for k in range(len(depths)))
+    log("four wavelengths: focal stack worst rel L2 %.3g" % worst)
+    assert worst < TOL_FIELD
