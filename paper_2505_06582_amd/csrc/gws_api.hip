@@ -207,11 +207,8 @@ static int isqrt_floor(long long v)
 static void factor_radices(int n, int32_t *r, int32_t *nr)
 {
     int k = 0;
-    while (n % 8 == 0) { r[k++] = 8; n /= 8; }
-    while (n % 4 == 0) { r[k++] = 4; n /= 4; }
-    while (n % 2 == 0) { r[k++] = 2; n /= 2; }
-    while (n % 5 == 0) { r[k++] = 5; n /= 5; }
-    while (n % 3 == 0) { r[k++] = 3; n /= 3; }
+    for (const int f : {16, 8, 4, 2, 15, 9, 5, 3})
+        while (n % f == 0) { r[k++] = f; n /= f; }
     *nr = k;
 }
 

@@ -97,6 +97,83 @@ static __device__ __forceinline__ void dft8(float2 *v)
     v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
 }
 
+// Composite radices 9 = 3 x 3, 15 = 3 x 5 and 16 = 4 x 4, one Cooley-Tukey step in registers:
+// with n = R2 n1 + n2 and k = k1 + R1 k2, X[k] = DFT_R2 over n2 of W^(n2 k1) DFT_R1 over n1 of
+// x[R2 n1 + n2], W = exp(-S j 2 pi / R).  TwR<R> holds cos and sin of 2 pi m / R.
+template <int R> struct TwR;
+template <> struct TwR<9> {
+    static constexpr float c[9] = {1.0f, 0.76604444311897801f, 0.17364817766693041f, -0.5f, -0.93969262078590832f,
+                                   -0.93969262078590843f, -0.5f, 0.17364817766692997f, 0.76604444311897779f};
+    static constexpr float s[9] = {0.0f, 0.64278760968653925f, 0.98480775301220802f, 0.86602540378443871f,
+                                   0.34202014332566888f, -0.34202014332566866f, -0.86602540378443837f,
+                                   -0.98480775301220813f, -0.64278760968653958f};
+};
+template <> struct TwR<15> {
+    static constexpr float c[15] = {1.0f, 0.91354545764260087f, 0.66913060635885824f, 0.30901699437494745f,
+                                    -0.10452846326765333f, -0.5f, -0.80901699437494734f, -0.97814760073380569f,
+                                    -0.97814760073380569f, -0.80901699437494756f, -0.5f, -0.10452846326765423f,
+                                    0.30901699437494723f, 0.66913060635885846f, 0.91354545764260098f};
+    static constexpr float s[15] = {0.0f, 0.40673664307580015f, 0.74314482547739413f, 0.95105651629515353f,
+                                    0.9945218953682734f, 0.86602540378443871f, 0.58778525229247325f,
+                                    0.20791169081775931f, -0.20791169081775907f, -0.58778525229247303f,
+                                    -0.86602540378443837f, -0.99452189536827329f, -0.95105651629515364f,
+                                    -0.74314482547739402f, -0.40673664307580015f};
+};
+template <> struct TwR<16> {
+    static constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654757f, 0.38268343236508984f, 0.0f,
+                                    -0.38268343236508973f, -0.70710678118654746f, -0.92387953251128674f, -1.0f,
+                                    -0.92387953251128685f, -0.70710678118654768f, -0.38268343236509034f, 0.0f,
+                                    0.38268343236509f, 0.70710678118654735f, 0.92387953251128652f};
+    static constexpr float s[16] = {0.0f, 0.38268343236508978f, 0.70710678118654746f, 0.92387953251128674f, 1.0f,
+                                    0.92387953251128674f, 0.70710678118654757f, 0.38268343236508989f, 0.0f,
+                                    -0.38268343236508967f, -0.70710678118654746f, -0.92387953251128652f, -1.0f,
+                                    -0.92387953251128663f, -0.70710678118654768f, -0.38268343236509039f};
+};
+
+template <int S, int R> static __device__ __forceinline__ void dftR(float2 *v);
+
+template <int S, int R1, int R2>
+static __device__ __forceinline__ void dft_ct(float2 *v)
+{
+    constexpr int R = R1 * R2;
+    float2 a[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[R2 * n1 + n2];
+        dftR<S, R1>(a[n2]);
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < R2; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) {
+            const int m = n2 * k1;
+            a[n2][k1] = cmul(a[n2][k1], make_float2(TwR<R>::c[m], -(float)S * TwR<R>::s[m]));
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        float2 t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[n2][k1];
+        dftR<S, R2>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+}
+
+template <int S, int R>
+static __device__ __forceinline__ void dftR(float2 *v)
+{
+    if constexpr (R == 2) dft2<S>(v);
+    else if constexpr (R == 3) dft3<S>(v);
+    else if constexpr (R == 4) dft4<S>(v);
+    else if constexpr (R == 5) dft5<S>(v);
+    else if constexpr (R == 8) dft8<S>(v);
+    else if constexpr (R == 9) dft_ct<S, 3, 3>(v);
+    else if constexpr (R == 15) dft_ct<S, 3, 5>(v);
+    else if constexpr (R == 16) dft_ct<S, 4, 4>(v);
+}
+
 // j / d for j < 2^16 and 2 <= d <= 2^14: with m = floor((2^32 - 1) / d) + 1, umulhi(j, m) = j / d
 // exactly (the error j (m - 2^32/d) / 2^32 < 2^-16 is below the smallest non-zero fraction 1/d).
 // (d = 1 would need m = 2^32; callers handle it.)
@@ -145,11 +222,7 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
                 if (S < 0) t.y = -t.y;
                 v[q][r] = cmul(v[q][r], t);
             }
-            if (R == 2) dft2<S>(v[q]);
-            if (R == 3) dft3<S>(v[q]);
-            if (R == 4) dft4<S>(v[q]);
-            if (R == 5) dft5<S>(v[q]);
-            if (R == 8) dft8<S>(v[q]);
+            dftR<S, R>(v[q]);
             const int o = jq * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[lds_pad(o + r * Ns)] = v[q][r];
@@ -169,6 +242,9 @@ static __device__ void fft_row_lds(float2 *buf, const RadixPlan &pl, const float
         case 3: row_pass_inplace<3, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
         case 4: row_pass_inplace<4, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
         case 5: row_pass_inplace<5, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 9: row_pass_inplace<9, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 15: row_pass_inplace<15, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 16: row_pass_inplace<16, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
         default: row_pass_inplace<8, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
         }
         Ns *= R;
@@ -252,11 +328,7 @@ static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n,
                 if (S < 0) w.y = -w.y;
                 v[q][r] = cmul(v[q][r], w);
             }
-            if (R == 2) dft2<S>(v[q]);
-            if (R == 3) dft3<S>(v[q]);
-            if (R == 4) dft4<S>(v[q]);
-            if (R == 5) dft5<S>(v[q]);
-            if (R == 8) dft8<S>(v[q]);
+            dftR<S, R>(v[q]);
             const int o = jq * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[((o + r * Ns) << lb) + c] = v[q][r];
@@ -323,6 +395,9 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
         case 3: stockham_pass_inplace<3, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
         case 4: stockham_pass_inplace<4, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
         case 5: stockham_pass_inplace<5, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 9: stockham_pass_inplace<9, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 15: stockham_pass_inplace<15, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
+        case 16: stockham_pass_inplace<16, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
         default: stockham_pass_inplace<8, S, LDSB>(lds, n, lb, Ns, tw_s, threadIdx.x); break;
         }
         Ns *= R;
