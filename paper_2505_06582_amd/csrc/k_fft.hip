@@ -1,4 +1,4 @@
-// Mixed-radix (2, 3, 4, 5, 8) Stockham FFT in LDS for gfx950: the one inverse 2D transform
+// Mixed-radix (2, 3, 4, 5, 8, 9, 15, 16) Stockham FFT in LDS for gfx950: the one inverse 2D transform
 // that brings the accumulated spectrum to the SLM plane (supplement Alg. 1 and Alg. 4, last
 // step), and the forward transform the adjoint needs.  Unnormalised:
 //   direction +1:  out[n] = sum_m in[m] exp(+j 2 pi m n / N)
@@ -13,10 +13,13 @@ namespace gws {
 constexpr int FFT_THREADS = 256;
 constexpr int FFT_MAX_RAD = 16;
 
+// sh[b]: the LDS layout of a row between pass b - 1 and pass b (b = 0: as loaded, b = nrad:
+// as stored), element i at i + (i >> sh[b]); 31 is the plain layout.
 struct RadixPlan {
     int n;
     int nrad;
     int r[FFT_MAX_RAD];
+    int sh[FFT_MAX_RAD + 1];
 };
 
 static __device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -179,35 +182,52 @@ static __device__ __forceinline__ void dftR(float2 *v)
 // (d = 1 would need m = 2^32; callers handle it.)
 static __device__ __forceinline__ int div_small(int j, uint32_t m) { return (int)__umulhi((uint32_t)j, m); }
 
-// Row transforms keep one row in ONE padded LDS buffer (element i at lds_pad(i): one element
-// of padding every 16 spreads the early passes' strided stores over the banks) and run each
-// Stockham pass in place: every thread reads the inputs of its butterflies into registers,
-// the work-group synchronises, then every thread writes its outputs.  NPT bounds the row
-// elements per thread (n <= NPT * FFT_THREADS), so a radix-R pass holds at most
-// ceil(NPT / R) butterflies per thread; one buffer and few registers let eight work-groups
-// share a CU.
-static __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
-static __host__ __device__ constexpr int lds_padded_len(int n) { return n + (n >> 4) + 1; }
+// Row transforms keep one row in ONE LDS buffer and run each Stockham pass in place: every
+// thread reads the inputs of its butterflies into registers, the work-group synchronises,
+// then every thread writes its outputs.  NPT bounds the row elements per thread
+// (n <= NPT * FFT_THREADS), so a radix-R pass holds at most ceil(NPT / R) butterflies per
+// thread; one buffer and few registers let eight work-groups share a CU.
+//
+// Layouts.  Between two passes element i sits at i + (i >> s): one element of padding every
+// 2^s spreads the early passes' strided stores over the banks.  The host picks s per pass
+// boundary (make_radix) so that a butterfly's R inputs j + r nb, and its R outputs
+// o + r Ns, stay evenly spaced in LDS: each element then costs one add of a uniform offset
+// instead of a shift, an add and a multiply.
+static __device__ __forceinline__ int lds_at(int i, int s) { return i + (i >> s); }
+constexpr int FFT_MIN_PAD_SHIFT = 3;  // padding at most every 8 elements
+static __host__ __device__ constexpr int lds_padded_len(int n) { return n + (n >> FFT_MIN_PAD_SHIFT) + 1; }
+
+// tw + off bytes: a 32-bit offset from the table's uniform base
+static __device__ __forceinline__ float2 tw_at(const float2 *tw, uint32_t off)
+{
+    return *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(tw) + off);
+}
 
 template <int R, int S, int NPT>
 static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int Ns, const float2 *__restrict__ tw,
-                                                        int tid)
+                                                        int tid, int sr, int sw)
 {
     constexpr int KB = (NPT + R - 1) / R;
     asm volatile("" : "+v"(tid));  // addresses formed per pass, not hoisted out of the pass loop
     const int nb = n / R, tstep = n / (Ns * R);
+    const int rstr = nb + (nb >> sr), wstr = Ns + (Ns >> sw);
     const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
     float2 v[KB][R], w[KB][R - 1];
+    int o[KB];
     // the twiddles are fetched from memory before the barrier, so their latency overlaps it
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
         const int j = tid + q * FFT_THREADS;
+        o[q] = 0;
         if (j < nb) {
             const int jq = Ns > 1 ? div_small(j, mNs) : j, k = j - jq * Ns;
+            o[q] = jq * Ns * R + k;
+            const uint32_t kt8 = (uint32_t)(k * tstep) * 8u;  // < 8 n / R: 24 bits
 #pragma unroll
-            for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r * k * tstep];
+            for (int r = 1; r < R; ++r) w[q][r - 1] = tw_at(tw, __umul24((uint32_t)r, kt8));
+            const int a = lds_at(j, sr);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lds_pad(j + r * nb)];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[a + r * rstr];
         }
     }
     __syncthreads();
@@ -215,7 +235,6 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
     for (int q = 0; q < KB; ++q) {
         const int j = tid + q * FFT_THREADS;
         if (j < nb) {
-            const int jq = Ns > 1 ? div_small(j, mNs) : j, k = j - jq * Ns;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 float2 t = w[q][r - 1];
@@ -223,9 +242,9 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
                 v[q][r] = cmul(v[q][r], t);
             }
             dftR<S, R>(v[q]);
-            const int o = jq * Ns * R + k;
+            const int a = lds_at(o[q], sw);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lds_pad(o + r * Ns)] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[a + r * wstr] = v[q][r];
         }
     }
     __syncthreads();
@@ -236,16 +255,16 @@ static __device__ void fft_row_lds(float2 *buf, const RadixPlan &pl, const float
 {
     int Ns = 1;
     for (int p = 0; p < pl.nrad; ++p) {
-        const int R = pl.r[p];
+        const int R = pl.r[p], sr = pl.sh[p], sw = pl.sh[p + 1];
         switch (R) {
-        case 2: row_pass_inplace<2, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        case 3: row_pass_inplace<3, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        case 4: row_pass_inplace<4, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        case 5: row_pass_inplace<5, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        case 9: row_pass_inplace<9, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        case 15: row_pass_inplace<15, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        case 16: row_pass_inplace<16, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
-        default: row_pass_inplace<8, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x); break;
+        case 2: row_pass_inplace<2, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        case 3: row_pass_inplace<3, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        case 4: row_pass_inplace<4, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        case 5: row_pass_inplace<5, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        case 9: row_pass_inplace<9, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        case 15: row_pass_inplace<15, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        case 16: row_pass_inplace<16, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
+        default: row_pass_inplace<8, S, NPT>(buf, pl.n, Ns, tw, threadIdx.x, sr, sw); break;
         }
         Ns *= R;
     }
@@ -265,17 +284,18 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
     extern __shared__ float2 lds[];
     const int64_t row = blockIdx.x;
     const float2 *src = in + row * pl.n;
+    const int s0 = pl.sh[0], s1 = pl.sh[pl.nrad];
     if (colin) {
         const int2 w = colin[row / rows_per_img];
         for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS)
-            lds[lds_pad(i)] = win_pos(i, w, pl.n) < w.y ? src[i] : make_float2(0.0f, 0.0f);
+            lds[lds_at(i, s0)] = win_pos(i, w, pl.n) < w.y ? src[i] : make_float2(0.0f, 0.0f);
     } else {
-        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) lds[lds_pad(i)] = src[i];
+        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) lds[lds_at(i, s0)] = src[i];
     }
     __syncthreads();
     fft_row_lds<S, NPT>(lds, pl, tw);
     float2 *dst = out + row * pl.n;
-    for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) dst[i] = lds[lds_pad(i)];
+    for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) dst[i] = lds[lds_at(i, s1)];
 }
 
 // Column transforms.  A work-group of FFT_COL_THREADS owns columns [c0, c0 + B) of one image
@@ -304,15 +324,16 @@ static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n,
     // instead of being hoisted out of the pass loop for every radix (which spills them)
     asm volatile("" : "+v"(tid));
     const int B = 1 << lb, nb = n / R, total = nb << lb, tstep = n / (Ns * R);
+    const int rstr = nb << lb, wstr = Ns << lb;  // a butterfly's elements are evenly spaced
     const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
     float2 v[KMAX][R];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
         const int idx = tid + q * FFT_COL_THREADS;
         if (idx < total) {
-            const int j = idx >> lb, c = idx & (B - 1);
+            const int a = idx;  // (j << lb) + c with j = idx >> lb, c = idx & (B - 1)
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[((j + r * nb) << lb) + c];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[a + r * rstr];
         }
     }
     __syncthreads();
@@ -322,16 +343,17 @@ static __device__ __forceinline__ void stockham_pass_inplace(float2 *buf, int n,
         if (idx < total) {
             const int j = idx >> lb, c = idx & (B - 1);
             const int jq = Ns > 1 ? div_small(j, mNs) : j, k = j - jq * Ns;
+            const uint32_t kt8 = (uint32_t)(k * tstep) * 8u;  // < 8 n / R: 24 bits
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[r * k * tstep];
+                float2 w = tw_at(tw, __umul24((uint32_t)r, kt8));
                 if (S < 0) w.y = -w.y;
                 v[q][r] = cmul(v[q][r], w);
             }
             dftR<S, R>(v[q]);
-            const int o = jq * Ns * R + k;
+            const int a = ((jq * Ns * R + k) << lb) + c;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[((o + r * Ns) << lb) + c] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[a + r * wstr] = v[q][r];
         }
     }
     __syncthreads();
@@ -471,23 +493,42 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows_stack(const float2 *__
                     const float cs = __builtin_amdgcn_cosf(th) * sa.scale, sn = __builtin_amdgcn_sinf(th) * sa.scale;
                     v = make_float2(sv[j].x * cs - sv[j].y * sn, sv[j].x * sn + sv[j].y * cs);
                 }
-                lds[lds_pad(i)] = v;
+                lds[lds_at(i, pl.sh[0])] = v;
             }
         }
         __syncthreads();
         fft_row_lds<S, NPT>(lds, pl, tw);
         float2 *dst = planes + ((int64_t)(k * sa.C + c) * ny + y) * nx;
-        for (int i = threadIdx.x; i < nx; i += FFT_THREADS) dst[i] = lds[lds_pad(i)];
+        for (int i = threadIdx.x; i < nx; i += FFT_THREADS) dst[i] = lds[lds_at(i, pl.sh[pl.nrad])];
         __syncthreads();
     }
 }
 
+// The layout shift of each pass boundary b: the padding period P = 2^s must keep the outputs
+// of pass b - 1 evenly spaced (Ns a multiple of P, or the whole span Ns R of a butterfly
+// inside one period) and the inputs of pass b (n / R a multiple of P).  P = 16 is preferred
+// (it spreads a stride-16 store over the banks), then 8, else the plain layout.
 static RadixPlan make_radix(int n, const int32_t *r, int nrad)
 {
     RadixPlan p;
     p.n = n;
     p.nrad = nrad;
     for (int i = 0; i < FFT_MAX_RAD; ++i) p.r[i] = i < nrad ? r[i] : 0;
+    int Ns = 1;  // at boundary b >= 1: Ns of pass b - 1, the product r[0] ... r[b - 2]
+    for (int b = 0; b <= nrad; ++b) {
+        p.sh[b] = 31;
+        for (const int s : {4, FFT_MIN_PAD_SHIFT}) {
+            const int P = 1 << s;
+            const bool wr_ok = b == 0 || Ns % P == 0 || P % (Ns * r[b - 1]) == 0;
+            const bool rd_ok = b == nrad || (n / r[b]) % P == 0;
+            if (wr_ok && rd_ok) {
+                p.sh[b] = s;
+                break;
+            }
+        }
+        if (b >= 1) Ns *= r[b - 1];
+    }
+    for (int b = nrad + 1; b <= FFT_MAX_RAD; ++b) p.sh[b] = 31;
     return p;
 }
 
