@@ -141,13 +141,21 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
     const int64_t pix = (int64_t)py * nx + px;
     float T = in ? t_in[pix] : 1.0f;
     if (ckpt && in) ckpt[pix] = T;
-    // tile centre, for the work-group-uniform window test
+    // tile centre, for the work-group-uniform window test: lane b of every wavefront tests
+    // batch Gaussian b, and only the Gaussians whose window meets the tile are walked
     const float tcx = tx * EXACT_TILE + 7.5f, tcy = ty * EXACT_TILE + 7.5f;
-    for (int b = 0; b < nb; ++b) {
-        const ERec &r = s_rec[b];
+    const int lane = threadIdx.x & 63;
+    bool meets = false;
+    if (lane < nb) {
+        const ERec &r = s_rec[lane];
         const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
-        const bool hit = r.hwx >= 0 && dcx <= (float)r.hwx + 8.5f && dcy <= (float)r.hwy + 8.5f;
-        if (hit) {
+        meets = r.hwx >= 0 && dcx <= (float)r.hwx + 8.5f && dcy <= (float)r.hwy + 8.5f;
+    }
+    const uint64_t hits = __ballot(meets);
+    for (uint64_t mk = hits; mk; mk &= mk - 1) {
+        const int b = __builtin_ctzll(mk);
+        const ERec &r = s_rec[b];
+        {
             float2 v = make_float2(0.0f, 0.0f);
             const float dx = wrap_d((float)px - r.cx, (float)nx), dy = wrap_d((float)py - r.cy, (float)ny);
             if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {  // the profile's window
@@ -302,7 +310,9 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
                                                       const float2 *__restrict__ gspec, float2 *__restrict__ imgs,
                                                       float *__restrict__ part)
 {
-    __shared__ float s_red[4][16];
+    // per wave and batch Gaussian, the wave's 12 sums: the four waves are summed in a fixed
+    // order once, after the batch, so the waves never wait for each other inside it
+    __shared__ float s_red[4][64][16];
     const int64_t M = (int64_t)k.nx * k.ny;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t mi[EXACT_GS_PER];
@@ -372,15 +382,15 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
         reduce_transposed<16, false>(x, unused, lane);
         if ((lane & 7) == 0) {
             const int v0 = 2 * (((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1));
-            s_red[wave][v0] = x[0];
-            s_red[wave][v0 + 1] = x[1];
+            s_red[wave][b][v0] = x[0];
+            s_red[wave][b][v0 + 1] = x[1];
         }
-        __syncthreads();
-        if (threadIdx.x < EXACT_NSPEC) {
-            const float t = s_red[0][threadIdx.x] + s_red[1][threadIdx.x] + s_red[2][threadIdx.x] + s_red[3][threadIdx.x];
-            part[((int64_t)blockIdx.x * 64 + b) * EXACT_NSPEC + threadIdx.x] = t;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb * EXACT_NSPEC; i += blockDim.x) {
+        const int b = i / EXACT_NSPEC, v = i - b * EXACT_NSPEC;
+        const float t = s_red[0][b][v] + s_red[1][b][v] + s_red[2][b][v] + s_red[3][b][v];
+        part[((int64_t)blockIdx.x * 64 + b) * EXACT_NSPEC + v] = t;
     }
 }
 
@@ -405,33 +415,41 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
     const int64_t pix = (int64_t)py * nx + px;
     const float tcx = tx * EXACT_BTILE + 3.5f, tcy = ty * EXACT_BTILE + 3.5f;
     const float fx = (float)px, fy = (float)py;
+    // the batch Gaussians whose window meets this tile (lane b tests Gaussian b); the others
+    // leave the map, D and their partial sums (zero) unchanged here
+    bool meets = false;
+    if (lane < nb) {
+        const ERec &r = s_rec[lane];
+        const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
+        meets = r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f;
+    }
+    const uint64_t hits = __ballot(meets);
+    const int64_t tile = (int64_t)ty * ntx + tx;
+    for (int i = lane; i < nb * EXACT_NSPAT; i += 64)
+        if (!((hits >> (i / EXACT_NSPAT)) & 1)) part[tile * 64 * EXACT_NSPAT + i] = 0.0f;
     // forward replay of the map over the batch
     float T = in ? tck[pix] : 1.0f;
-    for (int b = 0; b < nb; ++b) {
+    for (uint64_t m = hits; m; m &= m - 1) {
+        const int b = __builtin_ctzll(m);
         s_T[b][lane] = T;
         const ERec &r = s_rec[b];
-        const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
-        if (r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f) {
-            const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
-            if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {
-                const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
-                const float alpha = r.o * gk;
-                if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
-            }
+        const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
+        if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {
+            const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
+            const float alpha = r.o * gk;
+            if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
         }
     }
     // back to front
     const float ln2x2 = 2.0f * 0.69314718055994531f;
     float D = in ? dmap[pix] : 0.0f;
-    const int64_t tile = (int64_t)ty * ntx + tx;
-    for (int b = nb - 1; b >= 0; --b) {
+    for (uint64_t m = hits; m; m &= ~(1ull << (63 - __builtin_clzll(m)))) {
+        const int b = 63 - __builtin_clzll(m);
         const ERec &r = s_rec[b];
-        const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
-        const bool hit = r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f;
         float v[EXACT_NSPAT];
 #pragma unroll
         for (int i = 0; i < EXACT_NSPAT; ++i) v[i] = 0.0f;
-        if (hit) {
+        {
             const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
             if (in && fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {
                 const float Tb = s_T[b][lane];
