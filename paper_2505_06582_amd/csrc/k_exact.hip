@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
     for (int i = threadIdx.x; i < nb * EXACT_NSPEC; i += blockDim.x) {
         const int b = i / EXACT_NSPEC, v = i - b * EXACT_NSPEC;
         const float t = s_red[0][b][v] + s_red[1][b][v] + s_red[2][b][v] + s_red[3][b][v];
-        part[((int64_t)blockIdx.x * 64 + b) * EXACT_NSPEC + v] = t;
+        part[((int64_t)b * gridDim.x + blockIdx.x) * EXACT_NSPEC + v] = t;  // Gaussian-major
     }
 }
 
@@ -424,9 +424,12 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
         meets = r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f;
     }
     const uint64_t hits = __ballot(meets);
-    const int64_t tile = (int64_t)ty * ntx + tx;
-    for (int i = lane; i < nb * EXACT_NSPAT; i += 64)
-        if (!((hits >> (i / EXACT_NSPAT)) & 1)) part[tile * 64 * EXACT_NSPAT + i] = 0.0f;
+    // partial sums Gaussian-major: part[b][tile][8]
+    const int64_t tile = (int64_t)ty * ntx + tx, ntiles = (int64_t)ntx * gridDim.y;
+    for (int i = lane; i < nb * EXACT_NSPAT; i += 64) {
+        const int b = i / EXACT_NSPAT;
+        if (!((hits >> b) & 1)) part[((int64_t)b * ntiles + tile) * EXACT_NSPAT + (i - b * EXACT_NSPAT)] = 0.0f;
+    }
     // forward replay of the map over the batch
     float T = in ? tck[pix] : 1.0f;
     for (uint64_t m = hits; m; m &= m - 1) {
@@ -482,7 +485,7 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
         }
         if ((lane & 7) == 0) {
             const int i = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-            part[(tile * 64 + b) * EXACT_NSPAT + i] = v[0];
+            part[((int64_t)b * ntiles + tile) * EXACT_NSPAT + i] = v[0];
         }
     }
     if (in) dmap[pix] = D;
@@ -501,10 +504,10 @@ __global__ void __launch_bounds__(256) k_exact_gfinal(const ERec *__restrict__ r
     for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) acc[i] = 0.0;
     for (int q = t; q < nblk_spec; q += 256)
 #pragma unroll
-        for (int i = 0; i < EXACT_NSPEC; ++i) acc[i] += (double)pspec[((int64_t)q * 64 + b) * EXACT_NSPEC + i];
+        for (int i = 0; i < EXACT_NSPEC; ++i) acc[i] += (double)pspec[((int64_t)b * nblk_spec + q) * EXACT_NSPEC + i];
     for (int q = t; q < ntile; q += 256)
 #pragma unroll
-        for (int i = 0; i < EXACT_NSPAT; ++i) acc[EXACT_NSPEC + i] += (double)pspat[((int64_t)q * 64 + b) * EXACT_NSPAT + i];
+        for (int i = 0; i < EXACT_NSPAT; ++i) acc[EXACT_NSPEC + i] += (double)pspat[((int64_t)b * ntile + q) * EXACT_NSPAT + i];
 #pragma unroll
     for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) {
         double v = acc[i];
@@ -515,13 +518,16 @@ __global__ void __launch_bounds__(256) k_exact_gfinal(const ERec *__restrict__ r
     __syncthreads();
     if (t != 0) return;
     double S[EXACT_NSPEC + EXACT_NSPAT];
+#pragma unroll
     for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) S[i] = s_red[0][i] + s_red[1][i] + s_red[2][i] + s_red[3][i];
     const ERec &r = rec[b0 + b];
     const int64_t j = order[b0 + b];
     const double inv = 1.0 / ((double)k.nx * k.ny);
     double d_o = S[EXACT_NSPEC + 6], d_z = 0.0;
     const double o = g.opacity[j];
-    for (int c = 0; c < k.C && c < 3; ++c) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (c >= k.C) break;
         const double a = g.amplitude[(int64_t)c * g.amp_stride + j];
         const double rp = S[4 * c + 0] * inv, iq = S[4 * c + 3] * inv;
         if (out.amplitude) out.amplitude[(int64_t)c * out.amp_stride + j] = r.valid ? (float)(o * rp) : 0.0f;
