@@ -203,16 +203,38 @@ static __device__ __forceinline__ float2 tw_at(const float2 *tw, uint32_t off)
     return *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(tw) + off);
 }
 
+// Twiddles of a butterfly: only W^1, W^2, W^4, W^8 (those below R) are fetched, before the
+// barrier; W^r for other r is the product of the fetched powers in r's binary expansion (at
+// most three complex products, a few ulp).  Fewer registers held across the barrier let more
+// rows share a CU.
+#ifndef GWS_FFT_TW_POW
+#define GWS_FFT_TW_POW 1
+#endif
+template <int R> struct TwPow {
+    static constexpr int NP = R <= 2 ? 1 : (R <= 4 ? 2 : (R <= 8 ? 3 : 4));
+};
+template <int R>
+static __device__ __forceinline__ void twiddle_powers(const float2 *wp, float2 *wr)
+{
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const int hb = 1 << (31 - __builtin_clz(r));
+        if (hb == r) wr[r] = wp[__builtin_ctz(r)];
+        else wr[r] = cmul(wr[hb], wr[r - hb]);
+    }
+}
+
 template <int R, int S, int NPT>
 static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int Ns, const float2 *__restrict__ tw,
                                                         int tid, int sr, int sw)
 {
     constexpr int KB = (NPT + R - 1) / R;
+    constexpr int NW = GWS_FFT_TW_POW ? TwPow<R>::NP : R - 1;
     asm volatile("" : "+v"(tid));  // addresses formed per pass, not hoisted out of the pass loop
     const int nb = n / R, tstep = n / (Ns * R);
     const int rstr = nb + (nb >> sr), wstr = Ns + (Ns >> sw);
     const uint32_t mNs = Ns > 1 ? 0xffffffffu / (uint32_t)Ns + 1u : 0u;  // Ns = 1: quotient is j itself
-    float2 v[KB][R], w[KB][R - 1];
+    float2 v[KB][R], w[KB][NW];
     int o[KB];
     // the twiddles are fetched from memory before the barrier, so their latency overlaps it
 #pragma unroll
@@ -224,7 +246,8 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
             o[q] = jq * Ns * R + k;
             const uint32_t kt8 = (uint32_t)(k * tstep) * 8u;  // < 8 n / R: 24 bits
 #pragma unroll
-            for (int r = 1; r < R; ++r) w[q][r - 1] = tw_at(tw, __umul24((uint32_t)r, kt8));
+            for (int i = 0; i < NW; ++i)
+                w[q][i] = tw_at(tw, __umul24(GWS_FFT_TW_POW ? (1u << i) : (uint32_t)(i + 1), kt8));
             const int a = lds_at(j, sr);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = buf[a + r * rstr];
@@ -235,9 +258,16 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
     for (int q = 0; q < KB; ++q) {
         const int j = tid + q * FFT_THREADS;
         if (j < nb) {
+            float2 wr[R];
+            if (GWS_FFT_TW_POW) {
+                twiddle_powers<R>(w[q], wr);
+            } else {
+#pragma unroll
+                for (int r = 1; r < R; ++r) wr[r] = w[q][r - 1];
+            }
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 t = w[q][r - 1];
+                float2 t = wr[r];
                 if (S < 0) t.y = -t.y;
                 v[q][r] = cmul(v[q][r], t);
             }
