@@ -199,18 +199,26 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
         w[c] = prop[c] ? sqrt(w2) : 0.0;
         acc[c] = c < k.C ? spec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
     }
+    // the next Gaussian's spectrum value is fetched while this one is applied
+    float2 Sn = nb > 0 ? imgs[m] : make_float2(0.0f, 0.0f);
     for (int b = 0; b < nb; ++b) {
-        const ERec &r = rec[b0 + b];
-        if (!r.valid) continue;
-        const float2 S = imgs[(int64_t)b * M + m];
-        const double zd = (double)r.z;
+        const float2 S = Sn;
+        if (b + 1 < nb) Sn = imgs[(int64_t)(b + 1) * M + m];
+        const ERec &rr = rec[b0 + b];
+        // the fields used below, loaded together
+        const int valid = rr.valid;
+        const float rz = rr.z;
+        const float4 ramp = *reinterpret_cast<const float4 *>(rr.amp);
+        if (!valid) continue;
+        const float ampc[4] = {ramp.x, ramp.y, ramp.z, ramp.w};
+        const double zd = (double)rz;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!prop[c]) continue;
             const double ph = -zd * w[c];  // revolutions of H(nu, -z)
             const float t = (float)(ph - floor(ph));
             const float cs = __builtin_amdgcn_cosf(t), sn = __builtin_amdgcn_sinf(t);
-            const float A = r.amp[c] * scale;
+            const float A = ampc[c] * scale;
             const float hr = A * cs, hi = A * sn;
             acc[c].x = fmaf(hr, S.x, fmaf(-hi, S.y, acc[c].x));
             acc[c].y = fmaf(hr, S.y, fmaf(hi, S.x, acc[c].y));
@@ -340,17 +348,32 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
             gs[q][c] = (live[q] && c < k.C) ? gspec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
         }
     }
+    // the next Gaussian's spectrum values are fetched while this one is applied
+    float2 Fn[EXACT_GS_PER];
+#pragma unroll
+    for (int q = 0; q < EXACT_GS_PER; ++q) Fn[q] = (live[q] && nb > 0) ? imgs[mi[q]] : make_float2(0.0f, 0.0f);
     for (int b = 0; b < nb; ++b) {
-        const ERec &r = rec[b0 + b];
+        float2 Fb[EXACT_GS_PER];
+#pragma unroll
+        for (int q = 0; q < EXACT_GS_PER; ++q) {
+            Fb[q] = Fn[q];
+            if (live[q] && b + 1 < nb) Fn[q] = imgs[(int64_t)(b + 1) * M + mi[q]];
+        }
+        const ERec &rr = rec[b0 + b];
+        // the fields used below, loaded together
+        const int valid = rr.valid;
+        const float rz = rr.z;
+        const float4 ramp = *reinterpret_cast<const float4 *>(rr.amp);
+        const float ampc[4] = {ramp.x, ramp.y, ramp.z, ramp.w};
         float v[EXACT_NSPEC];
 #pragma unroll
         for (int i = 0; i < EXACT_NSPEC; ++i) v[i] = 0.0f;
-        const double zd = (double)r.z;
+        const double zd = (double)rz;
 #pragma unroll
         for (int q = 0; q < EXACT_GS_PER; ++q) {
             float2 V = make_float2(0.0f, 0.0f);
-            if (live[q] && r.valid) {
-                const float2 F = imgs[(int64_t)b * M + mi[q]];
+            if (live[q] && valid) {
+                const float2 F = Fb[q];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (!prop[q][c]) continue;
@@ -366,7 +389,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
                     v[4 * c + 2] = fmaf(wf, xr, v[4 * c + 2]);
                     v[4 * c + 3] = fmaf(wf, xi, v[4 * c + 3]);
                     // V += A_c Gs conj(H)
-                    const float A = r.amp[c];
+                    const float A = ampc[c];
                     V.x = fmaf(A, gs[q][c].x * hc + gs[q][c].y * hs, V.x);
                     V.y = fmaf(A, gs[q][c].y * hc - gs[q][c].x * hs, V.y);
                 }
