@@ -206,10 +206,7 @@ static __device__ __forceinline__ float2 tw_at(const float2 *tw, uint32_t off)
 // Twiddles of a butterfly: only W^1, W^2, W^4, W^8 (those below R) are fetched, before the
 // barrier; W^r for other r is the product of the fetched powers in r's binary expansion (at
 // most three complex products, a few ulp).  Fewer registers held across the barrier let more
-// rows share a CU.
-#ifndef GWS_FFT_TW_POW
-#define GWS_FFT_TW_POW 1
-#endif
+// rows share a CU (59 VGPRs instead of 71 with all R - 1 fetched: eight rows per CU, not seven).
 template <int R> struct TwPow {
     static constexpr int NP = R <= 2 ? 1 : (R <= 4 ? 2 : (R <= 8 ? 3 : 4));
 };
@@ -229,7 +226,7 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
                                                         int tid, int sr, int sw)
 {
     constexpr int KB = (NPT + R - 1) / R;
-    constexpr int NW = GWS_FFT_TW_POW ? TwPow<R>::NP : R - 1;
+    constexpr int NW = TwPow<R>::NP;
     asm volatile("" : "+v"(tid));  // addresses formed per pass, not hoisted out of the pass loop
     const int nb = n / R, tstep = n / (Ns * R);
     const int rstr = nb + (nb >> sr), wstr = Ns + (Ns >> sw);
@@ -247,7 +244,7 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
             const uint32_t kt8 = (uint32_t)(k * tstep) * 8u;  // < 8 n / R: 24 bits
 #pragma unroll
             for (int i = 0; i < NW; ++i)
-                w[q][i] = tw_at(tw, __umul24(GWS_FFT_TW_POW ? (1u << i) : (uint32_t)(i + 1), kt8));
+                w[q][i] = tw_at(tw, __umul24(1u << i, kt8));
             const int a = lds_at(j, sr);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = buf[a + r * rstr];
@@ -259,12 +256,7 @@ static __device__ __forceinline__ void row_pass_inplace(float2 *buf, int n, int 
         const int j = tid + q * FFT_THREADS;
         if (j < nb) {
             float2 wr[R];
-            if (GWS_FFT_TW_POW) {
-                twiddle_powers<R>(w[q], wr);
-            } else {
-#pragma unroll
-                for (int r = 1; r < R; ++r) wr[r] = w[q][r - 1];
-            }
+            twiddle_powers<R>(w[q], wr);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 float2 t = wr[r];
