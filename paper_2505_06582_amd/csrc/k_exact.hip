@@ -169,7 +169,8 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
             if (imgs && in) {
                 int2 cw, rw;
                 window_rect(r, nx, ny, cw, rw);
-                const int ex = ((px - cw.x) % nx + nx) % nx, ey = ((py - rw.x) % ny + ny) % ny;
+                // px, py and the window starts lie in [0, n): one wrap at most
+                const int ex = px - cw.x + (px < cw.x ? nx : 0), ey = py - rw.x + (py < rw.x ? ny : 0);
                 if (ex < cw.y && ey < rw.y) imgs[(int64_t)b * M + pix] = v;
             }
         }

@@ -293,8 +293,12 @@ static __device__ void fft_row_lds(float2 *buf, const RadixPlan &pl, const float
 }
 
 // Position d of index v inside the periodic window w = (start, len) of an axis of length n;
-// inside when d < len.
-static __device__ __forceinline__ int win_pos(int v, int2 w, int n) { return ((v - w.x) % n + n) % n; }
+// inside when d < len.  Both v and the start lie in [0, n).
+static __device__ __forceinline__ int win_pos(int v, int2 w, int n)
+{
+    const int d = v - w.x;
+    return d < 0 ? d + n : d;
+}
 
 // Row transforms: one row per work-group.  in/out: [rows][n].  With colin, each image's
 // input is nonzero only in its window of columns: the others are read as zero, not loaded.
