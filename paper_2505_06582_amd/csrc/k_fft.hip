@@ -302,10 +302,12 @@ static __device__ __forceinline__ int win_pos(int v, int2 w, int n)
 
 // Row transforms: one row per work-group.  in/out: [rows][n].  With colin, each image's
 // input is nonzero only in its window of columns: the others are read as zero, not loaded.
+// With colout, only each image's window of columns is stored.
 template <int S, int NPT>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                           RadixPlan pl, const float2 *__restrict__ tw,
-                                                          const int2 *__restrict__ colin, int rows_per_img)
+                                                          const int2 *__restrict__ colin,
+                                                          const int2 *__restrict__ colout, int rows_per_img)
 {
     extern __shared__ float2 lds[];
     const int64_t row = blockIdx.x;
@@ -321,7 +323,13 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
     __syncthreads();
     fft_row_lds<S, NPT>(lds, pl, tw);
     float2 *dst = out + row * pl.n;
-    for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) dst[i] = lds[lds_at(i, s1)];
+    if (colout) {
+        const int2 w = colout[row / rows_per_img];
+        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS)
+            if (win_pos(i, w, pl.n) < w.y) dst[i] = lds[lds_at(i, s1)];
+    } else {
+        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) dst[i] = lds[lds_at(i, s1)];
+    }
 }
 
 // Column transforms.  A work-group of FFT_COL_THREADS owns columns [c0, c0 + B) of one image
@@ -408,9 +416,9 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
     const int nslab = (width + B - 1) / B;
     const int64_t img = blk / nslab;
     const int c0 = (blk - (int)(img * nslab)) * B;
-    // colwin: only the slabs meeting each image's window of columns are transformed.  rowin
-    // (input support): the image is nonzero only inside colwin x rowin; what lies outside is
-    // read as zero, not loaded.
+    // colwin: only the slabs meeting each image's window of columns are transformed, and only
+    // the window's columns are loaded (the others are read as zero) and stored.  rowin (input
+    // support): the image is also zero outside that window of rows, which is not loaded.
     if (colwin) {
         const int2 w = colwin[img];
         const int d = ((c0 - w.x) % width + width) % width;
@@ -421,8 +429,9 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
     const int bw = min(B, width - c0);
     const float2 *src = in + img * (int64_t)n * width;
     float2 *dst = out + img * (int64_t)n * width;
-    if (rowin) {
-        const int2 wc = colwin[img], wr = rowin[img];
+    const int2 wc = colwin ? colwin[img] : make_int2(0, width);
+    if (colwin) {
+        const int2 wr = rowin ? rowin[img] : make_int2(0, n);
         for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
             const int r = i >> lb, c = i & (B - 1);
             const bool live = c < bw && win_pos(c0 + c, wc, width) < wc.y && win_pos(r, wr, n) < wr.y;
@@ -455,12 +464,12 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
         for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
             const int r = i >> lb, c = i & (B - 1);
             const float2 v = lds[i];
-            if (c < bw) dstf[(int64_t)r * width + c0 + c] = fmaf(v.x, v.x, v.y * v.y);
+            if (c < bw && win_pos(c0 + c, wc, width) < wc.y) dstf[(int64_t)r * width + c0 + c] = fmaf(v.x, v.x, v.y * v.y);
         }
     } else {
         for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
             const int r = i >> lb, c = i & (B - 1);
-            if (c < bw) dst[(int64_t)r * width + c0 + c] = lds[i];
+            if (c < bw && win_pos(c0 + c, wc, width) < wc.y) dst[(int64_t)r * width + c0 + c] = lds[i];
         }
     }
 }
@@ -604,21 +613,21 @@ static void allow_big_lds()
 // Row passes: the smallest elements-per-thread bound that covers n.
 template <int S>
 static void rows_launch(const Plan &p, const RadixPlan &px, int rows, const float2 *src, float2 *dst,
-                        const int2 *colin, hipStream_t s)
+                        const int2 *colin, hipStream_t s, const int2 *colout = nullptr)
 {
     const size_t lds = (size_t)lds_padded_len(p.nx) * sizeof(float2);
     const int npt = (p.nx + FFT_THREADS - 1) / FFT_THREADS;
     const dim3 g(rows), b(FFT_THREADS);
     if (npt <= 2)
-        hipLaunchKernelGGL((k_fft_rows<S, 2>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 2>), g, b, lds, s, src, dst, px, p.tw_x, colin, colout, p.ny);
     else if (npt <= 4)
-        hipLaunchKernelGGL((k_fft_rows<S, 4>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 4>), g, b, lds, s, src, dst, px, p.tw_x, colin, colout, p.ny);
     else if (npt <= 8)
-        hipLaunchKernelGGL((k_fft_rows<S, 8>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 8>), g, b, lds, s, src, dst, px, p.tw_x, colin, colout, p.ny);
     else if (npt <= 16)
-        hipLaunchKernelGGL((k_fft_rows<S, 16>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 16>), g, b, lds, s, src, dst, px, p.tw_x, colin, colout, p.ny);
     else
-        hipLaunchKernelGGL((k_fft_rows<S, 32>), g, b, lds, s, src, dst, px, p.tw_x, colin, p.ny);
+        hipLaunchKernelGGL((k_fft_rows<S, 32>), g, b, lds, s, src, dst, px, p.tw_x, colin, colout, p.ny);
 }
 
 // One column pass over nimg images [ny][nx] in place (or, with intensity, |x|^2 to it).
@@ -644,9 +653,9 @@ hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *i
 }
 
 // Rows then columns.  With windows, the input of each image is nonzero only inside its
-// rectangle colwin x rowwin (rowwin may be NULL: all rows): columns first, only the slabs
-// meeting colwin, loading only the rectangle; then every row, loading only colwin's columns
-// (what lies outside the rectangle is never read, so it need not be zero).  In place.
+// rectangle colwin x rowwin (rowwin may be NULL: all rows): columns first, only colwin's
+// columns, loading only the rectangle; then every row, loading only colwin's columns (what
+// lies outside the rectangle is never read, so it need not be zero).  In place.
 hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                             const int2 *colwin, const int2 *rowwin, hipStream_t s)
 {
@@ -674,8 +683,8 @@ hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float
     return hipGetLastError();
 }
 
-// Rows first over every row, then only the column slabs that meet colwin (the output is
-// wanted only in those columns; the others are left unfinished).  In place.
+// Rows first over every row, storing only colwin's columns, then only those columns (the
+// output is wanted only there; the others are left unfinished).  In place.
 hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int2 *colwin,
                                  hipStream_t s)
 {
@@ -683,10 +692,10 @@ hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2
     const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
     const RadixPlan py = make_radix(p.ny, p.radix_y, p.nrad_y);
     if (direction > 0) {
-        rows_launch<-1>(p, px, batch * p.ny, buf, buf, nullptr, s);
+        rows_launch<-1>(p, px, batch * p.ny, buf, buf, nullptr, s, colwin);
         cols_launch<-1, false>(p, py, batch, buf, colwin, nullptr, s);
     } else {
-        rows_launch<1>(p, px, batch * p.ny, buf, buf, nullptr, s);
+        rows_launch<1>(p, px, batch * p.ny, buf, buf, nullptr, s, colwin);
         cols_launch<1, false>(p, py, batch, buf, colwin, nullptr, s);
     }
     return hipGetLastError();
