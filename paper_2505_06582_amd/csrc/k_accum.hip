@@ -281,9 +281,23 @@ __global__ void __launch_bounds__(WG) k_reduce_partials(Consts k, const int32_t 
         const bool valid = mxp >= -hx && mxp < hx && myp >= -hy && myp < hy;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
+            // slots summed in order; eight loads are issued before their adds
+            const float2 *src = partials + (((int64_t)ts.y * C + c) * F + f) * WG + tid;
+            const int64_t stride = (int64_t)C * F * WG;
             float2 s = make_float2(0.0f, 0.0f);
-            for (int j = 0; j < ts.x; ++j) {
-                const float2 v = partials[(((int64_t)(ts.y + j) * C + c) * F + f) * WG + tid];
+            int j = 0;
+            for (; j + 8 <= ts.x; j += 8) {
+                float2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = src[(j + u) * stride];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    s.x += v[u].x;
+                    s.y += v[u].y;
+                }
+            }
+            for (; j < ts.x; ++j) {
+                const float2 v = src[j * stride];
                 s.x += v.x;
                 s.y += v.y;
             }
