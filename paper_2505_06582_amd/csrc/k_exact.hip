@@ -311,8 +311,9 @@ constexpr int EXACT_BTILE = 8;          // 8 x 8 pixels: one wavefront per work-
 constexpr int EXACT_NSPEC = 12;         // Re/Im P_c, Re/Im Q_c for c < 3
 constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, Sphi, So, pad
 
-// Four frequencies per thread (strided by the work-group size): spectral partial sums per
-// (work-group, Gaussian) and, in place of F_k, V_k = sum_c A_c Gs_c conj(H_c).
+// Two frequencies per thread (strided by the work-group size; few enough registers for eight
+// wavefronts per SIMD): spectral partial sums per (work-group, Gaussian) and, in place of
+// F_k, V_k = sum_c A_c Gs_c conj(H_c).
 constexpr int EXACT_GS_PER = 2;
 
 __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ rec, int b0, int nb, Consts k,

@@ -179,6 +179,26 @@ def test_exact_backward_matches_oracle(ctx, n, grid, seed):
         assert err < TOL_EXACT_GRAD, k
 
 
+def test_exact_backward_wraps_around_the_grid_edge(ctx):
+    """Gradients when every window wraps around both grid edges, over two batches: the
+    windowed transforms load and store only the windows' (wrapped) columns and rows."""
+    import torch
+    import paper_2505_06582_amd as gws
+    import oracle.exact_grad as eg
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    s = clustered_scene(70, grid, 2204)
+    s.mean_x[:] = (s.mean_x + np.float32(0.5 * grid.nx * grid.px)).astype(np.float32)
+    s.mean_y[:] = (s.mean_y + np.float32(0.5 * grid.ny * grid.py)).astype(np.float32)
+    t = gwsgen.make_target(grid, 2254) * 0.05
+    _, u, ref = eg.exact_loss_grads(s, grid, t)
+    G = torch.from_numpy((2.0 * (u - t)).astype(np.complex64)).cuda()
+    got = ctx.backward(problem(grid, blend=gws.BLEND_EXACT), scene_to_torch(s), G, want_depth=True)
+    for k in eg.PARAMS:
+        err = rel_l2(to_numpy(got[k]).astype(np.float64), np.asarray(ref[k]))
+        log("  wrap %-10s rel L2 %.3g" % (k, err))
+        assert err < TOL_EXACT_GRAD, k
+
+
 @pytest.mark.parametrize("blend", ["oit", "exact"])
 def test_render_autograd_matches_oracle(ctx, blend):
     """The torch.autograd.Function path (render + loss.backward) for both blending models."""
