@@ -47,6 +47,36 @@ def test_fft_matches_numpy_both_directions(ctx, ny, nx, batch):
     assert rel_l2(fwd, np.fft.fft2(xd)) < 2e-6
 
 
+def _sizes_235(lo, hi):
+    out = []
+    for n in range(lo, hi + 1, 2):
+        m = n
+        for f in (2, 3, 5):
+            while m % f == 0:
+                m //= f
+        if m == 1:
+            out.append(n)
+    return out
+
+
+def test_fft_every_length(ctx):
+    """Every even length 16..8192 with factors 2, 3, 5 as a row length and as a column length:
+    each radix order and each LDS layout the plans choose, in both directions."""
+    import torch
+    sizes = _sizes_235(16, 8192)
+    worst = 0.0
+    for n in sizes:
+        for ny, nx in ((16, n), (n, 16)):
+            x = gwsgen.make_target(Grid(nx, ny, 8e-6, 8e-6, (520e-9,)), 1000 + n)
+            xt = torch.from_numpy(x).cuda()
+            xd = x.astype(np.complex128)
+            e1 = rel_l2(to_numpy(ctx.dft2d(xt, +1)), np.fft.ifft2(xd) * (nx * ny))
+            e2 = rel_l2(to_numpy(ctx.dft2d(xt, -1)), np.fft.fft2(xd))
+            worst = max(worst, e1, e2)
+            assert e1 < 2e-6 and e2 < 2e-6, (ny, nx, e1, e2)
+    log("fft: %d lengths as rows and columns, worst rel L2 %.3g" % (len(sizes), worst))
+
+
 def run_forward(ctx, scene, grid, **kw):
     f, s = ctx.forward(problem(grid, **kw), scene_to_torch(scene), want_spectrum=True)
     return to_numpy(f), to_numpy(s)
