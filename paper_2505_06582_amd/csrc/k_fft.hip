@@ -4,7 +4,7 @@
 //   direction +1:  out[n] = sum_m in[m] exp(+j 2 pi m n / N)
 //   direction -1:  out[n] = sum_m in[m] exp(-j 2 pi m n / N)
 // Pass 1 transforms rows (one row per work-group); pass 2 transforms columns, a slab of
-// B adjacent columns per work-group, read and written as whole-cache-line row segments.
+// B adjacent columns per work-group, read and written as contiguous row segments.
 // Twiddles come from per-size FP32 tables computed on the host in FP64.
 #include "gws_internal.h"
 
