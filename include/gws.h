@@ -206,7 +206,8 @@ gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *problem, int32_
 /* Unnormalised 2D DFT of `batch` complex64 arrays [ny][nx] (in and out may alias):
  * direction +1: out[n] = sum_m in[m] exp(+j 2 pi m.n/N); -1: exp(-j 2 pi ...).
  * xform selects the FP32 FFT or the split-bf16 matrix-core DFT.  workspace may be NULL
- * for the FFT; the bf16 DFT needs gws_dft_workspace_size bytes. */
+ * for the FFT; the bf16 DFT needs gws_dft_workspace_size bytes.  nx, ny as for a problem;
+ * batch >= 1 with batch * max(nx, ny) < 2^31 (else GWS_ERR_SHAPE). */
 gws_status gws_dft_workspace_size(const gws_ctx *ctx, int32_t nx, int32_t ny, int32_t batch,
                                   int32_t xform, size_t *bytes);
 gws_status gws_dft2d(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t batch, int32_t direction,

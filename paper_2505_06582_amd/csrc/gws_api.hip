@@ -1131,12 +1131,18 @@ extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *prob
 // ---------------------------------------------------------------------------------
 // Stand-alone 2D DFT
 // ---------------------------------------------------------------------------------
+// Row and column launches index rows and slabs of the whole batch with 32-bit grid sizes.
+static bool dft_batch_fits(int32_t nx, int32_t ny, int32_t batch)
+{
+    return (int64_t)batch * std::max(nx, ny) < ((int64_t)1 << 31);
+}
+
 extern "C" gws_status gws_dft_workspace_size(const gws_ctx *ctx, int32_t nx, int32_t ny, int32_t batch, int32_t xform,
                                              size_t *bytes)
 {
     (void)ctx;
     if (!bytes || batch < 1) return GWS_ERR_INVALID_ARG;
-    if (check_grid(nx, ny) != GWS_OK) return GWS_ERR_SHAPE;
+    if (check_grid(nx, ny) != GWS_OK || !dft_batch_fits(nx, ny, batch)) return GWS_ERR_SHAPE;
     if (xform == GWS_XFORM_FFT_FP32) *bytes = 0;
     else if (xform == GWS_XFORM_DFT_BF16X3) *bytes = dft_bf16x3_workspace(nx, ny, batch);
     else return GWS_ERR_INVALID_ARG;
@@ -1150,6 +1156,7 @@ extern "C" gws_status gws_dft2d(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t ba
     if (!in || !out || batch < 1 || (direction != 1 && direction != -1))
         return fail(ctx, GWS_ERR_INVALID_ARG, "bad DFT arguments");
     if (check_grid(nx, ny) != GWS_OK) return fail(ctx, GWS_ERR_SHAPE, "unsupported DFT shape");
+    if (!dft_batch_fits(nx, ny, batch)) return fail(ctx, GWS_ERR_SHAPE, "DFT batch too large");
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     Plan *p = nullptr;
     gws_status st = get_plan(ctx, nx, ny, 4, &p);

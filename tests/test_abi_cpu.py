@@ -130,6 +130,19 @@ def test_exact_blending_workspace_sizes():
     assert sz.value == single
 
 
+def test_dft_workspace_query_validates_shape_and_batch():
+    lib = gws.load_library()
+    sz = ctypes.c_size_t()
+    assert lib.gws_dft_workspace_size(None, 1920, 1080, 3, 0, ctypes.byref(sz)) == 0 and sz.value == 0
+    assert lib.gws_dft_workspace_size(None, 1920, 1080, 3, 1, ctypes.byref(sz)) == 0 and sz.value > 0
+    assert lib.gws_dft_workspace_size(None, 1920, 1080, 0, 0, ctypes.byref(sz)) == -1
+    assert lib.gws_dft_workspace_size(None, 1921, 1080, 1, 0, ctypes.byref(sz)) == -2   # odd
+    assert lib.gws_dft_workspace_size(None, 1920, 1078, 1, 0, ctypes.byref(sz)) == -2   # factor 7
+    # the whole batch's rows (and column slabs) must fit a 32-bit grid
+    assert lib.gws_dft_workspace_size(None, 1920, 1080, (1 << 31) // 1920 + 1, 0, ctypes.byref(sz)) == -2
+    assert lib.gws_dft_workspace_size(None, 1920, 1080, (1 << 31) // 1920, 0, ctypes.byref(sz)) == 0
+
+
 def test_entry_points_reject_bad_arguments_without_a_device():
     lib = gws.load_library()
     h = ctypes.c_void_p()
