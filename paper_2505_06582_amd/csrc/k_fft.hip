@@ -311,24 +311,43 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
 {
     extern __shared__ float2 lds[];
     const int64_t row = blockIdx.x;
-    const float2 *src = in + row * pl.n;
+    const int n = pl.n;
+    const float2 *src = in + row * n;
+    float2 *dst = out + row * n;
     const int s0 = pl.sh[0], s1 = pl.sh[pl.nrad];
-    if (colin) {
-        const int2 w = colin[row / rows_per_img];
-        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS)
-            lds[lds_at(i, s0)] = win_pos(i, w, pl.n) < w.y ? src[i] : make_float2(0.0f, 0.0f);
+    const int2 wi = colin ? colin[row / rows_per_img] : make_int2(0, n);
+    const int2 wo = colout ? colout[row / rows_per_img] : make_int2(0, n);
+    // Rows are moved two elements (16 bytes) per access when both ends are 16-byte aligned
+    // (n is even): elements i and i + 1 of an even i are adjacent in every layout (padding
+    // comes at most every 8 elements).
+    if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0) {
+        const float4 *src4 = reinterpret_cast<const float4 *>(src);
+        for (int i = 2 * threadIdx.x; i < n; i += 2 * FFT_THREADS) {
+            const bool l0 = win_pos(i, wi, n) < wi.y, l1 = win_pos(i + 1, wi, n) < wi.y;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (l0 || l1) v = src4[i >> 1];
+            const int a = lds_at(i, s0);
+            lds[a] = l0 ? make_float2(v.x, v.y) : make_float2(0.0f, 0.0f);
+            lds[a + 1] = l1 ? make_float2(v.z, v.w) : make_float2(0.0f, 0.0f);
+        }
+        __syncthreads();
+        fft_row_lds<S, NPT>(lds, pl, tw);
+        float4 *dst4 = reinterpret_cast<float4 *>(dst);
+        for (int i = 2 * threadIdx.x; i < n; i += 2 * FFT_THREADS) {
+            const int a = lds_at(i, s1);
+            const float2 v0 = lds[a], v1 = lds[a + 1];
+            const bool l0 = win_pos(i, wo, n) < wo.y, l1 = win_pos(i + 1, wo, n) < wo.y;
+            if (l0 && l1) dst4[i >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
+            else if (l0) dst[i] = v0;
+            else if (l1) dst[i + 1] = v1;
+        }
     } else {
-        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) lds[lds_at(i, s0)] = src[i];
-    }
-    __syncthreads();
-    fft_row_lds<S, NPT>(lds, pl, tw);
-    float2 *dst = out + row * pl.n;
-    if (colout) {
-        const int2 w = colout[row / rows_per_img];
-        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS)
-            if (win_pos(i, w, pl.n) < w.y) dst[i] = lds[lds_at(i, s1)];
-    } else {
-        for (int i = threadIdx.x; i < pl.n; i += FFT_THREADS) dst[i] = lds[lds_at(i, s1)];
+        for (int i = threadIdx.x; i < n; i += FFT_THREADS)
+            lds[lds_at(i, s0)] = win_pos(i, wi, n) < wi.y ? src[i] : make_float2(0.0f, 0.0f);
+        __syncthreads();
+        fft_row_lds<S, NPT>(lds, pl, tw);
+        for (int i = threadIdx.x; i < n; i += FFT_THREADS)
+            if (win_pos(i, wo, n) < wo.y) dst[i] = lds[lds_at(i, s1)];
     }
 }
 
