@@ -407,7 +407,7 @@ static gws_status check_offsets(int S, const int64_t *offsets, int64_t n)
 struct ExactLayout {
     size_t off_keys_a = 0, off_keys_b = 0, off_vals_a = 0, off_vals_b = 0, off_sort_hist = 0, off_rec = 0,
            off_tmap = 0, off_imgs = 0, off_spec = 0, off_dft = 0, off_gspec = 0, off_ckpt = 0, off_dmap = 0,
-           off_pspec = 0, off_pspat = 0, off_win = 0, total = 0;
+           off_pspec = 0, off_pspat = 0, off_win = 0, off_pimgs = 0, total = 0;
     int sort_blocks = 1;
 };
 
@@ -426,9 +426,10 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
     L.off_rec = take((size_t)64 * n);
     L.off_tmap = take(sizeof(float) * M);
     L.off_imgs = take(sizeof(float2) * M * exact_batch(p->nx, p->ny));
+    L.off_pimgs = take(sizeof(float2) * M * ((exact_batch(p->nx, p->ny) + 1) / 2));
     L.off_spec = take(sizeof(float2) * M * p->n_lambda);
     L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? sizeof(float2) * M * p->n_lambda : 1);
-    L.off_win = take(sizeof(int2) * 2 * 64);
+    L.off_win = take(sizeof(int4) * 4 * 64);
     // adjoint: transformed field gradient, map checkpoints, back-to-front accumulator, partial sums
     L.off_gspec = take(sizeof(float2) * M * p->n_lambda);
     L.off_ckpt = take(sizeof(float) * M * (size_t)exact_ckpt_count(n, p->nx, p->ny));
@@ -872,8 +873,11 @@ static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const
     eb.rec = (void *)(base + L.off_rec);
     eb.tmap = (float *)(base + L.off_tmap);
     eb.imgs = (float2 *)(base + L.off_imgs);
-    eb.colwin = (int2 *)(base + L.off_win);
+    eb.pimgs = (float2 *)(base + L.off_pimgs);
+    eb.colwin = (int4 *)(base + L.off_win);
     eb.rowwin = eb.colwin + 64;
+    eb.pcolwin = eb.rowwin + 64;
+    eb.prowwin = eb.pcolwin + 64;
     float2 *spec = spectrum ? (float2 *)spectrum : (float2 *)(base + L.off_spec);
     {
         StageScope sc(ctx, s, ST_ACCUM);
@@ -914,8 +918,11 @@ static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, cons
     eb.rec = (void *)(base + L.off_rec);
     eb.tmap = (float *)(base + L.off_tmap);
     eb.imgs = (float2 *)(base + L.off_imgs);
-    eb.colwin = (int2 *)(base + L.off_win);
+    eb.pimgs = (float2 *)(base + L.off_pimgs);
+    eb.colwin = (int4 *)(base + L.off_win);
     eb.rowwin = eb.colwin + 64;
+    eb.pcolwin = eb.rowwin + 64;
+    eb.prowwin = eb.pcolwin + 64;
     ExactBwdBuffers bb;
     bb.gspec = (float2 *)(base + L.off_gspec);
     bb.ckpt = (float *)(base + L.off_ckpt);

@@ -355,8 +355,10 @@ struct ExactBuffers {
     int sort_blocks;
     void *rec;     // 64-byte records, front to back
     float *tmap;   // transmittance [ny][nx]
-    float2 *imgs;  // masked wavefronts of one batch [B][ny][nx]
-    int2 *colwin, *rowwin;  // per batch image: window columns / rows as (first, count)
+    float2 *imgs;   // the adjoint's per-Gaussian images of one batch [B][ny][nx]
+    float2 *pimgs;  // masked profiles of one batch, two Gaussians per image [(B + 1) / 2][ny][nx]
+    int4 *colwin, *rowwin;    // per batch Gaussian: window columns / rows as (first, count, 0, 0)
+    int4 *pcolwin, *prowwin;  // per packed image: the two Gaussians' windows
 };
 size_t exact_batch(int nx, int ny);
 // Extra device buffers of the exact-blending adjoint.
@@ -433,10 +435,12 @@ hipError_t launch_dpac(const float2 *u, int nx, int ny, int C, const uint32_t *a
                        float *phase, hipStream_t s);
 hipError_t launch_phase_field(const float *phase, int64_t n, float2 *u, hipStream_t s);
 
-hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int2 *colwin,
+// Windowed transforms of the exact-blending images; a window is one or two periodic intervals
+// (start, length, start, length), an unused second interval with length 0.
+hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int4 *colwin,
                                  hipStream_t s);
 hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
-                            const int2 *colwin, const int2 *rowwin, hipStream_t s);
+                            const int4 *colwin, const int4 *rowwin, hipStream_t s);
 hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in, float2 *out,
                              void *ws, hipStream_t s);
 size_t dft_bf16x3_workspace(int nx, int ny, int batch);

@@ -101,6 +101,12 @@ __global__ void __launch_bounds__(256) k_exact_records(GView g, Consts k, const 
     rec[i] = r;
 }
 
+// The index of the frequency -m (periodic) of m = (mx, my).
+static __device__ __forceinline__ int64_t neg_freq(int mx, int my, int nx, int ny)
+{
+    return (int64_t)(my == 0 ? 0 : ny - my) * nx + (mx == 0 ? 0 : nx - mx);
+}
+
 // Wrapped displacement of pixel coordinate v from centre c on a periodic axis of length n.
 static __device__ __forceinline__ float wrap_d(float d, float n)
 {
@@ -124,8 +130,12 @@ static __device__ __forceinline__ void window_rect(const ERec &r, int nx, int ny
 
 // One work-group per 16 x 16 pixel tile; walks Gaussians [b0, b0 + nb) in order.  Reads the
 // map from t_in; writes the map at the batch start to ckpt and at its end to t_out, and the
-// masked wavefronts to imgs (each optional) -- only inside each Gaussian's window rectangle
-// (zeros included); the rest of an image is never written and never read.
+// masked profiles to imgs (each optional).  The masked wavefront of Gaussian k is
+// e^{j phi_k} T g_k with T g_k real, so two Gaussians share one complex image: batch
+// Gaussians 2p and 2p + 1 write T g as the real and the imaginary part of image p (the phase
+// is applied after the transform, which separates the two by Hermitian symmetry).  Image p
+// is written only inside the union of the pair's window rectangles, each part zero outside
+// its own rectangle; the rest of an image is never written and never read.
 __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec, int b0, int nb, int nx, int ny,
                                                     const float *t_in, float *t_out, float2 *__restrict__ imgs,
                                                     float *__restrict__ ckpt)
@@ -152,33 +162,47 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
         meets = r.hwx >= 0 && dcx <= (float)r.hwx + 8.5f && dcy <= (float)r.hwy + 8.5f;
     }
     const uint64_t hits = __ballot(meets);
+    float pend = 0.0f;     // the value of a pair's first Gaussian, waiting for the second's
+    bool pend_in = false;  // is the pixel inside that first Gaussian's rectangle?
     for (uint64_t mk = hits; mk; mk &= mk - 1) {
         const int b = __builtin_ctzll(mk);
         const ERec &r = s_rec[b];
-        {
-            float2 v = make_float2(0.0f, 0.0f);
-            const float dx = wrap_d((float)px - r.cx, (float)nx), dy = wrap_d((float)py - r.cy, (float)ny);
-            if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {  // the profile's window
-                const float q = fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy));
-                const float gk = __builtin_amdgcn_exp2f(-q);
-                const float m = T * gk;
-                v = make_float2(m * r.cphi, m * r.sphi);
-                const float alpha = r.o * gk;
-                if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
-            }
-            if (imgs && in) {
-                int2 cw, rw;
-                window_rect(r, nx, ny, cw, rw);
-                // px, py and the window starts lie in [0, n): one wrap at most
-                const int ex = px - cw.x + (px < cw.x ? nx : 0), ey = py - rw.x + (py < rw.x ? ny : 0);
-                if (ex < cw.y && ey < rw.y) imgs[(int64_t)b * M + pix] = v;
+        float v = 0.0f;
+        const float dx = wrap_d((float)px - r.cx, (float)nx), dy = wrap_d((float)py - r.cy, (float)ny);
+        if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {  // the profile's window
+            const float q = fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy));
+            const float gk = __builtin_amdgcn_exp2f(-q);
+            v = T * gk;
+            const float alpha = r.o * gk;
+            if (alpha > EXACT_T_EPS) T *= 1.0f - alpha;
+        }
+        if (imgs && in) {
+            int2 cw, rw;
+            window_rect(r, nx, ny, cw, rw);
+            // px, py and the window starts lie in [0, n): one wrap at most
+            const int ex = px - cw.x + (px < cw.x ? nx : 0), ey = py - rw.x + (py < rw.x ? ny : 0);
+            const bool inb = ex < cw.y && ey < rw.y;
+            float2 *dst = imgs + (int64_t)(b >> 1) * M + pix;
+            if ((b & 1) == 0) {
+                if (b + 1 < nb && ((hits >> (b + 1)) & 1)) {  // its partner meets the tile too
+                    pend = v;
+                    pend_in = inb;
+                } else if (inb) {
+                    *dst = make_float2(v, 0.0f);
+                }
+            } else {
+                const bool first = ((hits >> (b - 1)) & 1) && pend_in;
+                if (first || inb) *dst = make_float2(first ? pend : 0.0f, inb ? v : 0.0f);
+                pend_in = false;
             }
         }
     }
     if (t_out && in) t_out[pix] = T;
 }
 
-// One thread per frequency (FFT order): U_c += a_{k,c} o_k H_c(nu, -z_k) FFT(T u_k) / (Nx Ny).
+// One thread per frequency (FFT order): U_c += a_{k,c} o_k H_c(nu, -z_k) FFT(T u_k) / (Nx Ny),
+// with FFT(T u_k) = e^{j phi_k} F_k separated from the packed transform Z of a pair (a, b):
+// F_a(m) = (Z(m) + conj Z(-m)) / 2, F_b(m) = (Z(m) - conj Z(-m)) / 2j.
 __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
                                                      const float2 *__restrict__ imgs, float2 *__restrict__ spec)
 {
@@ -200,17 +224,34 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
         w[c] = prop[c] ? sqrt(w2) : 0.0;
         acc[c] = c < k.C ? spec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
     }
-    // the next Gaussian's spectrum value is fetched while this one is applied
-    float2 Sn = nb > 0 ? imgs[m] : make_float2(0.0f, 0.0f);
+    const int64_t mn = neg_freq(mx, my, k.nx, k.ny);
+    const int P = (nb + 1) / 2;
+    // the next pair's values are fetched while this pair is applied
+    float2 Zn = make_float2(0.0f, 0.0f), Zrn = Zn;
+    if (P > 0) {
+        Zn = imgs[m];
+        Zrn = imgs[mn];
+    }
+    float2 Fa = make_float2(0.0f, 0.0f), Fb = Fa;
     for (int b = 0; b < nb; ++b) {
-        const float2 S = Sn;
-        if (b + 1 < nb) Sn = imgs[(int64_t)(b + 1) * M + m];
+        if ((b & 1) == 0) {
+            const float2 Z = Zn, Zr = Zrn;
+            const int p = b >> 1;
+            if (p + 1 < P) {
+                Zn = imgs[(int64_t)(p + 1) * M + m];
+                Zrn = imgs[(int64_t)(p + 1) * M + mn];
+            }
+            Fa = make_float2(0.5f * (Z.x + Zr.x), 0.5f * (Z.y - Zr.y));
+            Fb = make_float2(0.5f * (Z.y + Zr.y), 0.5f * (Zr.x - Z.x));
+        }
         const ERec &rr = rec[b0 + b];
         // the fields used below, loaded together
         const int valid = rr.valid;
-        const float rz = rr.z;
+        const float rz = rr.z, cph = rr.cphi, sph = rr.sphi;
         const float4 ramp = *reinterpret_cast<const float4 *>(rr.amp);
         if (!valid) continue;
+        const float2 F = (b & 1) ? Fb : Fa;
+        const float2 S = make_float2(cph * F.x - sph * F.y, cph * F.y + sph * F.x);  // e^{j phi} F
         const float ampc[4] = {ramp.x, ramp.y, ramp.z, ramp.w};
         const double zd = (double)rz;
 #pragma unroll
@@ -232,16 +273,27 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
 
 // Per batch image: the columns and rows of the profile's window, as (first, count) on the
 // periodic axes (count 0 for a Gaussian that contributes nothing).
+// Windows of a batch: per Gaussian (colwin, rowwin: one interval, the second empty) and per
+// packed image p (pcolwin, prowwin: the rectangles of Gaussians 2p and 2p + 1).
 __global__ void __launch_bounds__(64) k_exact_windows(const ERec *__restrict__ rec, int b0, int nb, int nx, int ny,
-                                                      int2 *__restrict__ colwin, int2 *__restrict__ rowwin)
+                                                      int4 *__restrict__ colwin, int4 *__restrict__ rowwin,
+                                                      int4 *__restrict__ pcolwin, int4 *__restrict__ prowwin)
 {
     const int b = threadIdx.x;
     if (b >= nb) return;
     int2 cw, rw;
     window_rect(rec[b0 + b], nx, ny, cw, rw);
-    colwin[b] = cw;
-    rowwin[b] = rw;
+    colwin[b] = make_int4(cw.x, cw.y, 0, 0);
+    rowwin[b] = make_int4(rw.x, rw.y, 0, 0);
+    if (2 * b < nb) {
+        int2 ca, ra, cb = make_int2(0, 0), rb = make_int2(0, 0);
+        window_rect(rec[b0 + 2 * b], nx, ny, ca, ra);
+        if (2 * b + 1 < nb) window_rect(rec[b0 + 2 * b + 1], nx, ny, cb, rb);
+        pcolwin[b] = make_int4(ca.x, ca.y, cb.x, cb.y);
+        prowwin[b] = make_int4(ra.x, ra.y, rb.x, rb.y);
+    }
 }
+
 
 __global__ void __launch_bounds__(256) k_exact_fill(float *__restrict__ tmap, float2 *__restrict__ spec, int64_t M,
                                                     int C)
@@ -282,13 +334,13 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
     for (int64_t b0 = 0; b0 < n; b0 += B) {
         const int nb = (int)std::min<int64_t>(B, n - b0);
         hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.tmap, eb.tmap,
-                           eb.imgs, (float *)nullptr);
+                           eb.pimgs, (float *)nullptr);
         hipLaunchKernelGGL(k_exact_windows, dim3(1), dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.colwin,
-                           eb.rowwin);
-        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, eb.rowwin, s);
+                           eb.rowwin, eb.pcolwin, eb.prowwin);
+        e = launch_fft2d_win(p, (nb + 1) / 2, -1, eb.pimgs, eb.pimgs, eb.pcolwin, eb.prowwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_splat, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec, (int)b0, nb, k,
-                           eb.imgs, spec);
+                           eb.pimgs, spec);
     }
     return hipGetLastError();
 }
@@ -317,7 +369,8 @@ constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, Sphi, So, pad
 constexpr int EXACT_GS_PER = 2;
 
 __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
-                                                      const float2 *__restrict__ gspec, float2 *__restrict__ imgs,
+                                                      const float2 *__restrict__ gspec,
+                                                      const float2 *__restrict__ pimgs, float2 *__restrict__ imgs,
                                                       float *__restrict__ part)
 {
     // per wave and batch Gaussian, the wave's 12 sums: the four waves are summed in a fixed
@@ -325,7 +378,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
     __shared__ float s_red[4][64][16];
     const int64_t M = (int64_t)k.nx * k.ny;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t mi[EXACT_GS_PER];
+    int64_t mi[EXACT_GS_PER], mn[EXACT_GS_PER];
     bool live[EXACT_GS_PER];
     double w[EXACT_GS_PER][3];
     bool prop[EXACT_GS_PER][3];
@@ -334,10 +387,12 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
     for (int q = 0; q < EXACT_GS_PER; ++q) {
         const int64_t m = ((int64_t)blockIdx.x * EXACT_GS_PER + q) * blockDim.x + threadIdx.x;
         mi[q] = m;
+        mn[q] = 0;
         live[q] = m < M;
         double nu2 = 0.0;
         if (live[q]) {
             const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
+            mn[q] = neg_freq(mx, my, k.nx, k.ny);
             const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
             const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
             nu2 = nux * nux + nuy * nuy;
@@ -350,21 +405,36 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
             gs[q][c] = (live[q] && c < k.C) ? gspec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
         }
     }
-    // the next Gaussian's spectrum values are fetched while this one is applied
-    float2 Fn[EXACT_GS_PER];
+    // F_k from the packed transforms of pairs (see k_exact_splat); V_k goes to imgs.  The
+    // next pair's values are fetched while this pair is applied.
+    const int P = (nb + 1) / 2;
+    float2 Zn[EXACT_GS_PER], Zrn[EXACT_GS_PER], Fa[EXACT_GS_PER], Fb[EXACT_GS_PER];
 #pragma unroll
-    for (int q = 0; q < EXACT_GS_PER; ++q) Fn[q] = (live[q] && nb > 0) ? imgs[mi[q]] : make_float2(0.0f, 0.0f);
+    for (int q = 0; q < EXACT_GS_PER; ++q) {
+        Zn[q] = Zrn[q] = make_float2(0.0f, 0.0f);
+        if (live[q] && P > 0) {
+            Zn[q] = pimgs[mi[q]];
+            Zrn[q] = pimgs[mn[q]];
+        }
+    }
     for (int b = 0; b < nb; ++b) {
-        float2 Fb[EXACT_GS_PER];
+        if ((b & 1) == 0) {
+            const int p = b >> 1;
 #pragma unroll
-        for (int q = 0; q < EXACT_GS_PER; ++q) {
-            Fb[q] = Fn[q];
-            if (live[q] && b + 1 < nb) Fn[q] = imgs[(int64_t)(b + 1) * M + mi[q]];
+            for (int q = 0; q < EXACT_GS_PER; ++q) {
+                const float2 Z = Zn[q], Zr = Zrn[q];
+                if (live[q] && p + 1 < P) {
+                    Zn[q] = pimgs[(int64_t)(p + 1) * M + mi[q]];
+                    Zrn[q] = pimgs[(int64_t)(p + 1) * M + mn[q]];
+                }
+                Fa[q] = make_float2(0.5f * (Z.x + Zr.x), 0.5f * (Z.y - Zr.y));
+                Fb[q] = make_float2(0.5f * (Z.y + Zr.y), 0.5f * (Zr.x - Z.x));
+            }
         }
         const ERec &rr = rec[b0 + b];
         // the fields used below, loaded together
         const int valid = rr.valid;
-        const float rz = rr.z;
+        const float rz = rr.z, cph = rr.cphi, sph = rr.sphi;
         const float4 ramp = *reinterpret_cast<const float4 *>(rr.amp);
         const float ampc[4] = {ramp.x, ramp.y, ramp.z, ramp.w};
         float v[EXACT_NSPEC];
@@ -375,7 +445,8 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
         for (int q = 0; q < EXACT_GS_PER; ++q) {
             float2 V = make_float2(0.0f, 0.0f);
             if (live[q] && valid) {
-                const float2 F = Fb[q];
+                const float2 Fr = (b & 1) ? Fb[q] : Fa[q];
+                const float2 F = make_float2(cph * Fr.x - sph * Fr.y, cph * Fr.y + sph * Fr.x);  // e^{j phi} F
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (!prop[q][c]) continue;
@@ -620,13 +691,13 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
         const int64_t b0 = q * B;
         const int nb = (int)std::min<int64_t>(B, n - b0);
         hipLaunchKernelGGL(k_exact_mask, tiles, dim3(256), 0, s, rec, (int)b0, nb, k.nx, k.ny, bb.ckpt + q * M,
-                           (float *)nullptr, eb.imgs, (float *)nullptr);
+                           (float *)nullptr, eb.pimgs, (float *)nullptr);
         hipLaunchKernelGGL(k_exact_windows, dim3(1), dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, eb.colwin,
-                           eb.rowwin);
-        e = launch_fft2d_win(p, nb, -1, eb.imgs, eb.imgs, eb.colwin, eb.rowwin, s);
+                           eb.rowwin, eb.pcolwin, eb.prowwin);
+        e = launch_fft2d_win(p, (nb + 1) / 2, -1, eb.pimgs, eb.pimgs, eb.pcolwin, eb.prowwin, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_exact_gsplat, dim3(gsblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.imgs,
-                           bb.pspec);
+        hipLaunchKernelGGL(k_exact_gsplat, dim3(gsblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.pimgs,
+                           eb.imgs, bb.pspec);
         // R is read only inside each window: full row pass, columns of the window only
         e = launch_fft2d_cols_out(p, nb, +1, eb.imgs, eb.colwin, s);
         if (e != hipSuccess) return e;

@@ -299,6 +299,18 @@ static __device__ __forceinline__ int win_pos(int v, int2 w, int n)
     const int d = v - w.x;
     return d < 0 ? d + n : d;
 }
+// A window is one or two periodic intervals (x, y) and (z, w) as (start, length); an unused
+// second interval has length 0.  v lies in [0, n).
+static __device__ __forceinline__ bool in_win(int v, int4 w, int n)
+{
+    return win_pos(v, make_int2(w.x, w.y), n) < w.y || win_pos(v, make_int2(w.z, w.w), n) < w.w;
+}
+// Does any of the b indexes v0 .. v0 + b - 1 lie in the interval (start, len)?
+static __device__ __forceinline__ bool interval_meets(int v0, int b, int start, int len, int n)
+{
+    const int d = win_pos(v0, make_int2(start, len), n);
+    return len > 0 && (d < len || d + b > n);
+}
 
 // Row transforms: one row per work-group.  in/out: [rows][n].  With colin, each image's
 // input is nonzero only in its window of columns: the others are read as zero, not loaded.
@@ -306,8 +318,8 @@ static __device__ __forceinline__ int win_pos(int v, int2 w, int n)
 template <int S, int NPT>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                           RadixPlan pl, const float2 *__restrict__ tw,
-                                                          const int2 *__restrict__ colin,
-                                                          const int2 *__restrict__ colout, int rows_per_img)
+                                                          const int4 *__restrict__ colin,
+                                                          const int4 *__restrict__ colout, int rows_per_img)
 {
     extern __shared__ float2 lds[];
     const int64_t row = blockIdx.x;
@@ -315,15 +327,15 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
     const float2 *src = in + row * n;
     float2 *dst = out + row * n;
     const int s0 = pl.sh[0], s1 = pl.sh[pl.nrad];
-    const int2 wi = colin ? colin[row / rows_per_img] : make_int2(0, n);
-    const int2 wo = colout ? colout[row / rows_per_img] : make_int2(0, n);
+    const int4 wi = colin ? colin[row / rows_per_img] : make_int4(0, n, 0, 0);
+    const int4 wo = colout ? colout[row / rows_per_img] : make_int4(0, n, 0, 0);
     // Rows are moved two elements (16 bytes) per access when both ends are 16-byte aligned
     // (n is even): elements i and i + 1 of an even i are adjacent in every layout (padding
     // comes at most every 8 elements).
     if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0) {
         const float4 *src4 = reinterpret_cast<const float4 *>(src);
         for (int i = 2 * threadIdx.x; i < n; i += 2 * FFT_THREADS) {
-            const bool l0 = win_pos(i, wi, n) < wi.y, l1 = win_pos(i + 1, wi, n) < wi.y;
+            const bool l0 = in_win(i, wi, n), l1 = in_win(i + 1, wi, n);
             float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (l0 || l1) v = src4[i >> 1];
             const int a = lds_at(i, s0);
@@ -336,18 +348,18 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_rows(const float2 *__restri
         for (int i = 2 * threadIdx.x; i < n; i += 2 * FFT_THREADS) {
             const int a = lds_at(i, s1);
             const float2 v0 = lds[a], v1 = lds[a + 1];
-            const bool l0 = win_pos(i, wo, n) < wo.y, l1 = win_pos(i + 1, wo, n) < wo.y;
+            const bool l0 = in_win(i, wo, n), l1 = in_win(i + 1, wo, n);
             if (l0 && l1) dst4[i >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
             else if (l0) dst[i] = v0;
             else if (l1) dst[i + 1] = v1;
         }
     } else {
         for (int i = threadIdx.x; i < n; i += FFT_THREADS)
-            lds[lds_at(i, s0)] = win_pos(i, wi, n) < wi.y ? src[i] : make_float2(0.0f, 0.0f);
+            lds[lds_at(i, s0)] = in_win(i, wi, n) ? src[i] : make_float2(0.0f, 0.0f);
         __syncthreads();
         fft_row_lds<S, NPT>(lds, pl, tw);
         for (int i = threadIdx.x; i < n; i += FFT_THREADS)
-            if (win_pos(i, wo, n) < wo.y) dst[i] = lds[lds_at(i, s1)];
+            if (in_win(i, wo, n)) dst[i] = lds[lds_at(i, s1)];
     }
 }
 
@@ -425,9 +437,9 @@ static __device__ __forceinline__ int xcd_contiguous(int i, int G)
 template <int S, bool INTENSITY, int LDSB>
 __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4 : 2) k_fft_cols(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                               RadixPlan pl, const float2 *__restrict__ tw, int width,
-                                                              int lb, const int2 *__restrict__ colwin,
+                                                              int lb, const int4 *__restrict__ colwin,
                                                               float *__restrict__ outf,
-                                                              const int2 *__restrict__ rowin)
+                                                              const int4 *__restrict__ rowin)
 {
     extern __shared__ float2 lds[];
     const int n = pl.n, B = 1 << lb;
@@ -437,23 +449,26 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
     const int c0 = (blk - (int)(img * nslab)) * B;
     // colwin: only the slabs meeting each image's window of columns are transformed, and only
     // the window's columns are loaded (the others are read as zero) and stored.  rowin (input
-    // support): the image is also zero outside that window of rows, which is not loaded.
+    // support): the image is zero outside the rectangles colwin.xy x rowin.xy and
+    // colwin.zw x rowin.zw, whose outside is not loaded.
     if (colwin) {
-        const int2 w = colwin[img];
-        const int d = ((c0 - w.x) % width + width) % width;
-        if (!(d < w.y || d + B > width)) return;
+        const int4 w = colwin[img];
+        if (!interval_meets(c0, B, w.x, w.y, width) && !interval_meets(c0, B, w.z, w.w, width)) return;
     }
     float2 *tw_s = lds + n * B;  // the twiddle table, read by every pass
     for (int i = threadIdx.x; i < n; i += FFT_COL_THREADS) tw_s[i] = tw[i];
     const int bw = min(B, width - c0);
     const float2 *src = in + img * (int64_t)n * width;
     float2 *dst = out + img * (int64_t)n * width;
-    const int2 wc = colwin ? colwin[img] : make_int2(0, width);
+    const int4 wc = colwin ? colwin[img] : make_int4(0, width, 0, 0);
     if (colwin) {
-        const int2 wr = rowin ? rowin[img] : make_int2(0, n);
+        const int4 wr = rowin ? rowin[img] : make_int4(0, n, 0, n);
         for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
-            const int r = i >> lb, c = i & (B - 1);
-            const bool live = c < bw && win_pos(c0 + c, wc, width) < wc.y && win_pos(r, wr, n) < wr.y;
+            const int r = i >> lb, c = i & (B - 1), v = c0 + c;
+            const bool live = c < bw && ((win_pos(v, make_int2(wc.x, wc.y), width) < wc.y &&
+                                          win_pos(r, make_int2(wr.x, wr.y), n) < wr.y) ||
+                                         (win_pos(v, make_int2(wc.z, wc.w), width) < wc.w &&
+                                          win_pos(r, make_int2(wr.z, wr.w), n) < wr.w));
             lds[i] = live ? src[(int64_t)r * width + c0 + c] : make_float2(0.0f, 0.0f);
         }
     } else {
@@ -483,12 +498,12 @@ __global__ void __launch_bounds__(FFT_COL_THREADS, LDSB == FFT_COL_LDS_SMALL ? 4
         for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
             const int r = i >> lb, c = i & (B - 1);
             const float2 v = lds[i];
-            if (c < bw && win_pos(c0 + c, wc, width) < wc.y) dstf[(int64_t)r * width + c0 + c] = fmaf(v.x, v.x, v.y * v.y);
+            if (c < bw && in_win(c0 + c, wc, width)) dstf[(int64_t)r * width + c0 + c] = fmaf(v.x, v.x, v.y * v.y);
         }
     } else {
         for (int i = threadIdx.x; i < n * B; i += FFT_COL_THREADS) {
             const int r = i >> lb, c = i & (B - 1);
-            if (c < bw && win_pos(c0 + c, wc, width) < wc.y) dst[(int64_t)r * width + c0 + c] = lds[i];
+            if (c < bw && in_win(c0 + c, wc, width)) dst[(int64_t)r * width + c0 + c] = lds[i];
         }
     }
 }
@@ -632,7 +647,7 @@ static void allow_big_lds()
 // Row passes: the smallest elements-per-thread bound that covers n.
 template <int S>
 static void rows_launch(const Plan &p, const RadixPlan &px, int rows, const float2 *src, float2 *dst,
-                        const int2 *colin, hipStream_t s, const int2 *colout = nullptr)
+                        const int4 *colin, hipStream_t s, const int4 *colout = nullptr)
 {
     const size_t lds = (size_t)lds_padded_len(p.nx) * sizeof(float2);
     const int npt = (p.nx + FFT_THREADS - 1) / FFT_THREADS;
@@ -651,8 +666,8 @@ static void rows_launch(const Plan &p, const RadixPlan &px, int rows, const floa
 
 // One column pass over nimg images [ny][nx] in place (or, with intensity, |x|^2 to it).
 template <int S, bool INTENSITY>
-static void cols_launch(const Plan &p, const RadixPlan &py, int nimg, float2 *buf, const int2 *colwin, float *outf,
-                        hipStream_t s, const int2 *rowin = nullptr)
+static void cols_launch(const Plan &p, const RadixPlan &py, int nimg, float2 *buf, const int4 *colwin, float *outf,
+                        hipStream_t s, const int4 *rowin = nullptr)
 {
     const ColCfg c = col_config(p.ny);
     const size_t lds = (size_t)(c.B + 1) * p.ny * sizeof(float2);
@@ -676,7 +691,7 @@ hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *i
 // columns, loading only the rectangle; then every row, loading only colwin's columns (what
 // lies outside the rectangle is never read, so it need not be zero).  In place.
 hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
-                            const int2 *colwin, const int2 *rowwin, hipStream_t s)
+                            const int4 *colwin, const int4 *rowwin, hipStream_t s)
 {
     allow_big_lds();
     const RadixPlan px = make_radix(p.nx, p.radix_x, p.nrad_x);
@@ -704,7 +719,7 @@ hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float
 
 // Rows first over every row, storing only colwin's columns, then only those columns (the
 // output is wanted only there; the others are left unfinished).  In place.
-hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int2 *colwin,
+hipError_t launch_fft2d_cols_out(const Plan &p, int batch, int direction, float2 *buf, const int4 *colwin,
                                  hipStream_t s)
 {
     allow_big_lds();
