@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
     __shared__ float s_red[4][64][16];
     const int64_t M = (int64_t)k.nx * k.ny;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t mi[EXACT_GS_PER], mn[EXACT_GS_PER];
+    int mi[EXACT_GS_PER], mn[EXACT_GS_PER];  // frequency m and -m (M < 2^31)
     bool live[EXACT_GS_PER];
     double w[EXACT_GS_PER][3];
     bool prop[EXACT_GS_PER][3];
@@ -386,13 +386,13 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
 #pragma unroll
     for (int q = 0; q < EXACT_GS_PER; ++q) {
         const int64_t m = ((int64_t)blockIdx.x * EXACT_GS_PER + q) * blockDim.x + threadIdx.x;
-        mi[q] = m;
+        mi[q] = (int)m;
         mn[q] = 0;
         live[q] = m < M;
         double nu2 = 0.0;
         if (live[q]) {
             const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
-            mn[q] = neg_freq(mx, my, k.nx, k.ny);
+            mn[q] = (int)neg_freq(mx, my, k.nx, k.ny);
             const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
             const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
             nu2 = nux * nux + nuy * nuy;
@@ -405,27 +405,17 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
             gs[q][c] = (live[q] && c < k.C) ? gspec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
         }
     }
-    // F_k from the packed transforms of pairs (see k_exact_splat); V_k goes to imgs.  The
-    // next pair's values are fetched while this pair is applied.
-    const int P = (nb + 1) / 2;
-    float2 Zn[EXACT_GS_PER], Zrn[EXACT_GS_PER], Fa[EXACT_GS_PER], Fb[EXACT_GS_PER];
-#pragma unroll
-    for (int q = 0; q < EXACT_GS_PER; ++q) {
-        Zn[q] = Zrn[q] = make_float2(0.0f, 0.0f);
-        if (live[q] && P > 0) {
-            Zn[q] = pimgs[mi[q]];
-            Zrn[q] = pimgs[mn[q]];
-        }
-    }
+    // F_k from the packed transforms of pairs (see k_exact_splat); V_k goes to imgs
+    float2 Fa[EXACT_GS_PER], Fb[EXACT_GS_PER];
     for (int b = 0; b < nb; ++b) {
         if ((b & 1) == 0) {
-            const int p = b >> 1;
+            const int64_t pb = (int64_t)(b >> 1) * M;
 #pragma unroll
             for (int q = 0; q < EXACT_GS_PER; ++q) {
-                const float2 Z = Zn[q], Zr = Zrn[q];
-                if (live[q] && p + 1 < P) {
-                    Zn[q] = pimgs[(int64_t)(p + 1) * M + mi[q]];
-                    Zrn[q] = pimgs[(int64_t)(p + 1) * M + mn[q]];
+                float2 Z = make_float2(0.0f, 0.0f), Zr = Z;
+                if (live[q]) {
+                    Z = pimgs[pb + mi[q]];
+                    Zr = pimgs[pb + mn[q]];
                 }
                 Fa[q] = make_float2(0.5f * (Z.x + Zr.x), 0.5f * (Z.y - Zr.y));
                 Fb[q] = make_float2(0.5f * (Z.y + Zr.y), 0.5f * (Zr.x - Z.x));
