@@ -200,31 +200,38 @@ __global__ void __launch_bounds__(256) k_exact_mask(const ERec *__restrict__ rec
     if (t_out && in) t_out[pix] = T;
 }
 
-// One thread per frequency (FFT order): U_c += a_{k,c} o_k H_c(nu, -z_k) FFT(T u_k) / (Nx Ny),
-// with FFT(T u_k) = e^{j phi_k} F_k separated from the packed transform Z of a pair (a, b):
-// F_a(m) = (Z(m) + conj Z(-m)) / 2, F_b(m) = (Z(m) - conj Z(-m)) / 2j.
+// U_c += a_{k,c} o_k H_c(nu, -z_k) FFT(T u_k) / (Nx Ny), with FFT(T u_k) = e^{j phi_k} F_k
+// separated from the packed transform Z of a pair (a, b): F_a(m) = (Z(m) + conj Z(-m)) / 2,
+// F_b(m) = (Z(m) - conj Z(-m)) / 2j.  The profiles are real, so F(-m) = conj F(m), and
+// H(nu, -z) depends on |nu| only: one thread takes the frequencies m and -m together, reads
+// Z at both once and evaluates H once for the two.  Threads cover rows 0 .. Ny / 2; in the
+// rows 0 and Ny / 2 (their own mirror) only columns 0 .. Nx / 2 (the rest are partners).
 __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
                                                      const float2 *__restrict__ imgs, float2 *__restrict__ spec)
 {
-    const int64_t M = (int64_t)k.nx * k.ny;
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
-    const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
-    const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
+    const int nx = k.nx, ny = k.ny, hy = ny / 2;
+    const int64_t M = (int64_t)nx * ny;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)(hy + 1) * nx) return;
+    const int my = (int)(t / nx), mx = (int)(t - (int64_t)my * nx);
+    if ((my == 0 || my == hy) && 2 * mx > nx) return;  // its partner's thread takes it
+    const int64_t m = (int64_t)my * nx + mx, mn = neg_freq(mx, my, nx, ny);
+    const bool pair = mn != m;
+    const int mxp = 2 * mx < nx ? mx : mx - nx, myp = 2 * my < ny ? my : my - ny;
+    const double nux = mxp / (nx * k.px), nuy = myp / (ny * k.py);
     const double nu2 = nux * nux + nuy * nuy;
-    const float scale = (float)(1.0 / ((double)k.nx * k.ny));
+    const float scale = (float)(1.0 / ((double)nx * ny));
     double w[4];
     bool prop[4];
-    float2 acc[4];
+    float2 acc[4], accn[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const double w2 = k.inv_lambda[c] * k.inv_lambda[c] - nu2;
         prop[c] = c < k.C && w2 > 0.0;
         w[c] = prop[c] ? sqrt(w2) : 0.0;
         acc[c] = c < k.C ? spec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
+        accn[c] = (c < k.C && pair) ? spec[(int64_t)c * M + mn] : make_float2(0.0f, 0.0f);
     }
-    const int64_t mn = neg_freq(mx, my, k.nx, k.ny);
     const int P = (nb + 1) / 2;
     // the next pair's values are fetched while this pair is applied
     float2 Zn = make_float2(0.0f, 0.0f), Zrn = Zn;
@@ -251,24 +258,31 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
         const float4 ramp = *reinterpret_cast<const float4 *>(rr.amp);
         if (!valid) continue;
         const float2 F = (b & 1) ? Fb : Fa;
-        const float2 S = make_float2(cph * F.x - sph * F.y, cph * F.y + sph * F.x);  // e^{j phi} F
+        // e^{j phi} F at m and e^{j phi} conj(F) at -m
+        const float2 S = make_float2(cph * F.x - sph * F.y, cph * F.y + sph * F.x);
+        const float2 Sn = make_float2(cph * F.x + sph * F.y, sph * F.x - cph * F.y);
         const float ampc[4] = {ramp.x, ramp.y, ramp.z, ramp.w};
         const double zd = (double)rz;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!prop[c]) continue;
             const double ph = -zd * w[c];  // revolutions of H(nu, -z)
-            const float t = (float)(ph - floor(ph));
-            const float cs = __builtin_amdgcn_cosf(t), sn = __builtin_amdgcn_sinf(t);
+            const float tt = (float)(ph - floor(ph));
+            const float cs = __builtin_amdgcn_cosf(tt), sn = __builtin_amdgcn_sinf(tt);
             const float A = ampc[c] * scale;
             const float hr = A * cs, hi = A * sn;
             acc[c].x = fmaf(hr, S.x, fmaf(-hi, S.y, acc[c].x));
             acc[c].y = fmaf(hr, S.y, fmaf(hi, S.x, acc[c].y));
+            accn[c].x = fmaf(hr, Sn.x, fmaf(-hi, Sn.y, accn[c].x));
+            accn[c].y = fmaf(hr, Sn.y, fmaf(hi, Sn.x, accn[c].y));
         }
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        if (c < k.C) spec[(int64_t)c * M + m] = acc[c];
+        if (c < k.C) {
+            spec[(int64_t)c * M + m] = acc[c];
+            if (pair) spec[(int64_t)c * M + mn] = accn[c];
+        }
 }
 
 // Per batch image: the columns and rows of the profile's window, as (first, count) on the
@@ -339,7 +353,8 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
                            eb.rowwin, eb.pcolwin, eb.prowwin);
         e = launch_fft2d_win(p, (nb + 1) / 2, -1, eb.pimgs, eb.pimgs, eb.pcolwin, eb.prowwin, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_exact_splat, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec, (int)b0, nb, k,
+        const int64_t half = (int64_t)(k.ny / 2 + 1) * k.nx;  // frequencies m, -m taken together
+        hipLaunchKernelGGL(k_exact_splat, dim3((unsigned)((half + 255) / 256)), dim3(256), 0, s, rec, (int)b0, nb, k,
                            eb.pimgs, spec);
     }
     return hipGetLastError();
