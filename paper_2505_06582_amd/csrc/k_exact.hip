@@ -378,11 +378,9 @@ constexpr int EXACT_BTILE = 8;          // 8 x 8 pixels: one wavefront per work-
 constexpr int EXACT_NSPEC = 12;         // Re/Im P_c, Re/Im Q_c for c < 3
 constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, Sphi, So, pad
 
-// Two frequencies per thread (strided by the work-group size; few enough registers for eight
-// wavefronts per SIMD): spectral partial sums per (work-group, Gaussian) and, in place of
-// F_k, V_k = sum_c A_c Gs_c conj(H_c).
-constexpr int EXACT_GS_PER = 2;
-
+// One thread per frequency pair {m, -m} (as in k_exact_splat; F(-m) = conj F(m), H shared):
+// spectral partial sums per (work-group, Gaussian) and V_k = sum_c A_c Gs_c conj(H_c) at both
+// frequencies, written to imgs (F_k comes from the packed pairs in pimgs).
 __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
                                                       const float2 *__restrict__ gspec,
                                                       const float2 *__restrict__ pimgs, float2 *__restrict__ imgs,
@@ -391,50 +389,43 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
     // per wave and batch Gaussian, the wave's 12 sums: the four waves are summed in a fixed
     // order once, after the batch, so the waves never wait for each other inside it
     __shared__ float s_red[4][64][16];
-    const int64_t M = (int64_t)k.nx * k.ny;
+    const int nx = k.nx, ny = k.ny, hy = ny / 2;
+    const int64_t M = (int64_t)nx * ny;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int mi[EXACT_GS_PER], mn[EXACT_GS_PER];  // frequency m and -m (M < 2^31)
-    bool live[EXACT_GS_PER];
-    double w[EXACT_GS_PER][3];
-    bool prop[EXACT_GS_PER][3];
-    float2 gs[EXACT_GS_PER][3];
-#pragma unroll
-    for (int q = 0; q < EXACT_GS_PER; ++q) {
-        const int64_t m = ((int64_t)blockIdx.x * EXACT_GS_PER + q) * blockDim.x + threadIdx.x;
-        mi[q] = (int)m;
-        mn[q] = 0;
-        live[q] = m < M;
-        double nu2 = 0.0;
-        if (live[q]) {
-            const int mx = (int)(m % k.nx), my = (int)(m / k.nx);
-            mn[q] = (int)neg_freq(mx, my, k.nx, k.ny);
-            const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
-            const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
-            nu2 = nux * nux + nuy * nuy;
-        }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int my = (int)(t / nx), mx = (int)(t - (int64_t)my * nx);
+    // rows 0 .. Ny / 2; in the rows 0 and Ny / 2 only columns 0 .. Nx / 2 (the rest are partners)
+    const bool live = t < (int64_t)(hy + 1) * nx && !((my == 0 || my == hy) && 2 * mx > nx);
+    if (!live) mx = my = 0;
+    const int m = my * nx + mx, mn = (int)neg_freq(mx, my, nx, ny);  // M < 2^31
+    const bool pair = live && mn != m;
+    double w[3];
+    bool prop[3];
+    float2 gs0[3], gs1[3];  // Gs_c at m and at -m
+    {
+        const int mxp = 2 * mx < nx ? mx : mx - nx, myp = 2 * my < ny ? my : my - ny;
+        const double nux = mxp / (nx * k.px), nuy = myp / (ny * k.py);
+        const double nu2 = nux * nux + nuy * nuy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double w2 = k.inv_lambda[c] * k.inv_lambda[c] - nu2;
-            prop[q][c] = live[q] && c < k.C && w2 > 0.0;
-            w[q][c] = prop[q][c] ? sqrt(w2) : 0.0;
-            gs[q][c] = (live[q] && c < k.C) ? gspec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
+            prop[c] = live && c < k.C && w2 > 0.0;
+            w[c] = prop[c] ? sqrt(w2) : 0.0;
+            gs0[c] = (live && c < k.C) ? gspec[(int64_t)c * M + m] : make_float2(0.0f, 0.0f);
+            gs1[c] = (pair && c < k.C) ? gspec[(int64_t)c * M + mn] : make_float2(0.0f, 0.0f);
         }
     }
-    // F_k from the packed transforms of pairs (see k_exact_splat); V_k goes to imgs
-    float2 Fa[EXACT_GS_PER], Fb[EXACT_GS_PER];
+    float2 Fa = make_float2(0.0f, 0.0f), Fb = Fa;
     for (int b = 0; b < nb; ++b) {
         if ((b & 1) == 0) {
             const int64_t pb = (int64_t)(b >> 1) * M;
-#pragma unroll
-            for (int q = 0; q < EXACT_GS_PER; ++q) {
-                float2 Z = make_float2(0.0f, 0.0f), Zr = Z;
-                if (live[q]) {
-                    Z = pimgs[pb + mi[q]];
-                    Zr = pimgs[pb + mn[q]];
-                }
-                Fa[q] = make_float2(0.5f * (Z.x + Zr.x), 0.5f * (Z.y - Zr.y));
-                Fb[q] = make_float2(0.5f * (Z.y + Zr.y), 0.5f * (Zr.x - Z.x));
+            float2 Z = make_float2(0.0f, 0.0f), Zr = Z;
+            if (live) {
+                Z = pimgs[pb + m];
+                Zr = pimgs[pb + mn];
             }
+            Fa = make_float2(0.5f * (Z.x + Zr.x), 0.5f * (Z.y - Zr.y));
+            Fb = make_float2(0.5f * (Z.y + Zr.y), 0.5f * (Zr.x - Z.x));
         }
         const ERec &rr = rec[b0 + b];
         // the fields used below, loaded together
@@ -446,34 +437,38 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
 #pragma unroll
         for (int i = 0; i < EXACT_NSPEC; ++i) v[i] = 0.0f;
         const double zd = (double)rz;
+        float2 V0 = make_float2(0.0f, 0.0f), V1 = V0;
+        if (live && valid) {
+            const float2 F = (b & 1) ? Fb : Fa;
+            // e^{j phi} F at m and e^{j phi} conj(F) at -m
+            const float2 S0 = make_float2(cph * F.x - sph * F.y, cph * F.y + sph * F.x);
+            const float2 S1 = make_float2(cph * F.x + sph * F.y, sph * F.x - cph * F.y);
 #pragma unroll
-        for (int q = 0; q < EXACT_GS_PER; ++q) {
-            float2 V = make_float2(0.0f, 0.0f);
-            if (live[q] && valid) {
-                const float2 Fr = (b & 1) ? Fb[q] : Fa[q];
-                const float2 F = make_float2(cph * Fr.x - sph * Fr.y, cph * Fr.y + sph * Fr.x);  // e^{j phi} F
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (!prop[q][c]) continue;
-                    const double ph = -zd * w[q][c];
-                    const float t = (float)(ph - floor(ph));
-                    const float hc = __builtin_amdgcn_cosf(t), hs = __builtin_amdgcn_sinf(t);
-                    // X = conj(Gs) H F
-                    const float hfr = hc * F.x - hs * F.y, hfi = hc * F.y + hs * F.x;
-                    const float xr = gs[q][c].x * hfr + gs[q][c].y * hfi, xi = gs[q][c].x * hfi - gs[q][c].y * hfr;
-                    const float wf = (float)w[q][c];
-                    v[4 * c + 0] += xr;
-                    v[4 * c + 1] += xi;
-                    v[4 * c + 2] = fmaf(wf, xr, v[4 * c + 2]);
-                    v[4 * c + 3] = fmaf(wf, xi, v[4 * c + 3]);
-                    // V += A_c Gs conj(H)
-                    const float A = ampc[c];
-                    V.x = fmaf(A, gs[q][c].x * hc + gs[q][c].y * hs, V.x);
-                    V.y = fmaf(A, gs[q][c].y * hc - gs[q][c].x * hs, V.y);
-                }
+            for (int c = 0; c < 3; ++c) {
+                if (!prop[c]) continue;
+                const double ph = -zd * w[c];
+                const float tt = (float)(ph - floor(ph));
+                const float hc = __builtin_amdgcn_cosf(tt), hs = __builtin_amdgcn_sinf(tt);
+                // X = conj(Gs) H F at m and at -m (zero there when -m = m: gs1 = 0)
+                const float h0r = hc * S0.x - hs * S0.y, h0i = hc * S0.y + hs * S0.x;
+                const float h1r = hc * S1.x - hs * S1.y, h1i = hc * S1.y + hs * S1.x;
+                const float xr = gs0[c].x * h0r + gs0[c].y * h0i + gs1[c].x * h1r + gs1[c].y * h1i;
+                const float xi = gs0[c].x * h0i - gs0[c].y * h0r + gs1[c].x * h1i - gs1[c].y * h1r;
+                const float wf = (float)w[c];
+                v[4 * c + 0] += xr;
+                v[4 * c + 1] += xi;
+                v[4 * c + 2] = fmaf(wf, xr, v[4 * c + 2]);
+                v[4 * c + 3] = fmaf(wf, xi, v[4 * c + 3]);
+                // V += A_c Gs conj(H)
+                const float A = ampc[c];
+                V0.x = fmaf(A, gs0[c].x * hc + gs0[c].y * hs, V0.x);
+                V0.y = fmaf(A, gs0[c].y * hc - gs0[c].x * hs, V0.y);
+                V1.x = fmaf(A, gs1[c].x * hc + gs1[c].y * hs, V1.x);
+                V1.y = fmaf(A, gs1[c].y * hc - gs1[c].x * hs, V1.y);
             }
-            if (live[q]) imgs[(int64_t)b * M + mi[q]] = V;
         }
+        if (live) imgs[(int64_t)b * M + m] = V0;
+        if (pair) imgs[(int64_t)b * M + mn] = V1;
         // one transposed butterfly over the 12 sums (padded to 16): afterwards lane l with
         // bits 0-2 clear holds sums 2 (4 b5 + 2 b4 + b3) and that + 1
         float x[16];
@@ -681,7 +676,7 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
     const dim3 tiles((k.nx + EXACT_TILE - 1) / EXACT_TILE, (k.ny + EXACT_TILE - 1) / EXACT_TILE);
     const dim3 btiles((k.nx + EXACT_BTILE - 1) / EXACT_BTILE, (k.ny + EXACT_BTILE - 1) / EXACT_BTILE);
     const unsigned mblk = (unsigned)((M + 255) / 256);
-    const unsigned gsblk = (unsigned)((M + 256 * EXACT_GS_PER - 1) / (256 * EXACT_GS_PER));
+    const unsigned gsblk = (unsigned)(((int64_t)(k.ny / 2 + 1) * k.nx + 255) / 256);  // pairs {m, -m}
     // forward sweep of the map, checkpointed at every batch start
     hipLaunchKernelGGL(k_exact_fill1, dim3(mblk), dim3(256), 0, s, eb.tmap, M, 1.0f);
     for (int64_t q = 0; q < nbatch; ++q) {
