@@ -422,10 +422,10 @@ def bench_exact(args):
     M, C = grid.nx * grid.ny, grid.n_lambda
     t = res["exact"]["stage_ms"]["accumulate"] * 1e-3
     # per Gaussian, the least the FFT route must move: two Gaussians' real masked profiles
-    # share one complex image, whose full spectrum the transform writes once (8 M bytes per
-    # pair) and the splat reads at m and -m (8 M bytes per Gaussian): 12 M bytes (the window
-    # strips the transform also moves are left out)
-    bytes_alg = scene.n * 12.0 * M
+    # share one complex image, whose full spectrum the transform writes once and the splat
+    # reads once (8 M bytes per pair each way): 8 M bytes per Gaussian (the window strips the
+    # transform also moves are left out)
+    bytes_alg = scene.n * 8.0 * M
     out = {"metric": "exact-blending forward holograms/s, 1000 Gaussians at 1080x1920x3",
            "value": 1e3 / res["exact"]["ms_per_forward"], "unit": "holograms/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["exact"]["ms_per_forward"],
@@ -434,7 +434,7 @@ def bench_exact(args):
            "variants": res,
            "roofline": {"bound": "hbm", "achieved": bytes_alg / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                         "frac": bytes_alg / t / PEAK_HBM, "traffic": None, "kernel": "exact mask + FFT + splat",
-                        "work_per_launch": "12 x M bytes per Gaussian (a pair's packed spectrum written once, read at m and -m)"}}
+                        "work_per_launch": "8 x M bytes per Gaussian (a pair's packed spectrum written once and read once)"}}
     print(json.dumps(out), flush=True)
 
 
