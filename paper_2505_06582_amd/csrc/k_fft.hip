@@ -687,9 +687,10 @@ hipError_t launch_fft2d(const Plan &p, int batch, int direction, const float2 *i
 }
 
 // Rows then columns.  With windows, the input of each image is nonzero only inside its
-// rectangle colwin x rowwin (rowwin may be NULL: all rows): columns first, only colwin's
-// columns, loading only the rectangle; then every row, loading only colwin's columns (what
-// lies outside the rectangle is never read, so it need not be zero).  In place.
+// rectangles colwin.xy x rowwin.xy and colwin.zw x rowwin.zw (rowwin may be NULL: all rows):
+// columns first, only colwin's columns, loading only the rectangles; then every row, loading
+// only colwin's columns (what lies outside the rectangles is never read, so it need not be
+// zero).  In place.
 hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float2 *in, float2 *out,
                             const int4 *colwin, const int4 *rowwin, hipStream_t s)
 {
