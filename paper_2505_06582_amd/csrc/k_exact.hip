@@ -588,20 +588,22 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
 }
 
 // One work-group per batch Gaussian: fixed-order sums of its partials, then the chain rule.
-__global__ void __launch_bounds__(256) k_exact_gfinal(const ERec *__restrict__ rec, int b0, GView g, Consts k,
+constexpr int EXACT_GF_THREADS = 512;  // one work-group per Gaussian: 8 wavefronts of loads in flight
+__global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *__restrict__ rec, int b0, GView g, Consts k,
                                                       const uint32_t *__restrict__ order,
                                                       const float *__restrict__ pspec, int nblk_spec,
                                                       const float *__restrict__ pspat, int ntile, GradView out)
 {
-    __shared__ double s_red[4][EXACT_NSPEC + EXACT_NSPAT];
+    constexpr int NW = EXACT_GF_THREADS / 64;
+    __shared__ double s_red[NW][EXACT_NSPEC + EXACT_NSPAT];
     const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double acc[EXACT_NSPEC + EXACT_NSPAT];
 #pragma unroll
     for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) acc[i] = 0.0;
-    for (int q = t; q < nblk_spec; q += 256)
+    for (int q = t; q < nblk_spec; q += EXACT_GF_THREADS)
 #pragma unroll
         for (int i = 0; i < EXACT_NSPEC; ++i) acc[i] += (double)pspec[((int64_t)b * nblk_spec + q) * EXACT_NSPEC + i];
-    for (int q = t; q < ntile; q += 256)
+    for (int q = t; q < ntile; q += EXACT_GF_THREADS)
 #pragma unroll
         for (int i = 0; i < EXACT_NSPAT; ++i) acc[EXACT_NSPEC + i] += (double)pspat[((int64_t)b * ntile + q) * EXACT_NSPAT + i];
 #pragma unroll
@@ -615,7 +617,11 @@ __global__ void __launch_bounds__(256) k_exact_gfinal(const ERec *__restrict__ r
     if (t != 0) return;
     double S[EXACT_NSPEC + EXACT_NSPAT];
 #pragma unroll
-    for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) S[i] = s_red[0][i] + s_red[1][i] + s_red[2][i] + s_red[3][i];
+    for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) {
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += s_red[w][i];  // fixed order
+        S[i] = v;
+    }
     const ERec &r = rec[b0 + b];
     const int64_t j = order[b0 + b];
     const double inv = 1.0 / ((double)k.nx * k.ny);
@@ -703,7 +709,8 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_back, btiles, dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, k.px, k.py, rscale,
                            bb.ckpt + q * M, bb.dmap, eb.imgs, bb.pspat);
-        hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(256), 0, s, rec, (int)b0, g, k, order, bb.pspec, (int)gsblk,
+        hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(EXACT_GF_THREADS), 0, s, rec, (int)b0, g, k, order, bb.pspec,
+                           (int)gsblk,
                            bb.pspat, (int)(btiles.x * btiles.y), out);
     }
     return hipGetLastError();
