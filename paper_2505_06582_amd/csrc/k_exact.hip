@@ -8,12 +8,16 @@
 // and alpha_k = o_k g_k, dropped where it does not exceed 1/255, updates the map.
 //
 // The map makes the work sequential in k, so it runs in batches of B Gaussians:
-//   k_exact_mask   one work-group per 16 x 16 pixel tile: walks the batch in order, writes
-//                  T u_k of every batch Gaussian into its own full-grid image (zero where
-//                  the Gaussian's eps-window misses the tile) and updates T in place;
-//   (FFT)          the batched forward 2D transform of the B images (k_fft);
-//   k_exact_splat  one thread per frequency: H(nu, -z_k) with the phase -z_k sqrt(1/l^2 -
-//                  |nu|^2) reduced in FP64, times a_{k,c} o_k, accumulated into the spectrum.
+//   k_exact_mask   one work-group per 16 x 16 pixel tile: walks the batch Gaussians whose
+//                  window meets the tile in order, writes the real masked profiles T g_k of
+//                  Gaussians 2p and 2p + 1 as the real and imaginary parts of image p (inside
+//                  the pair's window rectangles only) and updates T in place;
+//   (FFT)          the batched forward 2D transform of the B / 2 packed images (k_fft), only
+//                  over the windows' columns and rectangles;
+//   k_exact_splat  one thread per frequency pair {m, -m}: separates the pair's transforms by
+//                  Hermitian symmetry, applies e^{j phi_k} and H(nu, -z_k) (the phase
+//                  -z_k sqrt(1/l^2 - |nu|^2) reduced in FP64) times a_{k,c} o_k, and
+//                  accumulates into the spectrum.
 // The spectrum is kept in the library's convention (U (-1)^{m'} / (Nx Ny px py), FFT order),
 // so DFT(T u_k)(nu_m) = px py (-1)^{m'} FFT(T u_k)[m] enters as FFT(T u_k)[m] / (Nx Ny).
 // The profile is truncated where it falls below eps of its peak (the same eps as the
