@@ -402,11 +402,12 @@ static gws_status check_offsets(int S, const int64_t *offsets, int64_t n)
     return GWS_OK;
 }
 
-// Workspace of the exact-blending forward: sort buffers, records, transmittance map, one
-// batch of full-grid images, the spectrum, and the bf16 DFT's intermediate when used.
+// Workspace of exact blending: sort buffers, records, transmittance map, one batch of
+// full-grid images (two Gaussians each), the spectrum, the bf16 DFT's intermediate when used,
+// and the adjoint's buffers.
 struct ExactLayout {
     size_t off_keys_a = 0, off_keys_b = 0, off_vals_a = 0, off_vals_b = 0, off_sort_hist = 0, off_rec = 0,
-           off_tmap = 0, off_imgs = 0, off_spec = 0, off_dft = 0, off_gspec = 0, off_ckpt = 0, off_dmap = 0,
+           off_tmap = 0, off_spec = 0, off_dft = 0, off_gspec = 0, off_ckpt = 0, off_dmap = 0,
            off_pspec = 0, off_pspat = 0, off_win = 0, off_pimgs = 0, total = 0;
     int sort_blocks = 1;
 };
@@ -425,7 +426,6 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
     L.off_sort_hist = take(sizeof(uint32_t) * 256 * L.sort_blocks);
     L.off_rec = take((size_t)64 * n);
     L.off_tmap = take(sizeof(float) * M);
-    L.off_imgs = take(sizeof(float2) * M * exact_batch(p->nx, p->ny));
     L.off_pimgs = take(sizeof(float2) * M * ((exact_batch(p->nx, p->ny) + 1) / 2));
     L.off_spec = take(sizeof(float2) * M * p->n_lambda);
     L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? sizeof(float2) * M * p->n_lambda : 1);
@@ -872,7 +872,6 @@ static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const
     eb.sort_blocks = L.sort_blocks;
     eb.rec = (void *)(base + L.off_rec);
     eb.tmap = (float *)(base + L.off_tmap);
-    eb.imgs = (float2 *)(base + L.off_imgs);
     eb.pimgs = (float2 *)(base + L.off_pimgs);
     eb.colwin = (int4 *)(base + L.off_win);
     eb.rowwin = eb.colwin + 64;
@@ -917,7 +916,6 @@ static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, cons
     eb.sort_blocks = L.sort_blocks;
     eb.rec = (void *)(base + L.off_rec);
     eb.tmap = (float *)(base + L.off_tmap);
-    eb.imgs = (float2 *)(base + L.off_imgs);
     eb.pimgs = (float2 *)(base + L.off_pimgs);
     eb.colwin = (int4 *)(base + L.off_win);
     eb.rowwin = eb.colwin + 64;

@@ -355,8 +355,9 @@ struct ExactBuffers {
     int sort_blocks;
     void *rec;     // 64-byte records, front to back
     float *tmap;   // transmittance [ny][nx]
-    float2 *imgs;   // the adjoint's per-Gaussian images of one batch [B][ny][nx]
-    float2 *pimgs;  // masked profiles of one batch, two Gaussians per image [(B + 1) / 2][ny][nx]
+    float2 *pimgs;  // one batch, two Gaussians per image [(B + 1) / 2][ny][nx]: the masked
+                    // profiles and their transforms; in the adjoint also the spectra whose
+                    // inverse transforms are the real maps r_k
     int4 *colwin, *rowwin;    // per batch Gaussian: window columns / rows as (first, count, 0, 0)
     int4 *pcolwin, *prowwin;  // per packed image: the two Gaussians' windows
 };

@@ -370,24 +370,28 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
 // which splits into
 //   * the spectral sums P_{k,c} = sum_m conj(Gs_c) H F_k and Q_{k,c} = sum_m W_c conj(Gs_c) H F_k
 //     (W_c = sqrt(1/l^2 - |nu|^2)): dL/da_c = o Re P_c / NxNy, dL/do gains sum_c a_c Re P_c / NxNy,
-//     dL/dz = 2 pi sum_c A_c Im Q_c / NxNy (dH/dz = -j 2 pi W H);
-//   * the spatial part Re sum_x d(T_k u_k) conj(R_k), R_k = IFFT(sum_c A_c Gs_c conj(H_c)) / NxNy.
-//     Through u_k = e^{j phi} g_k it gives the mean, covariance and phase gradients; through the
-//     map, with w_k = Re(u_k conj R_k), dL/d alpha_j(x) = -T_j(x) D_j(x), where
+//     dL/dz = 2 pi sum_c A_c Im Q_c / NxNy (dH/dz = -j 2 pi W H), and, since phi enters only
+//     through the factor e^{j phi} of F_k, dL/dphi = -sum_c A_c Im P_c / NxNy;
+//   * the spatial part Re sum_x d(T_k g_k) r_k with the real r_k = Re(e^{-j phi} R_k),
+//     R_k = IFFT(sum_c A_c Gs_c conj(H_c)) / NxNy.  Through g_k it gives the mean and covariance
+//     gradients; through the map, with w_k = g_k r_k, dL/d alpha_j(x) = -T_j(x) D_j(x), where
 //     D_j = sum_{k > j} w_k prod_{j < i < k} (1 - alpha_i) is accumulated back to front
 //     (D_{j-1} = w_j + (1 - alpha_j) D_j): the map is recomputed from per-batch checkpoints and
 //     never divided by (1 - alpha).
 // ---------------------------------------------------------------------------------
 constexpr int EXACT_BTILE = 8;          // 8 x 8 pixels: one wavefront per work-group
 constexpr int EXACT_NSPEC = 12;         // Re/Im P_c, Re/Im Q_c for c < 3
-constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, Sphi, So, pad
+constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, So, pad, pad
 
 // One thread per frequency pair {m, -m} (as in k_exact_splat; F(-m) = conj F(m), H shared):
-// spectral partial sums per (work-group, Gaussian) and V_k = sum_c A_c Gs_c conj(H_c) at both
-// frequencies, written to imgs (F_k comes from the packed pairs in pimgs).
+// spectral partial sums per (work-group, Gaussian), and the spectra whose inverse transforms
+// give r_k.  With V_k = sum_c A_c Gs_c conj(H_c) and V'_k = e^{-j phi_k} V_k, r_k is the
+// inverse transform of the Hermitian part Vh_k(m) = (V'_k(m) + conj V'_k(-m)) / 2, which is
+// real, so Gaussians 2p and 2p + 1 share one image: Vh_{2p} + j Vh_{2p+1} overwrites the packed
+// transform of pair p in pimgs (each thread reads its own two entries of image p before it
+// writes them).
 __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ rec, int b0, int nb, Consts k,
-                                                      const float2 *__restrict__ gspec,
-                                                      const float2 *__restrict__ pimgs, float2 *__restrict__ imgs,
+                                                      const float2 *__restrict__ gspec, float2 *pimgs,
                                                       float *__restrict__ part)
 {
     // per wave and batch Gaussian, the wave's 12 sums: the four waves are summed in a fixed
@@ -420,9 +424,10 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
         }
     }
     float2 Fa = make_float2(0.0f, 0.0f), Fb = Fa;
+    float2 Ha = Fa;  // Vh of the pair's first Gaussian at m
     for (int b = 0; b < nb; ++b) {
+        const int64_t pb = (int64_t)(b >> 1) * M;
         if ((b & 1) == 0) {
-            const int64_t pb = (int64_t)(b >> 1) * M;
             float2 Z = make_float2(0.0f, 0.0f), Zr = Z;
             if (live) {
                 Z = pimgs[pb + m];
@@ -471,8 +476,22 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
                 V1.y = fmaf(A, gs1[c].y * hc - gs1[c].x * hs, V1.y);
             }
         }
-        if (live) imgs[(int64_t)b * M + m] = V0;
-        if (pair) imgs[(int64_t)b * M + mn] = V1;
+        // V' = e^{-j phi} V at m and -m, and Vh(m) (at a frequency that is its own mirror, the
+        // real part of V'(m))
+        const float2 P0 = make_float2(cph * V0.x + sph * V0.y, cph * V0.y - sph * V0.x);
+        const float2 P1 = make_float2(cph * V1.x + sph * V1.y, cph * V1.y - sph * V1.x);
+        const float2 Hm = pair ? make_float2(0.5f * (P0.x + P1.x), 0.5f * (P0.y - P1.y)) : make_float2(P0.x, 0.0f);
+        if ((b & 1) == 0) {
+            Ha = Hm;
+            if (b + 1 == nb && live) {  // no partner: Vh alone, Hermitian
+                pimgs[pb + m] = Ha;
+                if (pair) pimgs[pb + mn] = make_float2(Ha.x, -Ha.y);
+            }
+        } else if (live) {
+            // Vh_a + j Vh_b at m, and conj Vh_a + j conj Vh_b at -m
+            pimgs[pb + m] = make_float2(Ha.x - Hm.y, Ha.y + Hm.x);
+            if (pair) pimgs[pb + mn] = make_float2(Ha.x + Hm.y, Hm.x - Ha.y);
+        }
         // one transposed butterfly over the 12 sums (padded to 16): afterwards lane l with
         // bits 0-2 clear holds sums 2 (4 b5 + 2 b4 + b3) and that + 1
         float x[16];
@@ -560,10 +579,9 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
                 // Sigma^-1 d in pixel units (natural-log exponent -1/2 d^T Sigma^-1 d), then metres
                 const float ex = ln2x2 * (r.qa * dx + 0.5f * r.qb * dy) / (float)px_m;
                 const float ey = ln2x2 * (0.5f * r.qb * dx + r.qc * dy) / (float)py_m;
-                const float2 Rv = R[(int64_t)b * M + pix];
-                const float rr = Rv.x * rscale, ri = Rv.y * rscale;
-                // z = e^{j phi} conj(R)
-                const float zr = r.cphi * rr + r.sphi * ri, zi = r.sphi * rr - r.cphi * ri;
+                // r_k: Gaussian 2p in the real part of image p, 2p + 1 in the imaginary part
+                const float2 Rv = R[(int64_t)(b >> 1) * M + pix];
+                const float zr = ((b & 1) ? Rv.y : Rv.x) * rscale;
                 const float alpha = r.o * gk;
                 const bool kept = alpha > EXACT_T_EPS;
                 const float ga = kept ? -Tb * D : 0.0f;         // dL/d alpha at this pixel
@@ -574,8 +592,7 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
                 v[2] = cgg * ex * ex;
                 v[3] = cgg * ex * ey;
                 v[4] = cgg * ey * ey;
-                v[5] = -Tb * gk * zi;                          // phase
-                v[6] = ga * gk;                                // opacity through alpha
+                v[5] = ga * gk;                                // opacity through alpha
                 D = fmaf(kept ? 1.0f - alpha : 1.0f, D, gk * zr);
             }
             // one transposed butterfly over the 8 sums: afterwards lane l with bits 0-2 clear
@@ -629,7 +646,7 @@ __global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *_
     const ERec &r = rec[b0 + b];
     const int64_t j = order[b0 + b];
     const double inv = 1.0 / ((double)k.nx * k.ny);
-    double d_o = S[EXACT_NSPEC + 6], d_z = 0.0;
+    double d_o = S[EXACT_NSPEC + 5], d_z = 0.0, d_phi = 0.0;
     const double o = g.opacity[j];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -639,6 +656,7 @@ __global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *_
         if (out.amplitude) out.amplitude[(int64_t)c * out.amp_stride + j] = r.valid ? (float)(o * rp) : 0.0f;
         d_o += a * rp;
         d_z += 2.0 * M_PI * (double)r.amp[c] * iq;
+        d_phi -= (double)r.amp[c] * S[4 * c + 1] * inv;
     }
     const double* P = S + EXACT_NSPEC;
     const bool ok = r.valid != 0;
@@ -647,7 +665,7 @@ __global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *_
     if (out.cov_xx) out.cov_xx[j] = ok ? (float)(0.5 * P[2]) : 0.0f;
     if (out.cov_xy) out.cov_xy[j] = ok ? (float)P[3] : 0.0f;
     if (out.cov_yy) out.cov_yy[j] = ok ? (float)(0.5 * P[4]) : 0.0f;
-    if (out.phase) out.phase[j] = ok ? (float)P[5] : 0.0f;
+    if (out.phase) out.phase[j] = ok ? (float)d_phi : 0.0f;
     if (out.opacity) out.opacity[j] = ok ? (float)d_o : 0.0f;
     if (out.depth) out.depth[j] = ok ? (float)d_z : 0.0f;
 }
@@ -707,12 +725,12 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
         e = launch_fft2d_win(p, (nb + 1) / 2, -1, eb.pimgs, eb.pimgs, eb.pcolwin, eb.prowwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_gsplat, dim3(gsblk), dim3(256), 0, s, rec, (int)b0, nb, k, bb.gspec, eb.pimgs,
-                           eb.imgs, bb.pspec);
-        // R is read only inside each window: full row pass, columns of the window only
-        e = launch_fft2d_cols_out(p, nb, +1, eb.imgs, eb.colwin, s);
+                           bb.pspec);
+        // r is read only inside each window: full row pass, columns of the pair's windows only
+        e = launch_fft2d_cols_out(p, (nb + 1) / 2, +1, eb.pimgs, eb.pcolwin, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_back, btiles, dim3(64), 0, s, rec, (int)b0, nb, k.nx, k.ny, k.px, k.py, rscale,
-                           bb.ckpt + q * M, bb.dmap, eb.imgs, bb.pspat);
+                           bb.ckpt + q * M, bb.dmap, eb.pimgs, bb.pspat);
         hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(EXACT_GF_THREADS), 0, s, rec, (int)b0, g, k, order, bb.pspec,
                            (int)gsblk,
                            bb.pspat, (int)(btiles.x * btiles.y), out);
