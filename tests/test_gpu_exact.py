@@ -223,3 +223,23 @@ def test_render_autograd_matches_oracle(ctx, blend):
         err = rel_l2(to_numpy(params[k].grad).astype(np.float64), np.asarray(ref[k]))
         log("  render/%s %-10s rel L2 %.3g" % (blend, k, err))
         assert err < TOL_EXACT_GRAD, k
+
+
+def test_exact_backward_full_size_grid(ctx):
+    """Gradients at the benchmark's shape (1080 x 1920, three wavelengths) and launch
+    configuration, against the FP64 oracle: 17 Gaussians, so eight packed pairs and one
+    Gaussian alone in its image in the adjoint's inverse transforms."""
+    import torch
+    import paper_2505_06582_amd as gws
+    import oracle.exact_grad as eg
+    grid = gwsgen.Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    s = clustered_scene(17, grid, 2301, spread=0.05, depth_range=(-10e-3, 10e-3))
+    t = gwsgen.make_target(grid, 2351) * 0.05
+    _, u, ref = eg.exact_loss_grads(s, grid, t)
+    G = torch.from_numpy((2.0 * (u - t)).astype(np.complex64)).cuda()
+    del u
+    got = ctx.backward(problem(grid, blend=gws.BLEND_EXACT), scene_to_torch(s), G, want_depth=True)
+    for k in eg.PARAMS:
+        err = rel_l2(to_numpy(got[k]).astype(np.float64), np.asarray(ref[k]))
+        log("  full-size %-10s rel L2 %.3g" % (k, err))
+        assert err < TOL_EXACT_GRAD, k
