@@ -167,7 +167,8 @@ gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *problem, in
  * With blend = GWS_BLEND_EXACT (Eq. 5-6): depth sort, then per batch of up to 64 Gaussians
  * the masked wavefronts with the transmittance map, their batched forward FFT and the
  * propagated splat into the spectrum, then the inverse 2D transform.  The workspace for
- * EXACT holds one batch of full-grid images (about 1 GiB at 1080 x 1920). */
+ * EXACT holds one batch of full-grid complex images, two Gaussians per image (0.53 GB at
+ * 1080 x 1920, at most 1 GiB). */
 gws_status gws_forward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
                        const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
 

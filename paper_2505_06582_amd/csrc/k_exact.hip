@@ -323,9 +323,9 @@ __global__ void __launch_bounds__(256) k_exact_fill(float *__restrict__ tmap, fl
 
 size_t exact_batch(int nx, int ny)
 {
-    // up to 64 Gaussians per batch, their images within 1 GiB
+    // up to 64 Gaussians per batch, their images (two Gaussians each) within 1 GiB
     const size_t img = (size_t)nx * ny * sizeof(float2);
-    size_t b = ((size_t)1 << 30) / img;
+    size_t b = 2 * (((size_t)1 << 30) / img);
     if (b > 64) b = 64;
     if (b < 1) b = 1;
     return b;
