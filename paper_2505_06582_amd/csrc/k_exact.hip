@@ -458,22 +458,23 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
                 const double ph = -zd * w[c];
                 const float tt = (float)(ph - floor(ph));
                 const float hc = __builtin_amdgcn_cosf(tt), hs = __builtin_amdgcn_sinf(tt);
-                // X = conj(Gs) H F at m and at -m (zero there when -m = m: gs1 = 0)
-                const float h0r = hc * S0.x - hs * S0.y, h0i = hc * S0.y + hs * S0.x;
-                const float h1r = hc * S1.x - hs * S1.y, h1i = hc * S1.y + hs * S1.x;
-                const float xr = gs0[c].x * h0r + gs0[c].y * h0i + gs1[c].x * h1r + gs1[c].y * h1i;
-                const float xi = gs0[c].x * h0i - gs0[c].y * h0r + gs1[c].x * h1i - gs1[c].y * h1r;
+                // Y = Gs conj(H) at m and at -m (zero at -m when -m = m: gs1 = 0)
+                const float2 Y0 = make_float2(gs0[c].x * hc + gs0[c].y * hs, gs0[c].y * hc - gs0[c].x * hs);
+                const float2 Y1 = make_float2(gs1[c].x * hc + gs1[c].y * hs, gs1[c].y * hc - gs1[c].x * hs);
+                // X = conj(Gs) H e^{j phi} F = conj(Y) S, summed over the two frequencies
+                const float xr = Y0.x * S0.x + Y0.y * S0.y + Y1.x * S1.x + Y1.y * S1.y;
+                const float xi = Y0.x * S0.y - Y0.y * S0.x + Y1.x * S1.y - Y1.y * S1.x;
                 const float wf = (float)w[c];
                 v[4 * c + 0] += xr;
                 v[4 * c + 1] += xi;
                 v[4 * c + 2] = fmaf(wf, xr, v[4 * c + 2]);
                 v[4 * c + 3] = fmaf(wf, xi, v[4 * c + 3]);
-                // V += A_c Gs conj(H)
+                // V += A_c Y
                 const float A = ampc[c];
-                V0.x = fmaf(A, gs0[c].x * hc + gs0[c].y * hs, V0.x);
-                V0.y = fmaf(A, gs0[c].y * hc - gs0[c].x * hs, V0.y);
-                V1.x = fmaf(A, gs1[c].x * hc + gs1[c].y * hs, V1.x);
-                V1.y = fmaf(A, gs1[c].y * hc - gs1[c].x * hs, V1.y);
+                V0.x = fmaf(A, Y0.x, V0.x);
+                V0.y = fmaf(A, Y0.y, V0.y);
+                V1.x = fmaf(A, Y1.x, V1.x);
+                V1.y = fmaf(A, Y1.y, V1.y);
             }
         }
         // V' = e^{-j phi} V at m and -m, and Vh(m) (at a frequency that is its own mirror, the
