@@ -258,11 +258,11 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
         const ERec &rr = rec[b0 + b];
         // the fields used below, loaded together
         const int valid = rr.valid;
-        const float rz = rr.z, cph = rr.cphi, sph = rr.sphi;
+        const float rz = rr.z, cph = rr.cphi * scale, sph = rr.sphi * scale;
         const float4 ramp = *reinterpret_cast<const float4 *>(rr.amp);
         if (!valid) continue;
         const float2 F = (b & 1) ? Fb : Fa;
-        // e^{j phi} F at m and e^{j phi} conj(F) at -m
+        // e^{j phi} F at m and e^{j phi} conj(F) at -m, times 1 / (Nx Ny)
         const float2 S = make_float2(cph * F.x - sph * F.y, cph * F.y + sph * F.x);
         const float2 Sn = make_float2(cph * F.x + sph * F.y, sph * F.x - cph * F.y);
         const float ampc[4] = {ramp.x, ramp.y, ramp.z, ramp.w};
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(256) k_exact_splat(const ERec *__restrict__ re
             const double ph = -zd * w[c];  // revolutions of H(nu, -z)
             const float tt = (float)(ph - floor(ph));
             const float cs = __builtin_amdgcn_cosf(tt), sn = __builtin_amdgcn_sinf(tt);
-            const float A = ampc[c] * scale;
+            const float A = ampc[c];
             const float hr = A * cs, hi = A * sn;
             acc[c].x = fmaf(hr, S.x, fmaf(-hi, S.y, acc[c].x));
             acc[c].y = fmaf(hr, S.y, fmaf(hi, S.x, acc[c].y));
@@ -521,16 +521,16 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
                                                    const float *__restrict__ tck, float *__restrict__ dmap,
                                                    const float2 *__restrict__ R, float *__restrict__ part)
 {
-    __shared__ ERec s_rec[64];
+    // the map before each batch Gaussian, per pixel (each lane touches only its own column);
+    // the records are read from memory (uniform indices: scalar loads), which leaves 16 KB of
+    // LDS per work-group and ten work-groups per CU
     __shared__ float s_T[64][64];
+    const ERec *__restrict__ brec = rec + b0;
     const int lane = threadIdx.x;
     const int tx = blockIdx.x, ty = blockIdx.y;
     const int ntx = gridDim.x;
     const int px = tx * EXACT_BTILE + (lane & 7), py = ty * EXACT_BTILE + (lane >> 3);
     const bool in = px < nx && py < ny;
-    for (int i = lane; i < nb * 4; i += 64)
-        reinterpret_cast<float4 *>(s_rec)[i] = reinterpret_cast<const float4 *>(rec + b0)[i];
-    __syncthreads();
     const int64_t M = (int64_t)nx * ny;
     const int64_t pix = (int64_t)py * nx + px;
     const float tcx = tx * EXACT_BTILE + 3.5f, tcy = ty * EXACT_BTILE + 3.5f;
@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
     // leave the map, D and their partial sums (zero) unchanged here
     bool meets = false;
     if (lane < nb) {
-        const ERec &r = s_rec[lane];
+        const ERec &r = brec[lane];
         const float dcx = fabsf(wrap_d(tcx - r.cx, (float)nx)), dcy = fabsf(wrap_d(tcy - r.cy, (float)ny));
         meets = r.hwx >= 0 && dcx <= (float)r.hwx + 4.5f && dcy <= (float)r.hwy + 4.5f;
     }
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
     for (uint64_t m = hits; m; m &= m - 1) {
         const int b = __builtin_ctzll(m);
         s_T[b][lane] = T;
-        const ERec &r = s_rec[b];
+        const ERec &r = brec[b];
         const float dx = wrap_d(fx - r.cx, (float)nx), dy = wrap_d(fy - r.cy, (float)ny);
         if (fabsf(dx) <= (float)r.hwx && fabsf(dy) <= (float)r.hwy) {
             const float gk = __builtin_amdgcn_exp2f(-fmaf(r.qa * dx, dx, fmaf(r.qb * dx, dy, r.qc * dy * dy)));
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(64) k_exact_back(const ERec *__restrict__ rec,
     float D = in ? dmap[pix] : 0.0f;
     for (uint64_t m = hits; m; m &= ~(1ull << (63 - __builtin_clzll(m)))) {
         const int b = 63 - __builtin_clzll(m);
-        const ERec &r = s_rec[b];
+        const ERec &r = brec[b];
         float v[EXACT_NSPAT];
 #pragma unroll
         for (int i = 0; i < EXACT_NSPAT; ++i) v[i] = 0.0f;
