@@ -614,7 +614,8 @@ constexpr int EXACT_GF_THREADS = 512;  // one work-group per Gaussian: 8 wavefro
 __global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *__restrict__ rec, int b0, GView g, Consts k,
                                                       const uint32_t *__restrict__ order,
                                                       const float *__restrict__ pspec, int nblk_spec,
-                                                      const float *__restrict__ pspat, int ntile, GradView out)
+                                                      const float *__restrict__ pspat, int ntx, int ntile,
+                                                      GradView out)
 {
     constexpr int NW = EXACT_GF_THREADS / 64;
     __shared__ double s_red[NW][EXACT_NSPEC + EXACT_NSPAT];
@@ -625,9 +626,20 @@ __global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *_
     for (int q = t; q < nblk_spec; q += EXACT_GF_THREADS)
 #pragma unroll
         for (int i = 0; i < EXACT_NSPEC; ++i) acc[i] += (double)pspec[((int64_t)b * nblk_spec + q) * EXACT_NSPEC + i];
-    for (int q = t; q < ntile; q += EXACT_GF_THREADS)
+    // spatial partials: only the tiles near the Gaussian's window are read.  The test is the
+    // back-to-front kernel's with one pixel more of margin, so it passes every tile that kernel
+    // wrote sums for; the tiles skipped hold exact zeros and the sums are unchanged.
+    const ERec &rb = rec[b0 + b];
+    const bool any = rb.hwx >= 0;
+    const float lim_x = (float)rb.hwx + 5.5f, lim_y = (float)rb.hwy + 5.5f;
+    for (int q = t; any && q < ntile; q += EXACT_GF_THREADS) {
+        const int ty = q / ntx, tx = q - ty * ntx;
+        const float dcx = fabsf(wrap_d(tx * EXACT_BTILE + 3.5f - rb.cx, (float)k.nx));
+        const float dcy = fabsf(wrap_d(ty * EXACT_BTILE + 3.5f - rb.cy, (float)k.ny));
+        if (dcx > lim_x || dcy > lim_y) continue;
 #pragma unroll
         for (int i = 0; i < EXACT_NSPAT; ++i) acc[EXACT_NSPEC + i] += (double)pspat[((int64_t)b * ntile + q) * EXACT_NSPAT + i];
+    }
 #pragma unroll
     for (int i = 0; i < EXACT_NSPEC + EXACT_NSPAT; ++i) {
         double v = acc[i];
@@ -734,7 +746,7 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
                            bb.ckpt + q * M, bb.dmap, eb.pimgs, bb.pspat);
         hipLaunchKernelGGL(k_exact_gfinal, dim3(nb), dim3(EXACT_GF_THREADS), 0, s, rec, (int)b0, g, k, order, bb.pspec,
                            (int)gsblk,
-                           bb.pspat, (int)(btiles.x * btiles.y), out);
+                           bb.pspat, (int)btiles.x, (int)(btiles.x * btiles.y), out);
     }
     return hipGetLastError();
 }
