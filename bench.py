@@ -323,6 +323,7 @@ def bench_batched(args):
     G = torch.empty_like(fields)
     loss = torch.empty((), dtype=torch.float64, device=dev)
     grads = {k: torch.empty_like(v) for k, v in g.items()}
+    sgrads = [{k: torch.empty_like(v) for k, v in gi.items()} for gi in gs]
     stream = torch.cuda.Stream()
 
     def step_batched():
@@ -334,7 +335,7 @@ def bench_batched(args):
         for i in range(S):
             ctx.forward(prob, gs[i], out=fields[i])
             ctx.l2_loss_grad(fields[i], target[i], grad=G[i], loss=loss)
-            ctx.backward(prob, gs[i], G[i], out=grads, want_depth=False)
+            ctx.backward(prob, gs[i], G[i], out=sgrads[i], want_depth=False)
 
     res = {}
     with torch.cuda.stream(stream):

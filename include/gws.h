@@ -21,6 +21,11 @@
  *   - u_c[n] = 1/(nx ny px py) * sum_m U_c(nu_m) exp(+j 2 pi nu_m . x_n): a z = 0 Gaussian
  *     with amplitude a and opacity o peaks at a*o.
  *
+ * Results are deterministic: every reduction (partial spectra of a frequency tile, the
+ * per-Gaussian gradient sums, the loss) runs in a fixed order independent of scheduling,
+ * so the same inputs on the same device give bitwise the same outputs, batched or not.
+ * There is no non-deterministic mode.
+ *
  * Every pointer is a device pointer unless its comment says "host".  The caller owns
  * every input, output and workspace buffer; the context owns only per-shape plans
  * (tile order, twiddle tables, DFT matrices), the tuning cache and a small statistics
@@ -38,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GWS_ABI_VERSION 1
+#define GWS_ABI_VERSION 2
 #define GWS_MAX_LAMBDA 4
 
 /* Return codes.  Launch-time validation returns the code at once and leaves the
@@ -58,11 +63,14 @@ typedef enum gws_status {
 /* Blending model.  OIT is Eq. 12 (transmittance taken as 1).  EXACT is alpha wave
  * blending with a spatial transmittance map (Eq. 5-6, supplement Alg. 2): Gaussians front to
  * back (descending depth, ties by index); each splats its own wavefront e^{j phi} g(x)
- * (profile truncated below eps_support of its peak) masked by the map, propagated by
- * H(nu, -z) and scaled by a_c o; alpha = o g, dropped unless above 1/255, then updates the
- * map.  EXACT is supported by gws_forward, gws_backward (the map recomputed from per-batch
- * checkpoints, never divided by 1 - alpha), the batched calls (scene after scene) and the
- * workspace queries; gws_autotune returns GWS_ERR_UNSUPPORTED for it (it has no tiling). */
+ * (profile truncated below eps_support of its peak, and at most nx/2 - 1, ny/2 - 1 pixels from
+ * its centre: the nearest periodic image only; gws_stats.n_window_clamped counts the
+ * Gaussians cut there) masked by the map, propagated by H(nu, -z) and scaled by a_c o;
+ * alpha = o g in FP32, dropped unless above 1/255 (at pixels within FP32 rounding of the
+ * threshold either decision can be taken), then updates the map.  EXACT is supported by
+ * gws_forward, gws_backward (the map recomputed from per-batch checkpoints, never divided
+ * by 1 - alpha), the batched calls (scene after scene) and the workspace queries;
+ * gws_autotune returns GWS_ERR_UNSUPPORTED for it (it has no tiling). */
 typedef enum gws_blend { GWS_BLEND_OIT = 0, GWS_BLEND_EXACT = 1 } gws_blend;
 
 /* Inverse transform: mixed-radix FP32 FFT, or the DFT as two dense complex GEMMs on the
@@ -131,6 +139,11 @@ typedef struct gws_stats {
     int64_t n_candidates;     /* (tile, Gaussian) pairs tested */
     int32_t tile_config;      /* tiling used */
     int32_t graph_replayed;   /* batched call replayed a captured graph */
+    int64_t n_window_clamped; /* GWS_BLEND_EXACT: Gaussians whose eps-window (the profile's
+                                 extent above eps_support of its peak) reached past nx/2 - 1 or
+                                 ny/2 - 1 pixels from its centre and was cut there, so their
+                                 profile is truncated (a standard deviation above about
+                                 N / (2 sqrt(2 ln(1/eps))), N/11 at eps = 1e-7); 0 for OIT */
 } gws_stats;
 
 typedef struct gws_ctx gws_ctx;

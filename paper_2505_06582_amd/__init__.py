@@ -17,7 +17,7 @@ import threading
 from typing import Dict, Optional, Sequence
 
 __all__ = ["LIB_PATH", "GwsError", "Problem", "Context", "load_library", "render", "GaussianWaveSplat",
-           "STATUS", "XFORM_FFT_FP32", "XFORM_DFT_BF16X3"]
+           "STATUS", "XFORM_FFT_FP32", "XFORM_DFT_BF16X3", "check_gaussians", "check_tensor", "check_offsets"]
 
 # The in-tree build; GWS_LIBRARY names another build of the same library (e.g. to compare two).
 LIB_PATH = os.environ.get("GWS_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgws.so")
@@ -68,7 +68,8 @@ class _Grads(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("n_input", ctypes.c_int64), ("n_culled", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("n_items", ctypes.c_int64), ("chunk", ctypes.c_int64), ("n_pairs_evaluated", ctypes.c_int64),
-                ("n_candidates", ctypes.c_int64), ("tile_config", ctypes.c_int32), ("graph_replayed", ctypes.c_int32)]
+                ("n_candidates", ctypes.c_int64), ("tile_config", ctypes.c_int32), ("graph_replayed", ctypes.c_int32),
+                ("n_window_clamped", ctypes.c_int64)]
 
 
 class _View(ctypes.Structure):
@@ -219,16 +220,81 @@ def _torch():
     return torch
 
 
-def _gaussians_struct(g: Dict[str, "object"], n: int) -> _Gaussians:
+def check_gaussians(g: Dict[str, "object"], n_lambda: int) -> int:
+    """Number of Gaussians n after checking the sizes of the parameter tensors: every field
+    holds n elements, amplitude n_lambda * n, laid out channel-major ([n_lambda][n]).  The
+    kernels index these arrays by n alone, so a mis-sized tensor would be read out of bounds;
+    raises ValueError before anything reaches the library."""
+    missing = [k for k in PARAMS if k not in g or g[k] is None]
+    if missing:
+        raise ValueError("missing Gaussian parameters: %s" % ", ".join(missing))
+    n = int(g["mean_x"].numel())
+    for k in PARAMS:
+        t = g[k]
+        if k == "amplitude":
+            ok = (t.dim() == 1 and t.numel() == n_lambda * n) or (t.dim() == 2 and tuple(t.shape) == (n_lambda, n))
+            if not ok:
+                raise ValueError("amplitude must have shape (%d, %d) (n_lambda, n) or %d elements, got %s"
+                                 % (n_lambda, n, n_lambda * n, tuple(t.shape)))
+        elif t.numel() != n:
+            raise ValueError("%s has %d elements, mean_x has %d" % (k, t.numel(), n))
+    return n
+
+
+def check_tensor(t, name: str, shape, dtype_name: str):
+    """Shape, dtype and contiguity of a tensor handed to the library (ValueError); the device is
+    checked when its address is taken."""
+    torch = _torch()
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if t.dtype != getattr(torch, dtype_name):
+        raise ValueError("%s must be %s, got %s" % (name, dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _dptr(t) -> int:
+    """Device address of a tensor going to the library; host tensors are rejected."""
+    if not t.is_cuda:
+        raise ValueError("a %s tensor of shape %s is on the host; the library takes CUDA tensors"
+                         % (t.dtype, tuple(t.shape)))
+    return t.data_ptr()
+
+
+def check_offsets(offsets, n: int):
+    """CSR scene offsets: n_scenes + 1 non-decreasing entries from 0 to n, 1..64 scenes."""
+    offs = [int(v) for v in offsets]
+    if len(offs) < 2 or len(offs) > 65 or offs[0] != 0 or offs[-1] != n or any(
+            b < a for a, b in zip(offs, offs[1:])):
+        raise ValueError("offsets must be 2..65 non-decreasing entries from 0 to n = %d, got %s" % (n, offs))
+    return offs
+
+
+def _gaussians_struct(g: Dict[str, "object"], n_lambda: int) -> _Gaussians:
+    n = check_gaussians(g, n_lambda)
     s = _Gaussians()
     s.n = n
     for k in PARAMS:
         t = g[k]
-        if n > 0:
-            if not (t.is_cuda and t.dtype == _torch().float32 and t.is_contiguous()):
-                raise ValueError("%s must be a contiguous float32 CUDA tensor" % k)
-        setattr(s, k, t.data_ptr() if n > 0 else None)
+        if n > 0 and not (t.dtype == _torch().float32 and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float32 tensor" % k)
+        setattr(s, k, _dptr(t) if n > 0 else None)
     return s
+
+
+def _grads_struct(grads: Dict[str, "object"], g: Dict[str, "object"], n: int) -> _Grads:
+    """Gradient outputs: each the shape of its parameter, float32 CUDA, contiguous; depth may be None."""
+    keys = [k for k in PARAMS if not (k == "depth" and grads.get(k) is None)]
+    if n > 0:
+        for k in keys:
+            check_tensor(grads.get(k), "grad " + k, tuple(g[k].shape), "float32")
+    gr = _Grads()
+    for k in PARAMS:
+        setattr(gr, k, _dptr(grads[k]) if (n > 0 and k in keys) else None)
+    return gr
 
 
 class Context:
@@ -272,40 +338,39 @@ class Context:
     def forward(self, prob: Problem, g: Dict[str, "object"], want_spectrum: bool = False, out=None):
         """Field (n_lambda, ny, nx) complex64 (and the DFT-ready spectrum if asked)."""
         torch = _torch()
-        n = int(g["mean_x"].numel())
-        field = out if out is not None else torch.empty((prob.n_lambda, prob.ny, prob.nx), dtype=torch.complex64,
-                                                        device=self.torch_device)
+        n = check_gaussians(g, prob.n_lambda)
+        shape = (prob.n_lambda, prob.ny, prob.nx)
+        field = out if out is not None else torch.empty(shape, dtype=torch.complex64, device=self.torch_device)
+        check_tensor(field, "out", shape, "complex64")
+        gs = _gaussians_struct(g, prob.n_lambda)
         spec = torch.empty_like(field) if want_spectrum else None
         o = _Output()
-        o.field = field.data_ptr()
-        o.spectrum = spec.data_ptr() if spec is not None else None
+        o.field = _dptr(field)
+        o.spectrum = _dptr(spec) if spec is not None else None
         ws = self.workspace(self.workspace_size(prob, n))
-        gs = _gaussians_struct(g, n)
         _check(self.lib.gws_forward(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
-                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
+                                    ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
         return (field, spec) if want_spectrum else field
 
     def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True, out=None):
         """dL/d(parameter) for every Gaussian, given dL/dRe u + j dL/dIm u."""
         torch = _torch()
-        n = int(g["mean_x"].numel())
+        n = check_gaussians(g, prob.n_lambda)
         grad_field = grad_field.to(torch.complex64).contiguous()
+        check_tensor(grad_field, "grad_field", (prob.n_lambda, prob.ny, prob.nx), "complex64")
         grads = dict(out) if out is not None else {k: torch.empty_like(g[k]) for k in PARAMS}
         if not want_depth:
             grads["depth"] = None
         elif grads.get("depth") is None:
             grads["depth"] = torch.empty_like(g["depth"])
-        gr = _Grads()
-        for k in PARAMS:
-            t = grads[k]
-            setattr(gr, k, t.data_ptr() if (n > 0 and t is not None) else None)
-        ws = self.workspace(self.workspace_size(prob, n))
-        gs = _gaussians_struct(g, n)
+        gr = _grads_struct(grads, g, n)
+        gs = _gaussians_struct(g, prob.n_lambda)
         if n == 0:
             return grads
+        ws = self.workspace(self.workspace_size(prob, n))
         _check(self.lib.gws_backward(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs),
-                                     ctypes.c_void_p(grad_field.data_ptr()), ctypes.byref(gr),
-                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
+                                     ctypes.c_void_p(_dptr(grad_field)), ctypes.byref(gr),
+                                     ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
         return grads
 
     def workspace_size_batched(self, prob: Problem, offsets) -> int:
@@ -315,49 +380,55 @@ class Context:
                                                    ctypes.byref(sz)), self.handle)
         return sz.value
 
-    def forward_batched(self, prob: Problem, g: Dict[str, "object"], offsets, out=None):
-        """Fields of several scenes (Gaussians [offsets[s], offsets[s+1]) each), shape (S, C, ny, nx).
+    def forward_batched(self, prob: Problem, g: Dict[str, "object"], offsets, out=None, want_spectrum: bool = False,
+                        spectrum=None):
+        """Fields of several scenes (Gaussians [offsets[s], offsets[s+1]) each), shape (S, C, ny, nx)
+        (and their DFT-ready spectra, same shape, if asked).
 
         The first call for a given set of pointers and offsets captures the launch sequence
         into a hipGraph (on a non-default stream); later calls replay it."""
         torch = _torch()
+        offsets = check_offsets(offsets, check_gaussians(g, prob.n_lambda))
         S = len(offsets) - 1
-        n = int(g["mean_x"].numel())
-        field = out if out is not None else torch.empty((S, prob.n_lambda, prob.ny, prob.nx), dtype=torch.complex64,
-                                                        device=self.torch_device)
+        shape = (S, prob.n_lambda, prob.ny, prob.nx)
+        field = out if out is not None else torch.empty(shape, dtype=torch.complex64, device=self.torch_device)
+        check_tensor(field, "out", shape, "complex64")
+        if want_spectrum and spectrum is None:
+            spectrum = torch.empty_like(field)
+        if spectrum is not None:
+            check_tensor(spectrum, "spectrum", shape, "complex64")
+        gs = _gaussians_struct(g, prob.n_lambda)
         o = _Output()
-        o.field = field.data_ptr()
-        o.spectrum = None
-        offs = (ctypes.c_int64 * (S + 1))(*[int(v) for v in offsets])
+        o.field = _dptr(field)
+        o.spectrum = _dptr(spectrum) if spectrum is not None else None
+        offs = (ctypes.c_int64 * (S + 1))(*offsets)
         need = self.workspace_size_batched(prob, offsets)
         ws = self._batch_ws(need)
-        gs = _gaussians_struct(g, n)
         _check(self.lib.gws_forward_batched(self.handle, ctypes.byref(prob._c()), S, offs, ctypes.byref(gs),
-                                            ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                            ctypes.byref(o), ctypes.c_void_p(_dptr(ws)), ws.numel(),
                                             self._stream()), self.handle)
-        return field
+        return (field, spectrum) if spectrum is not None else field
 
     def backward_batched(self, prob: Problem, g: Dict[str, "object"], offsets, grad_fields, want_depth: bool = True,
                          out=None):
         """Gradients of every Gaussian of the batch, given (S, C, ny, nx) field gradients."""
         torch = _torch()
+        n = check_gaussians(g, prob.n_lambda)
+        offsets = check_offsets(offsets, n)
         S = len(offsets) - 1
-        n = int(g["mean_x"].numel())
+        check_tensor(grad_fields, "grad_fields", (S, prob.n_lambda, prob.ny, prob.nx), "complex64")
         grads = dict(out) if out is not None else {k: torch.empty_like(g[k]) for k in PARAMS}
         if not want_depth:
             grads["depth"] = None
         elif grads.get("depth") is None:
             grads["depth"] = torch.empty_like(g["depth"])
-        gr = _Grads()
-        for k in PARAMS:
-            t = grads[k]
-            setattr(gr, k, t.data_ptr() if t is not None else None)
-        offs = (ctypes.c_int64 * (S + 1))(*[int(v) for v in offsets])
+        gr = _grads_struct(grads, g, n)
+        gs = _gaussians_struct(g, prob.n_lambda)
+        offs = (ctypes.c_int64 * (S + 1))(*offsets)
         ws = self._batch_ws(self.workspace_size_batched(prob, offsets))
-        gs = _gaussians_struct(g, n)
         _check(self.lib.gws_backward_batched(self.handle, ctypes.byref(prob._c()), S, offs, ctypes.byref(gs),
-                                             ctypes.c_void_p(grad_fields.data_ptr()), ctypes.byref(gr),
-                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), self._stream()), self.handle)
+                                             ctypes.c_void_p(_dptr(grad_fields)), ctypes.byref(gr),
+                                             ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
         return grads
 
     def _batch_ws(self, nbytes: int):
@@ -376,13 +447,17 @@ class Context:
         """Unnormalised 2D DFT of (batch, ny, nx) complex64: exp(+j..) for direction +1."""
         torch = _torch()
         x = x.to(torch.complex64).contiguous()
+        if x.dim() != 3:
+            raise ValueError("x must have shape (batch, ny, nx), got %s" % (tuple(x.shape),))
         b, ny, nx = x.shape
         out = out if out is not None else torch.empty_like(x)
+        check_tensor(x, "x", (b, ny, nx), "complex64")
+        check_tensor(out, "out", (b, ny, nx), "complex64")
         sz = ctypes.c_size_t()
         _check(self.lib.gws_dft_workspace_size(self.handle, nx, ny, b, xform, ctypes.byref(sz)), self.handle)
         ws = self.workspace(sz.value) if sz.value else None
-        _check(self.lib.gws_dft2d(self.handle, nx, ny, b, direction, xform, ctypes.c_void_p(x.data_ptr()),
-                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+        _check(self.lib.gws_dft2d(self.handle, nx, ny, b, direction, xform, ctypes.c_void_p(_dptr(x)),
+                                  ctypes.c_void_p(_dptr(out)), ctypes.c_void_p(_dptr(ws) if ws is not None else 0),
                                   ws.numel() if ws is not None else 0, self._stream()), self.handle)
         return out
 
@@ -390,15 +465,20 @@ class Context:
         """loss = sum |u - t|^2 (float64 device scalar) and grad = 2 (u - t), in the library."""
         torch = _torch()
         n = field.numel()
+        shape = tuple(field.shape)
+        check_tensor(field, "field", shape, "complex64")
+        check_tensor(target, "target", shape, "complex64")
         if grad is None:
             grad = torch.empty_like(field)
+        check_tensor(grad, "grad", shape, "complex64")
         if loss is None:
             loss = torch.empty((), dtype=torch.float64, device=self.torch_device)
+        check_tensor(loss, "loss", (), "float64")
         if getattr(self, "_l2ws", None) is None:
             self._l2ws = torch.empty(int(self.lib.gws_l2_workspace_size()), dtype=torch.uint8, device=self.torch_device)
-        _check(self.lib.gws_l2_loss_grad(self.handle, n, ctypes.c_void_p(field.data_ptr()),
-                                         ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
-                                         ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(self._l2ws.data_ptr()),
+        _check(self.lib.gws_l2_loss_grad(self.handle, n, ctypes.c_void_p(_dptr(field)),
+                                         ctypes.c_void_p(_dptr(target)), ctypes.c_void_p(_dptr(grad)),
+                                         ctypes.c_void_p(_dptr(loss)), ctypes.c_void_p(_dptr(self._l2ws)),
                                          self._l2ws.numel(), self._stream()), self.handle)
         return loss, grad
 
@@ -407,6 +487,9 @@ class Context:
         float32 device tensors) to hologram-space in-plane Gaussians (dict of [n] tensors)."""
         torch = _torch()
         n = int(world["mean"].shape[0])
+        deg = int(view["sh_degree"])
+        for k, cols in (("mean", 3), ("quat", 4), ("scale", 3), ("opacity_sh", (max(deg, 0) + 1) ** 2)):
+            check_tensor(world.get(k), k, (n, cols), "float32")
         v = _View()
         for i, x in enumerate(view["world_to_view"]):
             v.world_to_view[i] = float(x)
@@ -415,10 +498,12 @@ class Context:
         for k in ("fx", "fy", "cx", "cy", "near", "depth_scale", "depth_offset"):
             setattr(v, k, float(view[k]))
         v.sh_degree = int(view["sh_degree"])
-        w = _WorldGaussians(n, *[ctypes.c_void_p(world[k].data_ptr()) for k in ("mean", "quat", "scale", "opacity_sh")])
+        w = _WorldGaussians(n, *[ctypes.c_void_p(_dptr(world[k])) for k in ("mean", "quat", "scale", "opacity_sh")])
         if out is None:
             out = {k: torch.empty(n, dtype=torch.float32, device=world["mean"].device) for k in PLANE_FIELDS}
-        pg = _PlaneGaussians(*[ctypes.c_void_p(out[k].data_ptr()) for k in PLANE_FIELDS])
+        for k in PLANE_FIELDS:
+            check_tensor(out.get(k), "out " + k, (n,), "float32")
+        pg = _PlaneGaussians(*[ctypes.c_void_p(_dptr(out[k])) for k in PLANE_FIELDS])
         _check(self.lib.gws_holographics(self.handle, ctypes.byref(v), ctypes.byref(w), ctypes.byref(pg),
                                          self._stream()), self.handle)
         return out
@@ -427,14 +512,18 @@ class Context:
         """Double-phase coding of a (C, ny, nx) complex64 field into a float32 phase-only
         pattern of the same shape; a_max None takes each channel's largest |u|."""
         torch = _torch()
+        if field.dim() != 3:
+            raise ValueError("field must have shape (C, ny, nx), got %s" % (tuple(field.shape),))
         C, ny, nx = field.shape
+        check_tensor(field, "field", (C, ny, nx), "complex64")
         out = out if out is not None else torch.empty((C, ny, nx), dtype=torch.float32, device=field.device)
+        check_tensor(out, "out", (C, ny, nx), "float32")
         am = 0.0 if a_max is None else float(a_max)
         if getattr(self, "_dpacws", None) is None:
             self._dpacws = torch.empty(int(self.lib.gws_dpac_workspace_size(4)), dtype=torch.uint8,
                                        device=self.torch_device)
-        _check(self.lib.gws_dpac_encode(self.handle, nx, ny, C, ctypes.c_void_p(field.data_ptr()), am,
-                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._dpacws.data_ptr()),
+        _check(self.lib.gws_dpac_encode(self.handle, nx, ny, C, ctypes.c_void_p(_dptr(field)), am,
+                                        ctypes.c_void_p(_dptr(out)), ctypes.c_void_p(_dptr(self._dpacws)),
                                         self._dpacws.numel(), self._stream()), self.handle)
         return out
 
@@ -446,18 +535,20 @@ class Context:
         flags = (FS_PHASE_INPUT if phase_input else 0) | (FS_HALF_BAND if half_band else 0) | \
             (FS_COMPLEX_OUTPUT if complex_output else 0)
         K = len(depths)
+        shape = (K, prob.n_lambda, prob.ny, prob.nx)
+        check_tensor(inp, "inp", (prob.n_lambda, prob.ny, prob.nx), "float32" if phase_input else "complex64")
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64 if complex_output else torch.float32,
+                              device=inp.device)
+        check_tensor(out, "out", shape, "complex64" if complex_output else "float32")
         dep = (ctypes.c_double * max(K, 1))(*[float(d) for d in depths])
         pc = prob._c()
         sz = ctypes.c_size_t()
         _check(self.lib.gws_focal_stack_workspace_size(self.handle, ctypes.byref(pc), K, flags, ctypes.byref(sz)),
                self.handle)
-        shape = (K, prob.n_lambda, prob.ny, prob.nx)
-        if out is None:
-            out = torch.empty(shape, dtype=torch.complex64 if complex_output else torch.float32,
-                              device=inp.device)
         ws = self.workspace(sz.value)
-        _check(self.lib.gws_focal_stack(self.handle, ctypes.byref(pc), ctypes.c_void_p(inp.data_ptr()), K, dep,
-                                        flags, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+        _check(self.lib.gws_focal_stack(self.handle, ctypes.byref(pc), ctypes.c_void_p(_dptr(inp)), K, dep,
+                                        flags, ctypes.c_void_p(_dptr(out)), ctypes.c_void_p(_dptr(ws)),
                                         ws.numel(), self._stream()), self.handle)
         return out
 

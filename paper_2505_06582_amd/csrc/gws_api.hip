@@ -408,7 +408,7 @@ static gws_status check_offsets(int S, const int64_t *offsets, int64_t n)
 struct ExactLayout {
     size_t off_keys_a = 0, off_keys_b = 0, off_vals_a = 0, off_vals_b = 0, off_sort_hist = 0, off_rec = 0,
            off_tmap = 0, off_spec = 0, off_dft = 0, off_gspec = 0, off_ckpt = 0, off_dmap = 0,
-           off_pspec = 0, off_pspat = 0, off_win = 0, off_pimgs = 0, total = 0;
+           off_pspec = 0, off_pspat = 0, off_win = 0, off_pimgs = 0, off_counters = 0, total = 0;
     int sort_blocks = 1;
 };
 
@@ -430,6 +430,7 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
     L.off_spec = take(sizeof(float2) * M * p->n_lambda);
     L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? sizeof(float2) * M * p->n_lambda : 1);
     L.off_win = take(sizeof(int4) * 4 * 64);
+    L.off_counters = take(sizeof(long long) * CTR_COUNT);
     // adjoint: transformed field gradient, map checkpoints, back-to-front accumulator, partial sums
     L.off_gspec = take(sizeof(float2) * M * p->n_lambda);
     L.off_ckpt = take(sizeof(float) * M * (size_t)exact_ckpt_count(n, p->nx, p->ny));
@@ -538,6 +539,7 @@ extern "C" gws_status gws_get_stats(gws_ctx *ctx, gws_stats *out)
     out->n_candidates = h[CTR_CAND];
     out->tile_config = ctx->last_tile_config;
     out->graph_replayed = ctx->last_graph;
+    out->n_window_clamped = h[CTR_CLAMPED];
     out->n_tiles = 0;
     for (auto &kv : ctx->plans) out->n_tiles = std::max<int64_t>(out->n_tiles, kv.second.ntiles);
     return GWS_OK;
@@ -877,6 +879,7 @@ static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const
     eb.rowwin = eb.colwin + 64;
     eb.pcolwin = eb.rowwin + 64;
     eb.prowwin = eb.pcolwin + 64;
+    eb.counters = (long long *)(base + L.off_counters);
     float2 *spec = spectrum ? (float2 *)spectrum : (float2 *)(base + L.off_spec);
     {
         StageScope sc(ctx, s, ST_ACCUM);
@@ -889,7 +892,7 @@ static gws_status exact_forward_run(gws_ctx *ctx, const gws_problem *prob, const
         else
             HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spec, (float2 *)field, (void *)(base + L.off_dft), s));
     }
-    HIP_CHECK(ctx, launch_sum_counters(nullptr, 0, ctx->d_stats, s));
+    HIP_CHECK(ctx, launch_sum_counters(&eb.counters, 1, ctx->d_stats, s));
     ctx->last_tile_config = 0;
     return GWS_OK;
 }
@@ -921,6 +924,7 @@ static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, cons
     eb.rowwin = eb.colwin + 64;
     eb.pcolwin = eb.rowwin + 64;
     eb.prowwin = eb.pcolwin + 64;
+    eb.counters = (long long *)(base + L.off_counters);
     ExactBwdBuffers bb;
     bb.gspec = (float2 *)(base + L.off_gspec);
     bb.ckpt = (float *)(base + L.off_ckpt);
@@ -932,7 +936,7 @@ static gws_status exact_backward_run(gws_ctx *ctx, const gws_problem *prob, cons
         StageScope sc(ctx, s, ST_ADJOINT);
         HIP_CHECK(ctx, run_exact_backward(*p, k, scene_view(g, off, n), eb, bb, (const float2 *)grad_field, gv, s));
     }
-    HIP_CHECK(ctx, launch_sum_counters(nullptr, 0, ctx->d_stats, s));
+    HIP_CHECK(ctx, launch_sum_counters(&eb.counters, 1, ctx->d_stats, s));
     ctx->last_tile_config = 0;
     return GWS_OK;
 }

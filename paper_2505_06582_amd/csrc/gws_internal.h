@@ -321,6 +321,7 @@ enum Counter {
     CTR_TRB = 7,
     CTR_PAIRS = 8,       // (tile, Gaussian) pairs evaluated
     CTR_CAND = 9,        // (tile, Gaussian) candidates tested
+    CTR_CLAMPED = 10,    // exact blending: eps-windows cut at half the grid
     CTR_COUNT = 16
 };
 
@@ -360,6 +361,7 @@ struct ExactBuffers {
                     // inverse transforms are the real maps r_k
     int4 *colwin, *rowwin;    // per batch Gaussian: window columns / rows as (first, count, 0, 0)
     int4 *pcolwin, *prowwin;  // per packed image: the two Gaussians' windows
+    long long *counters;      // CTR_COUNT counters: culled Gaussians, clamped windows
 };
 size_t exact_batch(int nx, int ny);
 // Extra device buffers of the exact-blending adjoint.

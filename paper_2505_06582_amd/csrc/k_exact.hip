@@ -58,12 +58,15 @@ __global__ void __launch_bounds__(256) k_exact_keys(GView g, uint64_t *__restric
     vals[i] = (uint32_t)i;
 }
 
-__global__ void __launch_bounds__(256) k_exact_records(GView g, Consts k, const uint32_t *__restrict__ order,
-                                                       ERec *__restrict__ rec)
+__global__ void k_exact_zero_counters(long long *__restrict__ counters)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
-    const int64_t j = order[i];
+    if (threadIdx.x < CTR_COUNT) counters[threadIdx.x] = 0;
+}
+
+// The record of input Gaussian j.  *culled: skipped as invalid; *clamped: its eps-window was
+// cut at half the grid (its profile is truncated there).
+static __device__ ERec make_erec(const GView &g, const Consts &k, int64_t j, bool *culled, bool *clamped)
+{
     const float sxx = g.cov_xx[j], sxy = g.cov_xy[j], syy = g.cov_yy[j];
     const float mx = g.mean_x[j], my = g.mean_y[j], z = g.depth[j], o = g.opacity[j], ph = g.phase[j];
     const double det = (double)sxx * syy - (double)sxy * sxy;
@@ -83,10 +86,12 @@ __global__ void __launch_bounds__(256) k_exact_records(GView g, Consts k, const 
     r.cphi = cosf(ph);
     r.sphi = sinf(ph);
     r.z = ok ? z : 0.0f;
-    // eps-window: g >= eps  <=>  d^T Sigma^-1 d <= 2 ln(1/eps) = 2 ln 2 tau2
+    // eps-window: g >= eps  <=>  d^T Sigma^-1 d <= 2 ln(1/eps) = 2 ln 2 tau2, cut at N/2 - 1
     const double r2 = 2.0 * log(2.0) * k.tau2;
-    r.hwx = ok ? (int)min(ceil(sqrt(r2 * a)), (double)(k.nx / 2 - 1)) : -1;
-    r.hwy = ok ? (int)min(ceil(sqrt(r2 * c)), (double)(k.ny / 2 - 1)) : -1;
+    const double wx = ceil(sqrt(r2 * a)), wy = ceil(sqrt(r2 * c));
+    const double cx = (double)(k.nx / 2 - 1), cy = (double)(k.ny / 2 - 1);
+    r.hwx = ok ? (int)min(wx, cx) : -1;
+    r.hwy = ok ? (int)min(wy, cy) : -1;
     for (int q = 0; q < 4; ++q) {
         float v = 0.0f;
         if (q < k.C) {
@@ -102,7 +107,24 @@ __global__ void __launch_bounds__(256) k_exact_records(GView g, Consts k, const 
         r.hwx = r.hwy = -1;
         for (int q = 0; q < 4; ++q) r.amp[q] = 0.0f;
     }
-    rec[i] = r;
+    *culled = !ok;
+    *clamped = ok && (wx > cx || wy > cy);
+    return r;
+}
+
+// Records in front-to-back order; counts the culled and the clamped Gaussians (one atomic
+// per wavefront and counter).
+__global__ void __launch_bounds__(256) k_exact_records(GView g, Consts k, const uint32_t *__restrict__ order,
+                                                       ERec *__restrict__ rec, long long *__restrict__ counters)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool culled = false, clamped = false;
+    if (i < g.n) rec[i] = make_erec(g, k, order[i], &culled, &clamped);
+    const int nc = __popcll(__ballot(culled)), nk = __popcll(__ballot(clamped));
+    if ((threadIdx.x & 63) == 0) {
+        if (nc) atomicAdd((unsigned long long *)&counters[CTR_NCULLED], (unsigned long long)nc);
+        if (nk) atomicAdd((unsigned long long *)&counters[CTR_CLAMPED], (unsigned long long)nk);
+    }
 }
 
 // The index of the frequency -m (periodic) of m = (mx, my).
@@ -337,6 +359,7 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
     ERec *rec = (ERec *)eb.rec;
     const int64_t n = g.n, M = (int64_t)k.nx * k.ny;
     const unsigned gn = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_exact_zero_counters, dim3(1), dim3(64), 0, s, eb.counters);
     hipLaunchKernelGGL(k_exact_fill, dim3((unsigned)((M * k.C + 255) / 256)), dim3(256), 0, s, eb.tmap, spec, M,
                        k.C);
     if (n == 0) return hipGetLastError();
@@ -346,7 +369,7 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
     hipError_t e = radix_sort_48(eb.keys_a, eb.vals_a, eb.keys_b, eb.vals_b, eb.sort_hist, n, eb.sort_blocks, s, &keys,
                                  &order);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_exact_records, dim3(gn), dim3(256), 0, s, g, k, order, rec);
+    hipLaunchKernelGGL(k_exact_records, dim3(gn), dim3(256), 0, s, g, k, order, rec, eb.counters);
     const int B = (int)exact_batch(k.nx, k.ny);
     const dim3 tiles((k.nx + EXACT_TILE - 1) / EXACT_TILE, (k.ny + EXACT_TILE - 1) / EXACT_TILE);
     for (int64_t b0 = 0; b0 < n; b0 += B) {
@@ -699,7 +722,8 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
                               const ExactBwdBuffers &bb, const float2 *grad_field, const GradView &out, hipStream_t s)
 {
     const int64_t n = g.n, M = (int64_t)k.nx * k.ny;
-    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exact_zero_counters, dim3(1), dim3(64), 0, s, eb.counters);
+    if (n == 0) return hipGetLastError();
     ERec *rec = (ERec *)eb.rec;
     const unsigned gn = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_exact_keys, dim3(gn), dim3(256), 0, s, g, eb.keys_a, eb.vals_a);
@@ -708,7 +732,7 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
     hipError_t e = radix_sort_48(eb.keys_a, eb.vals_a, eb.keys_b, eb.vals_b, eb.sort_hist, n, eb.sort_blocks, s, &keys,
                                  &order);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_exact_records, dim3(gn), dim3(256), 0, s, g, k, order, rec);
+    hipLaunchKernelGGL(k_exact_records, dim3(gn), dim3(256), 0, s, g, k, order, rec, eb.counters);
     // Gs = FFT(dL/du)
     e = launch_fft2d(p, k.C, -1, grad_field, bb.gspec, s);
     if (e != hipSuccess) return e;

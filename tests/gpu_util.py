@@ -1,5 +1,7 @@
 """Helpers shared by the GPU tests: move seeded scenes to the device, map oracle spectra to
 the library's DFT-ready layout, and compare."""
+import math
+
 import numpy as np
 
 import paper_2505_06582_amd as gws
@@ -35,3 +37,120 @@ def rel_l2(x, ref):
 
 def problem(grid, **kw):
     return gws.Problem.from_grid(grid, **kw)
+
+
+# Radius bands of the centred frequency plane, in units of the half-grid along each axis
+# (r = hypot(m'_x / (nx/2), m'_y / (ny/2))).  "dc" is the block of tiles around DC where
+# every Gaussian's support overlaps and work items are split into several chunks; "nyquist"
+# holds the frequencies with |m'_x| >= 0.9 nx/2 or |m'_y| >= 0.9 ny/2, reached only by the
+# smallest Gaussians' supports.
+BANDS = ("dc", "inner", "mid", "outer", "nyquist")
+
+
+def _band_of(sx, sy, grid):
+    hx, hy = grid.nx // 2, grid.ny // 2
+    r = np.hypot(sx / hx, sy / hy)
+    band = np.full(sx.shape, -1)
+    band[(np.abs(sx) < 32) & (np.abs(sy) < 32)] = 0
+    ny_mask = (np.abs(sx) >= 0.9 * hx) | (np.abs(sy) >= 0.9 * hy)
+    band[(band < 0) & ~ny_mask & (r < 0.25)] = 1
+    band[(band < 0) & ~ny_mask & (r >= 0.25) & (r < 0.6)] = 2
+    band[(band < 0) & ~ny_mask & (r >= 0.6)] = 3
+    band[(band < 0) & ny_mask] = 4
+    return band
+
+
+def stratified_freqs(grid, per_band, seed):
+    """FFT-order frequency indices, ``per_band`` drawn uniformly (without replacement) from
+    each radius band.  Returns (mx, my, band, weight) where weight = the band's frequency
+    count / its sample count, so sums of weight * |x|^2 estimate sums over the whole grid."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    sx_all = oracle.signed_freq_index(grid.nx)
+    sy_all = oracle.signed_freq_index(grid.ny)
+    SX, SY = np.meshgrid(sx_all, sy_all)
+    bands = _band_of(SX, SY, grid).ravel()
+    mx_all = np.broadcast_to(np.arange(grid.nx)[None, :], SX.shape).ravel()
+    my_all = np.broadcast_to(np.arange(grid.ny)[:, None], SX.shape).ravel()
+    mx, my, bd, w = [], [], [], []
+    for b in range(len(BANDS)):
+        idx = np.flatnonzero(bands == b)
+        k = min(per_band, idx.size)
+        pick = rng.choice(idx, k, replace=False)
+        mx.append(mx_all[pick])
+        my.append(my_all[pick])
+        bd.append(np.full(k, b))
+        w.append(np.full(k, idx.size / k))
+    return (np.concatenate(mx).astype(np.int32), np.concatenate(my).astype(np.int32), np.concatenate(bd),
+            np.concatenate(w))
+
+
+def oracle_dft_ready(scene, grid, mx, my):
+    """The oracle's spectrum at FFT-order indices (mx, my), in the library's DFT-ready scaling."""
+    import oracle
+    U = oracle.spectrum(scene, grid, mx, my)
+    sx = oracle.signed_freq_index(grid.nx)[mx]
+    sy = oracle.signed_freq_index(grid.ny)[my]
+    return U * np.where((sx + sy) % 2 == 0, 1.0, -1.0) / (grid.nx * grid.ny * grid.px * grid.py)
+
+
+# Per-band bound: relative 1e-5 within the band plus an absolute floor of 1e-7 of the grid's
+# RMS.  The floor is the support cut: terms below eps = 1e-7 of each Gaussian's peak are not
+# evaluated, so where a band's values are themselves of that order (the band next to
+# Nyquist, reached only by the tails of the smallest Gaussians) its relative error is not
+# meaningful, while its share of the whole-grid error stays below eps.
+BAND_FLOOR = 1e-7
+
+
+def stratified_errors(got, ref, band, weight):
+    """(estimated whole-grid relative L2, {band: RMS error / (1e-5 RMS_band(ref) + 1e-7 RMS_grid(ref))},
+    {band: plain relative L2 within the band}) for sampled spectra of shape (C, S).  A band
+    passes when its ratio is below 1."""
+    got = np.asarray(got, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    e2 = np.sum(np.abs(got - ref) ** 2, axis=0)
+    r2 = np.sum(np.abs(ref) ** 2, axis=0)
+    total = math.sqrt(np.sum(weight * e2) / np.sum(weight * r2))
+    rms_grid = math.sqrt(np.sum(weight * r2) / np.sum(weight))
+    per_band, plain = {}, {}
+    for b, name in enumerate(BANDS):
+        m = band == b
+        if not np.any(m):
+            continue
+        rms_e, rms_r = math.sqrt(np.mean(e2[m])), math.sqrt(np.mean(r2[m]))
+        per_band[name] = rms_e / (1e-5 * rms_r + BAND_FLOOR * rms_grid)
+        plain[name] = rms_e / max(rms_r, 1e-300)
+    return total, per_band, plain
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def physical_spectrum(spec, grid):
+    """The library's DFT-ready spectrum back in physical units (undo the centring sign and scale)."""
+    import oracle
+    sx = oracle.signed_freq_index(grid.nx)
+    sy = oracle.signed_freq_index(grid.ny)
+    sign = np.where(((sy[:, None] + sx[None, :]) % 2) == 0, 1.0, -1.0)
+    return np.asarray(spec, dtype=np.complex128) * sign * (grid.nx * grid.ny * grid.px * grid.py)
+
+
+def check_spectrum_and_transform(scene, grid, field, spec, per_band, seed, label):
+    """Sampled spectrum (by radius band) against the oracle, and the GPU field against an FP64
+    inverse DFT of the GPU spectrum; returns (spectrum error, transform error)."""
+    import oracle
+    mx, my, band, w = stratified_freqs(grid, per_band, seed)
+    ref = oracle_dft_ready(scene, grid, mx, my)
+    total, per, plain = stratified_errors(spec[:, my, mx], ref, band, w)
+    _log("  %s: spectrum rel L2 (band-weighted estimate over the grid) %.3e" % (label, total))
+    for name in per:
+        _log("    band %-8s relative L2 within band %.3e (bound ratio %.3f)" % (name, plain[name], per[name]))
+    f_ref = oracle.field_from_spectrum(physical_spectrum(spec, grid), grid)
+    e_xf = rel_l2(field, f_ref)
+    _log("  %s: transform stage rel L2 %.3e" % (label, e_xf))
+    assert total < 1e-5, (label, total)
+    for name, v in per.items():
+        assert v < 1.0, (label, name, plain[name], v)
+    assert e_xf < 2e-6, (label, e_xf)
+    return total, e_xf

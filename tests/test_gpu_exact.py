@@ -16,8 +16,9 @@ pytestmark = pytest.mark.gpu
 # FP32 tolerance for exact blending (relative L2 of the field), the same bar as the FP32
 # order-invariant path: the transmittance is a product of FP32 factors and the profile is
 # truncated at eps = 1e-7 of its peak (measured 4e-7 .. 2e-6).  The 1/255 alpha decision is
-# taken in FP32 on the GPU and in FP64 by the oracle; a pixel within rounding of the
-# threshold could flip it, which these seeded scenes do not hit.
+# taken in FP32 on the GPU and in FP64 by the oracle; at a pixel within rounding of the
+# threshold both are correct, which test_exact_alpha_straddling_the_threshold covers with a
+# bound of its own (these seeded scenes have no such pixel).
 TOL_EXACT = 1e-5
 
 
@@ -107,6 +108,66 @@ def test_exact_empty_and_zero_opacity(ctx):
     assert np.all(gpu_exact(ctx, s, grid) == 0)
     empty = s.subset(np.arange(0))
     assert np.all(gpu_exact(ctx, empty, grid) == 0)
+
+
+def test_exact_counts_culled_and_clamped_windows(ctx):
+    """Invalid Gaussians are skipped and counted; a Gaussian whose eps-window reaches past half
+    the grid is counted as clamped (its profile is cut at nx/2 - 1, ny/2 - 1 pixels)."""
+    import paper_2505_06582_amd as gws
+    grid = Grid(64, 48, 8e-6, 8e-6, (520e-9,))
+    s = clustered_scene(12, grid, 2111)
+    s.cov_xy[0] = np.float32(2.0 * np.sqrt(float(s.cov_xx[0]) * float(s.cov_yy[0])))  # not positive definite
+    s.mean_x[1] = np.float32(np.nan)
+    wide = (4, 9)
+    for i in wide:   # sigma 10 px: window 10 sqrt(2 ln 1e7) = 57 px > 31 and 23
+        s.cov_xx[i], s.cov_xy[i], s.cov_yy[i] = np.float32(100 * 64e-12), np.float32(0.0), np.float32(100 * 64e-12)
+    prob = problem(grid, blend=gws.BLEND_EXACT)
+    ctx.forward(prob, scene_to_torch(s))
+    st = ctx.stats()
+    log("exact stats: culled %d, clamped %d" % (st["n_culled"], st["n_window_clamped"]))
+    assert st["n_culled"] == 2 and st["n_window_clamped"] == len(wide)
+    G = gwsgen.make_target(grid, 2112)
+    import torch
+    ctx.backward(prob, scene_to_torch(s), torch.from_numpy(G).cuda())
+    st = ctx.stats()
+    assert st["n_culled"] == 2 and st["n_window_clamped"] == len(wide)
+    ctx.forward(problem(grid), scene_to_torch(s))
+    assert ctx.stats()["n_window_clamped"] == 0
+
+
+def test_exact_alpha_straddling_the_threshold(ctx):
+    """Front Gaussians whose alpha equals 1/255 to FP32 rounding on whole rings of pixels
+    (isotropic, centred on a pixel, opacity exp(r^2 / 2 sigma^2) / 255 for an integer r^2), over a
+    Gaussian behind them.  At those pixels either decision is a correct reading (the GPU takes
+    it in FP32, the oracle in FP64), so the GPU field must lie within the FP32 tolerance of the
+    oracle plus the distance between the oracle with the threshold moved down and up by 1e-5
+    (which brackets every mix of decisions at pixels within 1e-5 of it)."""
+    grid = Grid(64, 48, 8e-6, 8e-6, (520e-9,))
+    p = grid.px
+    front = [((0, 0), 3.0, 25), ((-14, 8), 2.5, 13), ((12, -9), 4.0, 50), ((9, 11), 3.5, 34)]
+    n = len(front) + 1
+    s = clustered_scene(n, grid, 2113)
+    for i, ((cx, cy), sig, r2) in enumerate(front):
+        s.mean_x[i], s.mean_y[i] = np.float32(cx * p), np.float32(cy * p)
+        s.cov_xx[i] = s.cov_yy[i] = np.float32(sig * sig * p * p)
+        s.cov_xy[i] = np.float32(0.0)
+        s.opacity[i] = np.float32(np.exp(r2 / (2 * sig * sig)) / 255.0)
+        s.depth[i] = np.float32(1e-3 + 1e-4 * i)
+    s.mean_x[-1], s.mean_y[-1] = np.float32(0.0), np.float32(0.0)
+    s.cov_xx[-1] = s.cov_yy[-1] = np.float32(144 * p * p)
+    s.cov_xy[-1] = np.float32(0.0)
+    s.opacity[-1] = np.float32(0.8)
+    s.depth[-1] = np.float32(-2e-3)
+    u = gpu_exact(ctx, s, grid)
+    mid = ex.exact_forward(s, grid)
+    lo = ex.exact_forward(s, grid, t_eps=ex.T_EPS * (1 - 1e-5))
+    hi = ex.exact_forward(s, grid, t_eps=ex.T_EPS * (1 + 1e-5))
+    spread = rel_l2(lo, hi)
+    err = rel_l2(u, mid)
+    log("straddling scene: oracle spread (threshold -/+ 1e-5) %.3e, GPU vs oracle %.3e, vs lower %.3e, "
+        "vs upper %.3e" % (spread, err, rel_l2(u, lo), rel_l2(u, hi)))
+    assert spread > 1e-6        # the scene does sit on the threshold
+    assert err <= TOL_EXACT + spread
 
 
 def test_exact_full_size_grid(ctx):

@@ -1,9 +1,10 @@
 """Parity at the full benchmark size (100k Gaussians, 1080x1920, 3 wavelengths), in the
 launch configuration bench.py times, on outputs the FP64 oracle can compute one by one:
-sampled spectrum entries (each an exact sum over all 100k Gaussians), the gradients of
-32 sampled Gaussians (each an exact dense sum over the whole grid) checked against the
-oracle gradient and against FP64 central differences, and Parseval between the GPU
-field and the GPU spectrum.  Also the 1M-Gaussian 2160x3840 precision workload."""
+spectrum entries sampled by radius band (each an exact sum over all 100k Gaussians), the
+transform stage against an FP64 inverse DFT of the GPU spectrum, and the gradients of 32
+sampled Gaussians (each an exact dense sum over the whole grid) checked against the oracle
+gradient and against FP64 central differences.  Also the 1M-Gaussian 2160x3840 precision
+workload."""
 import math
 import sys
 
@@ -12,7 +13,8 @@ import pytest
 
 import gwsgen
 import oracle
-from gpu_util import dft_ready, problem, rel_l2, scene_to_torch, to_numpy
+from gpu_util import (check_spectrum_and_transform, oracle_dft_ready, physical_spectrum, problem, rel_l2,
+                      scene_to_torch, stratified_errors, stratified_freqs, to_numpy)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,30 +36,16 @@ def bench_scene():
     return gwsgen.workload("fwdbwd100k")
 
 
-def test_fullsize_forward_sampled_spectrum_and_parseval(ctx, bench_scene):
+def test_fullsize_forward_sampled_by_band(ctx, bench_scene):
+    """Spectrum entries sampled in every radius band (the multi-chunk tiles around DC, three
+    rings and the band next to Nyquist), each an exact FP64 sum over all 100k Gaussians, and
+    the GPU field against an FP64 inverse DFT of the GPU spectrum."""
     scene, grid = bench_scene
     log("full-size forward: 100k Gaussians 1080x1920x3")
     field, spec = ctx.forward(problem(grid), scene_to_torch(scene), want_spectrum=True)
-    field, spec = to_numpy(field), to_numpy(spec)
-    rng = np.random.default_rng(31)
-    S = 384
-    # half the samples near DC where most Gaussians overlap, half anywhere
-    mx = np.concatenate([rng.integers(-40, 40, S // 2) % grid.nx, rng.integers(0, grid.nx, S // 2)]).astype(np.int32)
-    my = np.concatenate([rng.integers(-40, 40, S // 2) % grid.ny, rng.integers(0, grid.ny, S // 2)]).astype(np.int32)
-    U = oracle.spectrum(scene, grid, mx, my)                        # (3, S) exact sums, FP64
-    sx = oracle.signed_freq_index(grid.nx)[mx]
-    sy = oracle.signed_freq_index(grid.ny)[my]
-    ref = U * np.where((sx + sy) % 2 == 0, 1.0, -1.0) / (grid.nx * grid.ny * grid.px * grid.py)
-    got = spec[:, my, mx]
-    e = rel_l2(got, ref)
-    log("  sampled spectrum rel L2 %.3e" % e)
-    assert e < 1e-5
-    # Parseval between the GPU's own spectrum and field (unnormalised DFT): sum|u|^2 = M sum|S|^2
-    M = grid.nx * grid.ny
-    for c in range(3):
-        a = np.sum(np.abs(field[c].astype(np.complex128)) ** 2)
-        b = M * np.sum(np.abs(spec[c].astype(np.complex128)) ** 2)
-        assert abs(a / b - 1) < 1e-5
+    st = ctx.stats()
+    log("  %d work items, chunk %d" % (st["n_items"], st["chunk"]))
+    check_spectrum_and_transform(scene, grid, to_numpy(field), to_numpy(spec), 1024, 31, "fwdbwd100k")
 
 
 def test_fullsize_backward_32_sampled_gaussians(ctx, bench_scene):
@@ -105,24 +93,26 @@ def test_precision_workload_1m_gaussians_sampled(ctx):
     scene, grid = gwsgen.workload("precision1m")
     log("precision workload: 1M Gaussians 2160x3840x3")
     g = scene_to_torch(scene)
-    _, spec = ctx.forward(problem(grid), g, want_spectrum=True)
-    spec = to_numpy(spec)
-    rng = np.random.default_rng(41)
-    S = 64
-    mx = np.concatenate([rng.integers(-30, 30, S // 2) % grid.nx, rng.integers(0, grid.nx, S // 2)]).astype(np.int32)
-    my = np.concatenate([rng.integers(-30, 30, S // 2) % grid.ny, rng.integers(0, grid.ny, S // 2)]).astype(np.int32)
-    U = oracle.spectrum(scene, grid, mx, my)
+    field, spec = ctx.forward(problem(grid), g, want_spectrum=True)
+    field, spec = to_numpy(field), to_numpy(spec)
+    mx, my, band, w = stratified_freqs(grid, 256, 41)
     sx = oracle.signed_freq_index(grid.nx)[mx]
     sy = oracle.signed_freq_index(grid.ny)[my]
-    ref = U * np.where((sx + sy) % 2 == 0, 1.0, -1.0) / (grid.nx * grid.ny * grid.px * grid.py)
-    e = rel_l2(spec[:, my, mx], ref)
+    ref = oracle_dft_ready(scene, grid, mx, my)
+    e, per, plain = stratified_errors(spec[:, my, mx], ref, band, w)
+    log("  all 1M: spectrum rel L2 (band-weighted estimate) %.3e; relative L2 within each band %s"
+        % (e, {k: "%.2e" % v for k, v in plain.items()}))
+    assert all(v < 1.0 for v in per.values()), (plain, per)
+    e_xf = rel_l2(field, oracle.field_from_spectrum(physical_spectrum(spec, grid), grid))
+    log("  transform stage rel L2 %.3e" % e_xf)
+    assert e_xf < 2e-6
+    del field
     # the far subset alone
     far = np.flatnonzero(np.abs(scene.depth) > 15e-3)
     sub = scene.subset(far)
     _, spec_far = ctx.forward(problem(grid), scene_to_torch(sub), want_spectrum=True)
     _, spec_far32 = ctx.forward(problem(grid, phase_mode=1), scene_to_torch(sub), want_spectrum=True)
-    Uf = oracle.spectrum(sub, grid, mx, my)
-    ref_f = Uf * np.where((sx + sy) % 2 == 0, 1.0, -1.0) / (grid.nx * grid.ny * grid.px * grid.py)
+    ref_f = oracle_dft_ready(sub, grid, mx, my)
     e_far = rel_l2(to_numpy(spec_far)[:, my, mx], ref_f)
     e_far32 = rel_l2(to_numpy(spec_far32)[:, my, mx], ref_f)
     # away from DC (|m'| > 400 index units) the phase ramp m'.r reaches hundreds of revolutions
