@@ -33,6 +33,9 @@ class Grid:
     px: float = 8e-6
     py: float = 8e-6
     lambdas: tuple = (520e-9,)
+    # transverse frequency (cycles/m along x, y) of the illuminating reference plane wave,
+    # the same for every wavelength; (0, 0) is on-axis illumination
+    ref_nu: tuple = (0.0, 0.0)
 
     @property
     def n_lambda(self) -> int:

@@ -9,6 +9,8 @@ definitions:
 
 * O1  the closed-form angular spectrum of each in-plane 2D Gaussian (Sec. 4.1, Eq. 10;
       Fourier pair of Eq. 7 in ordinary frequency; det J = 1, det S = sqrt(det Sigma)),
+      shifted by the transverse frequency nu_r of the reference plane wave that
+      illuminates every Gaussian (Sec. 4.1): g_i(nu - nu_r),
 * O2  the angular-spectrum transfer function H(nu, d) = exp(j 2 pi d sqrt(1/l^2 - |nu|^2))
       inside the propagating band, 0 outside (Eq. 3-4), applied at d = -z_i (Eq. 5, 12),
 * O3  the order-invariant sum of Eq. 12 over Gaussians taken front to back (descending
@@ -64,11 +66,11 @@ def _load():
             i64p = ctypes.POINTER(ctypes.c_int64)
             lib.oracle_spectrum.argtypes = [ctypes.c_int64] + [dp] * 9 + [
                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp,
-                ctypes.c_int64, i32p, i32p, dp]
+                ctypes.c_double, ctypes.c_double, ctypes.c_int64, i32p, i32p, dp]
             lib.oracle_spectrum.restype = None
             lib.oracle_param_grads.argtypes = [ctypes.c_int64] + [dp] * 9 + [
                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp,
-                dp, ctypes.c_int64, i64p, dp]
+                ctypes.c_double, ctypes.c_double, dp, ctypes.c_int64, i64p, dp]
             lib.oracle_param_grads.restype = None
             _lib = lib
     return _lib
@@ -87,6 +89,12 @@ def _scene_f64(scene):
     return [_f64(scene.mean_x), _f64(scene.mean_y), _f64(scene.depth), _f64(scene.cov_xx),
             _f64(scene.cov_xy), _f64(scene.cov_yy), _f64(scene.opacity),
             _f64(np.reshape(scene.amplitude, (-1, scene.n))), _f64(scene.phase)]
+
+
+def _ref_nu(grid):
+    """Transverse frequency (cycles/m) of the reference plane wave, (0, 0) when the grid has none."""
+    r = getattr(grid, "ref_nu", (0.0, 0.0))
+    return float(r[0]), float(r[1])
 
 
 def depth_order(scene) -> np.ndarray:
@@ -119,7 +127,7 @@ def spectrum(scene, grid, freq_mx=None, freq_my=None, ordered: bool = True) -> n
     out = np.zeros((grid.n_lambda, freq_mx.size, 2), dtype=np.float64)
     args = _scene_f64(s)
     lib.oracle_spectrum(s.n, *[_ptr(a) for a in args], grid.nx, grid.ny, grid.px, grid.py,
-                        grid.n_lambda, _ptr(lam), freq_mx.size, _ptr(freq_mx, ctypes.c_int32),
+                        grid.n_lambda, _ptr(lam), *_ref_nu(grid), freq_mx.size, _ptr(freq_mx, ctypes.c_int32),
                         _ptr(freq_my, ctypes.c_int32), _ptr(out))
     u = out[..., 0] + 1j * out[..., 1]
     if full:
@@ -174,7 +182,7 @@ def param_grads_from_spectrum_grad(scene, grid, gs: np.ndarray, sel=None) -> dic
     out = np.zeros((sel.size, stride), dtype=np.float64)
     args = _scene_f64(scene)
     lib.oracle_param_grads(scene.n, *[_ptr(a) for a in args], grid.nx, grid.ny, grid.px, grid.py,
-                           grid.n_lambda, _ptr(lam), _ptr(gsv), sel.size,
+                           grid.n_lambda, _ptr(lam), *_ref_nu(grid), _ptr(gsv), sel.size,
                            _ptr(sel, ctypes.c_int64), _ptr(out))
     res = {name: out[:, k].copy() for k, name in enumerate(PARAM_NAMES)}
     res["amplitude"] = out[:, 9:].T.copy()

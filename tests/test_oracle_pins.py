@@ -30,11 +30,14 @@ def cov_from(su_px, sv_px, theta, p):
 
 
 def spatial_gaussian(scene, grid, c, periods=2):
-    """Sample a_c o e^{j phi} exp(-1/2 (x-mu)^T Sigma^-1 (x-mu)) on the grid, periodised."""
+    """Sample a_c o e^{j phi} exp(-1/2 (x-mu)^T Sigma^-1 (x-mu)) on the grid, periodised.  With a
+    reference plane wave (grid.ref_nu, on the frequency lattice so that it is periodic on the
+    grid) the samples are multiplied by exp(+j 2 pi nu_r . x), x measured from the SLM centre."""
     nx, ny, px, py = grid.nx, grid.ny, grid.px, grid.py
     x = (np.arange(nx) - nx // 2) * px
     y = (np.arange(ny) - ny // 2) * py
     X, Y = np.meshgrid(x, y)
+    tilt = np.exp(2j * math.pi * (grid.ref_nu[0] * X + grid.ref_nu[1] * Y))
     out = np.zeros((ny, nx), dtype=np.complex128)
     W, H = nx * px, ny * py
     for i in range(scene.n):
@@ -47,7 +50,7 @@ def spatial_gaussian(scene, grid, c, periods=2):
                 dx = X - float(scene.mean_x[i]) - kx * W
                 dy = Y - float(scene.mean_y[i]) - ky * H
                 out += amp * np.exp(-0.5 * (ixx * dx * dx + 2 * ixy * dx * dy + iyy * dy * dy))
-    return out
+    return out * tilt
 
 
 def freq_grid(grid):
@@ -288,3 +291,105 @@ def test_oracle_matches_its_committed_checksums():
     for k, (re, im) in ref["pixels"].items():
         iy, ix = map(int, k.split(","))
         assert abs(u[iy, ix] - complex(re, im)) < 1e-12 * ref["norm_l2"]
+
+
+# ---- the reference plane wave (Sec. 4.1): every Gaussian is illuminated by a plane wave of
+# transverse frequency nu_r, which shifts its angular spectrum by nu_r; the transfer function
+# H keeps the full frequency.  Pinned by spatial sampling, the modulation theorem and the
+# tilted Gaussian-beam closed form.
+
+
+def _lattice_ref(grid, sx, sy):
+    return (sx / (grid.nx * grid.px), sy / (grid.ny * grid.py))
+
+
+def test_r1_reference_wave_brute_force():
+    """Spatial samples times exp(j 2 pi nu_r.x) -> numpy FFT -> H(nu, -z) -> inverse FFT."""
+    rng = np.random.default_rng(17)
+    for (nx, ny, sx, sy) in [(64, 48, 3, -2), (40, 56, -5, 4)]:
+        base = Grid(nx, ny, 8e-6, 6e-6, (638e-9, 450e-9))
+        grid = Grid(nx, ny, 8e-6, 6e-6, (638e-9, 450e-9), ref_nu=_lattice_ref(base, sx, sy))
+        n = 3
+        sxx, sxy, syy = zip(*[cov_from(rng.uniform(2.5, 5), rng.uniform(2.5, 5), rng.uniform(0, math.pi), 7e-6)
+                              for _ in range(n)])
+        scene = Scene(mean_x=rng.uniform(-0.3, 0.3, n) * nx * grid.px, mean_y=rng.uniform(-0.3, 0.3, n) * ny * grid.py,
+                      depth=rng.uniform(-3e-3, 3e-3, n), cov_xx=np.array(sxx), cov_xy=np.array(sxy),
+                      cov_yy=np.array(syy), opacity=rng.uniform(0.1, 1, n), amplitude=rng.uniform(0, 1, (2, n)),
+                      phase=rng.uniform(0, 2 * math.pi, n))
+        u = oracle.forward(scene, grid)
+        ref = brute_force_field(scene, grid)
+        assert oracle.rel_l2(u, ref) < 1e-9, (nx, ny, oracle.rel_l2(u, ref))
+        # and it is not the on-axis field
+        assert oracle.rel_l2(u, oracle.forward(scene, base)) > 0.5
+
+
+def test_r2_reference_wave_at_zero_depth_is_modulation():
+    """z = 0: the field is the on-axis field times the plane wave exp(j 2 pi nu_r.x_n)."""
+    base = Grid(96, 80, 8e-6, 8e-6, (520e-9, 638e-9))
+    grid = Grid(96, 80, 8e-6, 8e-6, (520e-9, 638e-9), ref_nu=_lattice_ref(base, 7, -4))
+    sxx, sxy, syy = cov_from(4.0, 2.5, 0.6, 8e-6)
+    scene = one_gaussian(3.3e-5, -2.1e-5, 0.0, sxx, sxy, syy, o=0.7, a=(0.5, 0.9), phi=0.8)
+    x = (np.arange(grid.nx) - grid.nx // 2) * grid.px
+    y = (np.arange(grid.ny) - grid.ny // 2) * grid.py
+    X, Y = np.meshgrid(x, y)
+    plane = np.exp(2j * math.pi * (grid.ref_nu[0] * X + grid.ref_nu[1] * Y))
+    assert oracle.rel_l2(oracle.forward(scene, grid), oracle.forward(scene, base) * plane) < 1e-12
+
+
+def test_r3_reference_wave_tilted_gaussian_beam():
+    """Fresnel closed form of a tilted Gaussian beam: an isotropic Gaussian at depth z under a
+    plane wave of transverse frequency nu_r reaches the SLM as
+    exp(j 2 pi nu_r.x) exp(j pi lambda z |nu_r|^2) u_0(x + lambda z nu_r),
+    u_0 the on-axis beam (the walk-off lambda z nu_r is the beam travelling along the tilt)."""
+    base = Grid(256, 256, 8e-6, 8e-6, (520e-9,))
+    grid = Grid(256, 256, 8e-6, 8e-6, (520e-9,), ref_nu=_lattice_ref(base, 5, -3))
+    lam, sig, z = 520e-9, 10 * 8e-6, 3e-3
+    rx, ry = grid.ref_nu
+    scene = one_gaussian(0.0, 0.0, z, sig ** 2, 0.0, sig ** 2, o=0.5, a=(0.8,), phi=0.3)
+    u = oracle.forward(scene, grid)[0]
+    x = (np.arange(grid.nx) - grid.nx // 2) * grid.px
+    X, Y = np.meshgrid(x, x)
+    Q = sig ** 2 - 1j * lam * z / (2 * math.pi)
+
+    def beam(x0, y0):
+        return (0.4 * np.exp(1j * 0.3) * np.exp(-2j * math.pi * z / lam) * (sig ** 2 / Q)
+                * np.exp(-((X - x0) ** 2 + (Y - y0) ** 2) / (2 * Q)))
+
+    tilt = np.exp(2j * math.pi * (rx * X + ry * Y)) * np.exp(1j * math.pi * lam * z * (rx * rx + ry * ry))
+    ref = tilt * beam(-lam * z * rx, -lam * z * ry)
+    assert oracle.rel_l2(u, ref) < 5e-7  # non-paraxial residual ~1.4e-7 at this tilt and depth
+    # walk-off the other way, or none (the transfer function shifted with the spectrum), are far off
+    assert oracle.rel_l2(u, tilt * beam(lam * z * rx, lam * z * ry)) > 1e-2
+    assert oracle.rel_l2(u, np.exp(2j * math.pi * (rx * X + ry * Y)) * beam(0.0, 0.0)) > 1e-2
+
+
+def test_r4_reference_wave_gradients_match_central_differences():
+    rng = np.random.default_rng(23)
+    base = Grid(48, 40, 8e-6, 8e-6, (638e-9, 450e-9))
+    grid = Grid(48, 40, 8e-6, 8e-6, (638e-9, 450e-9), ref_nu=(2.7 / (48 * 8e-6), -1.9 / (40 * 8e-6)))
+    n = 2
+    sxx, sxy, syy = zip(*[cov_from(rng.uniform(2.5, 5), rng.uniform(2.5, 5), rng.uniform(0, math.pi), 8e-6)
+                          for _ in range(n)])
+    scene = Scene(mean_x=rng.uniform(-0.2, 0.2, n) * grid.nx * grid.px, mean_y=rng.uniform(-0.2, 0.2, n) * grid.ny * grid.py,
+                  depth=rng.uniform(-3e-3, 3e-3, n), cov_xx=np.array(sxx), cov_xy=np.array(sxy), cov_yy=np.array(syy),
+                  opacity=rng.uniform(0.2, 1, n), amplitude=rng.uniform(0.2, 1, (2, n)), phase=rng.uniform(0, 6, n))
+    target = gwsgen.make_target(base, 98).astype(np.complex128) * 0.05
+    fields = _single_fields(scene, grid)
+    u = sum(fields)
+    _, G = oracle.loss_and_field_grad(u, target)
+    grads = oracle.backward(scene, grid, G)
+
+    def loss_with(i, name, value):
+        s = scene.subset([i])
+        getattr(s, name)[0] = value
+        return oracle.loss_and_field_grad(u - fields[i] + oracle.forward(s, grid), target)[0]
+
+    for i in range(n):
+        for name in ("mean_x", "mean_y", "cov_xx", "cov_xy", "cov_yy", "depth"):
+            v = float(getattr(scene, name)[i])
+            scale = {"mean_x": 8e-6, "mean_y": 8e-6, "depth": 1e-5}.get(name, abs(v))
+            h = 1e-4 * scale
+            fd = (8 * (loss_with(i, name, v + h) - loss_with(i, name, v - h))
+                  - (loss_with(i, name, v + 2 * h) - loss_with(i, name, v - 2 * h))) / (12 * h)
+            an = grads[name][i]
+            assert abs(fd - an) <= 1e-6 * abs(an), (i, name, fd, an)
