@@ -160,8 +160,8 @@ def test_focal_stack_no_planes_and_bad_width(ctx):
     u = cuda(gwsgen.make_target(g, 3601))
     assert ctx.focal_stack(problem(g), u, []).shape == (0, 1, 48, 64)
     wide = Grid(5000, 16, 8e-6, 8e-6, (520e-9,))
-    with pytest.raises(gws.GwsError):
-        ctx.focal_stack(problem(wide), u, [0.0])
+    with pytest.raises(gws.GwsError):  # the library's width limit (GWS_ERR_SHAPE), not the binding's checks
+        ctx.focal_stack(problem(wide), cuda(gwsgen.make_target(wide, 3602)), [0.0])
 
 
 def test_four_wavelengths(ctx):
