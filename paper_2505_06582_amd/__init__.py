@@ -488,7 +488,9 @@ class Context:
         torch = _torch()
         n = int(world["mean"].shape[0])
         deg = int(view["sh_degree"])
-        for k, cols in (("mean", 3), ("quat", 4), ("scale", 3), ("opacity_sh", (max(deg, 0) + 1) ** 2)):
+        # a degree outside 0..3 is left to the library, which rejects it before reading anything
+        sh_cols = (deg + 1) ** 2 if 0 <= deg <= 3 else int(world["opacity_sh"].shape[-1])
+        for k, cols in (("mean", 3), ("quat", 4), ("scale", 3), ("opacity_sh", sh_cols)):
             check_tensor(world.get(k), k, (n, cols), "float32")
         v = _View()
         for i, x in enumerate(view["world_to_view"]):

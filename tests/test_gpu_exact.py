@@ -116,6 +116,10 @@ def test_exact_counts_culled_and_clamped_windows(ctx):
     import paper_2505_06582_amd as gws
     grid = Grid(64, 48, 8e-6, 8e-6, (520e-9,))
     s = clustered_scene(12, grid, 2111)
+    # every other Gaussian isotropic with sigma 2.5 px: window ceil(2.5 sqrt(2 ln 1e7)) = 15 px,
+    # inside the 31 x 23 px half-grid, so only the two wide ones below are clamped
+    s.cov_xx[:] = s.cov_yy[:] = np.float32(6.25 * 64e-12)
+    s.cov_xy[:] = np.float32(0.0)
     s.cov_xy[0] = np.float32(2.0 * np.sqrt(float(s.cov_xx[0]) * float(s.cov_yy[0])))  # not positive definite
     s.mean_x[1] = np.float32(np.nan)
     wide = (4, 9)
@@ -142,7 +146,7 @@ def test_exact_alpha_straddling_the_threshold(ctx):
     it in FP32, the oracle in FP64), so the GPU field must lie within the FP32 tolerance of the
     oracle plus the distance between the oracle with the threshold moved down and up by 1e-5
     (which brackets every mix of decisions at pixels within 1e-5 of it)."""
-    grid = Grid(64, 48, 8e-6, 8e-6, (520e-9,))
+    grid = Grid(128, 96, 8e-6, 8e-6, (520e-9,))
     p = grid.px
     front = [((0, 0), 3.0, 25), ((-14, 8), 2.5, 13), ((12, -9), 4.0, 50), ((9, 11), 3.5, 34)]
     n = len(front) + 1
@@ -154,11 +158,13 @@ def test_exact_alpha_straddling_the_threshold(ctx):
         s.opacity[i] = np.float32(np.exp(r2 / (2 * sig * sig)) / 255.0)
         s.depth[i] = np.float32(1e-3 + 1e-4 * i)
     s.mean_x[-1], s.mean_y[-1] = np.float32(0.0), np.float32(0.0)
-    s.cov_xx[-1] = s.cov_yy[-1] = np.float32(144 * p * p)
+    # sigma 6 px: window ceil(6 sqrt(2 ln 1e7)) = 35 px, inside the 63 x 47 px half-grid
+    s.cov_xx[-1] = s.cov_yy[-1] = np.float32(36 * p * p)
     s.cov_xy[-1] = np.float32(0.0)
     s.opacity[-1] = np.float32(0.8)
     s.depth[-1] = np.float32(-2e-3)
     u = gpu_exact(ctx, s, grid)
+    assert ctx.stats()["n_window_clamped"] == 0
     mid = ex.exact_forward(s, grid)
     lo = ex.exact_forward(s, grid, t_eps=ex.T_EPS * (1 - 1e-5))
     hi = ex.exact_forward(s, grid, t_eps=ex.T_EPS * (1 + 1e-5))
