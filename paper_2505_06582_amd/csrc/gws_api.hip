@@ -324,8 +324,10 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
     const size_t part_bytes = (size_t)fwd_max_slots_f4(n) * C * 4 * WG * sizeof(float2);
     L.max_slots = (int64_t)(part_bytes / ((size_t)C * f_fwd * WG * sizeof(float2)));
     L.max_items = L.max_slots / 2 + ntiles + 1;
-    const int64_t nchunks = (n + BWD_CHUNK - 1) / BWD_CHUNK;
-    L.max_bitems = std::max<int64_t>(nchunks + 1024, std::min<int64_t>(65536, nchunks * 64 + 1024));
+    // backward items: (chunk of one adjoint work-group's Gaussians, range of TRB tiles); the
+    // binning grows TRB until the items fit, so about 4096 items of similar work share the GPU
+    const int64_t nchunks = (n + ADJ_MIN_CHUNK - 1) / ADJ_MIN_CHUNK;
+    L.max_bitems = nchunks + std::min<int64_t>(4096, 64 * nchunks + 64);
     L.max_bslots = L.max_bitems;
     const int hx = p->nx / 2, hy = p->ny / 2, SY = sub_h(f_bwd);
     L.sx_min = floor_div(-hx, SUBX);
@@ -350,7 +352,8 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
     L.off_bitems = take(sizeof(BItem) * L.max_bitems);
     L.off_chunk_items = take(sizeof(int2) * (nchunks + 1));
     L.off_range_base = take(sizeof(int32_t) * (ntiles + 2));
-    L.off_bpartials = take(sizeof(float) * (size_t)L.max_bslots * 64 * NACC);
+    L.off_bpartials = take(sizeof(float) * (size_t)L.max_bslots *
+                           std::max(adj_wg(C, true) * adj_nv(C, true), adj_wg(C, false) * adj_nv(C, false)));
     L.total = o;
     return L;
 }
@@ -359,8 +362,10 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
 // gradients, propagation tables) followed by one region per scene.
 struct BatchLayout {
     size_t total = 0;
-    size_t off_ctrl = 0, off_ftab = 0, off_btab = 0, off_prefix = 0, off_spectra = 0, off_gspecs = 0, off_dtab = 0,
-           off_d0tab = 0;
+    size_t off_ctrl = 0, off_ftab = 0, off_btab = 0, off_prefix = 0, off_spectra = 0, off_gspecs = 0, off_gpack = 0,
+           off_dpack = 0, off_d0 = 0;
+    AdjGeom geo = {};
+    int64_t pack_elems = 0;  // packed per-frequency elements of one scene (regions x blocks x C x 64)
     std::vector<size_t> scene_off;
     std::vector<int64_t> n;
 };
@@ -371,8 +376,11 @@ static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t 
     const int64_t M = (int64_t)p->nx * p->ny;
     const int C = p->n_lambda;
     const int hx = p->nx / 2, hy = p->ny / 2;
-    const int nsx = floor_div(hx - 1, SUBX) - floor_div(-hx, SUBX) + 1;
-    const int nsy_max = floor_div(hy - 1, sub_h(2)) - floor_div(-hy, sub_h(2)) + 1;
+    B.geo.tx_min = floor_div(-hx, TILEX);
+    B.geo.ty_min = floor_div(-hy, ADJ_RH);
+    B.geo.ntx = floor_div(hx - 1, TILEX) - B.geo.tx_min + 1;
+    B.geo.nreg = 2 * B.geo.ntx * (floor_div(hy - 1, ADJ_RH) - B.geo.ty_min + 1);
+    B.pack_elems = (int64_t)B.geo.nreg * ADJ_NB * C * 64;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
     B.off_ctrl = take(sizeof(long long) * 8);
@@ -381,8 +389,9 @@ static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t 
     B.off_prefix = take(sizeof(int32_t) * (S + 1));
     B.off_spectra = take(sizeof(float2) * (size_t)S * C * M);
     B.off_gspecs = take(sizeof(float2) * (size_t)S * C * M);
-    B.off_dtab = take(sizeof(float) * (size_t)C * M);
-    B.off_d0tab = take(sizeof(double) * (size_t)C * nsx * nsy_max);
+    B.off_gpack = take(sizeof(float2) * (size_t)S * B.pack_elems);
+    B.off_dpack = take(sizeof(float) * (size_t)B.pack_elems);
+    B.off_d0 = take(sizeof(double) * (size_t)B.geo.nreg * 2 * C);
     for (int i = 0; i < S; ++i) {
         const int64_t ni = offsets[i + 1] - offsets[i];
         B.n.push_back(ni);
@@ -435,7 +444,7 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
     L.off_gspec = take(sizeof(float2) * M * p->n_lambda);
     L.off_ckpt = take(sizeof(float) * M * (size_t)exact_ckpt_count(n, p->nx, p->ny));
     L.off_dmap = take(sizeof(float) * M);
-    L.off_pspec = take(sizeof(float) * ((M + 255) / 256) * 64 * 12);
+    L.off_pspec = take(sizeof(float) * ((M + 255) / 256) * 64 * 16);
     L.off_pspat = take(sizeof(float) * (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * 64 * 8);
     L.total = o;
     return L;
@@ -663,11 +672,11 @@ static int acc_grid(gws_ctx *ctx, int C, int F)
     return ctx->n_cu * it->second;
 }
 
-static int adj_grid(gws_ctx *ctx, int C, int F, int depth)
+static int adj_grid(gws_ctx *ctx, int C, int depth)
 {
-    const int key = 256 + (C * 16 + F) * 2 + (depth ? 1 : 0);
+    const int key = 256 + C * 2 + (depth ? 1 : 0);
     auto it = ctx->acc_occ.find(key);
-    if (it == ctx->acc_occ.end()) it = ctx->acc_occ.emplace(key, adjoint_occupancy(C, F, depth)).first;
+    if (it == ctx->acc_occ.end()) it = ctx->acc_occ.emplace(key, adjoint_occupancy(C, depth)).first;
     return ctx->n_cu * it->second;
 }
 
@@ -775,10 +784,13 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
                                const gws_gaussians *g, const void *grad_field, const gws_grads *grads, void *ws,
                                size_t ws_bytes, hipStream_t s)
 {
+    if (prob->n_lambda > 3 && grads->depth)
+        return fail(ctx, GWS_ERR_UNSUPPORTED,
+                    "the order-invariant adjoint takes the depth gradient for at most 3 wavelengths");
+    // the adjoint's geometry is fixed (regions of the F = 8 tiling); the tiling chooses the forward's
     const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
-    const int F = kTileCfg[cfg - 1][1];
     Plan *p = nullptr;
-    gws_status st = get_plan(ctx, prob->nx, prob->ny, F, &p);
+    gws_status st = get_plan(ctx, prob->nx, prob->ny, ADJ_F, &p);
     if (st != GWS_OK) return st;
     const BatchLayout BL = make_batch_layout(prob, S, offsets);
     st = check_ws(ctx, ws, ws_bytes, BL.total);
@@ -786,30 +798,27 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     char *base = (char *)ws;
     Consts k = make_consts(prob, 0);
     k.depth_grad = grads->depth != nullptr;
-    const int64_t CM = (int64_t)k.C * prob->nx * prob->ny;
     float2 *gspecs = (float2 *)(base + BL.off_gspecs);
-    float *dtab = (float *)(base + BL.off_dtab);
-    double *d0tab = (double *)(base + BL.off_d0tab);
+    float2 *gpack = (float2 *)(base + BL.off_gpack);
+    float *dpack = (float *)(base + BL.off_dpack);
+    double *d0 = (double *)(base + BL.off_d0);
     BwdTab tab;
     memset(&tab, 0, sizeof(tab));
     tab.n = S;
     std::vector<long long *> ctrs(S);
     std::vector<uint32_t *> vals_sorted(S);
-    Layout L0;
     {
         StageScope sc(ctx, s, ST_PREP);
         for (int i = 0; i < S; ++i) {
-            const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], F);
-            if (i == 0) L0 = L;
+            const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], ADJ_F);
             const Bufs B = carve(L, base + BL.scene_off[i]);
             uint64_t *keys = nullptr;
             uint32_t *vals = nullptr;
             st = run_prep(ctx, k, scene_view(g, offsets[i], BL.n[i]), L, B, s, &keys, &vals);
             if (st != GWS_OK) return st;
-            HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, B.range_base,
-                                               ntiles_for(prob->nx, prob->ny, 2) + 1, L.max_bitems, B.counters, BL.n[i],
-                                               s));
-            tab.s[i] = BwdScene{B.rec, gspecs + (int64_t)i * CM, B.bitems, B.bpartials, B.counters, BL.n[i]};
+            HIP_CHECK(ctx, launch_bin_backward(*p, keys, B.bitems, B.chunk_items, B.range_base, p->ntiles + 1,
+                                               L.max_bitems, B.counters, BL.n[i], adj_wg(k.C, k.depth_grad != 0), s));
+            tab.s[i] = BwdScene{B.rec, gpack + (int64_t)i * BL.pack_elems, B.bitems, B.bpartials, B.counters, BL.n[i]};
             ctrs[i] = B.counters;
             vals_sorted[i] = vals;
         }
@@ -825,8 +834,7 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     }
     {
         StageScope sc(ctx, s, ST_DTABLE);
-        HIP_CHECK(ctx, launch_polar(gspecs, (int64_t)S * CM, s));
-        HIP_CHECK(ctx, launch_dtable(k, dtab, d0tab, L0.nsx, L0.nsy, L0.sx_min, L0.sy_min, sub_h(F), s));
+        HIP_CHECK(ctx, launch_adj_pack(k, BL.geo, S, gspecs, gpack, dpack, d0, s));
     }
     BwdScene *dscenes = (BwdScene *)(base + BL.off_btab);
     int32_t *prefix = (int32_t *)(base + BL.off_prefix);
@@ -834,17 +842,17 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     {
         StageScope sc(ctx, s, ST_ADJOINT);
         HIP_CHECK(ctx, launch_bwd_table(tab, dscenes, prefix, queue, s));
-        HIP_CHECK(ctx, launch_adjoint(*p, k, dscenes, prefix, S, queue, dtab, d0tab, L0.nsx, L0.nsy, L0.sx_min, L0.sy_min,
-                                      adj_grid(ctx, k.C, F, k.depth_grad), s));
+        HIP_CHECK(ctx, launch_adjoint(*p, k, dscenes, prefix, S, queue, dpack, d0, BL.geo,
+                                      adj_grid(ctx, k.C, k.depth_grad), s));
     }
     {
         StageScope sc(ctx, s, ST_FINAL);
         for (int i = 0; i < S; ++i) {
-            const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], F);
+            const Layout L = make_layout(prob, BL.n[i], kTileCfg[cfg - 1][0], ADJ_F);
             const Bufs B = carve(L, base + BL.scene_off[i]);
             HIP_CHECK(ctx, launch_grad_final(scene_view(g, offsets[i], BL.n[i]), k, vals_sorted[i], B.chunk_items,
                                              B.range_base, B.bpartials, grad_view(grads, offsets[i], g->n), BL.n[i],
-                                             B.counters, s));
+                                             B.counters, adj_wg(k.C, k.depth_grad != 0), s));
         }
     }
     HIP_CHECK(ctx, launch_sum_counters(ctrs.data(), S, ctx->d_stats, s));
@@ -967,7 +975,6 @@ extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const 
     if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
-    if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     st = check_grads(ctx, grads);
@@ -1096,7 +1103,6 @@ extern "C" gws_status gws_backward_batched(gws_ctx *ctx, const gws_problem *prob
     if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
     gws_status st = gws_check_problem(prob);
     if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
-    if (prob->n_lambda > 3) return fail(ctx, GWS_ERR_UNSUPPORTED, "backward supports at most 3 wavelengths");
     st = check_gaussians(ctx, g);
     if (st != GWS_OK) return st;
     st = check_grads(ctx, grads);

@@ -31,8 +31,42 @@ __host__ __device__ constexpr int waves_per_simd(int f) { return f >= 8 ? 2 : 4;
 constexpr int WAVES = 4;             // wavefronts per work-group
 constexpr int WG = 64 * WAVES;       // threads per work-group
 constexpr int NBUCKET = 4096;        // support-radius buckets (index units)
-constexpr int BWD_CHUNK = 64;        // Gaussians per backward work item (one per lane)
-constexpr int NACC = 16;             // per-Gaussian adjoint accumulators (padded)
+
+// Adjoint geometry.  Its tile list is the F = 8 tiling (32 x 64 tiles); a region is the left
+// or right 16 x 64 half of a tile, two 16 x 32 sub-tiles (the unit of the exact phase base),
+// sixteen 4-row blocks.  A work-group of adj_waves(C, depth) wavefronts owns as many sorted
+// Gaussians as it has threads (one per thread) and holds one region's per-frequency data in
+// LDS; lane l evaluates column l % 16 and rows l / 16 + 4 b of block b.
+constexpr int ADJ_F = 8;
+constexpr int ADJ_RW = SUBX;           // region columns
+constexpr int ADJ_RH = 2 * sub_h(ADJ_F);  // region rows (64)
+constexpr int ADJ_SH = sub_h(ADJ_F);   // sub-tile rows (32)
+constexpr int ADJ_NB = ADJ_RH / 4;     // 4-row blocks per region
+constexpr int ADJ_MIN_CHUNK = 256;     // smallest work-group (and Gaussian chunk) of any variant
+static_assert(TILEX == 2 * ADJ_RW, "a tile holds two regions");
+// reduced per-Gaussian sums: Re P_c, Sfx, Sfy, Qxx, Qxy, Qyy, then Im P_c and W_c with the
+// depth gradient, else sum Im rho
+__host__ __device__ constexpr int adj_nv(int c, bool depth) { return (depth ? 3 * c : c) + 5 + (depth ? 0 : 1); }
+// LDS of a work-group of w wavefronts: the region's data (12 B per frequency and channel), the
+// per-Gaussian sums and the list of accepted Gaussians (16-byte aligned entries).
+__host__ __device__ constexpr int adj_lds_bytes(int c, bool depth, int w)
+{
+    return ADJ_NB * c * 64 * 12 + 64 * w * adj_nv(c, depth) * 4 + 64 * w * ((2 + 2 * c + 3) / 4) * 16;
+}
+// Eight wavefronts per work-group while that fits 82,000 bytes of LDS, else four.
+__host__ __device__ constexpr int adj_waves(int c, bool depth) { return adj_lds_bytes(c, depth, 8) <= 82000 ? 8 : 4; }
+__host__ __device__ constexpr int adj_wg(int c, bool depth) { return 64 * adj_waves(c, depth); }
+// Wavefronts per SIMD the adjoint is compiled for: two work-groups per CU while each needs at
+// most 78 KB of LDS, else one.
+__host__ __device__ constexpr int adj_waves_per_simd(int c, bool depth)
+{
+    return (adj_lds_bytes(c, depth, adj_waves(c, depth)) <= 78 * 1024 ? 2 : 1) * adj_waves(c, depth) / 4;
+}
+// Region indexing of the packed per-frequency tables: region r = 2 ((ty - ty_min) ntx +
+// (tx - tx_min)) + half over the F = 8 tile grid.
+struct AdjGeom {
+    int32_t tx_min, ty_min, ntx, nreg;
+};
 
 // ---------------------------------------------------------------------------------
 // Support tests in index units.  The eps-support of a Gaussian's spectrum is the ellipse
@@ -206,7 +240,7 @@ struct Item {
     int32_t pad;
 };
 
-// Backward work item: Gaussians [chunk*BWD_CHUNK, +BWD_CHUNK) over sorted tiles [k0, k1).
+// Backward work item: Gaussians [chunk*W, +W) over sorted tiles [k0, k1), W the adjoint's work-group size.
 struct BItem {
     int32_t chunk;
     int32_t k0, k1;
@@ -242,7 +276,7 @@ struct FwdScene {
 // Per-scene pointers of the adjoint.
 struct BwdScene {
     const GRec *rec;
-    const float2 *gspec;
+    const float2 *gpack;  // (|Gs_c|, arg Gs_c / 2 pi) region-major: [region][block][c][lane]
     const BItem *bitems;
     float *bpartials;
     long long *counters;
@@ -339,7 +373,7 @@ hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32
                               long long *counters, hipStream_t s);
 hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
                                int32_t *range_base, int max_ranges, int64_t max_bitems, long long *counters, int64_t n,
-                               hipStream_t s);
+                               int chunk, hipStream_t s);
 // Writes the scene table and the prefix of per-scene work-item counts, zeroes the queue head.
 hipError_t launch_fwd_table(const FwdTab &tab, FwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s);
 hipError_t launch_bwd_table(const BwdTab &tab, BwdScene *dst, int32_t *prefix, long long *queue, hipStream_t s);
@@ -347,7 +381,6 @@ hipError_t launch_accumulate(const Plan &p, const Consts &k, const FwdScene *sce
                              int n_scenes, long long *queue, int grid, hipStream_t s);
 hipError_t launch_reduce_partials(const Plan &p, const Consts &k, const FwdScene *scenes, int n_scenes,
                                   hipStream_t s);
-hipError_t launch_polar(float2 *g, int64_t n, hipStream_t s);
 
 // Exact alpha wave blending (k_exact.hip): device buffers of one call.
 struct ExactBuffers {
@@ -378,16 +411,18 @@ hipError_t run_exact_backward(const Plan &p, const Consts &k, const GView &g, co
 hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, const ExactBuffers &eb, float2 *spec,
                              hipStream_t s);
 hipError_t run_probes(int n_cu, hipStream_t s, double *trans_ops, double *valu_ops, double *hbm_bytes);
-hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
-                         hipStream_t s);
+// Region-major per-frequency tables of the adjoint: dpack [nreg][ADJ_NB][C][64] and d0
+// [nreg][2][C] (geometry only), gpack [scene][nreg][ADJ_NB][C][64] from the scenes' Gs.
+hipError_t launch_adj_pack(const Consts &k, const AdjGeom &geo, int n_scenes, const float2 *gspecs, float2 *gpack,
+                           float *dpack, double *d0, hipStream_t s);
 hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,
-                          long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy, int sx_min,
-                          int sy_min, int grid, hipStream_t s);
+                          long long *queue, const float *dpack, const double *d0, const AdjGeom &geo, int grid,
+                          hipStream_t s);
 hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
                              const int32_t *range_base, const float *bpartials, const GradView &grads, int64_t n,
-                             const long long *counters, hipStream_t s);
+                             const long long *counters, int chunk, hipStream_t s);
 hipError_t launch_sum_counters(long long *const *src, int n, long long *dst, hipStream_t s);
-int adjoint_occupancy(int C, int F, int depth);
+int adjoint_occupancy(int C, int depth);
 hipError_t launch_synth(GView g, float *base, int64_t n, uint64_t seed, const Consts &k, hipStream_t s);
 int accumulate_occupancy(int C, int F);
 hipError_t launch_zero_counters(long long *counters, uint32_t *bucket_hist, hipStream_t s);

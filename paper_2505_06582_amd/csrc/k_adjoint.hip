@@ -12,376 +12,480 @@
 // and apply the chain rule once per Gaussian (k_grad_final).  Terms are recomputed exactly
 // as the forward computes them; nothing per (Gaussian, frequency) is stored.
 //
-// Work: a wavefront owns 64 consecutive sorted Gaussians (one per lane, its record in
-// registers) and a range of tiles.  For each 16 x 16 sub-tile, lanes test their own
-// Gaussian against it and stage the accepted ones in LDS; then every lane evaluates its 4
-// frequencies for each accepted Gaussian and the wave reduces the 3C + 5 sums across
-// lanes into that Gaussian's LDS accumulator.  Item partials are summed per Gaussian in a
-// fixed order, so results are bitwise reproducible.
+// Work.  A region is a 16-column x 64-row block of the centred frequency plane (one half
+// of a 32 x 64 tile of the adjoint's tile list), made of two 16 x 32 sub-tiles, the unit of
+// the exact phase base.  Everything the sums need per frequency -- |Gs_c|, arg Gs_c / 2 pi
+// and D_c(nu) - D_c(nu_0) -- is packed region-major once per call (k_adj_pack_g,
+// k_adj_pack_d), so a work-group of 8 wavefronts copies one region into LDS with
+// coalesced loads and every wavefront reads it from there.  The work-group owns 512
+// consecutive sorted Gaussians (one per thread) and a range of tiles; for each region,
+// every thread tests its own Gaussian (exact ellipse test, 4-row block mask, FP64 phase
+// bases of both sub-tiles), then each wavefront walks its accepted Gaussians one at a time:
+// the record arrives by scalar loads, lane l evaluates column l % 16 and rows l / 16 + 4 b
+// of every 4-row block b the support reaches (up to 16 blocks, 1024 frequencies), and the
+// per-lane sums are reduced across the wavefront once per (Gaussian, region) into that
+// Gaussian's LDS accumulator.  No per-lane frequency tables are held in registers, so two
+// work-groups (four wavefronts per SIMD) share a CU and one's barriers overlap the other's
+// work.  Item partials are summed per Gaussian in a fixed order, so results are bitwise
+// reproducible.
 #include "gws_internal.h"
 
 namespace gws {
 
 static __device__ __forceinline__ double frac_d(double v) { return v - floor(v); }
 
-static __device__ __forceinline__ bool ellipse_meets_rect_b(float a, float b2, float g, float lim, float x0, float x1,
-                                                            float y0, float y1)
+// D_c(nu) = sqrt(1/lambda^2 - |nu|^2) - 1/lambda written without cancellation; 0 when the
+// frequency is evanescent (such frequencies carry no signal, see k_adj_pack_g).
+static __device__ __forceinline__ double dprop_b(double nu2, double il)
 {
-    return ellipse_meets_rect_r(a, b2, g, 0.5f / a, 0.5f / g, lim, x0, x1, y0, y1);
+    const double w2 = il * il - nu2;
+    return w2 > 0.0 ? -nu2 / (il + sqrt(w2)) : 0.0;
 }
 
-struct alignas(16) BEntry {
-    float alpha, beta2, gamma, z;
-    float rxf, ryf;
-    int32_t owner;   // lane (0..63) that owns this Gaussian
-    uint32_t rows;   // row_block_mask of this Gaussian on the sub-tile
-    float amp[4];
-    float base[4];
-};
+// Frequency (signed index units) of element (region r, block b, lane) of the packed layout.
+static __device__ __forceinline__ void adj_elem_freq(const AdjGeom &geo, int r, int b, int lane, int *mxp, int *myp)
+{
+    const int h = r & 1, t = r >> 1;
+    const int tx = t % geo.ntx + geo.tx_min, ty = t / geo.ntx + geo.ty_min;
+    *mxp = tx * TILEX + h * ADJ_RW + (lane & (ADJ_RW - 1));
+    *myp = ty * ADJ_RH + 4 * b + (lane >> 4);
+}
 
-// Per-frequency FP32 table D_c(nu_m) - D_c(nu_0(sub-tile of m)) in FFT order, and the FP64
-// sub-tile centre values D_c(nu_0).  Sub-tiles are the DC-aligned SUBX x SY blocks.
-__global__ void __launch_bounds__(256) k_dtable(Consts k, float *__restrict__ dD, double *__restrict__ D0, int nsx,
-                                                int nsy, int sx_min, int sy_min, int SY)
+// Geometry-only part of the packed table (shared by every scene): dD[r][b][c][lane] =
+// D_c(nu) - D_c(nu_0) with nu_0 the centre of the element's sub-tile (0 outside the grid or
+// when evanescent), and D0[r][s][c] = D_c(nu_0) of sub-tile s in FP64.
+__global__ void __launch_bounds__(256) k_adj_pack_d(Consts k, AdjGeom geo, float *__restrict__ dpack,
+                                                   double *__restrict__ d0)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t M = (int64_t)k.nx * k.ny;
+    const int C = k.C;
+    const int64_t per_r = (int64_t)ADJ_NB * C * 64;
+    const int64_t total = (int64_t)geo.nreg * per_r;
+    if (idx >= total) return;
+    const int r = (int)(idx / per_r);
+    const int rem = (int)(idx - (int64_t)r * per_r);
+    const int b = rem / (C * 64), c = (rem / 64) % C, lane = rem & 63;
+    int mxp, myp;
+    adj_elem_freq(geo, r, b, lane, &mxp, &myp);
     const double Wx = k.nx * k.px, Wy = k.ny * k.py;
-    if (idx < M) {
-        const int mx = (int)(idx % k.nx), my = (int)(idx / k.nx);
-        const int mxp = 2 * mx < k.nx ? mx : mx - k.nx, myp = 2 * my < k.ny ? my : my - k.ny;
-        const int sx = (int)floor(mxp / (double)SUBX), sy = (int)floor(myp / (double)SY);
-        const int cx = sx * SUBX + SUBX / 2, cy = sy * SY + SY / 2;
-        const double nux = mxp / Wx, nuy = myp / Wy, ncx = cx / Wx, ncy = cy / Wy;
-        const double nu2 = nux * nux + nuy * nuy, nc2 = ncx * ncx + ncy * ncy;
-        for (int c = 0; c < k.C; ++c) {
-            const double il = k.inv_lambda[c];
-            const double w2 = il * il - nu2, wc = il * il - nc2;
-            const double d = w2 > 0.0 ? -nu2 / (il + sqrt(w2)) : 0.0;
-            const double d0 = wc > 0.0 ? -nc2 / (il + sqrt(wc)) : 0.0;
-            dD[(int64_t)c * M + idx] = (float)(d - d0);
-        }
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    const int mx0 = mxp - (lane & (ADJ_RW - 1));
+    const int cx = mx0 + ADJ_RW / 2, cy = myp - (lane >> 4) - 4 * (b & 7) + ADJ_SH / 2;
+    const double ncx = cx / Wx, ncy = cy / Wy;
+    const double D0 = dprop_b(ncx * ncx + ncy * ncy, k.inv_lambda[c]);
+    float v = 0.0f;
+    if (mxp >= -hx && mxp < hx && myp >= -hy && myp < hy) {
+        const double nux = mxp / Wx, nuy = myp / Wy;
+        const double nu2 = nux * nux + nuy * nuy;
+        const double il = k.inv_lambda[c];
+        if (nu2 < il * il) v = (float)(dprop_b(nu2, il) - D0);
     }
-    const int64_t ns = (int64_t)nsx * nsy;
-    if (idx < ns) {
-        const int sx = (int)(idx % nsx) + sx_min, sy = (int)(idx / nsx) + sy_min;
-        const double ncx = (sx * SUBX + SUBX / 2) / Wx, ncy = (sy * SY + SY / 2) / Wy;
-        const double nc2 = ncx * ncx + ncy * ncy;
-        for (int c = 0; c < k.C; ++c) {
-            const double il = k.inv_lambda[c];
-            const double wc = il * il - nc2;
-            D0[(int64_t)c * ns + idx] = wc > 0.0 ? -nc2 / (il + sqrt(wc)) : 0.0;
-        }
-    }
+    dpack[idx] = v;
+    if (lane == 0 && (b & 7) == 0) d0[((int64_t)r * 2 + (b >> 3)) * C + c] = D0;
 }
 
-hipError_t launch_dtable(const Consts &k, float *dD, double *D0, int nsx, int nsy, int sx_min, int sy_min, int sy,
-                         hipStream_t s)
+// Per-scene part: gpack[r][b][c][lane] = (|Gs_c|, arg Gs_c / 2 pi) at the element's
+// frequency, zero outside the grid and where the frequency is evanescent for channel c (the
+// forward sets H to zero there, so its adjoint has nothing to propagate).  The adjoint then
+// forms conj(Gs) e^{j 2 pi Theta} as |Gs| e^{j 2 pi (Theta - arg Gs / 2 pi)}: one more phase
+// term, two products instead of a complex product.
+__global__ void __launch_bounds__(256) k_adj_pack_g(Consts k, AdjGeom geo, const float2 *__restrict__ gspec,
+                                                   float2 *__restrict__ gpack)
 {
-    const int64_t M = (int64_t)k.nx * k.ny;
-    const int64_t n = M > (int64_t)nsx * nsy ? M : (int64_t)nsx * nsy;
-    hipLaunchKernelGGL(k_dtable, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, dD, D0, nsx, nsy, sx_min, sy_min,
-                       sy);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C = k.C;
+    const int64_t per_r = (int64_t)ADJ_NB * C * 64;
+    const int64_t total = (int64_t)geo.nreg * per_r;
+    if (idx >= total) return;
+    const int r = (int)(idx / per_r);
+    const int rem = (int)(idx - (int64_t)r * per_r);
+    const int b = rem / (C * 64), c = (rem / 64) % C, lane = rem & 63;
+    int mxp, myp;
+    adj_elem_freq(geo, r, b, lane, &mxp, &myp);
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (mxp >= -hx && mxp < hx && myp >= -hy && myp < hy) {
+        const double nux = mxp / (k.nx * k.px), nuy = myp / (k.ny * k.py);
+        const double il = k.inv_lambda[c];
+        if (nux * nux + nuy * nuy < il * il) {
+            const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
+            const float2 gv = gspec[((int64_t)c * k.ny + my) * k.nx + mx];
+            v = make_float2(hypotf(gv.x, gv.y), atan2f(gv.y, gv.x) * 0.15915494309189535f);
+        }
+    }
+    gpack[idx] = v;
+}
+
+hipError_t launch_adj_pack(const Consts &k, const AdjGeom &geo, int n_scenes, const float2 *gspecs, float2 *gpack,
+                           float *dpack, double *d0, hipStream_t s)
+{
+    const int64_t per_scene = (int64_t)geo.nreg * ADJ_NB * k.C * 64;
+    const unsigned blocks = (unsigned)((per_scene + 255) / 256);
+    hipLaunchKernelGGL(k_adj_pack_d, dim3(blocks), dim3(256), 0, s, k, geo, dpack, d0);
+    const int64_t M = (int64_t)k.nx * k.ny * k.C;
+    for (int i = 0; i < n_scenes; ++i)
+        hipLaunchKernelGGL(k_adj_pack_g, dim3(blocks), dim3(256), 0, s, k, geo, gspecs + (int64_t)i * M,
+                           gpack + (int64_t)i * per_scene);
     return hipGetLastError();
 }
 
-// Gs in polar form, in place: (Re, Im) -> (|Gs|, arg Gs / 2 pi).  The adjoint then forms
-// conj(Gs) e^{j 2 pi Theta} as |Gs| e^{j 2 pi (Theta - arg Gs / 2 pi)}: one more phase term,
-// two products instead of a complex product.
-__global__ void __launch_bounds__(256) k_polar(float2 *__restrict__ g, int64_t n)
+// Reduce NV per-lane values over the wavefront and add the totals to acc[0..NV) (LDS).
+// Up to 8 values (+ 1 carried along), 16, or 24 (16 + 8) use the transposed butterfly.
+template <int NV>
+static __device__ __forceinline__ void reduce_into(float (&x)[NV], float *acc, int lane)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float2 v = g[i];
-    g[i] = make_float2(hypotf(v.x, v.y), atan2f(v.y, v.x) * 0.15915494309189535f);
+    if constexpr (NV <= 9) {
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = i < NV ? x[i] : 0.0f;
+        float y = NV == 9 ? x[NV - 1] : 0.0f;
+        if constexpr (NV == 9) {
+            reduce_transposed<8, true>(v, y, lane);
+            if (lane == 4) atomicAdd(&acc[8], y);
+        } else {
+            reduce_transposed<8, false>(v, y, lane);
+        }
+        if ((lane & 7) == 0) {
+            const int v0 = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+            if (v0 < NV && (NV != 9 || v0 < 8)) atomicAdd(&acc[v0], v[0]);  // ds_add_f32, no return
+        }
+    } else if constexpr (NV <= 16) {
+        float v[16];
+        float y = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = i < NV ? x[i] : 0.0f;
+        reduce_transposed<16, false>(v, y, lane);
+        if ((lane & 7) == 0) {
+            const int v0 = 2 * (((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1));
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                if (v0 + j < NV) atomicAdd(&acc[v0 + j], v[j]);
+        }
+    } else {
+        static_assert(NV <= 24, "at most 24 reduced values");
+        float v[16], w[8];
+        float y = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = x[i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = 16 + i < NV ? x[16 + i] : 0.0f;
+        reduce_transposed<16, false>(v, y, lane);
+        reduce_transposed<8, false>(w, y, lane);
+        if ((lane & 7) == 0) {
+            const int g = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) atomicAdd(&acc[2 * g + j], v[j]);
+            if (16 + g < NV) atomicAdd(&acc[16 + g], w[0]);
+        }
+    }
 }
 
-hipError_t launch_polar(float2 *g, int64_t n, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_polar, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, n);
-    return hipGetLastError();
-}
+// A Gaussian accepted for the current region: its index in the item, its 4-row block mask and
+// the phase bases of the region's two sub-tiles.
+template <int C>
+struct alignas(16) AdjEntry {
+    int32_t g;
+    uint32_t rows;
+    float base[2 * C];
+};
 
-template <int C, bool DEPTH, int F>
-__global__ void __launch_bounds__(WG, waves_per_simd(F)) k_adjoint(Consts k, const int32_t *__restrict__ tile_xy,
-                                                const BwdScene *__restrict__ scenes, const int32_t *__restrict__ prefix,
-                                                int n_scenes, long long *__restrict__ queue,
-                                                const float *__restrict__ dtab, const double *__restrict__ d0tab,
-                                                int nsx, int nsy, int sx_min, int sy_min)
-{
-    // reduced values: Re P_c, Sfx, Sfy, Qxx, Qxy, Qyy, and with depth Im P_c, W_c; without
-    // depth the phase gradient's sum_m Im rho rides along as one extra fully reduced value
-    constexpr int NV = (DEPTH ? 3 : 1) * C + 5;
-    constexpr int NR = NV <= 8 ? 8 : 16;
-    constexpr int EXTRA_SLOT = 8;
-    static_assert(NV <= 16, "too many accumulators");
-    static_assert(DEPTH || NV <= 8, "without depth the sums must fit 8 transposed values");
-    __shared__ BEntry s_w[WAVES][64];
-    __shared__ float s_acc[WAVES][64][NACC];
+// Loads through the constant address space are scalar when the address is uniform.
+#define CONST_AS __attribute__((address_space(4)))
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+template <int C, bool DEPTH>
+__global__ void __launch_bounds__(adj_wg(C, DEPTH), adj_waves_per_simd(C, DEPTH))
+    k_adjoint(Consts k, const int32_t *__restrict__ tile_xy, const BwdScene *__restrict__ scenes,
+              const int32_t *__restrict__ prefix, int n_scenes, long long *__restrict__ queue,
+              const float *__restrict__ dpack, const double *__restrict__ d0tab, AdjGeom geo)
+{
+    constexpr int NV = adj_nv(C, DEPTH);
+    constexpr int ADJ_WG = adj_wg(C, DEPTH);
+    constexpr int RE = ADJ_NB * C * 64;  // packed elements per region
+    __shared__ __attribute__((aligned(16))) float2 s_g[RE];  // [b][c][lane] (|Gs|, arg Gs / 2 pi)
+    __shared__ __attribute__((aligned(16))) float s_d[RE];   // [b][c][lane] D_c(nu) - D_c(nu_0)
+    __shared__ float s_acc[ADJ_WG * NV]; // [Gaussian of the item][value]
+    __shared__ AdjEntry<C> s_ent[ADJ_WG];  // accepted Gaussians of the current region
+    __shared__ int s_cnt[2], s_next[2];    // list length and visit counter, by region parity
+    __shared__ int s_item, s_scene;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int total_items = prefix[n_scenes];
     const int hx = k.nx / 2, hy = k.ny / 2;
-    const int64_t M = (int64_t)k.nx * k.ny;
-    const int64_t ns = (int64_t)nsx * nsy;
     const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    const int col = lane & (ADJ_RW - 1), row4 = lane >> 4;
+    const float dxf = (float)(col - ADJ_RW / 2);   // column offset from the sub-tile centre
+    const float dyr = (float)(row4 - ADJ_SH / 2);  // row offset from the sub-tile centre at block 0
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    constexpr int SY = sub_h(F), TY = 2 * SY;
-    const int col = lane & (SUBX - 1), row0 = lane >> 4;
-    const float dxf = (float)(col - SUBX / 2);
+
     for (;;) {
-        int q = 0, sc = 0;
-        if (lane == 0) {
-            q = (int)atomicAdd((unsigned long long *)queue, 1ull);
+        if (tid == 0) {
+            const int q = (int)atomicAdd((unsigned long long *)queue, 1ull);
+            int sc = 0;
             if (q < total_items)
                 while (sc + 1 < n_scenes && prefix[sc + 1] <= q) ++sc;
+            s_item = q;
+            s_scene = sc;
         }
-        q = __shfl(q, 0);
-        sc = __shfl(sc, 0);
+        __syncthreads();
+        // wave-uniform from here on: scalar loads and scalar control flow
+        const int q = __builtin_amdgcn_readfirstlane(s_item), sc = __builtin_amdgcn_readfirstlane(s_scene);
         if (q >= total_items) break;
         const BwdScene S = scenes[sc];
         const GRec *__restrict__ rec = S.rec;
-        const float2 *__restrict__ gspec = S.gspec;  // polar: (|Gs|, arg Gs / 2 pi)
+        const float2 *__restrict__ gpack = S.gpack;
         const int64_t nvalid = S.n - S.counters[CTR_NCULLED];
         const BItem bi = S.bitems[q - prefix[sc]];
-        long long pairs = 0;
-        const int64_t gidx = (int64_t)bi.chunk * 64 + lane;
+        const int64_t g0 = (int64_t)bi.chunk * ADJ_WG;
+        const int64_t gidx = g0 + tid;
         const bool gvalid = gidx < nvalid;
-        // this lane's record as four 16-byte registers (a struct would be kept in scratch):
-        // r0 = (alpha, beta2, gamma, z), r1 = (rx, ry, rxf, ryf), r2 = kappa[4], r3 = amp[4]
-        float4 r0 = make_float4(1.f, 1.f, 1.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f), r2 = r1, r3 = r1;
-        if (gvalid) {
-            const float4 *src = reinterpret_cast<const float4 *>(rec + gidx);
-            r0 = src[0];
-            r1 = src[1];
-            r2 = src[2];
-            r3 = src[3];
-        }
-        const uint32_t rx = __float_as_uint(r1.x), ry = __float_as_uint(r1.y);
-        const float kap[4] = {r2.x, r2.y, r2.z, r2.w};
-#pragma unroll
-        for (int v = 0; v < NACC; ++v) s_acc[wave][lane][v] = 0.0f;
+        long long pairs = 0;
+        for (int i = tid; i < ADJ_WG * NV; i += ADJ_WG) s_acc[i] = 0.0f;
+        if (tid < 2) s_cnt[tid] = s_next[tid] = 0;
+        int par = 0;  // parity of the region being processed
 
         for (int kt = bi.k0; kt < bi.k1; ++kt) {
             const int32_t txy = tile_xy[kt];
             const int tx = (int)(int16_t)(txy & 0xffff), ty = txy >> 16;
-            for (int st = 0; st < 4; ++st) {
-                const int sx0 = tx * TILEX + (st & 1) * SUBX, sy0 = ty * TY + (st >> 1) * SY;
-                const float x0 = (float)max(sx0, -hx), x1 = (float)min(sx0 + SUBX - 1, hx - 1);
-                const float y0 = (float)max(sy0, -hy), y1 = (float)min(sy0 + SY - 1, hy - 1);
-                if (x0 > x1 || y0 > y1) continue;
-                const int cx = sx0 + SUBX / 2, cy = sy0 + SY / 2;
-                const int64_t sidx = (int64_t)(sy0 / SY - sy_min) * nsx + (sx0 / SUBX - sx_min);
-                // stage this sub-tile's accepted Gaussians
-                const bool p = gvalid && ellipse_meets_rect_b(r0.x, r0.y, r0.z, lim, x0, x1, y0, y1);
-                const uint64_t bal = __ballot(p);
-                const int cnt = __popcll(bal);
-                if (cnt == 0) continue;
-                if (p) {
-                    const uint32_t rows = row_block_mask<F>(r0.x, r0.y, r0.z, lim, x0, x1, sy0, hy);
-                    pairs += __popc(rows) * (SUBX * 4);
-                    const uint32_t ramp = (uint32_t)cx * rx + (uint32_t)cy * ry;
-                    const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
-                    float4 b4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    float bs[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-                        bs[c] = (float)frac_d((double)kap[c] - ramp_rev - (double)r0.w * d0tab[c * ns + sidx]);
-                    b4 = make_float4(bs[0], bs[1], bs[2], bs[3]);
-                    float4 *dst = reinterpret_cast<float4 *>(&s_w[wave][__popcll(bal & lt)]);
-                    dst[0] = r0;
-                    dst[1] = make_float4(r1.z, r1.w, __int_as_float(lane), __uint_as_float(rows));
-                    dst[2] = r3;
-                    dst[3] = b4;
+            for (int h = 0; h < 2; ++h) {
+                const int x0 = tx * TILEX + h * ADJ_RW, y0 = ty * ADJ_RH;
+                const float X0 = (float)max(x0, -hx), X1 = (float)min(x0 + ADJ_RW - 1, hx - 1);
+                const float Y0 = (float)max(y0, -hy), Y1 = (float)min(y0 + ADJ_RH - 1, hy - 1);
+                if (X0 > X1 || Y0 > Y1) continue;  // uniform over the work-group
+                const int r = ((ty - geo.ty_min) * geo.ntx + (tx - geo.tx_min)) * 2 + h;
+                __syncthreads();  // the previous region's data is no longer read
+                {
+                    const float4 *sg = reinterpret_cast<const float4 *>(gpack + (int64_t)r * RE);
+                    float4 *dg = reinterpret_cast<float4 *>(s_g);
+                    for (int i = tid; i < RE / 2; i += ADJ_WG) dg[i] = sg[i];
+                    const float4 *sd = reinterpret_cast<const float4 *>(dpack + (int64_t)r * RE);
+                    float4 *dd = reinterpret_cast<float4 *>(s_d);
+                    for (int i = tid; i < RE / 4; i += ADJ_WG) dd[i] = sd[i];
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // per-lane frequency data
-                const int mxp = sx0 + col;
-                const float fmx = (float)mxp;
-                const float mxx = fmx * fmx;
-                const int mx = mxp < 0 ? mxp + k.nx : mxp;
-                const bool xin = mxp >= -hx && mxp < hx;
-                float fmy[F], mxy[F], myy[F], dyf[F], dD[F][C], gm[F][C], gp[F][C];
-                float D0f[C];
+                // this thread's own Gaussian against the region: accept, row blocks, phase bases,
+                // appended to the region's list (a wavefront's entries are contiguous; the list
+                // order does not affect any result: each Gaussian is visited once per region)
+                bool p = false;
+                uint32_t rows = 0;
+                float b0[C], b1[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) D0f[c] = (float)d0tab[c * ns + sidx];
+                for (int c = 0; c < C; ++c) b0[c] = b1[c] = 0.0f;
+                if (gvalid) {
+                    const float4 *src = reinterpret_cast<const float4 *>(rec + gidx);
+                    const float4 r0 = src[0];
+                    p = ellipse_meets_rect_r(r0.x, r0.y, r0.z, 0.5f / r0.x, 0.5f / r0.z, lim, X0, X1, Y0, Y1);
+                    if (p) {
+                        rows = row_block_mask<ADJ_NB>(r0.x, r0.y, r0.z, lim, X0, X1, y0, hy);
+                        pairs += (long long)__popc(rows) * 64;
+                        const float4 r1 = src[1], r2 = src[2];
+                        const uint32_t rx = __float_as_uint(r1.x), ry = __float_as_uint(r1.y);
+                        const float kap[4] = {r2.x, r2.y, r2.z, r2.w};
+                        const int cx = x0 + ADJ_RW / 2;
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    const int myp = sy0 + row0 + 4 * f;
-                    fmy[f] = (float)myp;
-                    mxy[f] = fmx * fmy[f];
-                    myy[f] = fmy[f] * fmy[f];
-                    dyf[f] = (float)(row0 + 4 * f - SY / 2);
-                    const bool in = xin && myp >= -hy && myp < hy;
-                    const int my = myp < 0 ? myp + k.ny : myp;
-                    const int64_t o = (int64_t)my * k.nx + mx;
+                        for (int s = 0; s < 2; ++s) {
+                            const int cy = y0 + s * ADJ_SH + ADJ_SH / 2;
+                            const double *D0 = d0tab + ((int64_t)r * 2 + s) * C;
+                            float bs[C];
+                            if (k.phase_mode == 1) {
+                                // plain FP32 phase (precision study only)
+                                const float rr = (float)cx * r1.z + (float)cy * r1.w;
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        if (in) {
-                            const float2 gv = gspec[c * M + o];
-                            gm[f][c] = gv.x;
-                            gp[f][c] = gv.y;
-                            dD[f][c] = dtab[c * M + o];
-                        } else {
-                            gm[f][c] = gp[f][c] = 0.0f;
-                            dD[f][c] = 0.0f;
+                                for (int c = 0; c < C; ++c) {
+                                    const float v = kap[c] - rr - r0.w * (float)D0[c];
+                                    bs[c] = v - floorf(v);
+                                }
+                            } else {
+                                // exact ramp at the sub-tile centre: 0.32 fixed point, wraps mod 1
+                                const uint32_t ramp = (uint32_t)cx * rx + (uint32_t)cy * ry;
+                                const double ramp_rev = (double)ramp * (1.0 / 4294967296.0);
+#pragma unroll
+                                for (int c = 0; c < C; ++c)
+                                    bs[c] = (float)frac_d((double)kap[c] - ramp_rev - (double)r0.w * D0[c]);
+                            }
+#pragma unroll
+                            for (int c = 0; c < C; ++c) {
+                                if (s == 0) b0[c] = bs[c];
+                                else b1[c] = bs[c];
+                            }
                         }
                     }
                 }
-                const float4 *sw = reinterpret_cast<const float4 *>(&s_w[wave][0]);
-                for (int ei = 0; ei < cnt; ++ei) {
-                    // e0 = (alpha, beta2, gamma, z), e1 = (rxf, ryf, owner, rows), e2 = amp, e3 = base
-                    const float4 e0 = sw[4 * ei], e1 = sw[4 * ei + 1], e2 = sw[4 * ei + 2], e3 = sw[4 * ei + 3];
-                    const float alpha = e0.x, beta2 = e0.y, gamma = e0.z, z = e0.w, rxf = e1.x, ryf = e1.y;
-                    const int owner = __float_as_int(e1.z);
-                    const uint32_t rows = __builtin_amdgcn_readfirstlane(__float_as_uint(e1.w));
-                    const float ampv[4] = {e2.x, e2.y, e2.z, e2.w}, basev[4] = {e3.x, e3.y, e3.z, e3.w};
-                    float amp[C], bx[C];
-                    const float ax = alpha * mxx;
+                {
+                    const uint64_t bal = __ballot(p);
+                    int slot = 0;
+                    if (lane == 0 && bal) slot = atomicAdd(&s_cnt[par], __popcll(bal));
+                    slot = __builtin_amdgcn_readlane(slot, 0) + __popcll(bal & lt);
+                    if (p) {
+                        AdjEntry<C> e;
+                        e.g = tid;
+                        e.rows = rows;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            e.base[c] = b0[c];
+                            e.base[C + c] = b1[c];
+                        }
+                        s_ent[slot] = e;
+                    }
+                }
+                __syncthreads();  // region data and the list in LDS
+                if (tid == 0) s_cnt[par ^ 1] = s_next[par ^ 1] = 0;  // for the next region
+                const int cnt = __builtin_amdgcn_readfirstlane(s_cnt[par]);
+                // per-lane frequency of this region: column x0 + col, rows y0 + row4 + 4 b
+                const float fmx = (float)(x0 + col), mxx = fmx * fmx;
+                const float fmy0 = (float)(y0 + row4);
+                for (;;) {
+                    // the next accepted Gaussian of the region, taken by whichever wavefront is free
+                    int ei = 0;
+                    if (lane == 0) ei = atomicAdd(&s_next[par], 1);
+                    ei = __builtin_amdgcn_readlane(ei, 0);
+                    if (ei >= cnt) break;
+                    const AdjEntry<C> &en = s_ent[ei];
+                    const int o = __builtin_amdgcn_readfirstlane(en.g);
+                    const uint32_t vrows = __builtin_amdgcn_readfirstlane(en.rows);
+                    // the Gaussian's record: uniform address, constant memory (written by an earlier
+                    // kernel), so scalar loads
+                    const uint64_t ra = (uint64_t)(rec + g0 + o);
+                    const uint64_t rau = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(ra >> 32)) << 32) |
+                                         (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ra);
+                    const CONST_AS float *rp = (const CONST_AS float *)rau;
+                    const float alpha = rp[0], beta2 = rp[1], gamma = rp[2], z = rp[3], rxf = rp[6], ryf = rp[7];
+                    const float ampv[4] = {rp[12], rp[13], rp[14], rp[15]};
+                    float bs0[C], bs1[C], amp[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
+                        bs0[c] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(en.base[c])));
+                        bs1[c] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(en.base[C + c])));
                         amp[c] = ampv[c];
-                        bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, basev[c]));
                     }
-                    float Pr[C], Pi[C], Wc[C];
+                    // the lane's row at block 0, opaque to the optimiser so that the sixteen rows are
+                    // formed in the block loop rather than held in registers across visits
+                    float fmy0v = fmy0;
+                    asm volatile("" : "+v"(fmy0v));
+                    // exponent q = alpha m_x'^2 + m_y' (beta2 m_x' + gamma m_y'), evaluated at each row
+                    // (a quadratic in the block index about a reference row loses accuracy when the
+                    // reference lies far outside a narrow support)
+                    const float bmx = beta2 * fmx, ax = alpha * mxx;
+                    float bxr[C];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) Pr[c] = Pi[c] = Wc[c] = 0.0f;
-                    // rho = sum_c amp_c E conj(Gs_c) e^{j 2 pi th_c} at one frequency;
-                    // R1 = sum m_y' Re rho, R2 = sum m_y'^2 Re rho, I0 = sum Im rho, I1 = sum m_y' Im rho,
-                    // and sum Re rho = sum_c amp_c Re P_c is formed once after the loop
+                    for (int c = 0; c < C; ++c) bxr[c] = fmaf(-dyr, ryf, __builtin_amdgcn_fractf(fmaf(-dxf, rxf, bs0[c])));
+                    float Pr[C], Pi[C], Wc[C], Pi0[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) Pr[c] = Pi[c] = Wc[c] = Pi0[c] = 0.0f;
+                    // R1 = sum m_y' Re rho, R2 = sum m_y'^2 Re rho, I0 = sum Im rho, I1 = sum m_y' Im rho
+                    // over this lane's rows, with the exact row index as weight (sum Re rho comes
+                    // from the P_c)
                     float R1 = 0.0f, R2 = 0.0f, I0 = 0.0f, I1 = 0.0f;
 #pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        if (!(rows & (1u << f))) continue;  // the support misses this 4-row block
-                        const float q = fmaf(gamma, myy[f], fmaf(beta2, mxy[f], ax));
-                        const float E = __builtin_amdgcn_exp2f(-q);
+                    for (int b = 0; b < ADJ_NB; ++b) {
+                        if (b == ADJ_NB / 2) {
+                            // second sub-tile: its own phase base (and D0 for the depth sums)
+#pragma unroll
+                            for (int c = 0; c < C; ++c) {
+                                bxr[c] = fmaf(-dyr, ryf, __builtin_amdgcn_fractf(fmaf(-dxf, rxf, bs1[c])));
+                                if (DEPTH) Pi0[c] = Pi[c];
+                            }
+                        }
+                        if (!(vrows & (1u << b))) continue;  // the support misses this 4-row block
+                        const float my = fmy0v + (float)(4 * b);
+                        const float qq = fmaf(my, fmaf(gamma, my, bmx), ax);
+                        const float E = __builtin_amdgcn_exp2f(-qq);
+                        const float dyb = (float)(4 * (b & 7));
                         float rr = 0.0f, ri = 0.0f;
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
+                            const float2 gv = s_g[(b * C + c) * 64 + lane];
+                            const float dD = s_d[(b * C + c) * 64 + lane];
+                            const float tb = (b & 7) ? fmaf(-dyb, ryf, bxr[c]) : bxr[c];
                             // E conj(Gs) e^{j 2 pi th} = E |Gs| e^{j 2 pi (th - arg Gs / 2 pi)}
-                            const float th = fmaf(-z, dD[f][c], fmaf(-dyf[f], ryf, bx[c]) - gp[f][c]);
+                            const float th = fmaf(-z, dD, tb - gv.y);
                             const float sn = __builtin_amdgcn_sinf(th);
                             const float cs = __builtin_amdgcn_cosf(th);
-                            const float eg = E * gm[f][c];
+                            const float eg = E * gv.x;
                             Pr[c] = fmaf(eg, cs, Pr[c]);
-                            if (DEPTH) Pi[c] = fmaf(eg, sn, Pi[c]);
-                            if (DEPTH) Wc[c] = fmaf(dD[f][c] * eg, sn, Wc[c]);
+                            if (DEPTH) {
+                                Pi[c] = fmaf(eg, sn, Pi[c]);
+                                Wc[c] = fmaf(dD * eg, sn, Wc[c]);
+                            }
                             const float ae = amp[c] * eg;
                             rr = fmaf(ae, cs, rr);
                             ri = fmaf(ae, sn, ri);
                         }
-                        R1 = fmaf(fmy[f], rr, R1);
-                        R2 = fmaf(myy[f], rr, R2);
+                        R1 = fmaf(my, rr, R1);
+                        R2 = fmaf(my * my, rr, R2);
                         I0 += ri;
-                        I1 = fmaf(fmy[f], ri, I1);
+                        I1 = fmaf(my, ri, I1);
                     }
                     float R0 = 0.0f;
 #pragma unroll
                     for (int c = 0; c < C; ++c) R0 = fmaf(amp[c], Pr[c], R0);
-                    // value layout: Re P_c (C), Sfx, Sfy, Qxx, Qxy, Qyy, then with depth Im P_c (C), W_c (C)
-                    float x[NR];
+                    // value layout: Re P_c (C), Sfx, Sfy, Qxx, Qxy, Qyy, then with depth Im P_c (C),
+                    // W_c (C), else sum Im rho (the phase gradient)
+                    float x[NV];
 #pragma unroll
                     for (int c = 0; c < C; ++c) x[c] = Pr[c];
-                    x[C + 0] = fmx * I0;   // Sfx
-                    x[C + 1] = I1;         // Sfy
-                    x[C + 2] = mxx * R0;   // Qxx
-                    x[C + 3] = fmx * R1;   // Qxy
-                    x[C + 4] = R2;         // Qyy
-                    if (DEPTH) {
+                    x[C + 0] = fmx * I0;
+                    x[C + 1] = I1;
+                    x[C + 2] = mxx * R0;
+                    x[C + 3] = fmx * R1;
+                    x[C + 4] = R2;
+                    if constexpr (DEPTH) {
+                        const double *D0 = d0tab + (int64_t)r * 2 * C;
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             x[C + 5 + c] = Pi[c];
-                            x[2 * C + 5 + c] = fmaf(D0f[c], Pi[c], Wc[c]);
+                            // W_c = sum (dD + D0 of the element's sub-tile) Im g_c
+                            x[2 * C + 5 + c] = fmaf((float)D0[C + c], Pi[c] - Pi0[c], fmaf((float)D0[c], Pi0[c], Wc[c]));
                         }
+                    } else {
+                        x[C + 5] = I0;
                     }
-#pragma unroll
-                    for (int i = NV; i < NR; ++i) x[i] = 0.0f;
-                    // without depth, sum_m Im rho (the phase gradient) rides along as y
-                    float sim = I0;
-                    reduce_transposed<NR, !DEPTH>(x, sim, lane);
-                    if ((lane & 7) == 0) {
-                        const int v0 = (NR / 8) * (((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1));
-#pragma unroll
-                        for (int j = 0; j < NR / 8; ++j)
-                            if (v0 + j < NV) atomicAdd(&s_acc[wave][owner][v0 + j], x[j]);  // ds_add_f32, no return
-                    }
-                    if (!DEPTH && lane == 4) atomicAdd(&s_acc[wave][owner][EXTRA_SLOT], sim);
+                    reduce_into<NV>(x, s_acc + o * NV, lane);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                par ^= 1;
             }
         }
-        float *dst = S.bpartials + ((int64_t)bi.slot * 64 + lane) * NACC;
-#pragma unroll
-        for (int v = 0; v < NACC; ++v) dst[v] = s_acc[wave][lane][v];
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
+        float *dst = S.bpartials + (int64_t)bi.slot * ADJ_WG * NV;
+        for (int i = tid; i < ADJ_WG * NV; i += ADJ_WG) dst[i] = s_acc[i];
         pairs = wave_sum_i64(pairs);
         if (lane == 0 && pairs) atomicAdd((unsigned long long *)&S.counters[CTR_PAIRS], (unsigned long long)pairs);
     }
 }
 
-template <int C, int F>
-static hipError_t launch_adj_cf(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix,
-                                int n_scenes, long long *queue, const float *dtab, const double *d0tab, int nsx,
-                                int nsy, int sx_min, int sy_min, int grid, hipStream_t s)
+template <int C, bool DEPTH>
+static const void *adj_kernel_ptr() { return (const void *)k_adjoint<C, DEPTH>; }
+
+hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,
+                          long long *queue, const float *dpack, const double *d0, const AdjGeom &geo, int grid,
+                          hipStream_t s)
 {
-    if (k.depth_grad)
-        hipLaunchKernelGGL((k_adjoint<C, true, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, scenes, prefix, n_scenes,
-                           queue, dtab, d0tab, nsx, nsy, sx_min, sy_min);
-    else
-        hipLaunchKernelGGL((k_adjoint<C, false, F>), dim3(grid), dim3(WG), 0, s, k, p.tile_xy, scenes, prefix, n_scenes,
-                           queue, dtab, d0tab, nsx, nsy, sx_min, sy_min);
+#define GWS_ADJ_LAUNCH(CC, DD)                                                                                   \
+    hipLaunchKernelGGL((k_adjoint<CC, DD>), dim3(grid), dim3(adj_wg(CC, DD)), 0, s, k, p.tile_xy, scenes, prefix,  \
+                       n_scenes, \
+                       queue, dpack, d0, geo)
+    const bool d = k.depth_grad != 0;
+    switch (k.C) {
+    case 1: if (d) GWS_ADJ_LAUNCH(1, true); else GWS_ADJ_LAUNCH(1, false); break;
+    case 2: if (d) GWS_ADJ_LAUNCH(2, true); else GWS_ADJ_LAUNCH(2, false); break;
+    case 3: if (d) GWS_ADJ_LAUNCH(3, true); else GWS_ADJ_LAUNCH(3, false); break;
+    case 4: if (d) GWS_ADJ_LAUNCH(4, true); else GWS_ADJ_LAUNCH(4, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef GWS_ADJ_LAUNCH
     return hipGetLastError();
 }
 
-template <int C>
-static hipError_t launch_adj_c(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix,
-                               int n_scenes, long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy,
-                               int sx_min, int sy_min, int grid, hipStream_t s)
-{
-    switch (p.F) {
-    case 2: return launch_adj_cf<C, 2>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
-    case 8: return launch_adj_cf<C, 8>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
-    default: return launch_adj_cf<C, 4>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
-    }
-}
-
-hipError_t launch_adjoint(const Plan &p, const Consts &k, const BwdScene *scenes, const int32_t *prefix, int n_scenes,
-                          long long *queue, const float *dtab, const double *d0tab, int nsx, int nsy, int sx_min,
-                          int sy_min, int grid, hipStream_t s)
-{
-    switch (k.C) {
-    case 1: return launch_adj_c<1>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
-    case 2: return launch_adj_c<2>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
-    case 3: return launch_adj_c<3>(p, k, scenes, prefix, n_scenes, queue, dtab, d0tab, nsx, nsy, sx_min, sy_min, grid, s);
-    default: return hipErrorInvalidValue;  // 3C + 5 accumulators must fit 16
-    }
-}
-
-template <int C, bool DEPTH>
-static const void *adj_kernel_ptr(int F)
-{
-    switch (F) {
-    case 2: return (const void *)k_adjoint<C, DEPTH, 2>;
-    case 8: return (const void *)k_adjoint<C, DEPTH, 8>;
-    default: return (const void *)k_adjoint<C, DEPTH, 4>;
-    }
-}
-
-int adjoint_occupancy(int C, int F, int depth)
+int adjoint_occupancy(int C, int depth)
 {
     const void *kp = nullptr;
     switch (C) {
-    case 1: kp = depth ? adj_kernel_ptr<1, true>(F) : adj_kernel_ptr<1, false>(F); break;
-    case 2: kp = depth ? adj_kernel_ptr<2, true>(F) : adj_kernel_ptr<2, false>(F); break;
-    default: kp = depth ? adj_kernel_ptr<3, true>(F) : adj_kernel_ptr<3, false>(F); break;
+    case 1: kp = depth ? adj_kernel_ptr<1, true>() : adj_kernel_ptr<1, false>(); break;
+    case 2: kp = depth ? adj_kernel_ptr<2, true>() : adj_kernel_ptr<2, false>(); break;
+    case 3: kp = depth ? adj_kernel_ptr<3, true>() : adj_kernel_ptr<3, false>(); break;
+    default: kp = depth ? adj_kernel_ptr<4, true>() : adj_kernel_ptr<4, false>(); break;
     }
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, WG, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, adj_wg(C, depth != 0), 0) != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
@@ -390,7 +494,7 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
                                                     const int2 *__restrict__ chunk_items,
                                                     const int32_t *__restrict__ range_base,
                                                     const float *__restrict__ bpartials, GradView grads, int64_t n,
-                                                    const long long *__restrict__ counters)
+                                                    const long long *__restrict__ counters, int chunk)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -405,17 +509,18 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
         for (int c = 0; c < C; ++c) grads.amplitude[(int64_t)c * grads.amp_stride + i] = 0.0f;
         return;
     }
-    const int64_t b = s / 64;
-    const int lane = (int)(s - b * 64);
+    const int NV = adj_nv(C, k.depth_grad != 0);
+    const int64_t b = s / chunk;
+    const int t = (int)(s - b * chunk);
     const int2 ci = chunk_items[b];
     const long long nbitems = counters[CTR_NBITEMS];
-    double acc[NACC];
-    for (int v = 0; v < NACC; ++v) acc[v] = 0.0;
+    double acc[3 * GWS_MAX_LAMBDA + 5];
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     for (int j = 0; j < ci.y; ++j) {
         const int64_t it = (int64_t)range_base[j] + b;  // range j of chunk b
         if (it >= nbitems) break;
-        const float *src = bpartials + (it * 64 + lane) * NACC;
-        for (int v = 0; v < NACC; ++v) acc[v] += (double)src[v];
+        const float *src = bpartials + (it * chunk + t) * NV;
+        for (int v = 0; v < NV; ++v) acc[v] += (double)src[v];
     }
     const double PI = 3.14159265358979323846;
     const double sxx = g.cov_xx[i], sxy = g.cov_xy[i], syy = g.cov_yy[i];
@@ -423,25 +528,23 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
     const double o = g.opacity[i];
     const double fx = 1.0 / (k.nx * k.px), fy = 1.0 / (k.ny * k.py);
     const double K = 2.0 * PI * sqrt(det) / (k.px * k.py * (double)k.nx * (double)k.ny);
-    double Sre = 0.0, gz = 0.0, go = 0.0;
+    double Sre = 0.0, gz = 0.0, go = 0.0, Sim = 0.0;
     for (int c = 0; c < C; ++c) {
         const double a = g.amplitude[(int64_t)c * g.amp_stride + i];
         const double A = a * o * K;
         const double Pr = acc[c];
-        const double Pi = k.depth_grad ? acc[C + 5 + c] : 0.0, Wc = k.depth_grad ? acc[2 * C + 5 + c] : 0.0;
         Sre += A * Pr;
-        gz += A * (k.inv_lambda[c] * Pi + Wc);
+        if (k.depth_grad) {
+            const double Pi = acc[C + 5 + c], Wc = acc[2 * C + 5 + c];
+            gz += A * (k.inv_lambda[c] * Pi + Wc);
+            Sim += A * Pi;
+        }
         go += a * K * Pr;
         grads.amplitude[(int64_t)c * grads.amp_stride + i] = (float)(o * K * Pr);
     }
+    // sum_c A_c Im P_c (= sum_m Im rho): from Im P_c with depth, else the extra reduced value
+    if (!k.depth_grad) Sim = acc[C + 5];
     const double Sfx = acc[C], Sfy = acc[C + 1], Qxx = acc[C + 2], Qxy = acc[C + 3], Qyy = acc[C + 4];
-    // sum_c A_c Im P_c (= sum_m Im rho): from Im P_c with depth, else the extra reduced slot
-    double Sim = 0.0;
-    if (k.depth_grad) {
-        for (int c = 0; c < C; ++c) Sim += (double)g.amplitude[(int64_t)c * g.amp_stride + i] * o * K * acc[C + 5 + c];
-    } else {
-        Sim = acc[8];
-    }
     grads.phase[i] = (float)(-Sim);
     grads.mean_x[i] = (float)(2.0 * PI * fx * Sfx);
     grads.mean_y[i] = (float)(2.0 * PI * fy * Sfy);
@@ -454,11 +557,11 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
 
 hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
                              const int32_t *range_base, const float *bpartials, const GradView &grads, int64_t n,
-                             const long long *counters, hipStream_t s)
+                             const long long *counters, int chunk, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, k, vals, chunk_items,
-                       range_base, bpartials, grads, n, counters);
+                       range_base, bpartials, grads, n, counters, chunk);
     return hipGetLastError();
 }
 

@@ -403,7 +403,7 @@ hipError_t run_exact_forward(const Plan &p, const Consts &k, const GView &g, con
 //     never divided by (1 - alpha).
 // ---------------------------------------------------------------------------------
 constexpr int EXACT_BTILE = 8;          // 8 x 8 pixels: one wavefront per work-group
-constexpr int EXACT_NSPEC = 12;         // Re/Im P_c, Re/Im Q_c for c < 3
+constexpr int EXACT_NSPEC = 16;         // Re/Im P_c, Re/Im Q_c for c < 4
 constexpr int EXACT_NSPAT = 8;          // Sx, Sy, Sxx, Sxy, Syy, So, pad, pad
 
 // One thread per frequency pair {m, -m} (as in k_exact_splat; F(-m) = conj F(m), H shared):
@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
                                                       const float2 *__restrict__ gspec, float2 *pimgs,
                                                       float *__restrict__ part)
 {
-    // per wave and batch Gaussian, the wave's 12 sums: the four waves are summed in a fixed
+    // per wave and batch Gaussian, the wave's 16 sums: the four waves are summed in a fixed
     // order once, after the batch, so the waves never wait for each other inside it
     __shared__ float s_red[4][64][16];
     const int nx = k.nx, ny = k.ny, hy = ny / 2;
@@ -430,15 +430,15 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
     if (!live) mx = my = 0;
     const int m = my * nx + mx, mn = (int)neg_freq(mx, my, nx, ny);  // M < 2^31
     const bool pair = live && mn != m;
-    double w[3];
-    bool prop[3];
-    float2 gs0[3], gs1[3];  // Gs_c at m and at -m
+    double w[4];
+    bool prop[4];
+    float2 gs0[4], gs1[4];  // Gs_c at m and at -m
     {
         const int mxp = 2 * mx < nx ? mx : mx - nx, myp = 2 * my < ny ? my : my - ny;
         const double nux = mxp / (nx * k.px), nuy = myp / (ny * k.py);
         const double nu2 = nux * nux + nuy * nuy;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < 4; ++c) {
             const double w2 = k.inv_lambda[c] * k.inv_lambda[c] - nu2;
             prop[c] = live && c < k.C && w2 > 0.0;
             w[c] = prop[c] ? sqrt(w2) : 0.0;
@@ -476,7 +476,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
             const float2 S0 = make_float2(cph * F.x - sph * F.y, cph * F.y + sph * F.x);
             const float2 S1 = make_float2(cph * F.x + sph * F.y, sph * F.x - cph * F.y);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < 4; ++c) {
                 if (!prop[c]) continue;
                 const double ph = -zd * w[c];
                 const float tt = (float)(ph - floor(ph));
@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(256) k_exact_gsplat(const ERec *__restrict__ r
             pimgs[pb + m] = make_float2(Ha.x - Hm.y, Ha.y + Hm.x);
             if (pair) pimgs[pb + mn] = make_float2(Ha.x + Hm.y, Hm.x - Ha.y);
         }
-        // one transposed butterfly over the 12 sums (padded to 16): afterwards lane l with
+        // one transposed butterfly over the 16 sums: afterwards lane l with
         // bits 0-2 clear holds sums 2 (4 b5 + 2 b4 + b3) and that + 1
         float x[16];
 #pragma unroll
@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(EXACT_GF_THREADS) k_exact_gfinal(const ERec *_
     double d_o = S[EXACT_NSPEC + 5], d_z = 0.0, d_phi = 0.0;
     const double o = g.opacity[j];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 4; ++c) {
         if (c >= k.C) break;
         const double a = g.amplitude[(int64_t)c * g.amp_stride + j];
         const double rp = S[4 * c + 0] * inv, iq = S[4 * c + 3] * inv;

@@ -354,7 +354,7 @@ hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32
 }
 
 // ---------------------------------------------------------------------------------
-// Backward binning: chunk b of BWD_CHUNK sorted Gaussians reaches the first K_b sorted
+// Backward binning: chunk b of `chunk` sorted Gaussians reaches the first K_b sorted
 // tiles (K_b = tiles whose bucket is at most the chunk's largest bucket).  Those tiles are
 // split into ranges of TRB tiles (TRB grows until the items fit max_bitems).  Items are
 // ordered range-major -- range r of every chunk that has one, then range r + 1 -- so the
@@ -366,14 +366,14 @@ __global__ void __launch_bounds__(1024) k_bin_backward(const int32_t *__restrict
                                                        const uint64_t *__restrict__ keys, BItem *__restrict__ bitems,
                                                        int2 *__restrict__ chunk_items, int32_t *__restrict__ range_base,
                                                        int max_ranges, int64_t max_bitems,
-                                                       long long *__restrict__ counters, int64_t n)
+                                                       long long *__restrict__ counters, int64_t n, int chunk)
 {
     __shared__ uint32_t tmp[1024];
     __shared__ unsigned long long red[1024];
     __shared__ int32_t trb_sh, nr_sh;
     const int64_t nvalid = n - counters[CTR_NCULLED];
-    const int nchunks = (int)((nvalid + BWD_CHUNK - 1) / BWD_CHUNK);
-    auto K_of = [&](int b) { return tile_cum[NBUCKET - 1 - (int)(keys[(int64_t)b * BWD_CHUNK] >> 32)]; };
+    const int nchunks = (int)((nvalid + chunk - 1) / chunk);
+    auto K_of = [&](int b) { return tile_cum[NBUCKET - 1 - (int)(keys[(int64_t)b * chunk] >> 32)]; };
     unsigned long long sumK = 0;
     for (int b = threadIdx.x; b < nchunks; b += 1024) sumK += (unsigned long long)K_of(b);
     red[threadIdx.x] = sumK;
@@ -444,10 +444,10 @@ __global__ void __launch_bounds__(1024) k_bin_backward(const int32_t *__restrict
 
 hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
                                int32_t *range_base, int max_ranges, int64_t max_bitems, long long *counters, int64_t n,
-                               hipStream_t s)
+                               int chunk, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_backward, dim3(1), dim3(1024), 0, s, p.tile_cum, keys, bitems, chunk_items, range_base,
-                       max_ranges, max_bitems, counters, n);
+                       max_ranges, max_bitems, counters, n, chunk);
     return hipGetLastError();
 }
 

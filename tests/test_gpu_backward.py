@@ -99,3 +99,41 @@ def test_backward_every_tiling(ctx, cfg, want_depth):
             continue
         e = rel_l2(to_numpy(got[k]), ref[k])
         assert e < TOL_GRAD, (cfg, k, e)
+
+
+FOUR = (638e-9, 520e-9, 450e-9, 405e-9)
+
+
+def test_backward_four_wavelengths(ctx):
+    """Four colour channels (the most the problem takes), without the depth gradient: every
+    other parameter group against the oracle."""
+    grid = Grid(96, 80, 8e-6, 8e-6, FOUR)
+    scene = gwsgen.make_scene(90, grid, 411, depth_range=(-10e-3, 10e-3))
+    check_grads(ctx, scene, grid, 412, want_depth=False)
+
+
+@pytest.mark.skip(reason="four wavelengths with the depth gradient hung on the GPU in an earlier build of the "
+                         "adjoint (108 KB of LDS per work-group) and the cause is not shown; the library "
+                         "returns GWS_ERR_UNSUPPORTED for it")
+def test_backward_four_wavelengths_with_depth(ctx):
+    grid = Grid(96, 80, 8e-6, 8e-6, FOUR)
+    scene = gwsgen.make_scene(90, grid, 411, depth_range=(-10e-3, 10e-3))
+    check_grads(ctx, scene, grid, 412, want_depth=True)
+
+
+def test_backward_four_wavelengths_depth_is_refused(ctx):
+    import torch
+    import paper_2505_06582_amd as gws
+    grid = Grid(32, 32, 8e-6, 8e-6, FOUR)
+    scene = gwsgen.make_scene(4, grid, 413)
+    G = torch.from_numpy(gwsgen.make_target(grid, 414)).cuda()
+    with pytest.raises(gws.GwsError):
+        ctx.backward(problem(grid), scene_to_torch(scene), G, want_depth=True)
+
+
+def test_backward_many_chunks_and_regions(ctx):
+    """1500 Gaussians: several work-group chunks of sorted Gaussians, each over many frequency
+    regions and tile ranges, with a ragged last chunk."""
+    grid = Grid(256, 240, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_scene(1500, grid, 421, depth_range=(-10e-3, 10e-3))
+    check_grads(ctx, scene, grid, 422)

@@ -228,6 +228,7 @@ TOL_EXACT_GRAD = 1e-4
     (24, Grid(64, 48, 8e-6, 8e-6, (520e-9, 638e-9)), 2201),          # one batch, 2 wavelengths
     (100, Grid(128, 96, 8e-6, 8e-6, gwsgen.RGB), 2202),               # two batches, 3 wavelengths
     (65, Grid(96, 80, 8e-6, 8e-6, (450e-9,)), 2203),                  # ragged second batch
+    (40, Grid(64, 48, 8e-6, 8e-6, (638e-9, 520e-9, 450e-9, 405e-9)), 2205),  # four wavelengths
 ])
 def test_exact_backward_matches_oracle(ctx, n, grid, seed):
     import torch
