@@ -185,6 +185,23 @@ gws_status gws_workspace_size(const gws_ctx *ctx, const gws_problem *problem, in
 gws_status gws_forward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
                        const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Bytes of the device scratch array gws_forward_noalloc works in (each GPU holds one). */
+#define GWS_NOALLOC_SCRATCH_BYTES (256u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gws_forward with the order-invariant blend and the
+ * FP32 FFT, working in a scratch array of GWS_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device from gws_create until the process ends, instead of a caller workspace.  It calls
+ * no allocating routine: the per-shape plan must already exist, built by an earlier gws_forward
+ * on this context with the same grid and tiling (else GWS_ERR_UNSUPPORTED), and a problem whose
+ * forward-only workspace exceeds the scratch size is refused with GWS_ERR_WORKSPACE (at
+ * 1080 x 1920 x 3 it takes up to about 8800 Gaussians).  Everything it needs zeroed it clears
+ * itself on the stream.  The scratch is shared by every context and stream on the device: calls
+ * that overlap on one GPU (two streams, or two host threads) race and must be serialised by the
+ * caller.  Results are bitwise those of gws_forward. */
+gws_status gws_forward_noalloc(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
+                               const gws_output *out, void *stream);
+
 /* Backward: given grad_field = dL/dRe(u) + j dL/dIm(u) (complex64 [n_lambda][ny][nx], the
  * convention torch uses for complex tensors), write dL/d(parameter) for every Gaussian.
  * Recomputes preprocessing, sort and binning (no state is kept from gws_forward) and

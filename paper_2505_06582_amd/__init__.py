@@ -109,6 +109,8 @@ _SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_size_t)]),
     "gws_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
                                    ctypes.POINTER(_Output), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gws_forward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
+                                           ctypes.POINTER(_Output), ctypes.c_void_p]),
     "gws_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
                                     ctypes.c_void_p, ctypes.POINTER(_Grads), ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_void_p]),
@@ -351,6 +353,20 @@ class Context:
         _check(self.lib.gws_forward(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
                                     ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
         return (field, spec) if want_spectrum else field
+
+    def forward_noalloc(self, prob: Problem, g: Dict[str, "object"], out):
+        """forward() for callers that cannot allocate device memory: the library works in its own
+        per-device scratch array, the caller passes the output field (n_lambda, ny, nx) complex64.
+        The plan for this grid must exist (an earlier forward() with the same shape and tiling)."""
+        n = check_gaussians(g, prob.n_lambda)
+        check_tensor(out, "out", (prob.n_lambda, prob.ny, prob.nx), "complex64")
+        gs = _gaussians_struct(g, prob.n_lambda)
+        o = _Output()
+        o.field = _dptr(out)
+        o.spectrum = None
+        _check(self.lib.gws_forward_noalloc(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
+                                            self._stream()), self.handle)
+        return out
 
     def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True, out=None):
         """dL/d(parameter) for every Gaussian, given dL/dRe u + j dL/dIm u."""

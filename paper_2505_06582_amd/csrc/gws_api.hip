@@ -44,6 +44,7 @@ struct gws_ctx {
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    void *scratch = nullptr;  // this device's copy of the allocation-free forward's scratch array
 };
 
 static hipEvent_t pool_event(gws_ctx *ctx)
@@ -64,16 +65,18 @@ struct StageScope {
     hipStream_t s;
     int stage;
     hipEvent_t a = nullptr;
-    StageScope(gws_ctx *c, hipStream_t st, int sg) : ctx(c), s(st), stage(sg)
+    bool on;
+    StageScope(gws_ctx *c, hipStream_t st, int sg, bool enable = true) : ctx(c), s(st), stage(sg)
     {
-        if (ctx->profiling) {
+        on = enable && ctx->profiling;
+        if (on) {
             a = pool_event(ctx);
             if (a) hipEventRecord(a, s);
         }
     }
     ~StageScope()
     {
-        if (ctx->profiling && a) {
+        if (on && a) {
             hipEvent_t b = pool_event(ctx);
             if (b) {
                 hipEventRecord(b, s);
@@ -275,6 +278,13 @@ static void free_plan(Plan &p)
     free_dft_mats(p);
 }
 
+// The plan of a shape if an earlier call built it, else nullptr (never allocates).
+static Plan *find_plan(gws_ctx *ctx, int nx, int ny, int F)
+{
+    auto it = ctx->plans.find(std::make_tuple(nx, ny, F));
+    return it == ctx->plans.end() ? nullptr : &it->second;
+}
+
 static gws_status get_plan(gws_ctx *ctx, int nx, int ny, int F, Plan **out)
 {
     auto key = std::make_tuple(nx, ny, F);
@@ -313,7 +323,7 @@ static int ntiles_for(int nx, int ny, int F)
 // Per-scene region.  One region serves forward and backward under every tiling: tile
 // arrays are sized for the smallest tiles (F = 2), the partial-sum area is a fixed byte
 // budget whose slot count depends on the forward tiling.
-static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
+static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd, bool fwd_only = false)
 {
     Layout L;
     const int C = p->n_lambda;
@@ -349,10 +359,12 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd)
     L.off_tile_slots = take(sizeof(int2) * ntiles);
     L.off_items = take(sizeof(Item) * (L.max_slots_bound(part_bytes, C, ntiles)));
     L.off_partials = take(part_bytes);
-    L.off_bitems = take(sizeof(BItem) * L.max_bitems);
-    L.off_chunk_items = take(sizeof(int2) * (nchunks + 1));
-    L.off_range_base = take(sizeof(int32_t) * (ntiles + 2));
-    L.off_bpartials = take(sizeof(float) * (size_t)L.max_bslots *
+    // the adjoint's areas (empty in a forward-only layout)
+    const size_t bw = fwd_only ? 0 : 1;
+    L.off_bitems = take(bw * sizeof(BItem) * L.max_bitems);
+    L.off_chunk_items = take(bw * sizeof(int2) * (nchunks + 1));
+    L.off_range_base = take(bw * sizeof(int32_t) * (ntiles + 2));
+    L.off_bpartials = take(bw * sizeof(float) * (size_t)L.max_bslots *
                            std::max(adj_wg(C, true) * adj_nv(C, true), adj_wg(C, false) * adj_nv(C, false)));
     L.total = o;
     return L;
@@ -370,7 +382,7 @@ struct BatchLayout {
     std::vector<int64_t> n;
 };
 
-static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t *offsets)
+static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t *offsets, bool fwd_only = false)
 {
     BatchLayout B;
     const int64_t M = (int64_t)p->nx * p->ny;
@@ -388,15 +400,17 @@ static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t 
     B.off_btab = take(sizeof(BwdScene) * S);
     B.off_prefix = take(sizeof(int32_t) * (S + 1));
     B.off_spectra = take(sizeof(float2) * (size_t)S * C * M);
-    B.off_gspecs = take(sizeof(float2) * (size_t)S * C * M);
-    B.off_gpack = take(sizeof(float2) * (size_t)S * B.pack_elems);
-    B.off_dpack = take(sizeof(float) * (size_t)B.pack_elems);
-    B.off_d0 = take(sizeof(double) * (size_t)B.geo.nreg * 2 * C);
+    // the adjoint's areas (empty in a forward-only layout; the bf16 DFT forward also uses the first)
+    const size_t bw = fwd_only ? 0 : 1;
+    B.off_gspecs = take(bw * sizeof(float2) * (size_t)S * C * M);
+    B.off_gpack = take(bw * sizeof(float2) * (size_t)S * B.pack_elems);
+    B.off_dpack = take(bw * sizeof(float) * (size_t)B.pack_elems);
+    B.off_d0 = take(bw * sizeof(double) * (size_t)B.geo.nreg * 2 * C);
     for (int i = 0; i < S; ++i) {
         const int64_t ni = offsets[i + 1] - offsets[i];
         B.n.push_back(ni);
         B.scene_off.push_back(o);
-        o = align256(o + make_layout(p, ni, 2, 2).total);
+        o = align256(o + make_layout(p, ni, 2, 2, fwd_only).total);
     }
     B.total = o;
     return B;
@@ -492,6 +506,12 @@ extern "C" gws_status gws_workspace_size_batched(const gws_ctx *ctx, const gws_p
 // ---------------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------------
+// Scratch of gws_forward_noalloc: a file-scope device array, so each GPU the library runs on
+// holds its own copy until the process ends.  In host code its name is only a stand-in for the
+// symbol; the device address of this GPU's copy is taken once per context (gws_create) with
+// hipGetSymbolAddress and only that address is passed to kernels.
+static __device__ __align__(256) char scratch[GWS_NOALLOC_SCRATCH_BYTES];
+
 extern "C" gws_status gws_create(gws_ctx **out, int device)
 {
     if (!out) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx pointer is NULL");
@@ -511,6 +531,11 @@ extern "C" gws_status gws_create(gws_ctx **out, int device)
         return fail(nullptr, GWS_ERR_OOM, "cannot allocate the statistics buffer");
     }
     (void)hipMemset(ctx->d_stats, 0, sizeof(long long) * CTR_COUNT);
+    if (hipGetSymbolAddress(&ctx->scratch, HIP_SYMBOL(scratch)) != hipSuccess || !ctx->scratch) {
+        hipFree(ctx->d_stats);
+        delete ctx;
+        return fail(nullptr, GWS_ERR_HIP, "cannot take the device address of the scratch array");
+    }
     load_tune_cache(ctx, getenv("GWS_TUNE_CACHE"));
     *out = ctx;
     return GWS_OK;
@@ -717,15 +742,26 @@ static int64_t max_scene(int S, const int64_t *offsets)
     return m;
 }
 
+// noalloc: the allocation-free variant (forward-only layout in the given scratch, the plan
+// looked up but never built, no profiling events).
 static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, const int64_t *offsets,
-                              const gws_gaussians *g, const gws_output *out, void *ws, size_t ws_bytes, hipStream_t s)
+                              const gws_gaussians *g, const gws_output *out, void *ws, size_t ws_bytes, hipStream_t s,
+                              bool noalloc = false)
 {
     const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
     const int F = kTileCfg[cfg - 1][0];
     Plan *p = nullptr;
-    gws_status st = get_plan(ctx, prob->nx, prob->ny, F, &p);
-    if (st != GWS_OK) return st;
-    const BatchLayout BL = make_batch_layout(prob, S, offsets);
+    gws_status st = GWS_OK;
+    if (noalloc) {
+        p = find_plan(ctx, prob->nx, prob->ny, F);
+        if (!p)
+            return fail(ctx, GWS_ERR_UNSUPPORTED,
+                        "no plan for this grid and tiling yet: call gws_forward once for this shape first");
+    } else {
+        st = get_plan(ctx, prob->nx, prob->ny, F, &p);
+        if (st != GWS_OK) return st;
+    }
+    const BatchLayout BL = make_batch_layout(prob, S, offsets, noalloc);
     st = check_ws(ctx, ws, ws_bytes, BL.total);
     if (st != GWS_OK) return st;
     char *base = (char *)ws;
@@ -737,9 +773,9 @@ static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, cons
     tab.n = S;
     std::vector<long long *> ctrs(S);
     {
-        StageScope sc(ctx, s, ST_PREP);
+        StageScope sc(ctx, s, ST_PREP, !noalloc);
         for (int i = 0; i < S; ++i) {
-            const Layout L = make_layout(prob, BL.n[i], F, kTileCfg[cfg - 1][1]);
+            const Layout L = make_layout(prob, BL.n[i], F, kTileCfg[cfg - 1][1], noalloc);
             const Bufs B = carve(L, base + BL.scene_off[i]);
             uint64_t *keys = nullptr;
             uint32_t *vals = nullptr;
@@ -755,19 +791,19 @@ static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, cons
     int32_t *prefix = (int32_t *)(base + BL.off_prefix);
     long long *queue = (long long *)(base + BL.off_ctrl);
     {
-        StageScope sc(ctx, s, ST_BIN);
+        StageScope sc(ctx, s, ST_BIN, !noalloc);
         HIP_CHECK(ctx, launch_fwd_table(tab, dtab, prefix, queue, s));
     }
     {
-        StageScope sc(ctx, s, ST_ACCUM);
+        StageScope sc(ctx, s, ST_ACCUM, !noalloc);
         HIP_CHECK(ctx, launch_accumulate(*p, k, dtab, prefix, S, queue, acc_grid(ctx, k.C, F), s));
     }
     {
-        StageScope sc(ctx, s, ST_REDUCE);
+        StageScope sc(ctx, s, ST_REDUCE, !noalloc);
         HIP_CHECK(ctx, launch_reduce_partials(*p, k, dtab, S, s));
     }
     {
-        StageScope sc(ctx, s, ST_XFORM_INV);
+        StageScope sc(ctx, s, ST_XFORM_INV, !noalloc);
         if (prob->xform == GWS_XFORM_FFT_FP32)
             HIP_CHECK(ctx, launch_fft2d(*p, S * k.C, +1, spectra, (float2 *)out->field, s));
         else  // the bf16 DFT keeps its intermediate in the (forward-idle) gradient-spectrum area
@@ -967,6 +1003,29 @@ extern "C" gws_status gws_forward(gws_ctx *ctx, const gws_problem *prob, const g
         return exact_forward_run(ctx, prob, g, 0, g->n, out->field, out->spectrum, ws, ws_bytes, (hipStream_t)stream);
     }
     return forward_run(ctx, prob, 1, off, g, out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" gws_status gws_forward_noalloc(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g,
+                                          const gws_output *out, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = gws_check_problem(prob);
+    if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    st = check_gaussians(ctx, g);
+    if (st != GWS_OK) return st;
+    if (!out || !out->field) return fail(ctx, GWS_ERR_INVALID_ARG, "output field is NULL");
+    if (prob->blend != GWS_BLEND_OIT || prob->xform != GWS_XFORM_FFT_FP32)
+        return fail(ctx, GWS_ERR_UNSUPPORTED, "gws_forward_noalloc takes the order-invariant blend with the FP32 FFT");
+    const int64_t off[2] = {0, g->n};
+    const size_t need = make_batch_layout(prob, 1, off, true).total;
+    if (need > (size_t)GWS_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, GWS_ERR_WORKSPACE,
+                    "gws_forward_noalloc: this problem needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                        std::to_string((size_t)GWS_NOALLOC_SCRATCH_BYTES) + " the library holds; use gws_forward");
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    ctx->last_graph = 0;
+    return forward_run(ctx, prob, 1, off, g, out, ctx->scratch, (size_t)GWS_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream,
+                       true);
 }
 
 extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const void *grad_field,
