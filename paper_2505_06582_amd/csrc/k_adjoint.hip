@@ -365,9 +365,16 @@ __global__ void __launch_bounds__(adj_wg(C, DEPTH), adj_waves_per_simd(C, DEPTH)
                     // (a quadratic in the block index about a reference row loses accuracy when the
                     // reference lies far outside a narrow support)
                     const float bmx = beta2 * fmx, ax = alpha * mxx;
+                    // phase base of the lane's column and first row in the current sub-tile (formed only
+                    // for a sub-tile the support reaches; vrows is wave-uniform)
                     float bxr[C];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) bxr[c] = fmaf(-dyr, ryf, __builtin_amdgcn_fractf(fmaf(-dxf, rxf, bs0[c])));
+                    for (int c = 0; c < C; ++c) bxr[c] = 0.0f;
+                    if (vrows & 0xffu) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            bxr[c] = fmaf(-dyr, ryf, __builtin_amdgcn_fractf(fmaf(-dxf, rxf, bs0[c])));
+                    }
                     float Pr[C], Pi[C], Wc[C], Pi0[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) Pr[c] = Pi[c] = Wc[c] = Pi0[c] = 0.0f;
@@ -380,9 +387,12 @@ __global__ void __launch_bounds__(adj_wg(C, DEPTH), adj_waves_per_simd(C, DEPTH)
                         if (b == ADJ_NB / 2) {
                             // second sub-tile: its own phase base (and D0 for the depth sums)
 #pragma unroll
-                            for (int c = 0; c < C; ++c) {
-                                bxr[c] = fmaf(-dyr, ryf, __builtin_amdgcn_fractf(fmaf(-dxf, rxf, bs1[c])));
+                            for (int c = 0; c < C; ++c)
                                 if (DEPTH) Pi0[c] = Pi[c];
+                            if (vrows >> (ADJ_NB / 2)) {
+#pragma unroll
+                                for (int c = 0; c < C; ++c)
+                                    bxr[c] = fmaf(-dyr, ryf, __builtin_amdgcn_fractf(fmaf(-dxf, rxf, bs1[c])));
                             }
                         }
                         if (!(vrows & (1u << b))) continue;  // the support misses this 4-row block
