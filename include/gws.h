@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GWS_ABI_VERSION 2
+#define GWS_ABI_VERSION 3
 #define GWS_MAX_LAMBDA 4
 
 /* Return codes.  Launch-time validation returns the code at once and leaves the
@@ -97,7 +97,18 @@ typedef struct gws_problem {
                                   else the default; k in 1..gws_tile_config_count(): tiling k,
                                   a pair (frequencies per lane of the accumulation, of the
                                   adjoint) from {(4,4),(4,8),(8,8),(8,4),(2,4),(4,2),(2,2),
-                                  (2,8),(8,2)}; the default is 2 = (4,8) */
+                                  (2,8),(8,2)}; the default is 2 = (4,8); the order-invariant
+                                  adjoint's own geometry is fixed, so only the first of the
+                                  pair applies */
+    double ref_nu_x, ref_nu_y; /* transverse frequency (cycles per metre) of the reference plane
+                                  wave that illuminates every Gaussian (Sec. 4.1): each
+                                  Gaussian's wavefront is multiplied by exp(+j 2 pi nu_r . x), x
+                                  from the SLM centre, so its spectrum is evaluated at nu - nu_r
+                                  while H keeps the full nu; (0, 0) is on-axis illumination.
+                                  Finite, |nu_r| at most half the grid's band along each axis
+                                  (|nu_r,x| <= 1 / (2 pitch_x), likewise y); the order-invariant
+                                  blend only (GWS_BLEND_EXACT returns GWS_ERR_UNSUPPORTED for a
+                                  non-zero nu_r) */
 } gws_problem;
 
 /* Gaussians as structure-of-arrays float32 device buffers of length n.  amplitude is

@@ -45,7 +45,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pitch_x", ctypes.c_double),
                 ("pitch_y", ctypes.c_double), ("n_lambda", ctypes.c_int32),
                 ("lambdas", ctypes.c_double * MAX_LAMBDA), ("blend", ctypes.c_int32), ("xform", ctypes.c_int32),
-                ("eps_support", ctypes.c_double), ("phase_mode", ctypes.c_int32), ("tile_config", ctypes.c_int32)]
+                ("eps_support", ctypes.c_double), ("phase_mode", ctypes.c_int32), ("tile_config", ctypes.c_int32),
+                ("ref_nu_x", ctypes.c_double), ("ref_nu_y", ctypes.c_double)]
 
 
 _fp = ctypes.c_void_p
@@ -190,9 +191,11 @@ class Problem:
     phase_mode: int = 0
     tile_config: int = 0
     blend: int = BLEND_OIT
+    ref_nu: Sequence[float] = (0.0, 0.0)  # reference plane wave's transverse frequency (cycles/m)
 
     @staticmethod
     def from_grid(grid, **kw) -> "Problem":
+        kw.setdefault("ref_nu", tuple(getattr(grid, "ref_nu", (0.0, 0.0))))
         return Problem(nx=grid.nx, ny=grid.ny, pitch_x=grid.px, pitch_y=grid.py, lambdas=tuple(grid.lambdas), **kw)
 
     @property
@@ -207,6 +210,7 @@ class Problem:
             p.lambdas[i] = float(self.lambdas[i]) if i < len(self.lambdas) else 0.0
         p.blend, p.xform, p.eps_support = self.blend, self.xform, self.eps_support
         p.phase_mode, p.tile_config = self.phase_mode, self.tile_config
+        p.ref_nu_x, p.ref_nu_y = float(self.ref_nu[0]), float(self.ref_nu[1])
         return p
 
 

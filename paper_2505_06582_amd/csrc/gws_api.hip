@@ -21,7 +21,8 @@ struct gws_ctx {
     int device = 0;
     int n_cu = 0;
     std::string last_error;
-    std::map<std::tuple<int, int, int>, Plan> plans;
+    // per (nx, ny, F, m_r quantised): the tile order depends on the supports' common centre m_r
+    std::map<std::tuple<int, int, int, long long, long long>, Plan> plans;
     long long *d_stats = nullptr;  // copy of the counters of the last call
     int64_t last_n = 0;
     int last_tile_config = 1;
@@ -156,6 +157,10 @@ extern "C" gws_status gws_check_problem(const gws_problem *p)
     if (p->eps_support != 0.0 && !(p->eps_support > 0.0 && p->eps_support <= 1e-3)) return GWS_ERR_INVALID_ARG;
     if (p->phase_mode != 0 && p->phase_mode != 1 && p->phase_mode != 2) return GWS_ERR_INVALID_ARG;
     if (p->tile_config < 0 || p->tile_config > gws_tile_config_count()) return GWS_ERR_INVALID_ARG;
+    if (!isfinite(p->ref_nu_x) || !isfinite(p->ref_nu_y) || fabs(p->ref_nu_x) * p->pitch_x > 0.5 ||
+        fabs(p->ref_nu_y) * p->pitch_y > 0.5)
+        return GWS_ERR_INVALID_ARG;
+    if (p->blend == GWS_BLEND_EXACT && (p->ref_nu_x != 0.0 || p->ref_nu_y != 0.0)) return GWS_ERR_UNSUPPORTED;
     const gws_status gs = check_grid(p->nx, p->ny);
     if (gs != GWS_OK) return gs;
     return GWS_OK;
@@ -191,6 +196,10 @@ static Consts make_consts(const gws_problem *p, int forward)
     k.K2 = 2.0 * M_PI * M_PI / log(2.0);
     k.forward = forward;
     k.phase_mode = p->phase_mode == 1 ? 1 : 0;
+    k.nurx = p->ref_nu_x;
+    k.nury = p->ref_nu_y;
+    k.mrx = p->ref_nu_x * p->nx * p->pitch_x;
+    k.mry = p->ref_nu_y * p->ny * p->pitch_y;
     return k;
 }
 
@@ -215,7 +224,9 @@ static void factor_radices(int n, int32_t *r, int32_t *nr)
     *nr = k;
 }
 
-static gws_status build_plan(gws_ctx *ctx, Plan &p, int nx, int ny, int F)
+// Tiles are ordered by their distance (index units) from m_r, the centre every spectral
+// support shares (DC under on-axis illumination, nu_r N p under a reference plane wave).
+static gws_status build_plan(gws_ctx *ctx, Plan &p, int nx, int ny, int F, double mrx, double mry)
 {
     p.nx = nx;
     p.ny = ny;
@@ -236,9 +247,15 @@ static gws_status build_plan(gws_ctx *ctx, Plan &p, int nx, int ny, int F)
         for (int tx = p.tx_min; tx <= tx_max; ++tx) {
             const int x0 = std::max(tx * TILEX, -hx), x1 = std::min(tx * TILEX + TILEX - 1, hx - 1);
             const int y0 = std::max(ty * TH, -hy), y1 = std::min(ty * TH + TH - 1, hy - 1);
-            const long long dx = x0 > 0 ? x0 : (x1 < 0 ? -x1 : 0);
-            const long long dy = y0 > 0 ? y0 : (y1 < 0 ? -y1 : 0);
-            int b = isqrt_floor(dx * dx + dy * dy);
+            int b;
+            if (mrx == 0.0 && mry == 0.0) {
+                const long long dx = x0 > 0 ? x0 : (x1 < 0 ? -x1 : 0);
+                const long long dy = y0 > 0 ? y0 : (y1 < 0 ? -y1 : 0);
+                b = isqrt_floor(dx * dx + dy * dy);
+            } else {
+                const double dx = std::max({x0 - mrx, mrx - x1, 0.0}), dy = std::max({y0 - mry, mry - y1, 0.0});
+                b = (int)std::min(floor(sqrt(dx * dx + dy * dy)), (double)(NBUCKET - 1));
+            }
             if (b > NBUCKET - 1) b = NBUCKET - 1;
             tiles.push_back({b, ty, tx});
         }
@@ -278,16 +295,18 @@ static void free_plan(Plan &p)
     free_dft_mats(p);
 }
 
+static long long mr_key(double mr) { return llround(mr * 1048576.0); }
+
 // The plan of a shape if an earlier call built it, else nullptr (never allocates).
-static Plan *find_plan(gws_ctx *ctx, int nx, int ny, int F)
+static Plan *find_plan(gws_ctx *ctx, int nx, int ny, int F, double mrx = 0.0, double mry = 0.0)
 {
-    auto it = ctx->plans.find(std::make_tuple(nx, ny, F));
+    auto it = ctx->plans.find(std::make_tuple(nx, ny, F, mr_key(mrx), mr_key(mry)));
     return it == ctx->plans.end() ? nullptr : &it->second;
 }
 
-static gws_status get_plan(gws_ctx *ctx, int nx, int ny, int F, Plan **out)
+static gws_status get_plan(gws_ctx *ctx, int nx, int ny, int F, Plan **out, double mrx = 0.0, double mry = 0.0)
 {
-    auto key = std::make_tuple(nx, ny, F);
+    auto key = std::make_tuple(nx, ny, F, mr_key(mrx), mr_key(mry));
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
         *out = &it->second;
@@ -295,7 +314,7 @@ static gws_status get_plan(gws_ctx *ctx, int nx, int ny, int F, Plan **out)
     }
     HIP_CHECK(ctx, hipSetDevice(ctx->device));
     Plan p;
-    const gws_status st = build_plan(ctx, p, nx, ny, F);
+    const gws_status st = build_plan(ctx, p, nx, ny, F, mrx, mry);
     if (st != GWS_OK) {
         free_plan(p);
         return st;
@@ -752,13 +771,14 @@ static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, cons
     const int F = kTileCfg[cfg - 1][0];
     Plan *p = nullptr;
     gws_status st = GWS_OK;
+    const double mrx = prob->ref_nu_x * prob->nx * prob->pitch_x, mry = prob->ref_nu_y * prob->ny * prob->pitch_y;
     if (noalloc) {
-        p = find_plan(ctx, prob->nx, prob->ny, F);
+        p = find_plan(ctx, prob->nx, prob->ny, F, mrx, mry);
         if (!p)
             return fail(ctx, GWS_ERR_UNSUPPORTED,
                         "no plan for this grid and tiling yet: call gws_forward once for this shape first");
     } else {
-        st = get_plan(ctx, prob->nx, prob->ny, F, &p);
+        st = get_plan(ctx, prob->nx, prob->ny, F, &p, mrx, mry);
         if (st != GWS_OK) return st;
     }
     const BatchLayout BL = make_batch_layout(prob, S, offsets, noalloc);
@@ -826,7 +846,8 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
     // the adjoint's geometry is fixed (regions of the F = 8 tiling); the tiling chooses the forward's
     const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
     Plan *p = nullptr;
-    gws_status st = get_plan(ctx, prob->nx, prob->ny, ADJ_F, &p);
+    gws_status st = get_plan(ctx, prob->nx, prob->ny, ADJ_F, &p, prob->ref_nu_x * prob->nx * prob->pitch_x,
+                             prob->ref_nu_y * prob->ny * prob->pitch_y);
     if (st != GWS_OK) return st;
     const BatchLayout BL = make_batch_layout(prob, S, offsets);
     st = check_ws(ctx, ws, ws_bytes, BL.total);
@@ -1103,9 +1124,11 @@ static void key_ptrs_g(std::vector<uintptr_t> &v, const gws_gaussians *g)
 static gws_status prepare_plans(gws_ctx *ctx, const gws_problem *prob, int S, const int64_t *offsets)
 {
     const int cfg = resolve_tile_config(ctx, prob, max_scene(S, offsets));
+    const double mrx = prob->ref_nu_x * prob->nx * prob->pitch_x, mry = prob->ref_nu_y * prob->ny * prob->pitch_y;
     for (int d = 0; d < 2; ++d) {
         Plan *p = nullptr;
-        const gws_status st = get_plan(ctx, prob->nx, prob->ny, kTileCfg[cfg - 1][d], &p);
+        // the forward's tiling, and the adjoint's fixed one
+        const gws_status st = get_plan(ctx, prob->nx, prob->ny, d == 0 ? kTileCfg[cfg - 1][0] : ADJ_F, &p, mrx, mry);
         if (st != GWS_OK) return st;
         if (prob->xform == GWS_XFORM_DFT_BF16X3) HIP_CHECK(ctx, build_dft_mats(*p));
         (void)acc_grid(ctx, prob->n_lambda, kTileCfg[cfg - 1][0]);

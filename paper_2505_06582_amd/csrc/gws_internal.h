@@ -91,7 +91,8 @@ __device__ __forceinline__ bool ellipse_meets_rect_r(float a, float b2, float g,
 }
 
 // Bit f is set when the support meets the 4-row block f of a sub-tile: columns [x0, x1],
-// rows [sy0 + 4f, sy0 + 4f + 3], rows clipped to the grid [-hy, hy - 1].  Lane rows
+// rows [sy0 + 4f, sy0 + 4f + 3], rows clipped to the grid [-hy, hy - 1].  With a support
+// centred at m_r instead of DC, x0, x1 are passed relative to m_r and ysh = m_r,y.  Lane rows
 // l / SUBX + 4 f of the tiling are exactly block f, so a wavefront skips block f of a
 // Gaussian whose bit is clear.
 //
@@ -104,7 +105,7 @@ __device__ __forceinline__ bool ellipse_meets_rect_r(float a, float b2, float g,
 // meets, so the strip is never empty.
 template <int F>
 __device__ __forceinline__ uint32_t row_block_mask(float a, float b2, float g, float lim, float x0, float x1, int sy0,
-                                                   int hy)
+                                                   int hy, float ysh = 0.0f)
 {
     const float dg = g - b2 * b2 * (0.25f / a);
     const float yt = sqrtf(lim / dg), xt = -b2 * yt * (0.5f / a);
@@ -126,7 +127,7 @@ __device__ __forceinline__ uint32_t row_block_mask(float a, float b2, float g, f
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int r0 = max(sy0 + 4 * f, -hy), r1 = min(sy0 + 4 * f + 3, hy - 1);
-        if (r0 <= r1 && (float)r0 <= yhi && (float)r1 >= ylo) m |= 1u << f;
+        if (r0 <= r1 && (float)r0 - ysh <= yhi && (float)r1 - ysh >= ylo) m |= 1u << f;
     }
     return m;
 }
@@ -306,6 +307,8 @@ struct Consts {
     int32_t phase_mode; // 0 exact base, 1 FP32 base (precision study)
     int32_t depth_grad; // backward: accumulate the depth-gradient sums
     int32_t pad1;
+    double nurx, nury;  // reference plane wave's transverse frequency (cycles / m)
+    double mrx, mry;    // the same in index units (nu_r N p): centre of every spectral support
 };
 
 // Per-shape plan owned by the context.

@@ -63,6 +63,9 @@ __global__ void __launch_bounds__(WG, waves_per_simd(F)) k_accumulate(Consts k, 
     const int hx = k.nx / 2, hy = k.ny / 2;
     const double Wx = k.nx * k.px, Wy = k.ny * k.py;
     const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    // every support is an ellipse centred at m_r (DC unless a reference plane wave tilts the
+    // illumination): the support tests and the envelope take frequencies relative to it
+    const float mrxf = (float)k.mrx, mryf = (float)k.mry;
 
     for (;;) {
         if (tid == 0) {
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(WG, waves_per_simd(F)) k_accumulate(Consts k, 
         // per-lane frequency constants
         const int col = lane & (SUBX - 1), row0 = lane >> 4;
         const int mxp = sx0 + col;
-        const float fmx = (float)mxp;
+        const float fmx = (float)((double)mxp - k.mrx);  // envelope coordinate, relative to m_r
         const float mxx = fmx * fmx, dxf = (float)(col - SUBX / 2);
         float mxy[F], myy[F], dyf[F], dD[F][C], msk[F][C];
         double D0[C];
@@ -110,7 +113,7 @@ __global__ void __launch_bounds__(WG, waves_per_simd(F)) k_accumulate(Consts k, 
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             const int myp = sy0 + row0 + 4 * f;
-            const float fmy = (float)myp;
+            const float fmy = (float)((double)myp - k.mry);
             mxy[f] = fmx * fmy;
             myy[f] = fmy * fmy;
             dyf[f] = (float)(row0 + 4 * f - SY / 2);
@@ -140,7 +143,7 @@ __global__ void __launch_bounds__(WG, waves_per_simd(F)) k_accumulate(Consts k, 
                 r1 = src[1];
                 r2 = src[2];
                 r3 = src[3];
-                pred = ellipse_meets_rect(r0.x, r0.y, r0.z, lim, X0, X1, Y0, Y1);
+                pred = ellipse_meets_rect(r0.x, r0.y, r0.z, lim, X0 - mrxf, X1 - mrxf, Y0 - mryf, Y1 - mryf);
             }
             const uint64_t bal = __ballot(pred);
             const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -168,11 +171,13 @@ __global__ void __launch_bounds__(WG, waves_per_simd(F)) k_accumulate(Consts k, 
                     WEntry e = {};
                     if (j < total) {
                         const GRec q = s_rec[j];
-                        p = ellipse_meets_rect(q.alpha, q.beta2, q.gamma, lim, x0, x1, y0, y1);
+                        p = ellipse_meets_rect(q.alpha, q.beta2, q.gamma, lim, x0 - mrxf, x1 - mrxf, y0 - mryf,
+                                               y1 - mryf);
                         if (p) {
                             e.alpha = q.alpha; e.beta2 = q.beta2; e.gamma = q.gamma; e.z = q.z;
                             e.rxf = q.rxf; e.ryf = q.ryf; e.pad1 = 0.0f;
-                            e.rows = row_block_mask<F>(q.alpha, q.beta2, q.gamma, lim, x0, x1, sy0, hy);
+                            e.rows = row_block_mask<F>(q.alpha, q.beta2, q.gamma, lim, x0 - mrxf, x1 - mrxf, sy0, hy,
+                                                       mryf);
                             pairs += __popc(e.rows) * (SUBX * 4);
                             // exact ramp at the sub-tile centre: 0.32 fixed point, wraps mod 1
                             const uint32_t ramp = (uint32_t)cx * q.rx + (uint32_t)cy * q.ry;

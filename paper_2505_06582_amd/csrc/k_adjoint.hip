@@ -213,6 +213,10 @@ __global__ void __launch_bounds__(adj_wg(C, DEPTH), adj_waves_per_simd(C, DEPTH)
     const int total_items = prefix[n_scenes];
     const int hx = k.nx / 2, hy = k.ny / 2;
     const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    // every support is an ellipse centred at m_r (DC unless a reference plane wave tilts the
+    // illumination): support tests, envelope and the frequency weights of the sums are taken
+    // relative to it (the weights are those of nu - nu_r, the argument of the Gaussian's spectrum)
+    const float mrxf = (float)k.mrx, mryf = (float)k.mry;
     const int col = lane & (ADJ_RW - 1), row4 = lane >> 4;
     const float dxf = (float)(col - ADJ_RW / 2);   // column offset from the sub-tile centre
     const float dyr = (float)(row4 - ADJ_SH / 2);  // row offset from the sub-tile centre at block 0
@@ -273,9 +277,10 @@ __global__ void __launch_bounds__(adj_wg(C, DEPTH), adj_waves_per_simd(C, DEPTH)
                 if (gvalid) {
                     const float4 *src = reinterpret_cast<const float4 *>(rec + gidx);
                     const float4 r0 = src[0];
-                    p = ellipse_meets_rect_r(r0.x, r0.y, r0.z, 0.5f / r0.x, 0.5f / r0.z, lim, X0, X1, Y0, Y1);
+                    p = ellipse_meets_rect_r(r0.x, r0.y, r0.z, 0.5f / r0.x, 0.5f / r0.z, lim, X0 - mrxf, X1 - mrxf,
+                                             Y0 - mryf, Y1 - mryf);
                     if (p) {
-                        rows = row_block_mask<ADJ_NB>(r0.x, r0.y, r0.z, lim, X0, X1, y0, hy);
+                        rows = row_block_mask<ADJ_NB>(r0.x, r0.y, r0.z, lim, X0 - mrxf, X1 - mrxf, y0, hy, mryf);
                         pairs += (long long)__popc(rows) * 64;
                         const float4 r1 = src[1], r2 = src[2];
                         const uint32_t rx = __float_as_uint(r1.x), ry = __float_as_uint(r1.y);
@@ -331,8 +336,8 @@ __global__ void __launch_bounds__(adj_wg(C, DEPTH), adj_waves_per_simd(C, DEPTH)
                 if (tid == 0) s_cnt[par ^ 1] = s_next[par ^ 1] = 0;  // for the next region
                 const int cnt = __builtin_amdgcn_readfirstlane(s_cnt[par]);
                 // per-lane frequency of this region: column x0 + col, rows y0 + row4 + 4 b
-                const float fmx = (float)(x0 + col), mxx = fmx * fmx;
-                const float fmy0 = (float)(y0 + row4);
+                const float fmx = (float)((double)(x0 + col) - k.mrx), mxx = fmx * fmx;
+                const float fmy0 = (float)((double)(y0 + row4) - k.mry);
                 for (;;) {
                     // the next accepted Gaussian of the region, taken by whichever wavefront is free
                     int ei = 0;

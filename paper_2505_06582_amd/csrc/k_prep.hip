@@ -218,7 +218,10 @@ __global__ void __launch_bounds__(256) k_records(GView g, Consts k, const uint64
     r.ryf = (float)((double)(int32_t)r.ry * (1.0 / 4294967296.0));
     const double o = g.opacity[i];
     const double norm = 6.283185307179586 * sqrt(det) / (k.px * k.py * (double)k.nx * (double)k.ny);
-    const double phi_rev = (double)g.phase[i] * 0.15915494309189535;
+    // carrier: the Gaussian's phase, the propagation's z / lambda, and under reference-wave
+    // illumination (spectrum taken at nu - nu_r) the ramp's constant part +nu_r . mu
+    const double phi_rev =
+        frac_d((double)g.phase[i] * 0.15915494309189535 + k.nurx * (double)g.mean_x[i] + k.nury * (double)g.mean_y[i]);
     for (int c = 0; c < 4; ++c) {
         if (c < k.C) {
             r.kappa[c] = (float)frac_d(phi_rev - (double)z * k.inv_lambda[c]);

@@ -21,7 +21,7 @@ def declared_symbols():
 
 def test_header_compiles_as_c_and_cxx(tmp_path):
     src = tmp_path / "t.c"
-    src.write_text('#include "gws.h"\nint main(void){gws_problem p; gws_stats s; (void)p; (void)s; return GWS_ABI_VERSION == 2 ? 0 : 1;}\n')
+    src.write_text('#include "gws.h"\nint main(void){gws_problem p; gws_stats s; (void)p; (void)s; return GWS_ABI_VERSION == 3 ? 0 : 1;}\n')
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)])
     subprocess.check_call(["g++", "-std=c++17", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", "-I",
                            os.path.dirname(HEADER), str(src)])
@@ -83,7 +83,7 @@ def _check(prob):
 
 def test_problem_validation_codes():
     lib = gws.load_library()
-    assert lib.gws_abi_version() == 2
+    assert lib.gws_abi_version() == 3
     ok = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9))
     assert _check(ok) == 0
     assert _check(gws.Problem(1921, 1080)) == -2          # odd
