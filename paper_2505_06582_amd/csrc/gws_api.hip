@@ -394,7 +394,7 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd,
 struct BatchLayout {
     size_t total = 0;
     size_t off_ctrl = 0, off_ftab = 0, off_btab = 0, off_prefix = 0, off_spectra = 0, off_gspecs = 0, off_gpack = 0,
-           off_dpack = 0, off_d0 = 0;
+           off_dpack = 0, off_d0 = 0, off_dftws = 0;
     AdjGeom geo = {};
     int64_t pack_elems = 0;  // packed per-frequency elements of one scene (regions x blocks x C x 64)
     std::vector<size_t> scene_off;
@@ -425,6 +425,8 @@ static BatchLayout make_batch_layout(const gws_problem *p, int S, const int64_t 
     B.off_gpack = take(bw * sizeof(float2) * (size_t)S * B.pack_elems);
     B.off_dpack = take(bw * sizeof(float) * (size_t)B.pack_elems);
     B.off_d0 = take(bw * sizeof(double) * (size_t)B.geo.nreg * 2 * C);
+    // the split-bf16 DFT's operand planes (both directions), when that transform is chosen
+    B.off_dftws = take(p->xform == GWS_XFORM_DFT_BF16X3 ? dft_bf16x3_workspace(p->nx, p->ny, S * C) : 0);
     for (int i = 0; i < S; ++i) {
         const int64_t ni = offsets[i + 1] - offsets[i];
         B.n.push_back(ni);
@@ -470,7 +472,7 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
     L.off_tmap = take(sizeof(float) * M);
     L.off_pimgs = take(sizeof(float2) * M * ((exact_batch(p->nx, p->ny) + 1) / 2));
     L.off_spec = take(sizeof(float2) * M * p->n_lambda);
-    L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? sizeof(float2) * M * p->n_lambda : 1);
+    L.off_dft = take(p->xform == GWS_XFORM_DFT_BF16X3 ? dft_bf16x3_workspace(p->nx, p->ny, p->n_lambda) : 1);
     L.off_win = take(sizeof(int4) * 4 * 64);
     L.off_counters = take(sizeof(long long) * CTR_COUNT);
     // adjoint: transformed field gradient, map checkpoints, back-to-front accumulator, partial sums
@@ -826,9 +828,9 @@ static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, cons
         StageScope sc(ctx, s, ST_XFORM_INV, !noalloc);
         if (prob->xform == GWS_XFORM_FFT_FP32)
             HIP_CHECK(ctx, launch_fft2d(*p, S * k.C, +1, spectra, (float2 *)out->field, s));
-        else  // the bf16 DFT keeps its intermediate in the (forward-idle) gradient-spectrum area
+        else
             HIP_CHECK(ctx, launch_dft_bf16x3(*p, S * k.C, +1, spectra, (float2 *)out->field,
-                                             (void *)(base + BL.off_gspecs), s));
+                                             (void *)(base + BL.off_dftws), s));
     }
     HIP_CHECK(ctx, launch_sum_counters(ctrs.data(), S, ctx->d_stats, s));
     ctx->last_n = g->n;
@@ -887,7 +889,7 @@ static gws_status backward_run(gws_ctx *ctx, const gws_problem *prob, int S, con
             HIP_CHECK(ctx, launch_fft2d(*p, S * k.C, -1, (const float2 *)grad_field, gspecs, s));
         else
             HIP_CHECK(ctx, launch_dft_bf16x3(*p, S * k.C, -1, (const float2 *)grad_field, gspecs,
-                                             (void *)(base + BL.off_spectra), s));
+                                             (void *)(base + BL.off_dftws), s));
     }
     {
         StageScope sc(ctx, s, ST_DTABLE);
