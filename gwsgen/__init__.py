@@ -21,7 +21,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Grid", "Scene", "make_scene", "make_target", "WORKLOADS", "workload"]
+__all__ = ["Grid", "Scene", "TiltedScene", "make_scene", "make_tilted_scene", "make_target", "WORKLOADS",
+           "workload"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -122,6 +123,73 @@ def make_scene(n: int, grid: Grid, seed: int, depth_range=(-5e-3, 5e-3),
     return Scene(mean_x=f32(mean_x), mean_y=f32(mean_y), depth=f32(depth),
                  cov_xx=f32(cov_xx), cov_xy=f32(cov_xy), cov_yy=f32(cov_yy),
                  opacity=f32(opacity), amplitude=f32(amplitude), phase=f32(phase))
+
+
+@dataclasses.dataclass
+class TiltedScene:
+    """Structure-of-arrays float32 tilted 2D Gaussians: centre (mean_x, mean_y, depth), unit
+    quaternion (w, x, y, z) of the rotation that places the Gaussian's plane, the two in-plane
+    scales (metres), opacity, per-channel amplitude (n_lambda, n) and phase."""
+
+    mean_x: np.ndarray
+    mean_y: np.ndarray
+    depth: np.ndarray
+    quat_w: np.ndarray
+    quat_x: np.ndarray
+    quat_y: np.ndarray
+    quat_z: np.ndarray
+    scale_u: np.ndarray
+    scale_v: np.ndarray
+    opacity: np.ndarray
+    amplitude: np.ndarray
+    phase: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.mean_x.shape[0])
+
+    def fields(self):
+        return {f.name: getattr(self, f.name) for f in dataclasses.fields(self)}
+
+    def subset(self, idx) -> "TiltedScene":
+        idx = np.asarray(idx)
+        return TiltedScene(**{k: (v[:, idx] if k == "amplitude" else v[idx]) for k, v in self.fields().items()})
+
+    def copy(self) -> "TiltedScene":
+        return TiltedScene(**{k: v.copy() for k, v in self.fields().items()})
+
+
+def make_tilted_scene(n: int, grid: Grid, seed: int, depth_range=(-5e-3, 5e-3), sigma_px=(2.0, 20.0),
+                      opacity_range=(0.1, 1.0), tilt_max_deg: float = 2.0) -> TiltedScene:
+    """Draw ``n`` random tilted Gaussians: as ``make_scene`` for position, depth, scales,
+    in-plane angle theta, opacity, amplitude and phase, then a tilt: its axis at angle psi
+    uniform in [0, 2 pi) in the SLM plane and its angle uniform in [0, ``tilt_max_deg``].
+    The rotation is the tilt applied after the in-plane rotation, q = q_tilt * q_z(theta)
+    (Hamilton product), stored as a float32 quaternion (w, x, y, z).
+
+    Draw order: mean_x, mean_y, depth, s_u, s_v, theta, psi, tilt, opacity, amplitude[c],
+    phase."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W, H = grid.nx * grid.px, grid.ny * grid.py
+    mean_x = rng.uniform(-W / 2, W / 2, n)
+    mean_y = rng.uniform(-H / 2, H / 2, n)
+    depth = rng.uniform(depth_range[0], depth_range[1], n)
+    s_u = rng.uniform(sigma_px[0], sigma_px[1], n) * grid.px
+    s_v = rng.uniform(sigma_px[0], sigma_px[1], n) * grid.py
+    theta = rng.uniform(0.0, math.pi, n)
+    psi = rng.uniform(0.0, 2.0 * math.pi, n)
+    tilt = np.radians(rng.uniform(0.0, tilt_max_deg, n))
+    opacity = rng.uniform(opacity_range[0], opacity_range[1], n)
+    amplitude = np.stack([rng.uniform(0.0, 1.0, n) for _ in range(grid.n_lambda)])
+    phase = rng.uniform(0.0, 2.0 * math.pi, n)
+    # q_tilt = (cos t/2, cos psi sin t/2, sin psi sin t/2, 0), q_z = (cos th/2, 0, 0, sin th/2)
+    a0, ax, ay = np.cos(tilt / 2), np.cos(psi) * np.sin(tilt / 2), np.sin(psi) * np.sin(tilt / 2)
+    b0, bz = np.cos(theta / 2), np.sin(theta / 2)
+    qw, qx, qy, qz = a0 * b0, ax * b0 + ay * bz, ay * b0 - ax * bz, a0 * bz
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return TiltedScene(mean_x=f32(mean_x), mean_y=f32(mean_y), depth=f32(depth), quat_w=f32(qw), quat_x=f32(qx),
+                       quat_y=f32(qy), quat_z=f32(qz), scale_u=f32(s_u), scale_v=f32(s_v), opacity=f32(opacity),
+                       amplitude=f32(amplitude), phase=f32(phase))
 
 
 def make_target(grid: Grid, seed: int) -> np.ndarray:
