@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="fwdbwd100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-config", type=int, default=0, help="0: tuned/default tiling; k: explicit tiling k")
+    ap.add_argument("--phase-mode", type=int, default=0,
+                    help="0: exact phase bases (the product setting); 1: plain FP32 bases (precision study)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -135,7 +137,7 @@ def main():
     log("bench: generating workload %s" % args.workload)
     scene, grid = gwsgen.workload(args.workload)
     target = gwsgen.make_target(grid, 2003)
-    prob = gws.Problem.from_grid(grid, tile_config=args.tile_config)
+    prob = gws.Problem.from_grid(grid, tile_config=args.tile_config, phase_mode=args.phase_mode)
     ctx = gws.context(0)
     dev = torch.device("cuda", 0)
     g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.fields().items()}
@@ -671,8 +673,12 @@ def bench_precision(args):
     g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.fields().items()}
     field = torch.empty((grid.n_lambda, grid.ny, grid.nx), dtype=torch.complex64, device=dev)
     res = {}
-    for name, xf in (("fft_fp32", gws.XFORM_FFT_FP32), ("dft_bf16x3", gws.XFORM_DFT_BF16X3)):
-        prob = gws.Problem.from_grid(grid, xform=xf, tile_config=args.tile_config)
+    # the FP32 FFT and the split-bf16 DFT with exact phase bases, then the FFT path with plain
+    # FP32 phase bases (what the exact bases cost in the accumulation)
+    runs = (("fft_fp32", gws.XFORM_FFT_FP32, 0), ("dft_bf16x3", gws.XFORM_DFT_BF16X3, 0),
+            ("fft_fp32_fp32_phase_base", gws.XFORM_FFT_FP32, 1))
+    for name, xf, pm in runs:
+        prob = gws.Problem.from_grid(grid, xform=xf, tile_config=args.tile_config, phase_mode=pm)
         for _ in range(max(1, args.warmup)):
             ctx.forward(prob, g, out=field)
         torch.cuda.synchronize()
@@ -690,6 +696,23 @@ def bench_precision(args):
                      "stage_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}}
         log("bench precision1m: %s %.2f ms per forward" % (name, res[name]["ms_per_forward"]))
     C, M, nx, ny = grid.n_lambda, grid.nx * grid.ny, grid.nx, grid.ny
+    # error of each transform against an FP64 inverse DFT of the same (GPU) spectrum
+    errs = {}
+    for name, xf in (("fft_fp32", gws.XFORM_FFT_FP32), ("dft_bf16x3", gws.XFORM_DFT_BF16X3)):
+        prob = gws.Problem.from_grid(grid, xform=xf, tile_config=args.tile_config)
+        f, sp = ctx.forward(prob, g, want_spectrum=True)
+        torch.cuda.synchronize()
+        if name == "fft_fp32":
+            s64 = sp.cpu().numpy().astype(np.complex128)
+            ref = np.fft.ifft2(s64) * (nx * ny)
+            del s64
+        got = f.cpu().numpy().astype(np.complex128)
+        errs[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        del got, f, sp
+        log("bench precision1m: %s transform rel L2 vs FP64 inverse DFT of the same spectrum %.3e" % (name, errs[name]))
+    del ref
+    for name in errs:
+        res[name]["transform_rel_l2_vs_fp64"] = errs[name]
     t_fft = res["fft_fp32"]["stage_ms"]["xform_inverse"] * 1e-3
     t_dft = res["dft_bf16x3"]["stage_ms"]["xform_inverse"] * 1e-3
     flops = C * 24.0 * (ny * nx * nx + nx * ny * ny)   # two complex GEMMs, 3 bf16 products each
@@ -699,6 +722,8 @@ def bench_precision(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "precision1m", "gaussians": scene.n, "ny": ny, "nx": nx, "n_lambda": C},
            "variants": res,
+           "accumulate_ms_by_phase_base": {"exact_fp64": res["fft_fp32"]["stage_ms"]["accumulate"],
+                                            "plain_fp32": res["fft_fp32_fp32_phase_base"]["stage_ms"]["accumulate"]},
            "transform_roofline": {
                "fft_fp32": {"bound": "hbm", "achieved": 2 * C * M * 8 / t_fft / 1e9, "peak": 8000.0, "unit": "GB/s",
                             "frac": 2 * C * M * 8 / t_fft / 8e12, "algorithmic_bytes": 2 * C * M * 8,
