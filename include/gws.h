@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GWS_ABI_VERSION 3
+#define GWS_ABI_VERSION 4
 #define GWS_MAX_LAMBDA 4
 
 /* Return codes.  Launch-time validation returns the code at once and leaves the
@@ -212,6 +212,43 @@ gws_status gws_forward(gws_ctx *ctx, const gws_problem *problem, const gws_gauss
  * caller.  Results are bitwise those of gws_forward. */
 gws_status gws_forward_noalloc(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
                                const gws_output *out, void *stream);
+
+/* ---- Tilted Gaussians (Sec. 4.1, Eq. 8-10; the supplement's translation, rotation and
+ * scaling steps) ----
+ *
+ * A tilted Gaussian is the canonical 2D Gaussian of the plane z_c = 0 placed in hologram space
+ * by x = R S x_c + mu: S = diag(scale_u, scale_v, 0), R the rotation of the quaternion (w, x,
+ * y, z) (normalised here; any non-zero norm), mu = (mean_x, mean_y, depth).  Its spectrum on
+ * the plane z = depth is |det J| G_o(R^T k) e^{-j 2 pi nu . mu_xy} with k = (nu, k_z),
+ * det J = k_oz / k_z (taken in magnitude: R and R diag(1, -1, -1) describe the same disk),
+ * G_o the scaled canonical spectrum 2 pi s_u s_v exp(-2 pi^2 (s_u^2 k_ox^2 + s_v^2 k_oy^2));
+ * it is then propagated by H(nu, -depth), weighted by amplitude_c * opacity * e^{j phase}
+ * and summed order-invariantly (Eq. 12).  A rotation about z alone is exactly the in-plane
+ * Gaussian with Sigma = R S^2 R^T.  Device float32 arrays of n elements, amplitude
+ * [n_lambda][n].  Gaussians with a non-finite value, a scale <= 0, a zero quaternion, zero
+ * opacity or all-zero amplitudes are culled and counted in gws_stats.n_culled. */
+typedef struct gws_tilted_gaussians {
+    int64_t n;
+    const float *mean_x, *mean_y, *depth;
+    const float *quat_w, *quat_x, *quat_y, *quat_z;
+    const float *scale_u, *scale_v;
+    const float *opacity, *amplitude, *phase;
+} gws_tilted_gaussians;
+
+/* Bytes of workspace gws_forward_tilted needs for n Gaussians (host-only; ctx may be NULL):
+ * 104 bytes per Gaussian (record and tile rectangle), the spectrum, and the split-bf16 DFT's
+ * planes when problem->xform selects it. */
+gws_status gws_workspace_size_tilted(const gws_ctx *ctx, const gws_problem *problem, int64_t n, size_t *bytes);
+
+/* Forward of tilted Gaussians: field (and optionally spectrum) as gws_forward.  Takes the
+ * order-invariant blend and on-axis illumination only: blend = GWS_BLEND_EXACT or a non-zero
+ * ref_nu returns GWS_ERR_UNSUPPORTED.  eps_support cuts each term where its Gaussian factor
+ * is below eps (the Jacobian factor |det J| is not part of the test).  Steps on the stream:
+ * records and tile rectangles in input order, spectrum accumulation (one persistent launch,
+ * every frequency written once, sum in input order: bitwise reproducible), inverse 2D
+ * transform.  No host synchronisation. */
+gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *problem, const gws_tilted_gaussians *g,
+                              const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Backward: given grad_field = dL/dRe(u) + j dL/dIm(u) (complex64 [n_lambda][ny][nx], the
  * convention torch uses for complex tensors), write dL/d(parameter) for every Gaussian.

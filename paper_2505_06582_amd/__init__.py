@@ -57,6 +57,14 @@ class _Gaussians(ctypes.Structure):
         "mean_x", "mean_y", "depth", "cov_xx", "cov_xy", "cov_yy", "opacity", "amplitude", "phase")]
 
 
+TILTED_PARAMS = ("mean_x", "mean_y", "depth", "quat_w", "quat_x", "quat_y", "quat_z", "scale_u", "scale_v",
+                 "opacity", "amplitude", "phase")
+
+
+class _TiltedGaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, _fp) for k in TILTED_PARAMS]
+
+
 class _Output(ctypes.Structure):
     _fields_ = [("field", _fp), ("spectrum", _fp)]
 
@@ -112,6 +120,10 @@ _SIGNATURES = {
                                    ctypes.POINTER(_Output), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gws_forward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
                                            ctypes.POINTER(_Output), ctypes.c_void_p]),
+    "gws_workspace_size_tilted": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int64,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "gws_forward_tilted": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_TiltedGaussians),
+                                          ctypes.POINTER(_Output), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gws_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
                                     ctypes.c_void_p, ctypes.POINTER(_Grads), ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_void_p]),
@@ -226,16 +238,16 @@ def _torch():
     return torch
 
 
-def check_gaussians(g: Dict[str, "object"], n_lambda: int) -> int:
+def check_gaussians(g: Dict[str, "object"], n_lambda: int, params=PARAMS) -> int:
     """Number of Gaussians n after checking the sizes of the parameter tensors: every field
     holds n elements, amplitude n_lambda * n, laid out channel-major ([n_lambda][n]).  The
     kernels index these arrays by n alone, so a mis-sized tensor would be read out of bounds;
     raises ValueError before anything reaches the library."""
-    missing = [k for k in PARAMS if k not in g or g[k] is None]
+    missing = [k for k in params if k not in g or g[k] is None]
     if missing:
         raise ValueError("missing Gaussian parameters: %s" % ", ".join(missing))
     n = int(g["mean_x"].numel())
-    for k in PARAMS:
+    for k in params:
         t = g[k]
         if k == "amplitude":
             ok = (t.dim() == 1 and t.numel() == n_lambda * n) or (t.dim() == 2 and tuple(t.shape) == (n_lambda, n))
@@ -284,6 +296,18 @@ def _gaussians_struct(g: Dict[str, "object"], n_lambda: int) -> _Gaussians:
     s = _Gaussians()
     s.n = n
     for k in PARAMS:
+        t = g[k]
+        if n > 0 and not (t.dtype == _torch().float32 and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float32 tensor" % k)
+        setattr(s, k, _dptr(t) if n > 0 else None)
+    return s
+
+
+def _tilted_struct(g: Dict[str, "object"], n_lambda: int) -> _TiltedGaussians:
+    n = check_gaussians(g, n_lambda, TILTED_PARAMS)
+    s = _TiltedGaussians()
+    s.n = n
+    for k in TILTED_PARAMS:
         t = g[k]
         if n > 0 and not (t.dtype == _torch().float32 and t.is_contiguous()):
             raise ValueError("%s must be a contiguous float32 tensor" % k)
@@ -371,6 +395,30 @@ class Context:
         _check(self.lib.gws_forward_noalloc(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
                                             self._stream()), self.handle)
         return out
+
+    def workspace_size_tilted(self, prob: Problem, n: int) -> int:
+        sz = ctypes.c_size_t()
+        _check(self.lib.gws_workspace_size_tilted(self.handle, ctypes.byref(prob._c()), n, ctypes.byref(sz)),
+               self.handle)
+        return sz.value
+
+    def forward_tilted(self, prob: Problem, g: Dict[str, "object"], want_spectrum: bool = False, out=None):
+        """Field (n_lambda, ny, nx) complex64 of tilted Gaussians (fields TILTED_PARAMS), and the
+        DFT-ready spectrum if asked."""
+        torch = _torch()
+        n = check_gaussians(g, prob.n_lambda, TILTED_PARAMS)
+        shape = (prob.n_lambda, prob.ny, prob.nx)
+        field = out if out is not None else torch.empty(shape, dtype=torch.complex64, device=self.torch_device)
+        check_tensor(field, "out", shape, "complex64")
+        gs = _tilted_struct(g, prob.n_lambda)
+        spec = torch.empty_like(field) if want_spectrum else None
+        o = _Output()
+        o.field = _dptr(field)
+        o.spectrum = _dptr(spec) if spec is not None else None
+        ws = self.workspace(self.workspace_size_tilted(prob, n))
+        _check(self.lib.gws_forward_tilted(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
+                                           ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
+        return (field, spec) if want_spectrum else field
 
     def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True, out=None):
         """dL/d(parameter) for every Gaussian, given dL/dRe u + j dL/dIm u."""

@@ -1051,6 +1051,100 @@ extern "C" gws_status gws_forward_noalloc(gws_ctx *ctx, const gws_problem *prob,
                        true);
 }
 
+// ---------------------------------------------------------------------------------
+// Tilted Gaussians
+// ---------------------------------------------------------------------------------
+struct TiltLayout {
+    size_t off_rec, off_rect, off_counters, off_spectrum, off_dftws, total;
+};
+
+static TiltLayout tilt_layout(const gws_problem *p, int64_t n)
+{
+    TiltLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t at = o; o += align256(b); return at; };
+    L.off_rec = take((size_t)std::max<int64_t>(n, 1) * sizeof(TRec));
+    L.off_rect = take((size_t)std::max<int64_t>(n, 1) * sizeof(int2));
+    L.off_counters = take(CTR_COUNT * sizeof(long long));
+    L.off_spectrum = take((size_t)p->n_lambda * p->nx * p->ny * sizeof(float2));
+    L.off_dftws = take(p->xform == GWS_XFORM_DFT_BF16X3 ? dft_bf16x3_workspace(p->nx, p->ny, p->n_lambda) : 0);
+    L.total = o;
+    return L;
+}
+
+static gws_status check_tilted(gws_ctx *ctx, const gws_problem *prob, const gws_tilted_gaussians *g)
+{
+    if (!g) return fail(ctx, GWS_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0 || g->n > (int64_t)0x7fffffff) return fail(ctx, GWS_ERR_INVALID_ARG, "bad Gaussian count");
+    if (g->n > 0 && (!g->mean_x || !g->mean_y || !g->depth || !g->quat_w || !g->quat_x || !g->quat_y || !g->quat_z ||
+                     !g->scale_u || !g->scale_v || !g->opacity || !g->amplitude || !g->phase))
+        return fail(ctx, GWS_ERR_INVALID_ARG, "a Gaussian array is NULL");
+    if (prob->blend != GWS_BLEND_OIT)
+        return fail(ctx, GWS_ERR_UNSUPPORTED, "tilted Gaussians take the order-invariant blend only");
+    if (prob->ref_nu_x != 0.0 || prob->ref_nu_y != 0.0)
+        return fail(ctx, GWS_ERR_UNSUPPORTED, "tilted Gaussians take on-axis illumination only (ref_nu = 0)");
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_workspace_size_tilted(const gws_ctx *ctx, const gws_problem *problem, int64_t n,
+                                                size_t *bytes)
+{
+    (void)ctx;
+    if (!bytes || n < 0 || n > (int64_t)0x7fffffff) return GWS_ERR_INVALID_ARG;
+    const gws_status st = gws_check_problem(problem);
+    if (st != GWS_OK) return st;
+    *bytes = tilt_layout(problem, n).total;
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *prob, const gws_tilted_gaussians *g,
+                                         const gws_output *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = gws_check_problem(prob);
+    if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    st = check_tilted(ctx, prob, g);
+    if (st != GWS_OK) return st;
+    if (!out || !out->field) return fail(ctx, GWS_ERR_INVALID_ARG, "output field is NULL");
+    const TiltLayout L = tilt_layout(prob, g->n);
+    st = check_ws(ctx, ws, ws_bytes, L.total);
+    if (st != GWS_OK) return st;
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const hipStream_t s = (hipStream_t)stream;
+    Plan *p = nullptr;  // the transform's tables (the tiling is not used here)
+    st = get_plan(ctx, prob->nx, prob->ny, kTileCfg[kDefaultTileCfg - 1][0], &p);
+    if (st != GWS_OK) return st;
+    char *base = (char *)ws;
+    const Consts k = make_consts(prob, 1);
+    TRec *rec = (TRec *)(base + L.off_rec);
+    int2 *rect = (int2 *)(base + L.off_rect);
+    long long *counters = (long long *)(base + L.off_counters);
+    float2 *spectrum = out->spectrum ? (float2 *)out->spectrum : (float2 *)(base + L.off_spectrum);
+    const TView tv{g->n,       g->mean_x,  g->mean_y,  g->depth,   g->quat_w,    g->quat_x, g->quat_y,
+                   g->quat_z,  g->scale_u, g->scale_v, g->opacity, g->amplitude, g->phase};
+    ctx->last_graph = 0;
+    {
+        StageScope sc(ctx, s, ST_PREP);
+        HIP_CHECK(ctx, launch_tilt_records(tv, k, rec, rect, counters, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_ACCUM);
+        HIP_CHECK(ctx, launch_tilt_accumulate(k, rec, rect, g->n, spectrum, counters, ctx->n_cu, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_XFORM_INV);
+        if (prob->xform == GWS_XFORM_FFT_FP32)
+            HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spectrum, (float2 *)out->field, s));
+        else
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spectrum, (float2 *)out->field, (void *)(base + L.off_dftws), s));
+    }
+    long long *ctrs[1] = {counters};
+    HIP_CHECK(ctx, launch_sum_counters(ctrs, 1, ctx->d_stats, s));
+    ctx->last_n = g->n;
+    ctx->last_tile_config = 0;
+    return GWS_OK;
+}
+
 extern "C" gws_status gws_backward(gws_ctx *ctx, const gws_problem *prob, const gws_gaussians *g, const void *grad_field,
                                    const gws_grads *grads, void *ws, size_t ws_bytes, void *stream)
 {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -232,6 +233,26 @@ struct alignas(16) GRec {
     float amp[4];                   // a_c o 2 pi sqrt(det) / (px py nx ny)
 };
 static_assert(sizeof(GRec) == 64, "record must stay 64 B");
+
+// Tilted-Gaussian record (input order), 96 bytes, written by k_tilt_records: the exp2-units
+// linear forms u = U . (m_x, m_y, k_z), v = V . (...) and k_oz = N . (...) (m in index units,
+// k_z in cycles per metre), depth, ramp (as GRec), carrier and amplitude a_c o 2 pi s_u s_v /
+// (px py nx ny).
+struct alignas(16) TRec {
+    float U[3], V[3], N[3], z;
+    uint32_t rx, ry;
+    float rxf, ryf, pad0, pad1;
+    float kappa[4];
+    float amp[4];
+};
+static_assert(sizeof(TRec) == 96, "tilted record must stay 96 B");
+
+// Tilted Gaussians of one call (device arrays, amplitude [C][n]).
+struct TView {
+    int64_t n;
+    const float *mean_x, *mean_y, *depth, *quat_w, *quat_x, *quat_y, *quat_z, *scale_u, *scale_v, *opacity,
+        *amplitude, *phase;
+};
 
 // Forward work item: candidates [chunk*CH, min((chunk+1)*CH, L)) of sorted tile k.
 struct Item {
@@ -485,6 +506,10 @@ hipError_t launch_fft2d_win(const Plan &p, int batch, int direction, const float
 hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in, float2 *out,
                              void *ws, hipStream_t s);
 size_t dft_bf16x3_workspace(int nx, int ny, int batch);
+hipError_t launch_tilt_records(const TView &g, const Consts &k, TRec *rec, int2 *rect, long long *counters,
+                               hipStream_t s);
+hipError_t launch_tilt_accumulate(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, float2 *spectrum,
+                                  long long *counters, int n_cu, hipStream_t s);
 hipError_t build_dft_mats(Plan &p);
 void free_dft_mats(Plan &p);
 

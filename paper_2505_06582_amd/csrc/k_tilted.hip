@@ -1,0 +1,483 @@
+// Tilted 2D Gaussians (Sec. 4.1, Eq. 8-10; the supplement's translation, rotation and scaling
+// steps) summed order-invariantly (Sec. 4.2, Eq. 12) on gfx950.
+//
+// A tilted Gaussian is the canonical Gaussian of the plane z_c = 0 placed by x = R S x_c + mu,
+// S = diag(s_u, s_v, 0), R from a unit quaternion.  On the plane through its centre parallel
+// to the SLM its spectrum is |det J| G_o(k_ox, k_oy) with k_o = R^T k, k = (nu_x, nu_y, k_z),
+// k_z = sqrt(1/lambda^2 - |nu|^2), det J = k_oz / k_z (the magnitude: the disk radiates to
+// both sides, and R, R diag(1,-1,-1) describe the same disk), G_o the scaled canonical
+// spectrum 2 pi s_u s_v exp(-2 pi^2 (s_u^2 k_ox^2 + s_v^2 k_oy^2)).  The ramp, the carrier and
+// the propagation H(nu, -z) are those of an in-plane Gaussian, so the term of Gaussian i at
+// wavelength c and frequency m (index units) is
+//   A_c |w_c(m)| / k_z,c(m) exp2(-(u_c(m)^2 + v_c(m)^2)) exp(j 2 pi Theta_c(m)),
+//   u_c = U . (m_x, m_y, k_z,c),  v_c = V . (...),  w_c = N . (...)  (= k_oz, 1/m),
+// with U = sqrt(2 pi^2 log2 e) s_u (R11 / W, R21 / H, R31), V likewise from column 2 and s_v,
+// N = (R13 / W, R23 / H, R33), W = nx px, H = ny py, and Theta_c as in the in-plane kernel.
+// Unlike an in-plane Gaussian, the exponent depends on the wavelength (through k_z), so there
+// is one exp2 per (Gaussian, frequency, wavelength).
+//
+// Precision: u, v, w are large sums of nearly cancelling terms (R31 k_z alone reaches
+// ~1e2 in exp2 units at a few degrees of tilt), so as the phase they are split into an FP64
+// base at the centre of each 16 x 16 sub-tile (per sub-tile and Gaussian, one lane per
+// Gaussian) and FP32 deltas per lane: u = u0 + U_x dx + U_y dy + U_z (D_c(m) - D_c(m0)),
+// D_c = k_z,c - 1/lambda_c.
+//
+// Work.  The support of a tilted Gaussian sits near n_xy / lambda_c (n = R e_z, the disk's
+// normal), one off-centre patch per wavelength, so the in-plane path's DC-centred binning does
+// not apply.  Each Gaussian gets a conservative rectangle of 32 x 32 tiles (the union over
+// wavelengths and both sides of the disk of the bounding box of its eps-support on the sphere
+// |k| = 1/lambda).  A persistent work-group takes tiles from a queue in rings around DC, scans
+// every Gaussian's rectangle in input order (8 bytes each, L2-resident), stages the ones that
+// reach the tile, and each wavefront tests them against its 16 x 16 sub-tile and 4-row blocks
+// (bounds of u and v over the block), forms the FP64 bases and evaluates.  Every frequency of
+// the grid belongs to one tile, so the spectrum is written once with no partial sums, and the
+// order of the sum is fixed: results are bitwise reproducible.
+#include "gws_internal.h"
+
+namespace gws {
+
+constexpr int TT = 32;          // tile side (frequencies)
+constexpr int TF = 4;           // 4-row blocks per sub-tile (16 rows)
+constexpr int TWG = 256;        // threads per work-group (4 wavefronts, one 16 x 16 sub-tile each)
+
+static __device__ __forceinline__ bool finite_t(float v) { return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u; }
+static __device__ __forceinline__ double frac_t(double v) { return v - floor(v); }
+static __device__ __forceinline__ int floor_div_t(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// D_c(nu) = k_z - 1/lambda (negative, no cancellation); -1/lambda (k_z = 0) when evanescent.
+static __device__ __forceinline__ double dprop_t(double nu2, double il)
+{
+    const double w2 = il * il - nu2;
+    return w2 > 0.0 ? -nu2 / (il + sqrt(w2)) : -il;
+}
+
+__global__ void k_tilt_zero(long long *__restrict__ counters)
+{
+    if (threadIdx.x < CTR_COUNT) counters[threadIdx.x] = 0;
+}
+
+// One thread per Gaussian (input order): validity, record, tile rectangle.
+__global__ void __launch_bounds__(256) k_tilt_records(TView g, Consts k, TRec *__restrict__ rec,
+                                                       int2 *__restrict__ rect, long long *__restrict__ counters)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const float mx = g.mean_x[i], my = g.mean_y[i], z = g.depth[i], o = g.opacity[i], ph = g.phase[i];
+    const float qw = g.quat_w[i], qx = g.quat_x[i], qy = g.quat_y[i], qz = g.quat_z[i];
+    const float su = g.scale_u[i], sv = g.scale_v[i];
+    bool ok = finite_t(mx) && finite_t(my) && finite_t(z) && finite_t(o) && finite_t(ph) && finite_t(qw) &&
+              finite_t(qx) && finite_t(qy) && finite_t(qz) && finite_t(su) && finite_t(sv) && su > 0.0f && sv > 0.0f;
+    bool any_amp = false;
+    for (int c = 0; c < k.C; ++c) {
+        const float a = g.amplitude[(int64_t)c * g.n + i];
+        ok = ok && finite_t(a);
+        any_amp = any_amp || (a != 0.0f);
+    }
+    const double qn = (double)qw * qw + (double)qx * qx + (double)qy * qy + (double)qz * qz;
+    ok = ok && qn > 0.0 && o != 0.0f && any_amp;
+    TRec r = {};
+    int2 box = make_int2(1, 0);  // empty: tx0 > tx1
+    if (ok) {
+        // rotation of the normalised quaternion
+        const double s = 1.0 / sqrt(qn);
+        const double w = qw * s, x = qx * s, y = qy * s, zq = qz * s;
+        const double R[3][3] = {{1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y)},
+                                {2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x)},
+                                {2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)}};
+        const double Wx = k.nx * k.px, Wy = k.ny * k.py;
+        const double sk = sqrt(k.K2);
+        const double su_d = su, sv_d = sv;
+        r.U[0] = (float)(sk * su_d * R[0][0] / Wx);
+        r.U[1] = (float)(sk * su_d * R[1][0] / Wy);
+        r.U[2] = (float)(sk * su_d * R[2][0]);
+        r.V[0] = (float)(sk * sv_d * R[0][1] / Wx);
+        r.V[1] = (float)(sk * sv_d * R[1][1] / Wy);
+        r.V[2] = (float)(sk * sv_d * R[2][1]);
+        r.N[0] = (float)(R[0][2] / Wx);
+        r.N[1] = (float)(R[1][2] / Wy);
+        r.N[2] = (float)R[2][2];
+        r.z = z;
+        const double fx = frac_t((double)mx / Wx + 0.5), fy = frac_t((double)my / Wy + 0.5);
+        r.rx = (uint32_t)(uint64_t)llrint(fx * 4294967296.0);
+        r.ry = (uint32_t)(uint64_t)llrint(fy * 4294967296.0);
+        r.rxf = (float)((double)(int32_t)r.rx * (1.0 / 4294967296.0));
+        r.ryf = (float)((double)(int32_t)r.ry * (1.0 / 4294967296.0));
+        const double norm = 6.283185307179586 * su_d * sv_d / (k.px * k.py * (double)k.nx * (double)k.ny);
+        const double phi_rev = frac_t((double)ph * 0.15915494309189535);
+        for (int c = 0; c < 4; ++c) {
+            r.kappa[c] = c < k.C ? (float)frac_t(phi_rev - (double)z * k.inv_lambda[c]) : 0.0f;
+            r.amp[c] = c < k.C ? (float)((double)g.amplitude[(int64_t)c * g.n + i] * (double)o * norm) : 0.0f;
+        }
+        // Bounding box of the eps-support u^2 + v^2 <= tau2: in the disk frame an ellipse of
+        // semi-axes A = sqrt(tau2 / K2) / s_u, B = .../ s_v in (k_ox, k_oy); on the sphere
+        // k_o = (a, b, +-w), w in [w_min, 1/lambda].  nu = R k_o, so each transverse component
+        // is bounded by the ellipse's support function plus the range of R_j3 (+-w); a side
+        // whose waves cannot reach k_z > 0 is skipped.  Union over wavelengths and sides,
+        // clipped to the propagating disk and the grid.
+        const double t = sqrt(k.tau2 / k.K2);
+        const double A = t / su_d, B = t / sv_d, rho2 = fmax(A, B) * fmax(A, B);
+        const double hxx = t * sqrt(R[0][0] * R[0][0] / (su_d * su_d) + R[0][1] * R[0][1] / (sv_d * sv_d));
+        const double hyy = t * sqrt(R[1][0] * R[1][0] / (su_d * su_d) + R[1][1] * R[1][1] / (sv_d * sv_d));
+        const double gz = t * sqrt(R[2][0] * R[2][0] / (su_d * su_d) + R[2][1] * R[2][1] / (sv_d * sv_d));
+        double lox = 1e300, hix = -1e300, loy = 1e300, hiy = -1e300;
+        for (int c = 0; c < k.C; ++c) {
+            const double il = k.inv_lambda[c];
+            const double wmin = sqrt(fmax(0.0, il * il - rho2));
+            for (int sd = -1; sd <= 1; sd += 2) {
+                const double z0 = sd * R[2][2] * wmin, z1 = sd * R[2][2] * il;
+                if (fmax(z0, z1) + gz <= 0.0) continue;  // no wave of this side heads for the SLM
+                const double x0 = sd * R[0][2] * wmin, x1 = sd * R[0][2] * il;
+                const double y0 = sd * R[1][2] * wmin, y1 = sd * R[1][2] * il;
+                lox = fmin(lox, fmax(fmin(x0, x1) - hxx, -il));
+                hix = fmax(hix, fmin(fmax(x0, x1) + hxx, il));
+                loy = fmin(loy, fmax(fmin(y0, y1) - hyy, -il));
+                hiy = fmax(hiy, fmin(fmax(y0, y1) + hyy, il));
+            }
+        }
+        if (lox <= hix && loy <= hiy) {
+            const int hx = k.nx / 2, hy = k.ny / 2;
+            const int mx0 = (int)fmax(floor(lox * Wx) - 1.0, (double)-hx), mx1 = (int)fmin(ceil(hix * Wx) + 1.0, (double)(hx - 1));
+            const int my0 = (int)fmax(floor(loy * Wy) - 1.0, (double)-hy), my1 = (int)fmin(ceil(hiy * Wy) + 1.0, (double)(hy - 1));
+            if (mx0 <= mx1 && my0 <= my1) {
+                const int tx0 = floor_div_t(mx0, TT), tx1 = floor_div_t(mx1, TT);
+                const int ty0 = floor_div_t(my0, TT), ty1 = floor_div_t(my1, TT);
+                box = make_int2((int)(((uint32_t)tx0 & 0xffffu) | ((uint32_t)tx1 << 16)),
+                                (int)(((uint32_t)ty0 & 0xffffu) | ((uint32_t)ty1 << 16)));
+            }
+        }
+    } else {
+        atomicAdd((unsigned long long *)&counters[CTR_NCULLED], 1ull);
+    }
+    rec[i] = r;
+    rect[i] = box;
+}
+
+// Tile of queue index q: rings of tiles around DC (ring r is the square [-r-1, r]^2 minus
+// [-r, r-1]^2), each walked along its top, right, bottom and left edges.
+static __device__ __forceinline__ void ring_tile(int q, int *tx, int *ty)
+{
+    int r = (int)(sqrtf((float)q) * 0.5f);
+    while (4 * (r + 1) * (r + 1) <= q) ++r;
+    while (4 * r * r > q) --r;
+    int p = q - 4 * r * r;
+    const int side = 2 * r + 2;
+    if (p < side) { *tx = -r - 1 + p; *ty = -r - 1; return; }
+    p -= side;
+    if (p < side - 1) { *tx = r; *ty = -r + p; return; }
+    p -= side - 1;
+    if (p < side - 1) { *tx = r - 1 - p; *ty = r; return; }
+    p -= side - 1;
+    *tx = -r - 1;
+    *ty = r - 1 - p;
+}
+
+// The terms of one staged Gaussian at a lane's frequencies (4-row blocks in `rows`).  Phase
+// delta z (D_c(m) - D_c(m0)) in revolutions: one FP32 product while it stays below 16
+// revolutions (error <= 16 x 2^-24); WIDE (sub-tiles where D_c changes fast, towards the
+// evanescent edge or at fine pitch): z times the double-float delta, its integer part removed
+// inside one fused product so that the fraction keeps full precision.
+template <int C, bool WIDE>
+static __device__ __forceinline__ void tilt_eval(uint32_t rows, float U1, float U2, float V1, float V2, float N1,
+                                                 float N2, float z, float ryf, const float (&u0)[C],
+                                                 const float (&v0)[C], const float (&w0)[C], const float (&bx)[C],
+                                                 const float (&amp)[C], const float (&dyf)[TF],
+                                                 const float (&dD)[TF][C], const float (&dlo)[TF][C][64], int lane,
+                                                 const float (&ikz)[TF][C], float (&acc_re)[TF][C],
+                                                 float (&acc_im)[TF][C])
+{
+#pragma unroll
+    for (int f = 0; f < TF; ++f) {
+        if (!(rows & (1u << f))) continue;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float u = fmaf(U2, dD[f][c], fmaf(U1, dyf[f], u0[c]));
+            const float v = fmaf(V2, dD[f][c], fmaf(V1, dyf[f], v0[c]));
+            const float kw = fmaf(N2, dD[f][c], fmaf(N1, dyf[f], w0[c]));
+            const float E = __builtin_amdgcn_exp2f(-fmaf(u, u, v * v));
+            const float wgt = amp[c] * fabsf(kw) * ikz[f][c] * E;
+            const float t = fmaf(-dyf[f], ryf, bx[c]);
+            float th;
+            if (!WIDE) {
+                th = fmaf(-z, dD[f][c], t);
+            } else {
+                // an integer near the product (any rounding of it will do), then the product
+                // minus that integer in one fused operation: |result| <= 1/2, one rounding
+                const float r = rintf(z * dD[f][c]);
+                const float pr = fmaf(z, dD[f][c], -r);
+                th = fmaf(-z, dlo[f][c][lane], t - pr);
+            }
+            const float sn = __builtin_amdgcn_sinf(th);
+            const float cs = __builtin_amdgcn_cosf(th);
+            acc_re[f][c] = fmaf(wgt, cs, acc_re[f][c]);
+            acc_im[f][c] = fmaf(wgt, sn, acc_im[f][c]);
+        }
+    }
+}
+
+// Per-(sub-tile, Gaussian) entry in LDS: the record's linear forms, then per wavelength the
+// FP64-formed bases.  Layout (floats): U[3] V[3] N[3] z rxf ryf rows | u0[C] v0[C] w0[C] base[C] amp[C].
+__host__ __device__ constexpr int te_floats(int c) { return (13 + 5 * c + 3) & ~3; }
+
+// Wavefronts per SIMD the accumulation is compiled for: 4 (128 VGPRs) for one wavelength;
+// with more the per-lane tables (2 x 4 x C) and accumulators (2 x 4 x C) need more.
+__host__ __device__ constexpr int tilt_waves(int c) { return c <= 1 ? 4 : 2; }
+
+template <int C>
+__global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k, const TRec *__restrict__ rec,
+                                                           const int2 *__restrict__ rect, int64_t n,
+                                                           float2 *__restrict__ spectrum, int n_queue,
+                                                           long long *__restrict__ counters)
+{
+    constexpr int TE = te_floats(C);
+    __shared__ int s_idx[TWG];
+    __shared__ int s_cnt[4];
+    __shared__ int s_tile;
+    __shared__ __align__(16) float s_w[4][64][TE];
+    __shared__ float s_lo[4][TF][C][64];   // low part of each lane's D_c(m) - D_c(m0) (read only near the evanescent edge)
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    const double Wx = k.nx * k.px, Wy = k.ny * k.py;
+    const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int col = lane & 15, row0 = lane >> 4;
+    const float dxf = (float)(col - 8);
+    float dyf[TF];
+#pragma unroll
+    for (int f = 0; f < TF; ++f) dyf[f] = (float)(row0 + 4 * f - 8);
+    long long pairs = 0, cand = 0;
+
+    for (;;) {
+        if (tid == 0) s_tile = (int)atomicAdd((unsigned long long *)&counters[CTR_WORK], 1ull);
+        __syncthreads();
+        const int q = s_tile;
+        __syncthreads();
+        if (q >= n_queue) break;
+        int tx, ty;
+        ring_tile(q, &tx, &ty);
+        if (tx * TT >= hx || (tx + 1) * TT <= -hx || ty * TT >= hy || (ty + 1) * TT <= -hy) continue;
+        // this wavefront's 16 x 16 sub-tile and its per-lane tables
+        const int sx0 = tx * TT + (wave & 1) * 16, sy0 = ty * TT + (wave >> 1) * 16;
+        const int cx = sx0 + 8, cy = sy0 + 8;
+        const int mxp = sx0 + col;
+        double D0[C];
+        float dD[TF][C], ikz[TF][C], dmax[C];
+        {
+            const double ncx = cx / Wx, ncy = cy / Wy;
+            for (int c = 0; c < C; ++c) D0[c] = dprop_t(ncx * ncx + ncy * ncy, k.inv_lambda[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) dmax[c] = 0.0f;
+#pragma unroll
+        for (int f = 0; f < TF; ++f) {
+            const int myp = sy0 + row0 + 4 * f;
+            const double nux = mxp / Wx, nuy = myp / Wy;
+            const double nu2 = nux * nux + nuy * nuy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double il = k.inv_lambda[c];
+                const double w2 = il * il - nu2;
+                if (w2 > 0.0) {
+                    const double kz = sqrt(w2);
+                    const double d = -nu2 / (il + kz) - D0[c];
+                    dD[f][c] = (float)d;
+                    s_lo[wave][f][c][lane] = (float)(d - (double)dD[f][c]);
+                    ikz[f][c] = (float)(1.0 / kz);
+                } else {
+                    dD[f][c] = 0.0f;   // evanescent: the term vanishes (1/k_z taken as 0)
+                    s_lo[wave][f][c][lane] = 0.0f;
+                    ikz[f][c] = 0.0f;
+                }
+                dmax[c] = fmaxf(dmax[c], fabsf(dD[f][c]));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            for (int o = 32; o >= 1; o >>= 1) dmax[c] = fmaxf(dmax[c], __shfl_xor(dmax[c], o));
+        float dmax_all = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) dmax_all = fmaxf(dmax_all, dmax[c]);
+        float acc_re[TF][C], acc_im[TF][C];
+#pragma unroll
+        for (int f = 0; f < TF; ++f)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc_re[f][c] = acc_im[f][c] = 0.0f;
+        // grid clipping of the sub-tile's rows (for the block masks)
+        const int rlo = max(sy0, -hy), rhi = min(sy0 + 15, hy - 1);
+        const bool wave_live = (max(sx0, -hx) <= min(sx0 + 15, hx - 1)) && (rlo <= rhi);
+
+        for (int64_t base = 0; base < n; base += TWG) {
+            const int64_t gi = base + tid;
+            bool pred = false;
+            if (gi < n) {
+                const int2 b = rect[gi];
+                const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
+                const int ty0 = (int)(int16_t)(b.y & 0xffff), ty1 = b.y >> 16;
+                pred = tx >= tx0 && tx <= tx1 && ty >= ty0 && ty <= ty1;
+            }
+            const uint64_t bal = __ballot(pred);
+            if (lane == 0) s_cnt[wave] = __popcll(bal);
+            __syncthreads();
+            int off = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int cw = s_cnt[w];
+                off += (w < wave) ? cw : 0;
+                total += cw;
+            }
+            if (pred) s_idx[off + __popcll(bal & lt)] = (int)gi;
+            __syncthreads();
+            if (tid == 0) cand += total;
+            if (wave_live) {
+                for (int j0 = 0; j0 < total; j0 += 64) {
+                    // each lane forms the entry of one staged Gaussian in its own slot
+                    const int j = j0 + lane;
+                    uint32_t rows = 0;
+                    if (j < total) {
+                        const TRec &r = rec[s_idx[j]];
+                        const float4 *src = reinterpret_cast<const float4 *>(&r);
+                        const float4 a0 = src[0], a1 = src[1], a2 = src[2];
+                        const float U0 = a0.x, U1 = a0.y, U2 = a0.z, V0 = a0.w, V1 = a1.x, V2 = a1.y;
+                        const float N0 = a1.z, N1 = a1.w, N2 = a2.x, z = a2.y;
+                        float *e = &s_w[wave][lane][0];
+                        // per wavelength: bases at the sub-tile centre (FP64), then the bounds of
+                        // u, v over each 4-row block of the sub-tile
+                        const double ramp_rev =
+                            (double)((uint32_t)cx * __float_as_uint(a2.z) + (uint32_t)cy * __float_as_uint(a2.w)) *
+                            (1.0 / 4294967296.0);
+                        const float ez0 = fabsf(U0) * 8.0f + fabsf(U1) * 1.5f, fz0 = fabsf(V0) * 8.0f + fabsf(V1) * 1.5f;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            const double kz0 = k.inv_lambda[c] + D0[c];
+                            const float u0 = (float)((double)U0 * cx + (double)U1 * cy + (double)U2 * kz0);
+                            const float v0 = (float)((double)V0 * cx + (double)V1 * cy + (double)V2 * kz0);
+                            const float kap = r.kappa[c];
+                            float bs;
+                            if (k.phase_mode == 1) {
+                                const float v = kap - ((float)cx * r.rxf + (float)cy * r.ryf) - z * (float)D0[c];
+                                bs = v - floorf(v);
+                            } else {
+                                bs = (float)frac_t((double)kap - ramp_rev - (double)z * D0[c]);
+                            }
+                            e[13 + c] = u0;
+                            e[13 + C + c] = v0;
+                            e[13 + 2 * C + c] = (float)((double)N0 * cx + (double)N1 * cy + (double)N2 * kz0);
+                            e[13 + 3 * C + c] = bs;
+                            e[13 + 4 * C + c] = r.amp[c];
+                            const float eu = fmaf(fabsf(U2), dmax[c], ez0), ev = fmaf(fabsf(V2), dmax[c], fz0);
+#pragma unroll
+                            for (int f = 0; f < TF; ++f) {
+                                const int b0 = sy0 + 4 * f;
+                                if (b0 + 3 < rlo || b0 > rhi) continue;   // block outside the grid
+                                const float dyc = (float)(4 * f) - 6.5f;
+                                const float mu = fmaxf(fabsf(fmaf(U1, dyc, u0)) - eu, 0.0f);
+                                const float mv = fmaxf(fabsf(fmaf(V1, dyc, v0)) - ev, 0.0f);
+                                if (fmaf(mu, mu, mv * mv) <= lim) rows |= 1u << f;
+                            }
+                        }
+                        if (rows) {
+                            reinterpret_cast<float4 *>(e)[0] = a0;
+                            reinterpret_cast<float4 *>(e)[1] = a1;
+                            reinterpret_cast<float4 *>(e)[2] = make_float4(N2, z, r.rxf, r.ryf);
+                            e[12] = __uint_as_float(rows);
+                            pairs += __popc(rows) * 64;
+                        }
+                    }
+                    uint64_t live = __ballot(rows != 0);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    while (live) {
+                        const int ei = __builtin_ctzll(live);
+                        live &= live - 1;
+                        const float *w = &s_w[wave][ei][0];
+                        const float U0 = w[0], U1 = w[1], U2 = w[2], V0 = w[3], V1 = w[4], V2 = w[5];
+                        const float N0 = w[6], N1 = w[7], N2 = w[8], z = w[9], rxf = w[10], ryf = w[11];
+                        const uint32_t rows = __builtin_amdgcn_readfirstlane(__float_as_uint(w[12]));
+                        const float lux = U0 * dxf, lvx = V0 * dxf, lwx = N0 * dxf;
+                        float u0[C], v0[C], w0[C], bx[C], amp[C];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            u0[c] = w[13 + c] + lux;
+                            v0[c] = w[13 + C + c] + lvx;
+                            w0[c] = w[13 + 2 * C + c] + lwx;
+                            bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, w[13 + 3 * C + c]));
+                            amp[c] = w[13 + 4 * C + c];
+                        }
+                        const bool wide = fabsf(z) * dmax_all > 16.0f;
+                        if (!wide)
+                            tilt_eval<C, false>(rows, U1, U2, V1, V2, N1, N2, z, ryf, u0, v0, w0, bx, amp, dyf, dD, s_lo[wave], lane,
+                                                ikz, acc_re, acc_im);
+                        else
+                            tilt_eval<C, true>(rows, U1, U2, V1, V2, N1, N2, z, ryf, u0, v0, w0, bx, amp, dyf, dD, s_lo[wave], lane,
+                                               ikz, acc_re, acc_im);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __syncthreads();
+        }
+        // every frequency of the tile is written once (zeros where no Gaussian reaches)
+#pragma unroll
+        for (int f = 0; f < TF; ++f) {
+            const int myp = sy0 + row0 + 4 * f;
+            if (mxp >= -hx && mxp < hx && myp >= -hy && myp < hy) {
+                const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    spectrum[((int64_t)c * k.ny + my) * k.nx + mx] = make_float2(acc_re[f][c], acc_im[f][c]);
+            }
+        }
+    }
+    pairs = wave_sum_i64(pairs);
+    if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
+    if (tid == 0 && cand) atomicAdd((unsigned long long *)&counters[CTR_CAND], (unsigned long long)cand);
+}
+
+hipError_t launch_tilt_records(const TView &g, const Consts &k, TRec *rec, int2 *rect, long long *counters,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tilt_zero, dim3(1), dim3(64), 0, s, counters);
+    if (g.n > 0)
+        hipLaunchKernelGGL(k_tilt_records, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, k, rec, rect,
+                           counters);
+    return hipGetLastError();
+}
+
+// Queue length: the rings around DC that cover the grid's tiles.
+static int tilt_queue_len(int nx, int ny)
+{
+    const int hx = nx / 2, hy = ny / 2;
+    const int txmax = (hx - 1) / TT, txmin = -((hx + TT - 1) / TT), tymax = (hy - 1) / TT, tymin = -((hy + TT - 1) / TT);
+    const int r = std::max(std::max(txmax, -1 - txmin), std::max(tymax, -1 - tymin));
+    return 4 * (r + 1) * (r + 1);
+}
+
+template <int C>
+static const void *tilt_kernel() { return (const void *)k_tilt_accumulate<C>; }
+
+hipError_t launch_tilt_accumulate(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, float2 *spectrum,
+                                  long long *counters, int n_cu, hipStream_t s)
+{
+    const void *kp = nullptr;
+    switch (k.C) {
+    case 1: kp = tilt_kernel<1>(); break;
+    case 2: kp = tilt_kernel<2>(); break;
+    case 3: kp = tilt_kernel<3>(); break;
+    case 4: kp = tilt_kernel<4>(); break;
+    default: return hipErrorInvalidValue;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, TWG, 0) != hipSuccess || nb < 1) nb = 1;
+    const int nq = tilt_queue_len(k.nx, k.ny);
+    const int grid = std::max(1, std::min(n_cu * nb, nq));
+    switch (k.C) {
+    case 1: hipLaunchKernelGGL(k_tilt_accumulate<1>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
+    case 2: hipLaunchKernelGGL(k_tilt_accumulate<2>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
+    case 3: hipLaunchKernelGGL(k_tilt_accumulate<3>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
+    default: hipLaunchKernelGGL(k_tilt_accumulate<4>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gws

@@ -21,7 +21,7 @@ def declared_symbols():
 
 def test_header_compiles_as_c_and_cxx(tmp_path):
     src = tmp_path / "t.c"
-    src.write_text('#include "gws.h"\nint main(void){gws_problem p; gws_stats s; (void)p; (void)s; return GWS_ABI_VERSION == 3 ? 0 : 1;}\n')
+    src.write_text('#include "gws.h"\nint main(void){gws_problem p; gws_stats s; (void)p; (void)s; return GWS_ABI_VERSION == 4 ? 0 : 1;}\n')
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)])
     subprocess.check_call(["g++", "-std=c++17", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", "-I",
                            os.path.dirname(HEADER), str(src)])
@@ -66,6 +66,30 @@ def test_holographics_struct_layouts_match_the_header(tmp_path):
     assert got == want
 
 
+def test_tilted_struct_layout_and_workspace_on_the_host(tmp_path):
+    src = tmp_path / "szt.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gws.h"\nint main(void){printf("%zu %zu %zu\\n",'
+                   ' sizeof(gws_tilted_gaussians), offsetof(gws_tilted_gaussians, quat_w),'
+                   ' offsetof(gws_tilted_gaussians, phase)); return 0;}\n')
+    exe = tmp_path / "szt"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
+    assert got == [ctypes.sizeof(gws._TiltedGaussians), gws._TiltedGaussians.quat_w.offset,
+                   gws._TiltedGaussians.phase.offset]
+    lib = gws.load_library()
+    prob = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9))._c()
+    sz, sz2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.gws_workspace_size_tilted(None, ctypes.byref(prob), 1000, ctypes.byref(sz)) == 0
+    assert lib.gws_workspace_size_tilted(None, ctypes.byref(prob), 100000, ctypes.byref(sz2)) == 0
+    spec = 3 * 1920 * 1080 * 8
+    assert spec + 1000 * 104 <= sz.value < spec + 1000 * 104 + 4096
+    assert sz2.value - sz.value >= 99000 * 104 - 512   # each area rounded to 256 bytes
+    assert lib.gws_workspace_size_tilted(None, ctypes.byref(prob), -1, ctypes.byref(sz)) == -1
+    bad = gws.Problem(1921, 1080)._c()
+    assert lib.gws_workspace_size_tilted(None, ctypes.byref(bad), 10, ctypes.byref(sz)) != 0
+    assert lib.gws_forward_tilted(None, ctypes.byref(prob), None, None, None, 0, None) == -1
+
+
 def test_holographics_validates_on_the_host():
     lib = gws.load_library()
     v = gws._View()
@@ -83,7 +107,7 @@ def _check(prob):
 
 def test_problem_validation_codes():
     lib = gws.load_library()
-    assert lib.gws_abi_version() == 3
+    assert lib.gws_abi_version() == 4
     ok = gws.Problem(1920, 1080, lambdas=(638e-9, 520e-9, 450e-9))
     assert _check(ok) == 0
     assert _check(gws.Problem(1921, 1080)) == -2          # odd

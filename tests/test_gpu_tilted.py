@@ -1,0 +1,168 @@
+"""Tilted Gaussians (Sec. 4.1, Eq. 8-10) on the GPU against the FP64 oracle (oracle/tilted.py):
+field and spectrum on small grids (one to three wavelengths, ragged tile edges, tilts of a few
+degrees at the workloads' 8 um pitch, and 20-28 degree tilts on fine grids whose band reaches
+the evanescent edge), edge cases (no Gaussians, culled ones, a flipped description of the same
+disk, a rotation about z alone against the in-plane path), determinism, and the 100k-Gaussian
+1080 x 1920 x 3 workload on sampled frequencies."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import gwsgen
+import oracle
+import oracle.tilted as otl
+from gwsgen import Grid
+from gpu_util import dft_ready, problem, rel_l2, scene_to_torch, stratified_freqs, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2505_06582_amd as gws
+    assert torch.cuda.is_available()
+    return gws.context(0)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+CASES = [
+    # (nx, ny, pitch, lambdas, n, seed, sigma_px, tilt_max_deg)
+    (96, 80, 8e-6, gwsgen.RGB, 200, 901, (2.0, 20.0), 2.0),
+    (160, 90, 8e-6, gwsgen.RGB, 300, 902, (2.0, 20.0), 2.0),
+    (48, 40, 8e-6, (520e-9,), 60, 903, (1.0, 6.0), 3.0),
+    (128, 96, 1e-6, (520e-9, 450e-9), 120, 904, (1.0, 4.0), 25.0),
+    (64, 72, 0.25e-6, (633e-9,), 80, 905, (2.0, 6.0), 28.0),   # band past 1/lambda: evanescent corners
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=["%dx%d-%dl-t%g" % (c[0], c[1], len(c[3]), c[7]) for c in CASES])
+def test_tilted_forward_matches_oracle(ctx, case):
+    nx, ny, pitch, lams, n, seed, sig, tilt = case
+    grid = Grid(nx, ny, pitch, pitch, lams)
+    scene = gwsgen.make_tilted_scene(n, grid, seed, depth_range=(-10e-3, 10e-3), sigma_px=sig, tilt_max_deg=tilt)
+    u, s = ctx.forward_tilted(problem(grid), scene_to_torch(scene), want_spectrum=True)
+    U = otl.spectrum(scene, grid)
+    es = rel_l2(to_numpy(s), dft_ready(U, grid))
+    eu = rel_l2(to_numpy(u), oracle.field_from_spectrum(U, grid))
+    st = ctx.stats()
+    log("tilted %dx%d pitch %g C=%d tilt<=%g: spectrum %.3e field %.3e (pairs %d, staged %d)"
+        % (nx, ny, pitch, len(lams), tilt, es, eu, st["n_pairs_evaluated"], st["n_candidates"]))
+    assert es < TOL and eu < TOL
+
+
+def test_tilted_split_bf16_transform(ctx):
+    import paper_2505_06582_amd as gws
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_tilted_scene(150, grid, 906, depth_range=(-10e-3, 10e-3))
+    u = to_numpy(ctx.forward_tilted(problem(grid, xform=gws.XFORM_DFT_BF16X3), scene_to_torch(scene)))
+    e = rel_l2(u, otl.forward(scene, grid))
+    log("tilted split-bf16 transform: %.3e" % e)
+    assert e < 1e-4
+
+
+def test_tilted_empty_and_culled(ctx):
+    import torch
+    grid = Grid(64, 48, 8e-6, 8e-6, gwsgen.RGB)
+    sc = gwsgen.make_tilted_scene(12, grid, 907)
+    # no Gaussians: a zero field
+    empty = {k: (v[:, :0] if k == "amplitude" else v[:0]) for k, v in scene_to_torch(sc).items()}
+    u = ctx.forward_tilted(problem(grid), empty)
+    assert torch.count_nonzero(u).item() == 0
+    # every Gaussian invalid in a different way: all culled, zero field, counted
+    bad = sc.copy()
+    bad.opacity[0] = 0.0
+    bad.scale_u[1] = 0.0
+    bad.scale_v[2] = -1e-5
+    bad.quat_w[3] = bad.quat_x[3] = bad.quat_y[3] = bad.quat_z[3] = 0.0
+    bad.mean_x[4] = np.nan
+    bad.amplitude[:, 5] = 0.0
+    bad.phase[6] = np.inf
+    bad.depth[7] = np.nan
+    bad.quat_y[8] = np.inf
+    bad.amplitude[1, 9] = np.nan
+    bad.scale_v[10] = np.nan
+    bad.opacity[11] = np.nan
+    u = ctx.forward_tilted(problem(grid), scene_to_torch(bad))
+    assert torch.count_nonzero(u).item() == 0
+    assert ctx.stats()["n_culled"] == 12
+    # culled Gaussians among valid ones change nothing
+    keep = np.arange(12) % 3 == 0
+    mix = sc.copy()
+    for i in np.flatnonzero(~keep):
+        mix.opacity[i] = 0.0
+    a = to_numpy(ctx.forward_tilted(problem(grid), scene_to_torch(mix)))
+    b = to_numpy(ctx.forward_tilted(problem(grid), scene_to_torch(sc.subset(np.flatnonzero(keep)))))
+    assert np.array_equal(a, b)
+
+
+def test_tilted_flipped_description_and_determinism(ctx):
+    grid = Grid(96, 80, 2e-6, 2e-6, (520e-9, 450e-9))
+    sc = gwsgen.make_tilted_scene(100, grid, 908, sigma_px=(1.0, 5.0), tilt_max_deg=20.0)
+    fl = sc.copy()
+    w, x, y, z = sc.quat_w.copy(), sc.quat_x.copy(), sc.quat_y.copy(), sc.quat_z.copy()
+    fl.quat_w, fl.quat_x, fl.quat_y, fl.quat_z = -x, w, z, -y   # R -> R diag(1, -1, -1)
+    g = scene_to_torch(sc)
+    a = to_numpy(ctx.forward_tilted(problem(grid), g))
+    a2 = to_numpy(ctx.forward_tilted(problem(grid), g))
+    b = to_numpy(ctx.forward_tilted(problem(grid), scene_to_torch(fl)))
+    assert np.array_equal(a, a2)
+    e = rel_l2(b, a)
+    log("tilted flipped description: %.3e" % e)
+    assert e < 2e-6
+
+
+def test_rotation_about_z_matches_in_plane_path(ctx):
+    grid = Grid(160, 90, 8e-6, 8e-6, gwsgen.RGB)
+    sc = gwsgen.make_tilted_scene(300, grid, 909, depth_range=(-10e-3, 10e-3), tilt_max_deg=0.0)
+    # the in-plane Gaussians with Sigma = R S^2 R^T for the same float32 scales and rotation
+    R = np.stack([oracle.holographics.quat_to_matrix([sc.quat_w[i], sc.quat_x[i], sc.quat_y[i], sc.quat_z[i]])
+                  for i in range(sc.n)])
+    su, sv = sc.scale_u.astype(np.float64), sc.scale_v.astype(np.float64)
+    cxx = R[:, 0, 0] ** 2 * su ** 2 + R[:, 0, 1] ** 2 * sv ** 2
+    cxy = R[:, 0, 0] * R[:, 1, 0] * su ** 2 + R[:, 0, 1] * R[:, 1, 1] * sv ** 2
+    cyy = R[:, 1, 0] ** 2 * su ** 2 + R[:, 1, 1] ** 2 * sv ** 2
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    ip = gwsgen.Scene(mean_x=sc.mean_x, mean_y=sc.mean_y, depth=sc.depth, cov_xx=f(cxx), cov_xy=f(cxy),
+                      cov_yy=f(cyy), opacity=sc.opacity, amplitude=sc.amplitude, phase=sc.phase)
+    a = to_numpy(ctx.forward_tilted(problem(grid), scene_to_torch(sc)))
+    b = to_numpy(ctx.forward(problem(grid), scene_to_torch(ip)))
+    e = rel_l2(a, b)
+    log("tilted path with tilt 0 vs in-plane path: %.3e" % e)
+    assert e < 1e-5
+
+
+def test_tilted_refuses_exact_blend_and_reference_wave(ctx):
+    import paper_2505_06582_amd as gws
+    grid = Grid(64, 48, 8e-6, 8e-6, (520e-9,))
+    g = scene_to_torch(gwsgen.make_tilted_scene(4, grid, 910))
+    with pytest.raises(gws.GwsError):
+        ctx.forward_tilted(problem(grid, blend=gws.BLEND_EXACT), g)
+    with pytest.raises(gws.GwsError):
+        ctx.forward_tilted(problem(dataclasses.replace(grid, ref_nu=(100.0, 0.0))), g)
+
+
+def test_tilted_workload_100k_sampled(ctx):
+    """The bench's tilted workload (100k Gaussians, tilts up to 2 degrees, 1080 x 1920 x 3) in the
+    launch configuration the bench times, on frequencies sampled by radius band."""
+    nx, ny = 1920, 1080
+    grid = Grid(nx, ny, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_tilted_scene(100_000, grid, 1005, depth_range=(-10e-3, 10e-3), tilt_max_deg=2.0)
+    u, s = ctx.forward_tilted(problem(grid), scene_to_torch(scene), want_spectrum=True)
+    mx, my, band, w = stratified_freqs(grid, 120, 911)
+    log("tilted 100k: oracle at %d sampled frequencies" % mx.size)
+    U = otl.spectrum(scene, grid, mx, my)
+    sxf = oracle.signed_freq_index(nx)[mx]
+    syf = oracle.signed_freq_index(ny)[my]
+    ref = U * np.where((sxf + syf) % 2 == 0, 1.0, -1.0) / (nx * ny * grid.px * grid.py)
+    got = to_numpy(s)[:, my, mx]
+    e = rel_l2(got, ref)
+    log("tilted 100k sampled spectrum: rel L2 %.3e" % e)
+    assert e < TOL
+    assert np.all(np.isfinite(to_numpy(u)))
