@@ -733,7 +733,7 @@ def bench_tilted(args):
     stage = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
     C = grid.n_lambda
     triples = tilted_support_triples(scene, grid)
-    evaluated = float(st["n_pairs_evaluated"]) * C
+    evaluated = float(st["n_pairs_evaluated"])   # (Gaussian, frequency, wavelength) triples
     t_acc = stage["accumulate"] * 1e-3
     log("bench tilted100k: %.3f ms per forward; stages %s; support triples %.4g, evaluated %.4g"
         % (ms, {k: round(v, 4) for k, v in stage.items()}, triples, evaluated))

@@ -146,7 +146,9 @@ typedef struct gws_stats {
     int64_t n_items;          /* accumulation work items launched */
     int64_t chunk;            /* candidate Gaussians per work item */
     int64_t n_pairs_evaluated; /* (Gaussian, frequency) pairs evaluated: accepted Gaussians x the
-                                  frequencies of each wavefront sub-tile they were tested on */
+                                  frequencies of each wavefront sub-tile they were tested on;
+                                  gws_forward_tilted counts (Gaussian, frequency, wavelength)
+                                  triples (its exponent depends on the wavelength) */
     int64_t n_candidates;     /* (tile, Gaussian) pairs tested */
     int32_t tile_config;      /* tiling used */
     int32_t graph_replayed;   /* batched call replayed a captured graph */

@@ -236,8 +236,8 @@ static_assert(sizeof(GRec) == 64, "record must stay 64 B");
 
 // Tilted-Gaussian record (input order), 96 bytes, written by k_tilt_records: the exp2-units
 // linear forms u = U . (m_x, m_y, k_z), v = V . (...) and k_oz = N . (...) (m in index units,
-// k_z in cycles per metre), depth, ramp (as GRec), carrier and amplitude a_c o 2 pi s_u s_v /
-// (px py nx ny).
+// k_z in cycles per metre), depth, ramp (as GRec), carrier and amplitude a_c o 2 pi s_u s_v
+// lambda_c / (px py nx ny).
 struct alignas(16) TRec {
     float U[3], V[3], N[3], z;
     uint32_t rx, ry;

@@ -9,7 +9,8 @@
 // spectrum 2 pi s_u s_v exp(-2 pi^2 (s_u^2 k_ox^2 + s_v^2 k_oy^2)).  The ramp, the carrier and
 // the propagation H(nu, -z) are those of an in-plane Gaussian, so the term of Gaussian i at
 // wavelength c and frequency m (index units) is
-//   A_c |w_c(m)| / k_z,c(m) exp2(-(u_c(m)^2 + v_c(m)^2)) exp(j 2 pi Theta_c(m)),
+//   A_c |w_c(m)| / k_z,c(m) exp2(-(u_c(m)^2 + v_c(m)^2)) exp(j 2 pi Theta_c(m))
+//     = (A_c lambda_c) |w_c(m)| exp2(log2(1 / (k_z,c lambda_c)) - u_c^2 - v_c^2) exp(j 2 pi Theta_c),
 //   u_c = U . (m_x, m_y, k_z,c),  v_c = V . (...),  w_c = N . (...)  (= k_oz, 1/m),
 // with U = sqrt(2 pi^2 log2 e) s_u (R11 / W, R21 / H, R31), V likewise from column 2 and s_v,
 // N = (R13 / W, R23 / H, R33), W = nx px, H = ny py, and Theta_c as in the in-plane kernel.
@@ -106,7 +107,8 @@ __global__ void __launch_bounds__(256) k_tilt_records(TView g, Consts k, TRec *_
         const double phi_rev = frac_t((double)ph * 0.15915494309189535);
         for (int c = 0; c < 4; ++c) {
             r.kappa[c] = c < k.C ? (float)frac_t(phi_rev - (double)z * k.inv_lambda[c]) : 0.0f;
-            r.amp[c] = c < k.C ? (float)((double)g.amplitude[(int64_t)c * g.n + i] * (double)o * norm) : 0.0f;
+            r.amp[c] = c < k.C ? (float)((double)g.amplitude[(int64_t)c * g.n + i] * (double)o * norm * k.lambda[c])
+                               : 0.0f;
         }
         // Bounding box of the eps-support u^2 + v^2 <= tau2: in the disk frame an ellipse of
         // semi-axes A = sqrt(tau2 / K2) / s_u, B = .../ s_v in (k_ox, k_oy); on the sphere
@@ -171,7 +173,8 @@ static __device__ __forceinline__ void ring_tile(int q, int *tx, int *ty)
     *ty = r - 1 - p;
 }
 
-// The terms of one staged Gaussian at a lane's frequencies (4-row blocks in `rows`).  Phase
+// The terms of one staged Gaussian at a lane's frequencies (bit c * 4 + f of `rows`: wavelength c
+// reaches 4-row block f).  Phase
 // delta z (D_c(m) - D_c(m0)) in revolutions: one FP32 product while it stays below 16
 // revolutions (error <= 16 x 2^-24); WIDE (sub-tiles where D_c changes fast, towards the
 // evanescent edge or at fine pitch): z times the double-float delta, its integer part removed
@@ -182,19 +185,20 @@ static __device__ __forceinline__ void tilt_eval(uint32_t rows, float U1, float 
                                                  const float (&v0)[C], const float (&w0)[C], const float (&bx)[C],
                                                  const float (&amp)[C], const float (&dyf)[TF],
                                                  const float (&dD)[TF][C], const float (&dlo)[TF][C][64], int lane,
-                                                 const float (&ikz)[TF][C], float (&acc_re)[TF][C],
+                                                 const float (&lkz)[TF][C], float (&acc_re)[TF][C],
                                                  float (&acc_im)[TF][C])
 {
 #pragma unroll
     for (int f = 0; f < TF; ++f) {
-        if (!(rows & (1u << f))) continue;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
+            if (!(rows & (1u << (c * TF + f)))) continue;   // this wavelength's support misses the block
             const float u = fmaf(U2, dD[f][c], fmaf(U1, dyf[f], u0[c]));
             const float v = fmaf(V2, dD[f][c], fmaf(V1, dyf[f], v0[c]));
             const float kw = fmaf(N2, dD[f][c], fmaf(N1, dyf[f], w0[c]));
-            const float E = __builtin_amdgcn_exp2f(-fmaf(u, u, v * v));
-            const float wgt = amp[c] * fabsf(kw) * ikz[f][c] * E;
+            // exp2(log2(1 / (k_z lambda)) - u^2 - v^2): 1/k_z folded into the exponent, lambda into amp
+            const float E = __builtin_amdgcn_exp2f(-fmaf(u, u, fmaf(v, v, -lkz[f][c])));
+            const float wgt = amp[c] * fabsf(kw) * E;
             const float t = fmaf(-dyf[f], ryf, bx[c]);
             float th;
             if (!WIDE) {
@@ -218,9 +222,10 @@ static __device__ __forceinline__ void tilt_eval(uint32_t rows, float U1, float 
 // FP64-formed bases.  Layout (floats): U[3] V[3] N[3] z rxf ryf rows | u0[C] v0[C] w0[C] base[C] amp[C].
 __host__ __device__ constexpr int te_floats(int c) { return (13 + 5 * c + 3) & ~3; }
 
-// Wavefronts per SIMD the accumulation is compiled for: 4 (128 VGPRs) for one wavelength;
-// with more the per-lane tables (2 x 4 x C) and accumulators (2 x 4 x C) need more.
-__host__ __device__ constexpr int tilt_waves(int c) { return c <= 1 ? 4 : 2; }
+// Wavefronts per SIMD the accumulation is compiled for: 4 (128 VGPRs) for one wavelength, 3
+// (168) for two or three, 2 for four: the per-lane tables (2 x 4 x C) and accumulators
+// (2 x 4 x C) grow with the wavelengths.
+__host__ __device__ constexpr int tilt_waves(int c) { return c <= 1 ? 4 : (c <= 3 ? 3 : 2); }
 
 template <int C>
 __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k, const TRec *__restrict__ rec,
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
         const int cx = sx0 + 8, cy = sy0 + 8;
         const int mxp = sx0 + col;
         double D0[C];
-        float dD[TF][C], ikz[TF][C], dmax[C];
+        float dD[TF][C], lkz[TF][C], dmax[C];
         {
             const double ncx = cx / Wx, ncy = cy / Wy;
             for (int c = 0; c < C; ++c) D0[c] = dprop_t(ncx * ncx + ncy * ncy, k.inv_lambda[c]);
@@ -282,11 +287,11 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
                     const double d = -nu2 / (il + kz) - D0[c];
                     dD[f][c] = (float)d;
                     s_lo[wave][f][c][lane] = (float)(d - (double)dD[f][c]);
-                    ikz[f][c] = (float)(1.0 / kz);
+                    lkz[f][c] = (float)log2(il / kz);
                 } else {
                     dD[f][c] = 0.0f;   // evanescent: the term vanishes (1/k_z taken as 0)
                     s_lo[wave][f][c][lane] = 0.0f;
-                    ikz[f][c] = 0.0f;
+                    lkz[f][c] = -1000.0f;   // exp2 underflows to 0
                 }
                 dmax[c] = fmaxf(dmax[c], fabsf(dD[f][c]));
             }
@@ -372,7 +377,7 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
                                 const float dyc = (float)(4 * f) - 6.5f;
                                 const float mu = fmaxf(fabsf(fmaf(U1, dyc, u0)) - eu, 0.0f);
                                 const float mv = fmaxf(fabsf(fmaf(V1, dyc, v0)) - ev, 0.0f);
-                                if (fmaf(mu, mu, mv * mv) <= lim) rows |= 1u << f;
+                                if (fmaf(mu, mu, mv * mv) <= lim) rows |= 1u << (c * TF + f);
                             }
                         }
                         if (rows) {
@@ -380,7 +385,7 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
                             reinterpret_cast<float4 *>(e)[1] = a1;
                             reinterpret_cast<float4 *>(e)[2] = make_float4(N2, z, r.rxf, r.ryf);
                             e[12] = __uint_as_float(rows);
-                            pairs += __popc(rows) * 64;
+                            pairs += __popc(rows) * 64;   // (Gaussian, frequency, wavelength) triples
                         }
                     }
                     uint64_t live = __ballot(rows != 0);
@@ -407,10 +412,10 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
                         const bool wide = fabsf(z) * dmax_all > 16.0f;
                         if (!wide)
                             tilt_eval<C, false>(rows, U1, U2, V1, V2, N1, N2, z, ryf, u0, v0, w0, bx, amp, dyf, dD, s_lo[wave], lane,
-                                                ikz, acc_re, acc_im);
+                                                lkz, acc_re, acc_im);
                         else
                             tilt_eval<C, true>(rows, U1, U2, V1, V2, N1, N2, z, ryf, u0, v0, w0, bx, amp, dyf, dD, s_lo[wave], lane,
-                                               ikz, acc_re, acc_im);
+                                               lkz, acc_re, acc_im);
                     }
                     __builtin_amdgcn_wave_barrier();
                 }
