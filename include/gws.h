@@ -260,7 +260,9 @@ gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *problem, const gw
  * (about 8 MB per 64 Gaussians at 1080 x 1920), then the batches run back to front,
  * recomputing the masked wavefronts, the map within the batch and a back-to-front
  * accumulator instead of storing or dividing them; the 1/255 decision is held fixed (its
- * derivative is taken as zero). */
+ * derivative is taken as zero).  The order-invariant adjoint takes the depth gradient for at
+ * most three wavelengths: n_lambda = 4 with grads->depth non-NULL returns GWS_ERR_UNSUPPORTED
+ * (pass depth = NULL to skip it; every other gradient is available at four). */
 gws_status gws_backward(gws_ctx *ctx, const gws_problem *problem, const gws_gaussians *g,
                         const void *grad_field, const gws_grads *grads,
                         void *workspace, size_t workspace_bytes, void *stream);

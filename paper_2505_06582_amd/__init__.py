@@ -668,6 +668,10 @@ class GaussianWaveSplat:
                     g = dict(mean_x=mean_x, mean_y=mean_y, depth=depth, cov_xx=cov_xx, cov_xy=cov_xy, cov_yy=cov_yy,
                              opacity=opacity, amplitude=amplitude, phase=phase)
                     g = {k: v.detach().contiguous() for k, v in g.items()}
+                    if prob.n_lambda > 3 and prob.blend == BLEND_OIT and fctx.needs_input_grad[3]:
+                        # refused by the library's backward: say so now, not at loss.backward()
+                        raise ValueError("the order-invariant adjoint takes the depth gradient for at most 3 "
+                                         "wavelengths; detach depth or use fewer wavelengths")
                     fctx.prob = prob
                     fctx.save_for_backward(*[g[k] for k in PARAMS])
                     return context(mean_x.device.index or 0).forward(prob, g)

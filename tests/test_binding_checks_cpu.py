@@ -130,3 +130,13 @@ def test_other_entry_points_reject_bad_shapes():
     view = dict(gwsgen.make_camera(1), sh_degree=3)
     with pytest.raises(ValueError, match="opacity_sh"):
         ctx.holographics(view, world)
+
+
+def test_render_refuses_four_wavelength_depth_gradient_at_forward_time():
+    # the library's order-invariant adjoint takes the depth gradient for at most three
+    # wavelengths; render() says so when the graph is built, before any device work
+    import torch
+    prob = gws.Problem(64, 48, lambdas=(638e-9, 520e-9, 450e-9, 405e-9))
+    p = lambda: torch.zeros(3, requires_grad=True)
+    with pytest.raises(ValueError, match="depth gradient"):
+        gws.render(prob, p(), p(), p(), p(), p(), p(), p(), torch.zeros(4, 3, requires_grad=True), p())
