@@ -57,7 +57,10 @@ typedef enum gws_status {
     GWS_ERR_WORKSPACE = -4,   /* workspace null, misaligned (256 B) or smaller than required */
     GWS_ERR_NO_DEVICE = -5,   /* no HIP device, or the device is not gfx950 */
     GWS_ERR_HIP = -6,         /* a HIP runtime call failed; see gws_last_error */
-    GWS_ERR_OOM = -7          /* the context could not allocate a per-shape plan */
+    GWS_ERR_OOM = -7,         /* the context could not allocate a per-shape plan */
+    GWS_STATUS_MAX_ENUM = 0x7fffffff /* not a status: makes the enum a full 32-bit int, so any
+                                        int a caller passes (e.g. to gws_status_string) is a
+                                        valid value of the type */
 } gws_status;
 
 /* Blending model.  OIT is Eq. 12 (transmittance taken as 1).  EXACT is alpha wave
