@@ -96,13 +96,13 @@ typedef struct gws_problem {
                                   (default); 1: the same terms in plain FP32 (precision study
                                   only: loses accuracy for far off-axis, deep Gaussians);
                                   2: same as 0 */
-    int32_t tile_config;       /* 0: the autotuned tiling for this shape if gws_autotune ran,
-                                  else the default; k in 1..gws_tile_config_count(): tiling k,
-                                  a pair (frequencies per lane of the accumulation, of the
-                                  adjoint) from {(4,4),(4,8),(8,8),(8,4),(2,4),(4,2),(2,2),
-                                  (2,8),(8,2)}; the default is 2 = (4,8); the order-invariant
-                                  adjoint's own geometry is fixed, so only the first of the
-                                  pair applies */
+    int32_t tile_config;       /* 0: the autotuned configuration for this shape if gws_autotune
+                                  ran, else the default; k in 1..gws_tile_config_count():
+                                  forward configuration k, a pair (frequencies per lane of the
+                                  accumulation F, tile 32 x 8F; base chunk of candidates per
+                                  work item) from {(4,512),(4,1024),(8,1024),(8,512),(2,1024),
+                                  (4,2048),(2,512),(2,2048),(8,2048)}; the default is 2 =
+                                  (4,1024).  The order-invariant adjoint's geometry is fixed. */
     double ref_nu_x, ref_nu_y; /* transverse frequency (cycles per metre) of the reference plane
                                   wave that illuminates every Gaussian (Sec. 4.1): each
                                   Gaussian's wavefront is multiplied by exp(+j 2 pi nu_r . x), x
@@ -303,8 +303,9 @@ gws_status gws_dft2d(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t batch, int32_
 /* Number of explicit tilings gws_problem.tile_config may name (1..count). */
 int gws_tile_config_count(void);
 
-/* Time every tiling on the device for this problem with n_hint synthetic Gaussians drawn
- * on the device, keep the fastest in the context for problems of this shape, and if
+/* Time every forward configuration (tile_config 1..count: frequencies per lane and base
+ * chunk) on the device for this problem with n_hint synthetic Gaussians drawn on the device,
+ * keep the fastest in the context for problems of this shape and size class, and if
  * cache_path (host string) is non-NULL merge the choice into that JSON file, which later
  * contexts read at gws_create time if GWS_TUNE_CACHE names it.  Synchronises. */
 gws_status gws_autotune(gws_ctx *ctx, const gws_problem *problem, int64_t n_hint, const char *cache_path,

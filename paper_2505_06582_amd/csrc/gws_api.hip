@@ -168,12 +168,16 @@ extern "C" gws_status gws_check_problem(const gws_problem *p)
 
 // Tilings: frequencies per lane (F) of the forward accumulation and of the adjoint.  The
 // work-group tile is 32 x 8F frequencies, the wavefront sub-tile 16 x 4F.
-static const int kTileCfg[][2] = {{4, 4}, {4, 8}, {8, 8}, {8, 4}, {2, 4}, {4, 2}, {2, 2}, {2, 8}, {8, 2}};
+// Forward configurations the autotuner chooses among: (F, frequencies per lane of the
+// accumulation: tile 32 x 8F; base chunk, candidates per work item before the binning grows it
+// to fit the partial-sum budget).  Small chunks split the long DC tiles into more, shorter
+// items (better balance, more partial sums to reduce); large ones the reverse.  The adjoint's
+// geometry is fixed (regions of the F = 8 tiling), so a configuration only shapes the forward.
+static const int kTileCfg[][2] = {{4, 512}, {4, 1024}, {8, 1024}, {8, 512}, {2, 1024},
+                                  {4, 2048}, {2, 512}, {2, 2048}, {8, 2048}};
 static const int kNumTileCfg = (int)(sizeof(kTileCfg) / sizeof(kTileCfg[0]));
-// Untuned default: F = 4 for the accumulation, F = 8 for the adjoint (its cross-lane
-// reductions amortised over twice the rows; row-block culling keeps the evaluated terms
-// those of 16 x 4 blocks); the fastest pair measured on MI355X for 1e5 Gaussians at
-// 1080 x 1920 x 3.
+// Untuned default: F = 4 with 1024-candidate chunks, the fastest measured on MI355X for 1e5
+// Gaussians at 1080 x 1920 x 3.
 static const int kDefaultTileCfg = 2;
 
 extern "C" int gws_tile_config_count(void) { return kNumTileCfg; }
@@ -797,14 +801,14 @@ static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, cons
     {
         StageScope sc(ctx, s, ST_PREP, !noalloc);
         for (int i = 0; i < S; ++i) {
-            const Layout L = make_layout(prob, BL.n[i], F, kTileCfg[cfg - 1][1], noalloc);
+            const Layout L = make_layout(prob, BL.n[i], F, ADJ_F, noalloc);
             const Bufs B = carve(L, base + BL.scene_off[i]);
             uint64_t *keys = nullptr;
             uint32_t *vals = nullptr;
             st = run_prep(ctx, k, scene_view(g, offsets[i], BL.n[i]), L, B, s, &keys, &vals);
             if (st != GWS_OK) return st;
             HIP_CHECK(ctx, launch_bin_forward(*p, B.bucket_hist, B.cum, B.tile_L, B.tile_slots, B.items, L.max_items,
-                                              L.max_slots, B.counters, s));
+                                              L.max_slots, kTileCfg[cfg - 1][1], B.counters, s));
             tab.s[i] = FwdScene{B.rec, B.tile_L, B.items, B.tile_slots, B.partials, spectra + (int64_t)i * CM, B.counters};
             ctrs[i] = B.counters;
         }
@@ -1371,14 +1375,17 @@ extern "C" gws_status gws_dft2d(gws_ctx *ctx, int32_t nx, int32_t ny, int32_t ba
 // Autotuner: time each accumulation tiling and each adjoint tiling on synthetic
 // Gaussians of the requested count, keep the fastest pair for this grid and size class.
 // ---------------------------------------------------------------------------------
-static std::string tune_line(const gws_problem *p, int nb, int cfg, const double *tf, const double *tb)
+static std::string tune_line(const gws_problem *p, int nb, int cfg, const double *tf)
 {
-    char buf[512];
-    snprintf(buf, sizeof(buf),
-             "{\"arch\": \"gfx950\", \"nx\": %d, \"ny\": %d, \"n_lambda\": %d, \"n_bucket\": %d, \"tile_config\": %d, "
-             "\"fwd_ms\": {\"2\": %.4f, \"4\": %.4f, \"8\": %.4f}, \"bwd_ms\": {\"2\": %.4f, \"4\": %.4f, \"8\": %.4f}}",
-             p->nx, p->ny, p->n_lambda, nb, cfg, tf[0], tf[1], tf[2], tb[0], tb[1], tb[2]);
-    return buf;
+    std::string l = "{\"arch\": \"gfx950\", \"nx\": " + std::to_string(p->nx) + ", \"ny\": " + std::to_string(p->ny) +
+                    ", \"n_lambda\": " + std::to_string(p->n_lambda) + ", \"n_bucket\": " + std::to_string(nb) +
+                    ", \"tile_config\": " + std::to_string(cfg) + ", \"fwd_ms\": {";
+    for (int c = 0; c < kNumTileCfg; ++c) {
+        char buf[96];
+        snprintf(buf, sizeof(buf), "%s\"F%d/chunk%d\": %.4f", c ? ", " : "", kTileCfg[c][0], kTileCfg[c][1], tf[c]);
+        l += buf;
+    }
+    return l + "}}";
 }
 
 static bool parse_tune_line(const std::string &l, int *nx, int *ny, int *C, int *nb, int *cfg)
@@ -1467,32 +1474,27 @@ extern "C" gws_status gws_autotune(gws_ctx *ctx, const gws_problem *prob, int64_
         return fail(ctx, GWS_ERR_HIP, "synthetic Gaussians");
     }
     gws_output out{field, nullptr};
-    const int Fs[3] = {2, 4, 8};
-    double tf[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+    double tf[kNumTileCfg];
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const int prof = ctx->profiling;
     ctx->profiling = 0;
     gws_problem q = *prob;
-    for (int d = 0; d < 2 && st == GWS_OK; ++d)
-        for (int j = 0; j < 3 && st == GWS_OK; ++j) {
-            // any tiling whose F for this direction is Fs[j]
-            int cfg = 1;
-            for (int c = 0; c < kNumTileCfg; ++c)
-                if (kTileCfg[c][d] == Fs[j]) { cfg = c + 1; break; }
-            q.tile_config = cfg;
-            for (int rep = 0; rep < 3 && st == GWS_OK; ++rep) {
-                if (rep == 1) (void)hipEventRecord(e0, s);
-                st = d == 0 ? forward_run(ctx, &q, 1, off, &g, &out, ws, ws_bytes, s)
-                            : backward_run(ctx, &q, 1, off, &g, field, &gr, ws, ws_bytes, s);
-            }
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            (d == 0 ? tf : tb)[j] = ms / 2.0;
+    // every forward configuration (the adjoint's geometry does not depend on it): one untimed
+    // call (plan and first-touch), then the mean of two
+    for (int c = 0; c < kNumTileCfg && st == GWS_OK; ++c) {
+        q.tile_config = c + 1;
+        for (int rep = 0; rep < 3 && st == GWS_OK; ++rep) {
+            if (rep == 1) (void)hipEventRecord(e0, s);
+            st = forward_run(ctx, &q, 1, off, &g, &out, ws, ws_bytes, s);
         }
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        tf[c] = ms / 2.0;
+    }
     ctx->profiling = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1500,13 +1502,10 @@ extern "C" gws_status gws_autotune(gws_ctx *ctx, const gws_problem *prob, int64_
     cleanup();
     if (st != GWS_OK) return st;
     if (se != hipSuccess) return fail(ctx, GWS_ERR_HIP, hipGetErrorString(se));
-    const int bf = (int)(std::min_element(tf, tf + 3) - tf), bb = (int)(std::min_element(tb, tb + 3) - tb);
-    int best = kDefaultTileCfg;
-    for (int c = 0; c < kNumTileCfg; ++c)
-        if (kTileCfg[c][0] == Fs[bf] && kTileCfg[c][1] == Fs[bb]) best = c + 1;
+    const int best = (int)(std::min_element(tf, tf + kNumTileCfg) - tf) + 1;
     const int nb = n_bucket(n);
     ctx->tuned[std::make_tuple(prob->nx, prob->ny, C, nb)] = best;
-    if (cache_path) merge_tune_cache(cache_path, prob, nb, tune_line(prob, nb, best, tf, tb));
+    if (cache_path) merge_tune_cache(cache_path, prob, nb, tune_line(prob, nb, best, tf));
     return GWS_OK;
 }
 

@@ -393,7 +393,7 @@ hipError_t launch_records(const GView &g, const Consts &k, const uint64_t *keys,
                           const uint32_t *vals, GRec *rec, int64_t n, const long long *counters,
                           hipStream_t s);
 hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32_t *cum, int32_t *tile_L,
-                              int2 *tile_slots, Item *items, int64_t max_items, int64_t max_slots,
+                              int2 *tile_slots, Item *items, int64_t max_items, int64_t max_slots, int base_chunk,
                               long long *counters, hipStream_t s);
 hipError_t launch_bin_backward(const Plan &p, const uint64_t *keys, BItem *bitems, int2 *chunk_items,
                                int32_t *range_base, int max_ranges, int64_t max_bitems, long long *counters, int64_t n,

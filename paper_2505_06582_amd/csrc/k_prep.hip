@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(1024) k_bin_forward(const int32_t *__restrict_
                                                       const uint32_t *__restrict__ bucket_hist, uint32_t *__restrict__ cum,
                                                       int32_t *__restrict__ tile_L, int2 *__restrict__ tile_slots,
                                                       Item *__restrict__ items,
-                                                      int64_t max_items, int64_t max_slots,
+                                                      int64_t max_items, int64_t max_slots, int base_chunk,
                                                       long long *__restrict__ counters)
 {
     __shared__ uint32_t tmp[1024];
@@ -306,8 +306,8 @@ __global__ void __launch_bounds__(1024) k_bin_forward(const int32_t *__restrict_
     }
     if (threadIdx.x == 0) {
         const unsigned long long S = red[0];
-        // multi-chunk tiles need <= 2 S / CH slots
-        long long ch = 1024;
+        // multi-chunk tiles need <= 2 S / CH slots: the configured base chunk, grown to fit
+        long long ch = base_chunk;
         const long long need = (long long)((2ull * S + (unsigned long long)max_slots - 1) / (unsigned long long)max_slots);
         if (need > ch) ch = (need + 255) / 256 * 256;
         if (ch > (1ll << 30)) ch = 1ll << 30;
@@ -348,11 +348,11 @@ __global__ void __launch_bounds__(1024) k_bin_forward(const int32_t *__restrict_
 }
 
 hipError_t launch_bin_forward(const Plan &p, const uint32_t *bucket_hist, uint32_t *cum, int32_t *tile_L,
-                              int2 *tile_slots, Item *items, int64_t max_items, int64_t max_slots, long long *counters,
-                              hipStream_t s)
+                              int2 *tile_slots, Item *items, int64_t max_items, int64_t max_slots, int base_chunk,
+                              long long *counters, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_forward, dim3(1), dim3(1024), 0, s, p.tile_bucket, p.ntiles, bucket_hist, cum, tile_L,
-                       tile_slots, items, max_items, max_slots, counters);
+                       tile_slots, items, max_items, max_slots, base_chunk, counters);
     return hipGetLastError();
 }
 
