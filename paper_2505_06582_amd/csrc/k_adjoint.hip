@@ -504,7 +504,9 @@ int adjoint_occupancy(int C, int depth)
     return nb;
 }
 
-// Per Gaussian: sum the item partials of its chunk in order (FP64), then the chain rule.
+// Per Gaussian: sum the item partials of its chunk in order (FP64), then the chain rule.  The
+// number of sums is a compile-time constant of the variant, so they stay in registers.
+template <int C, bool DEPTH>
 __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uint32_t *__restrict__ vals,
                                                     const int2 *__restrict__ chunk_items,
                                                     const int32_t *__restrict__ range_base,
@@ -515,26 +517,28 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
     if (s >= n) return;
     const int64_t nvalid = n - counters[CTR_NCULLED];
     const int64_t i = vals[s];
-    const int C = k.C;
     if (s >= nvalid) {
         grads.mean_x[i] = grads.mean_y[i] = 0.0f;
         if (grads.depth) grads.depth[i] = 0.0f;
         grads.cov_xx[i] = grads.cov_xy[i] = grads.cov_yy[i] = 0.0f;
         grads.opacity[i] = grads.phase[i] = 0.0f;
+#pragma unroll
         for (int c = 0; c < C; ++c) grads.amplitude[(int64_t)c * grads.amp_stride + i] = 0.0f;
         return;
     }
-    const int NV = adj_nv(C, k.depth_grad != 0);
+    constexpr int NV = adj_nv(C, DEPTH);
     const int64_t b = s / chunk;
     const int t = (int)(s - b * chunk);
     const int2 ci = chunk_items[b];
     const long long nbitems = counters[CTR_NBITEMS];
-    double acc[3 * GWS_MAX_LAMBDA + 5];
+    double acc[NV];
+#pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     for (int j = 0; j < ci.y; ++j) {
         const int64_t it = (int64_t)range_base[j] + b;  // range j of chunk b
         if (it >= nbitems) break;
         const float *src = bpartials + (it * chunk + t) * NV;
+#pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] += (double)src[v];
     }
     const double PI = 3.14159265358979323846;
@@ -544,12 +548,13 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
     const double fx = 1.0 / (k.nx * k.px), fy = 1.0 / (k.ny * k.py);
     const double K = 2.0 * PI * sqrt(det) / (k.px * k.py * (double)k.nx * (double)k.ny);
     double Sre = 0.0, gz = 0.0, go = 0.0, Sim = 0.0;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
         const double a = g.amplitude[(int64_t)c * g.amp_stride + i];
         const double A = a * o * K;
         const double Pr = acc[c];
         Sre += A * Pr;
-        if (k.depth_grad) {
+        if constexpr (DEPTH) {
             const double Pi = acc[C + 5 + c], Wc = acc[2 * C + 5 + c];
             gz += A * (k.inv_lambda[c] * Pi + Wc);
             Sim += A * Pi;
@@ -558,7 +563,7 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
         grads.amplitude[(int64_t)c * grads.amp_stride + i] = (float)(o * K * Pr);
     }
     // sum_c A_c Im P_c (= sum_m Im rho): from Im P_c with depth, else the extra reduced value
-    if (!k.depth_grad) Sim = acc[C + 5];
+    if constexpr (!DEPTH) Sim = acc[C + 5];
     const double Sfx = acc[C], Sfy = acc[C + 1], Qxx = acc[C + 2], Qxy = acc[C + 3], Qyy = acc[C + 4];
     grads.phase[i] = (float)(-Sim);
     grads.mean_x[i] = (float)(2.0 * PI * fx * Sfx);
@@ -567,7 +572,7 @@ __global__ void __launch_bounds__(256) k_grad_final(GView g, Consts k, const uin
     grads.cov_xx[i] = (float)(syy / (2.0 * det) * Sre - 2.0 * PI * PI * fx * fx * Qxx);
     grads.cov_yy[i] = (float)(sxx / (2.0 * det) * Sre - 2.0 * PI * PI * fy * fy * Qyy);
     grads.cov_xy[i] = (float)(-sxy / det * Sre - 4.0 * PI * PI * fx * fy * Qxy);
-    if (grads.depth) grads.depth[i] = (float)(2.0 * PI * gz);
+    if (DEPTH && grads.depth) grads.depth[i] = (float)(2.0 * PI * gz);
 }
 
 hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *vals, const int2 *chunk_items,
@@ -575,8 +580,19 @@ hipError_t launch_grad_final(const GView &g, const Consts &k, const uint32_t *va
                              const long long *counters, int chunk, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, k, vals, chunk_items,
-                       range_base, bpartials, grads, n, counters, chunk);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define GWS_GF(CC, DD)                                                                                                  \
+    hipLaunchKernelGGL((k_grad_final<CC, DD>), grid, block, 0, s, g, k, vals, chunk_items, range_base, bpartials, grads, \
+                       n, counters, chunk)
+    const bool d = k.depth_grad != 0;
+    switch (k.C) {
+    case 1: if (d) GWS_GF(1, true); else GWS_GF(1, false); break;
+    case 2: if (d) GWS_GF(2, true); else GWS_GF(2, false); break;
+    case 3: if (d) GWS_GF(3, true); else GWS_GF(3, false); break;
+    case 4: if (d) GWS_GF(4, true); else GWS_GF(4, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef GWS_GF
     return hipGetLastError();
 }
 
