@@ -240,9 +240,9 @@ typedef struct gws_tilted_gaussians {
     const float *opacity, *amplitude, *phase;
 } gws_tilted_gaussians;
 
-/* Bytes of workspace gws_forward_tilted needs for n Gaussians (host-only; ctx may be NULL):
- * 104 bytes per Gaussian (record and tile rectangle), the spectrum, and the split-bf16 DFT's
- * planes when problem->xform selects it. */
+/* Bytes of workspace gws_forward_tilted and gws_backward_tilted need for n Gaussians
+ * (host-only; ctx may be NULL): 112 bytes per Gaussian (record, tile rectangle, slot offset),
+ * the spectrum, and the split-bf16 DFT's planes when problem->xform selects it. */
 gws_status gws_workspace_size_tilted(const gws_ctx *ctx, const gws_problem *problem, int64_t n, size_t *bytes);
 
 /* Forward of tilted Gaussians: field (and optionally spectrum) as gws_forward.  Takes the
@@ -254,6 +254,27 @@ gws_status gws_workspace_size_tilted(const gws_ctx *ctx, const gws_problem *prob
  * transform.  No host synchronisation. */
 gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *problem, const gws_tilted_gaussians *g,
                               const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Gradient outputs of gws_backward_tilted: float32 device arrays shaped like the inputs
+ * (amplitude [n_lambda][n]); overwritten, never accumulated.  All are required. */
+typedef struct gws_tilted_grads {
+    float *mean_x, *mean_y, *depth;
+    float *quat_w, *quat_x, *quat_y, *quat_z;
+    float *scale_u, *scale_v;
+    float *opacity, *amplitude, *phase;
+} gws_tilted_grads;
+
+/* Backward of gws_forward_tilted: given grad_field = dL/dRe(u) + j dL/dIm(u) (complex64
+ * [n_lambda][ny][nx]), write dL/d(parameter) for every tilted Gaussian, the quaternion's
+ * gradient taken through its normalisation.  The workspace is the one gws_forward_tilted uses
+ * (gws_workspace_size_tilted).  Recomputes every term; per (Gaussian, frequency tile of 32 x 32
+ * reached by its support rectangle) it stores C + 13 floats of partial sums in a buffer the
+ * context owns and grows (hipMalloc when a call needs more; freed by gws_destroy), so it
+ * synchronises the stream once to read the slot count.  Culled Gaussians, and Gaussians whose
+ * support lies outside the band, get zero gradients.  Bitwise reproducible. */
+gws_status gws_backward_tilted(gws_ctx *ctx, const gws_problem *problem, const gws_tilted_gaussians *g,
+                               const void *grad_field, const gws_tilted_grads *grads, void *workspace,
+                               size_t workspace_bytes, void *stream);
 
 /* Backward: given grad_field = dL/dRe(u) + j dL/dIm(u) (complex64 [n_lambda][ny][nx], the
  * convention torch uses for complex tensors), write dL/d(parameter) for every Gaussian.

@@ -65,6 +65,10 @@ class _TiltedGaussians(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, _fp) for k in TILTED_PARAMS]
 
 
+class _TiltedGrads(ctypes.Structure):
+    _fields_ = [(k, _fp) for k in TILTED_PARAMS]
+
+
 class _Output(ctypes.Structure):
     _fields_ = [("field", _fp), ("spectrum", _fp)]
 
@@ -124,6 +128,10 @@ _SIGNATURES = {
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "gws_forward_tilted": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_TiltedGaussians),
                                           ctypes.POINTER(_Output), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gws_backward_tilted": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem),
+                                           ctypes.POINTER(_TiltedGaussians), ctypes.c_void_p,
+                                           ctypes.POINTER(_TiltedGrads), ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p]),
     "gws_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.POINTER(_Gaussians),
                                     ctypes.c_void_p, ctypes.POINTER(_Grads), ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_void_p]),
@@ -419,6 +427,28 @@ class Context:
         _check(self.lib.gws_forward_tilted(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs), ctypes.byref(o),
                                            ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
         return (field, spec) if want_spectrum else field
+
+    def backward_tilted(self, prob: Problem, g: Dict[str, "object"], grad_field, out=None) -> dict:
+        """Gradients of every tilted-Gaussian parameter (TILTED_PARAMS) given grad_field =
+        dL/dRe u + j dL/dIm u, complex64 (n_lambda, ny, nx)."""
+        torch = _torch()
+        n = check_gaussians(g, prob.n_lambda, TILTED_PARAMS)
+        check_tensor(grad_field, "grad_field", (prob.n_lambda, prob.ny, prob.nx), "complex64")
+        gs = _tilted_struct(g, prob.n_lambda)
+        grads = dict(out) if out is not None else {}
+        for k in TILTED_PARAMS:
+            if grads.get(k) is None:
+                grads[k] = torch.empty_like(g[k])
+            elif n > 0:
+                check_tensor(grads[k], "grad " + k, tuple(g[k].shape), "float32")
+        gr = _TiltedGrads()
+        for k in TILTED_PARAMS:
+            setattr(gr, k, _dptr(grads[k]) if n > 0 else None)
+        ws = self.workspace(self.workspace_size_tilted(prob, n))
+        _check(self.lib.gws_backward_tilted(self.handle, ctypes.byref(prob._c()), ctypes.byref(gs),
+                                            ctypes.c_void_p(_dptr(grad_field)), ctypes.byref(gr),
+                                            ctypes.c_void_p(_dptr(ws)), ws.numel(), self._stream()), self.handle)
+        return grads
 
     def backward(self, prob: Problem, g: Dict[str, "object"], grad_field, want_depth: bool = True, out=None):
         """dL/d(parameter) for every Gaussian, given dL/dRe u + j dL/dIm u."""

@@ -46,6 +46,8 @@ struct gws_ctx {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     void *scratch = nullptr;  // this device's copy of the allocation-free forward's scratch array
+    float *tilt_part = nullptr;  // per-(Gaussian, tile) sums of the tilted adjoint, grown on demand
+    size_t tilt_part_bytes = 0;
 };
 
 static hipEvent_t pool_event(gws_ctx *ctx)
@@ -577,6 +579,7 @@ extern "C" gws_status gws_destroy(gws_ctx *ctx)
         hipEventDestroy(r.b);
     }
     for (auto e : ctx->pool) hipEventDestroy(e);
+    hipFree(ctx->tilt_part);
     hipFree(ctx->d_stats);
     delete ctx;
     return GWS_OK;
@@ -1059,7 +1062,7 @@ extern "C" gws_status gws_forward_noalloc(gws_ctx *ctx, const gws_problem *prob,
 // Tilted Gaussians
 // ---------------------------------------------------------------------------------
 struct TiltLayout {
-    size_t off_rec, off_rect, off_counters, off_spectrum, off_dftws, total;
+    size_t off_rec, off_rect, off_counters, off_spectrum, off_dftws, off_off, off_bsum, total;
 };
 
 static TiltLayout tilt_layout(const gws_problem *p, int64_t n)
@@ -1072,6 +1075,9 @@ static TiltLayout tilt_layout(const gws_problem *p, int64_t n)
     L.off_counters = take(CTR_COUNT * sizeof(long long));
     L.off_spectrum = take((size_t)p->n_lambda * p->nx * p->ny * sizeof(float2));
     L.off_dftws = take(p->xform == GWS_XFORM_DFT_BF16X3 ? dft_bf16x3_workspace(p->nx, p->ny, p->n_lambda) : 0);
+    // the adjoint's slot offsets (n + 1) and the scan's block totals
+    L.off_off = take((size_t)(n + 1) * sizeof(int64_t));
+    L.off_bsum = take((size_t)((n + 1023) / 1024 + 1) * sizeof(int64_t));
     L.total = o;
     return L;
 }
@@ -1141,6 +1147,92 @@ extern "C" gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *prob, 
             HIP_CHECK(ctx, launch_fft2d(*p, k.C, +1, spectrum, (float2 *)out->field, s));
         else
             HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, +1, spectrum, (float2 *)out->field, (void *)(base + L.off_dftws), s));
+    }
+    long long *ctrs[1] = {counters};
+    HIP_CHECK(ctx, launch_sum_counters(ctrs, 1, ctx->d_stats, s));
+    ctx->last_n = g->n;
+    ctx->last_tile_config = 0;
+    return GWS_OK;
+}
+
+static gws_status check_tilted_grads(gws_ctx *ctx, const gws_tilted_grads *gr)
+{
+    if (!gr || !gr->mean_x || !gr->mean_y || !gr->depth || !gr->quat_w || !gr->quat_x || !gr->quat_y || !gr->quat_z ||
+        !gr->scale_u || !gr->scale_v || !gr->opacity || !gr->amplitude || !gr->phase)
+        return fail(ctx, GWS_ERR_INVALID_ARG, "a gradient array is NULL");
+    return GWS_OK;
+}
+
+extern "C" gws_status gws_backward_tilted(gws_ctx *ctx, const gws_problem *prob, const gws_tilted_gaussians *g,
+                                          const void *grad_field, const gws_tilted_grads *grads, void *ws,
+                                          size_t ws_bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, GWS_ERR_INVALID_ARG, "ctx is NULL");
+    gws_status st = gws_check_problem(prob);
+    if (st != GWS_OK) return fail(ctx, st, std::string("problem rejected: ") + gws_status_string(st));
+    st = check_tilted(ctx, prob, g);
+    if (st != GWS_OK) return st;
+    if (g->n == 0) return GWS_OK;
+    if (!grad_field) return fail(ctx, GWS_ERR_INVALID_ARG, "grad_field is NULL");
+    st = check_tilted_grads(ctx, grads);
+    if (st != GWS_OK) return st;
+    const TiltLayout L = tilt_layout(prob, g->n);
+    st = check_ws(ctx, ws, ws_bytes, L.total);
+    if (st != GWS_OK) return st;
+    HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const hipStream_t s = (hipStream_t)stream;
+    Plan *p = nullptr;
+    st = get_plan(ctx, prob->nx, prob->ny, kTileCfg[kDefaultTileCfg - 1][0], &p);
+    if (st != GWS_OK) return st;
+    char *base = (char *)ws;
+    const Consts k = make_consts(prob, 0);  // keep Gaussians that add nothing: their gradients do not vanish
+    TRec *rec = (TRec *)(base + L.off_rec);
+    int2 *rect = (int2 *)(base + L.off_rect);
+    long long *counters = (long long *)(base + L.off_counters);
+    float2 *gspec = (float2 *)(base + L.off_spectrum);
+    int64_t *off = (int64_t *)(base + L.off_off);
+    int64_t *bsum = (int64_t *)(base + L.off_bsum);
+    const TView tv{g->n,       g->mean_x,  g->mean_y,  g->depth,   g->quat_w,    g->quat_x, g->quat_y,
+                   g->quat_z,  g->scale_u, g->scale_v, g->opacity, g->amplitude, g->phase};
+    const TGrads tg{grads->mean_x, grads->mean_y, grads->depth,   grads->quat_w,  grads->quat_x,    grads->quat_y,
+                    grads->quat_z, grads->scale_u, grads->scale_v, grads->opacity, grads->amplitude, grads->phase};
+    ctx->last_graph = 0;
+    {
+        StageScope sc(ctx, s, ST_PREP);
+        HIP_CHECK(ctx, launch_tilt_records(tv, k, rec, rect, counters, s));
+        HIP_CHECK(ctx, launch_tilt_offsets(rect, g->n, off, bsum, s));
+    }
+    {
+        // Gs = forward DFT of the field gradient (adjoint of the unnormalised inverse DFT)
+        StageScope sc(ctx, s, ST_XFORM_FWD);
+        if (prob->xform == GWS_XFORM_FFT_FP32)
+            HIP_CHECK(ctx, launch_fft2d(*p, k.C, -1, (const float2 *)grad_field, gspec, s));
+        else
+            HIP_CHECK(ctx, launch_dft_bf16x3(*p, k.C, -1, (const float2 *)grad_field, gspec,
+                                             (void *)(base + L.off_dftws), s));
+    }
+    // the number of (Gaussian, tile) slots sizes the context's partial-sum buffer: one read-back
+    int64_t nslots = 0;
+    HIP_CHECK(ctx, hipMemcpyAsync(&nslots, off + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(ctx, hipStreamSynchronize(s));
+    const size_t need = (size_t)std::max<int64_t>(nslots, 1) * tilt_slot_floats(k.C) * sizeof(float);
+    if (need > ctx->tilt_part_bytes) {
+        HIP_CHECK(ctx, hipFree(ctx->tilt_part));
+        ctx->tilt_part = nullptr;
+        ctx->tilt_part_bytes = 0;
+        if (hipMalloc(&ctx->tilt_part, need) != hipSuccess) {
+            ctx->tilt_part = nullptr;
+            return fail(ctx, GWS_ERR_OOM, "tilted adjoint: " + std::to_string(need) + " bytes of partial sums");
+        }
+        ctx->tilt_part_bytes = need;
+    }
+    {
+        StageScope sc(ctx, s, ST_ADJOINT);
+        HIP_CHECK(ctx, launch_tilt_adjoint(k, rec, rect, g->n, gspec, off, ctx->tilt_part, counters, ctx->n_cu, s));
+    }
+    {
+        StageScope sc(ctx, s, ST_FINAL);
+        HIP_CHECK(ctx, launch_tilt_grad_final(tv, k, rect, off, ctx->tilt_part, tg, s));
     }
     long long *ctrs[1] = {counters};
     HIP_CHECK(ctx, launch_sum_counters(ctrs, 1, ctx->d_stats, s));

@@ -254,6 +254,12 @@ struct TView {
         *amplitude, *phase;
 };
 
+// Gradient outputs of the tilted adjoint (device arrays, amplitude [C][n]).
+struct TGrads {
+    float *mean_x, *mean_y, *depth, *quat_w, *quat_x, *quat_y, *quat_z, *scale_u, *scale_v, *opacity, *amplitude,
+        *phase;
+};
+
 // Forward work item: candidates [chunk*CH, min((chunk+1)*CH, L)) of sorted tile k.
 struct Item {
     int32_t tile;    // index into the rho-sorted tile list
@@ -510,6 +516,12 @@ hipError_t launch_tilt_records(const TView &g, const Consts &k, TRec *rec, int2 
                                hipStream_t s);
 hipError_t launch_tilt_accumulate(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, float2 *spectrum,
                                   long long *counters, int n_cu, hipStream_t s);
+hipError_t launch_tilt_offsets(const int2 *rect, int64_t n, int64_t *off, int64_t *bsum, hipStream_t s);
+hipError_t launch_tilt_adjoint(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, const float2 *gspec,
+                               const int64_t *off, float *part, long long *counters, int n_cu, hipStream_t s);
+hipError_t launch_tilt_grad_final(const TView &g, const Consts &k, const int2 *rect, const int64_t *off,
+                                  const float *part, const TGrads &gr, hipStream_t s);
+int tilt_slot_floats(int C);  // floats per (Gaussian, tile) slot of the tilted adjoint
 hipError_t build_dft_mats(Plan &p);
 void free_dft_mats(Plan &p);
 

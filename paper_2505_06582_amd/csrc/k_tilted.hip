@@ -57,6 +57,11 @@ __global__ void k_tilt_zero(long long *__restrict__ counters)
     if (threadIdx.x < CTR_COUNT) counters[threadIdx.x] = 0;
 }
 
+__global__ void k_tilt_zero64(int64_t *__restrict__ p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
 // One thread per Gaussian (input order): validity, record, tile rectangle.
 __global__ void __launch_bounds__(256) k_tilt_records(TView g, Consts k, TRec *__restrict__ rec,
                                                        int2 *__restrict__ rect, long long *__restrict__ counters)
@@ -75,7 +80,9 @@ __global__ void __launch_bounds__(256) k_tilt_records(TView g, Consts k, TRec *_
         any_amp = any_amp || (a != 0.0f);
     }
     const double qn = (double)qw * qw + (double)qx * qx + (double)qy * qy + (double)qz * qz;
-    ok = ok && qn > 0.0 && o != 0.0f && any_amp;
+    // the forward also skips Gaussians that add nothing; the adjoint keeps them (their opacity and
+    // amplitude gradients are not zero)
+    ok = ok && qn > 0.0 && (!k.forward || (o != 0.0f && any_amp));
     TRec r = {};
     int2 box = make_int2(1, 0);  // empty: tx0 > tx1
     if (ok) {
@@ -438,6 +445,537 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
     if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
     if (tid == 0 && cand) atomicAdd((unsigned long long *)&counters[CTR_CAND], (unsigned long long)cand);
 }
+
+// ---------------------------------------------------------------------------------
+// Adjoint.  For a real loss L with Gs = dL/dS (the forward DFT of dL/du), the gradient of a
+// parameter t of Gaussian i is Re sum_{c,m} conj(Gs_c[m]) dS_ic[m]/dt, where S_ic = A_c g_c with
+// g_c = |w| exp2(L - u^2 - v^2) e^{j 2 pi Theta} (A_c, u, v, w, L as in the forward).  With
+// rho_c = conj(Gs_c) S_ic, every derivative is rho times a factor, so per Gaussian the sums
+//   P_c = Re sum_m conj(Gs_c) g_c,     I0 = sum Im rho,   Sx = sum m_x Im rho,  Sy = sum m_y Im rho,
+//   Z = sum k_z Im rho,                SU_j = sum u x_j Re rho,  SV_j = sum v x_j Re rho,
+//   SN_j = sum x_j Re rho / w,         x = (m_x, m_y, k_z)
+// carry the whole gradient (chain rule in k_tilt_grad_final).  The kernel is the forward's tile
+// walk; each wavefront reduces a staged Gaussian's sums over its sub-tile, the work-group adds its
+// four sub-tiles in a fixed order and writes one slot per (Gaussian, tile) -- slot off[i] + the
+// tile's place in Gaussian i's rectangle -- so every slot is written once, and the per-Gaussian
+// sums over slots run in a fixed order: results are bitwise reproducible.
+// ---------------------------------------------------------------------------------
+__host__ __device__ constexpr int tilt_nv(int c) { return c + 13; }
+__host__ __device__ constexpr int tilt_nvp(int c) { return tilt_nv(c) <= 16 ? 16 : 24; }
+// The adjoint holds 2 x 4 x C per-lane tables and C + 13 running sums: two wavefronts per SIMD.
+constexpr int TILT_ADJ_WAVES = 2;
+
+template <int C, bool WIDE>
+static __device__ __forceinline__ void tilt_adj_eval(uint32_t rows, float U1, float U2, float V1, float V2,
+                                                     float N1, float N2, float z, float ryf, float mx,
+                                                     const float (&u0)[C], const float (&v0)[C],
+                                                     const float (&w0)[C], const float (&bx)[C],
+                                                     const float (&amp)[C], const float (&kz0)[C],
+                                                     const float (&dyf)[TF], const float (&myf)[TF],
+                                                     const float (&dD)[TF][C], const float (&lkz)[TF][C],
+                                                     const double (&D0)[C], const double (&il)[C], double iwx,
+                                                     double iwy, const float2 (&gs)[TF][C][64], int lane,
+                                                     float (&x)[tilt_nvp(C)])
+{
+#pragma unroll
+    for (int f = 0; f < TF; ++f) {
+        const float my = myf[f];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (!(rows & (1u << (c * TF + f)))) continue;
+            const float d = dD[f][c];
+            const float u = fmaf(U2, d, fmaf(U1, dyf[f], u0[c]));
+            const float v = fmaf(V2, d, fmaf(V1, dyf[f], v0[c]));
+            const float kw = fmaf(N2, d, fmaf(N1, dyf[f], w0[c]));
+            const float2 g = gs[f][c][lane];   // (|Gs|, arg Gs / 2 pi)
+            const float eg = __builtin_amdgcn_exp2f(-fmaf(u, u, fmaf(v, v, -lkz[f][c]))) * g.x;
+            const float t = fmaf(-dyf[f], ryf, bx[c]) - g.y;
+            float th;
+            if (!WIDE) {
+                th = fmaf(-z, d, t);
+            } else {
+                // D_c(m) - D_c(m0) again in FP64 and the product reduced in FP64 (this path is
+                // taken only where |z| (D_c(m) - D_c(m0)) can exceed 16 revolutions)
+                const double nux = mx * iwx, nuy = my * iwy, nu2 = nux * nux + nuy * nuy;
+                const double w2 = il[c] * il[c] - nu2;
+                const double dd = w2 > 0.0 ? -nu2 / (il[c] + sqrt(w2)) - D0[c] : 0.0;
+                const double p = (double)z * dd;
+                th = (float)((double)t - (p - rint(p)));
+            }
+            const float sn = __builtin_amdgcn_sinf(th);
+            const float cs = __builtin_amdgcn_cosf(th);
+            const float gr = eg * cs, gi = eg * sn;
+            const float aw = fabsf(kw);
+            x[c] = fmaf(aw, gr, x[c]);               // P_c
+            const float rr = amp[c] * aw * gr, ri = amp[c] * aw * gi;
+            const float kz = kz0[c] + d;
+            x[C + 0] += ri;                          // I0
+            x[C + 1] = fmaf(mx, ri, x[C + 1]);       // Sx
+            x[C + 2] = fmaf(my, ri, x[C + 2]);       // Sy
+            x[C + 3] = fmaf(kz, ri, x[C + 3]);       // Z
+            const float ur = u * rr, vr = v * rr;
+            x[C + 4] = fmaf(ur, mx, x[C + 4]);
+            x[C + 5] = fmaf(ur, my, x[C + 5]);
+            x[C + 6] = fmaf(ur, kz, x[C + 6]);
+            x[C + 7] = fmaf(vr, mx, x[C + 7]);
+            x[C + 8] = fmaf(vr, my, x[C + 8]);
+            x[C + 9] = fmaf(vr, kz, x[C + 9]);
+            const float sr = copysignf(amp[c], kw) * gr;   // Re rho / w
+            x[C + 10] = fmaf(sr, mx, x[C + 10]);
+            x[C + 11] = fmaf(sr, my, x[C + 11]);
+            x[C + 12] = fmaf(sr, kz, x[C + 12]);
+        }
+    }
+}
+
+template <int C>
+__global__ void __launch_bounds__(TWG, TILT_ADJ_WAVES) k_tilt_adjoint(Consts k, const TRec *__restrict__ rec,
+                                                                        const int2 *__restrict__ rect, int64_t n,
+                                                                        const float2 *__restrict__ gspec,
+                                                                        const int64_t *__restrict__ off,
+                                                                        float *__restrict__ part, int n_queue,
+                                                                        long long *__restrict__ counters)
+{
+    constexpr int TE = te_floats(C);
+    constexpr int NV = tilt_nv(C), NVP = tilt_nvp(C);
+    __shared__ int s_idx[TWG];
+    __shared__ int s_cnt[4];
+    __shared__ int s_tile;
+    __shared__ __align__(16) float s_w[4][64][TE];
+    __shared__ float2 s_g[4][TF][C][64];
+    __shared__ float s_part[4][64][NV];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int hx = k.nx / 2, hy = k.ny / 2;
+    const double Wx = k.nx * k.px, Wy = k.ny * k.py;
+    double ilam[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ilam[c] = k.inv_lambda[c];
+    const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int col = lane & 15, row0 = lane >> 4;
+    const float dxf = (float)(col - 8);
+    float dyf[TF];
+#pragma unroll
+    for (int f = 0; f < TF; ++f) dyf[f] = (float)(row0 + 4 * f - 8);
+    long long pairs = 0;
+
+    for (;;) {
+        if (tid == 0) s_tile = (int)atomicAdd((unsigned long long *)&counters[CTR_WORK], 1ull);
+        __syncthreads();
+        const int q = s_tile;
+        __syncthreads();
+        if (q >= n_queue) break;
+        int tx, ty;
+        ring_tile(q, &tx, &ty);
+        if (tx * TT >= hx || (tx + 1) * TT <= -hx || ty * TT >= hy || (ty + 1) * TT <= -hy) continue;
+        const int sx0 = tx * TT + (wave & 1) * 16, sy0 = ty * TT + (wave >> 1) * 16;
+        const int cx = sx0 + 8, cy = sy0 + 8;
+        const int mxp = sx0 + col;
+        const float mxw = (float)mxp;
+        double D0[C];
+        float dD[TF][C], lkz[TF][C], dmax[C], kz0[C], myf[TF];
+        {
+            const double ncx = cx / Wx, ncy = cy / Wy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                D0[c] = dprop_t(ncx * ncx + ncy * ncy, k.inv_lambda[c]);
+                kz0[c] = (float)(k.inv_lambda[c] + D0[c]);
+                dmax[c] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < TF; ++f) {
+            const int myp = sy0 + row0 + 4 * f;
+            myf[f] = (float)myp;
+            const double nux = mxp / Wx, nuy = myp / Wy;
+            const double nu2 = nux * nux + nuy * nuy;
+            const bool in_grid = mxp >= -hx && mxp < hx && myp >= -hy && myp < hy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double il = k.inv_lambda[c];
+                const double w2 = il * il - nu2;
+                float2 gv = make_float2(0.0f, 0.0f);
+                if (w2 > 0.0) {
+                    const double kz = sqrt(w2);
+                    const double dd = -nu2 / (il + kz) - D0[c];
+                    dD[f][c] = (float)dd;
+                    lkz[f][c] = (float)log2(il / kz);
+                    if (in_grid) {
+                        const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
+                        const float2 g = gspec[((int64_t)c * k.ny + my) * k.nx + mx];
+                        gv = make_float2(hypotf(g.x, g.y), atan2f(g.y, g.x) * 0.15915494309189535f);
+                    }
+                } else {
+                    dD[f][c] = 0.0f;
+                    lkz[f][c] = -1000.0f;
+                }
+                s_g[wave][f][c][lane] = gv;   // outside the grid |Gs| = 0: no contribution
+                dmax[c] = fmaxf(dmax[c], fabsf(dD[f][c]));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            for (int o = 32; o >= 1; o >>= 1) dmax[c] = fmaxf(dmax[c], __shfl_xor(dmax[c], o));
+        float dmax_all = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) dmax_all = fmaxf(dmax_all, dmax[c]);
+        const int rlo = max(sy0, -hy), rhi = min(sy0 + 15, hy - 1);
+        const bool wave_live = (max(sx0, -hx) <= min(sx0 + 15, hx - 1)) && (rlo <= rhi);
+
+        for (int64_t base = 0; base < n; base += TWG) {
+            const int64_t gi = base + tid;
+            bool pred = false;
+            if (gi < n) {
+                const int2 b = rect[gi];
+                const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
+                const int ty0 = (int)(int16_t)(b.y & 0xffff), ty1 = b.y >> 16;
+                pred = tx >= tx0 && tx <= tx1 && ty >= ty0 && ty <= ty1;
+            }
+            const uint64_t bal = __ballot(pred);
+            if (lane == 0) s_cnt[wave] = __popcll(bal);
+            __syncthreads();
+            int offs = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int cw = s_cnt[w];
+                offs += (w < wave) ? cw : 0;
+                total += cw;
+            }
+            if (pred) s_idx[offs + __popcll(bal & lt)] = (int)gi;
+            __syncthreads();
+            // groups of 64 staged Gaussians, every wavefront taking part in each group's barriers
+            for (int j0 = 0; j0 < total; j0 += 64) {
+                const int j = j0 + lane;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s_part[wave][lane][v] = 0.0f;
+                uint32_t rows = 0;
+                if (wave_live && j < total) {
+                    const TRec &r = rec[s_idx[j]];
+                    const float4 *src = reinterpret_cast<const float4 *>(&r);
+                    const float4 a0 = src[0], a1 = src[1], a2 = src[2];
+                    const float U0 = a0.x, U1 = a0.y, U2 = a0.z, V0 = a0.w, V1 = a1.x, V2 = a1.y;
+                    const float N0 = a1.z, N1 = a1.w, N2 = a2.x, z = a2.y;
+                    float *e = &s_w[wave][lane][0];
+                    const double ramp_rev =
+                        (double)((uint32_t)cx * __float_as_uint(a2.z) + (uint32_t)cy * __float_as_uint(a2.w)) *
+                        (1.0 / 4294967296.0);
+                    const float ez0 = fabsf(U0) * 8.0f + fabsf(U1) * 1.5f, fz0 = fabsf(V0) * 8.0f + fabsf(V1) * 1.5f;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const double kzc = k.inv_lambda[c] + D0[c];
+                        const float u0 = (float)((double)U0 * cx + (double)U1 * cy + (double)U2 * kzc);
+                        const float v0 = (float)((double)V0 * cx + (double)V1 * cy + (double)V2 * kzc);
+                        const float kap = r.kappa[c];
+                        float bs;
+                        if (k.phase_mode == 1) {
+                            const float vv = kap - ((float)cx * r.rxf + (float)cy * r.ryf) - z * (float)D0[c];
+                            bs = vv - floorf(vv);
+                        } else {
+                            bs = (float)frac_t((double)kap - ramp_rev - (double)z * D0[c]);
+                        }
+                        e[13 + c] = u0;
+                        e[13 + C + c] = v0;
+                        e[13 + 2 * C + c] = (float)((double)N0 * cx + (double)N1 * cy + (double)N2 * kzc);
+                        e[13 + 3 * C + c] = bs;
+                        e[13 + 4 * C + c] = r.amp[c];
+                        const float eu = fmaf(fabsf(U2), dmax[c], ez0), ev = fmaf(fabsf(V2), dmax[c], fz0);
+#pragma unroll
+                        for (int f = 0; f < TF; ++f) {
+                            const int b0 = sy0 + 4 * f;
+                            if (b0 + 3 < rlo || b0 > rhi) continue;
+                            const float dyc = (float)(4 * f) - 6.5f;
+                            const float mu = fmaxf(fabsf(fmaf(U1, dyc, u0)) - eu, 0.0f);
+                            const float mv = fmaxf(fabsf(fmaf(V1, dyc, v0)) - ev, 0.0f);
+                            if (fmaf(mu, mu, mv * mv) <= lim) rows |= 1u << (c * TF + f);
+                        }
+                    }
+                    if (rows) {
+                        reinterpret_cast<float4 *>(e)[0] = a0;
+                        reinterpret_cast<float4 *>(e)[1] = a1;
+                        reinterpret_cast<float4 *>(e)[2] = make_float4(N2, z, r.rxf, r.ryf);
+                        e[12] = __uint_as_float(rows);
+                        pairs += __popc(rows) * 64;
+                    }
+                }
+                uint64_t live = __ballot(rows != 0);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                while (live) {
+                    const int ei = __builtin_ctzll(live);
+                    live &= live - 1;
+                    const float *w = &s_w[wave][ei][0];
+                    const float U0 = w[0], U1 = w[1], U2 = w[2], V0 = w[3], V1 = w[4], V2 = w[5];
+                    const float N0 = w[6], N1 = w[7], N2 = w[8], z = w[9], rxf = w[10], ryf = w[11];
+                    const uint32_t erows = __builtin_amdgcn_readfirstlane(__float_as_uint(w[12]));
+                    const float lux = U0 * dxf, lvx = V0 * dxf, lwx = N0 * dxf;
+                    float u0[C], v0[C], w0[C], bx[C], amp[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        u0[c] = w[13 + c] + lux;
+                        v0[c] = w[13 + C + c] + lvx;
+                        w0[c] = w[13 + 2 * C + c] + lwx;
+                        bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, w[13 + 3 * C + c]));
+                        amp[c] = w[13 + 4 * C + c];
+                    }
+                    float x[NVP];
+#pragma unroll
+                    for (int v = 0; v < NVP; ++v) x[v] = 0.0f;
+                    if (fabsf(z) * dmax_all > 16.0f)
+                        tilt_adj_eval<C, true>(erows, U1, U2, V1, V2, N1, N2, z, ryf, mxw, u0, v0, w0, bx, amp, kz0,
+                                               dyf, myf, dD, lkz, D0, ilam, 1.0 / Wx, 1.0 / Wy, s_g[wave], lane, x);
+                    else
+                        tilt_adj_eval<C, false>(erows, U1, U2, V1, V2, N1, N2, z, ryf, mxw, u0, v0, w0, bx, amp, kz0,
+                                                dyf, myf, dD, lkz, D0, ilam, 1.0 / Wx, 1.0 / Wy, s_g[wave], lane, x);
+                    // sums over the wavefront: after the transposed butterfly register j of lane l
+                    // holds value 2 (4 b5 + 2 b4 + b3) + j (and + 16 for the second block)
+                    float y0 = 0.0f;
+                    float xa[16];
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) xa[v] = x[v];
+                    reduce_transposed<16, false>(xa, y0, lane);
+                    const int g8 = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+                    if ((lane & 7) == 0) {
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj)
+                            if (2 * g8 + jj < NV) s_part[wave][ei][2 * g8 + jj] = xa[jj];
+                    }
+                    if constexpr (NVP > 16) {
+                        float xb[8];
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) xb[v] = x[16 + v];
+                        reduce_transposed<8, false>(xb, y0, lane);
+                        if ((lane & 7) == 0 && 16 + g8 < NV) s_part[wave][ei][16 + g8] = xb[0];
+                    }
+                }
+                __syncthreads();   // every wavefront's sums of this group are in LDS
+                const int cnt = min(64, total - j0);
+                for (int t = tid; t < cnt * NV; t += TWG) {
+                    const int jj = t / NV, v = t - jj * NV;
+                    const int gidx = s_idx[j0 + jj];
+                    const int2 b = rect[gidx];
+                    const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
+                    const int ty0 = (int)(int16_t)(b.y & 0xffff);
+                    const int64_t slot = off[gidx] + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
+                    part[slot * NV + v] = ((s_part[0][jj][v] + s_part[1][jj][v]) + s_part[2][jj][v]) + s_part[3][jj][v];
+                }
+                __syncthreads();   // before the next group overwrites the sums
+            }
+        }
+    }
+    pairs = wave_sum_i64(pairs);
+    if (lane == 0 && pairs) atomicAdd((unsigned long long *)&counters[CTR_PAIRS], (unsigned long long)pairs);
+}
+
+// Rectangle areas (tiles per Gaussian) and their exclusive prefix: off[i] = first slot of
+// Gaussian i, off[n] = all slots.  Three passes: per 1024-block scans, a scan of the block
+// totals in one work-group, the block offsets added.
+__global__ void __launch_bounds__(1024) k_tilt_scan1(const int2 *__restrict__ rect, int64_t n, int64_t *__restrict__ off,
+                                                    int64_t *__restrict__ bsum)
+{
+    __shared__ int64_t sh[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    int64_t a = 0;
+    if (i < n) {
+        const int2 b = rect[i];
+        const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
+        const int ty0 = (int)(int16_t)(b.y & 0xffff), ty1 = b.y >> 16;
+        a = (tx1 >= tx0 && ty1 >= ty0) ? (int64_t)(tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (i < n) off[i] = sh[threadIdx.x] - a;
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = sh[1023];
+}
+
+__global__ void __launch_bounds__(1024) k_tilt_scan2(int64_t *__restrict__ bsum, int nb, int64_t *__restrict__ total)
+{
+    __shared__ int64_t sh[1024];
+    const int per = (nb + 1023) / 1024, b0 = threadIdx.x * per;
+    int64_t s = 0;
+    for (int j = 0; j < per && b0 + j < nb; ++j) s += bsum[b0 + j];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = sh[threadIdx.x] - s;
+    for (int j = 0; j < per && b0 + j < nb; ++j) {
+        const int64_t v = bsum[b0 + j];
+        bsum[b0 + j] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) *total = sh[1023];
+}
+
+__global__ void __launch_bounds__(1024) k_tilt_scan3(int64_t *__restrict__ off, int64_t n, const int64_t *__restrict__ bsum)
+{
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) off[i] += bsum[blockIdx.x];
+}
+
+hipError_t launch_tilt_offsets(const int2 *rect, int64_t n, int64_t *off, int64_t *bsum, hipStream_t s)
+{
+    const int nb = (int)std::max<int64_t>(1, (n + 1023) / 1024);
+    if (n > 0) hipLaunchKernelGGL(k_tilt_scan1, dim3(nb), dim3(1024), 0, s, rect, n, off, bsum);
+    else hipLaunchKernelGGL(k_tilt_zero64, dim3(1), dim3(64), 0, s, bsum, 1);
+    hipLaunchKernelGGL(k_tilt_scan2, dim3(1), dim3(1024), 0, s, bsum, nb, off + n);
+    if (n > 0) hipLaunchKernelGGL(k_tilt_scan3, dim3(nb), dim3(1024), 0, s, off, n, bsum);
+    return hipGetLastError();
+}
+
+// Per Gaussian (one wavefront): its slots summed in a fixed order (FP64), then the chain rule to
+// the parameters.  A Gaussian with no slots (culled, or its support outside the band) gets zeros.
+template <int C>
+__global__ void __launch_bounds__(256) k_tilt_grad_final(TView g, Consts k, const int2 *__restrict__ rect,
+                                                         const int64_t *__restrict__ off,
+                                                         const float *__restrict__ part, TGrads gr)
+{
+    constexpr int NV = tilt_nv(C);
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= g.n) return;
+    const int64_t s0 = off[i], ns = off[i + 1] - s0;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t t = lane; t < ns; t += 64) {
+        const float *src = part + (s0 + t) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += (double)src[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int o = 32; o >= 1; o >>= 1) acc[v] += __shfl_xor(acc[v], o);
+    if (lane != 0) return;
+    if (ns == 0) {
+        gr.mean_x[i] = gr.mean_y[i] = gr.depth[i] = 0.0f;
+        gr.quat_w[i] = gr.quat_x[i] = gr.quat_y[i] = gr.quat_z[i] = 0.0f;
+        gr.scale_u[i] = gr.scale_v[i] = gr.opacity[i] = gr.phase[i] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) gr.amplitude[(int64_t)c * g.n + i] = 0.0f;
+        return;
+    }
+    const double PI = 3.14159265358979323846, LN2 = 0.69314718055994530942;
+    const double qw0 = g.quat_w[i], qx0 = g.quat_x[i], qy0 = g.quat_y[i], qz0 = g.quat_z[i];
+    const double qn = sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+    const double w = qw0 / qn, x = qx0 / qn, y = qy0 / qn, z = qz0 / qn;
+    const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    const double Wx = k.nx * k.px, Wy = k.ny * k.py, sk = sqrt(k.K2);
+    const double su = g.scale_u[i], sv = g.scale_v[i], o = g.opacity[i];
+    const double K = 2.0 * PI * su * sv / (k.px * k.py * (double)k.nx * (double)k.ny);
+    const double cs[3] = {1.0 / Wx, 1.0 / Wy, 1.0};
+    // amplitude, opacity and the part of the scale gradient through A_c = a_c o K lambda_c
+    double R0 = 0.0, go = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double a = g.amplitude[(int64_t)c * g.n + i];
+        const double P = acc[c];
+        gr.amplitude[(int64_t)c * g.n + i] = (float)(o * K * k.lambda[c] * P);
+        go += a * K * k.lambda[c] * P;
+        R0 += a * o * K * k.lambda[c] * P;
+    }
+    const double I0 = acc[C], Sx = acc[C + 1], Sy = acc[C + 2], Zs = acc[C + 3];
+    gr.opacity[i] = (float)go;
+    gr.phase[i] = (float)(-I0);
+    gr.mean_x[i] = (float)(2.0 * PI / Wx * Sx);
+    gr.mean_y[i] = (float)(2.0 * PI / Wy * Sy);
+    gr.depth[i] = (float)(2.0 * PI * Zs);
+    // u = U.x, v = V.x, w = N.x: dL/dU_j = -2 ln2 SU_j, dL/dV_j = -2 ln2 SV_j, dL/dN_j = SN_j
+    double gU[3], gV[3], gN[3], GR[3][3];
+    for (int j = 0; j < 3; ++j) {
+        gU[j] = -2.0 * LN2 * acc[C + 4 + j];
+        gV[j] = -2.0 * LN2 * acc[C + 7 + j];
+        gN[j] = acc[C + 10 + j];
+        GR[j][0] = gU[j] * sk * su * cs[j];
+        GR[j][1] = gV[j] * sk * sv * cs[j];
+        GR[j][2] = gN[j] * cs[j];
+    }
+    double dsu = R0 / su, dsv = R0 / sv;
+    for (int j = 0; j < 3; ++j) {
+        dsu += gU[j] * sk * R[j][0] * cs[j];
+        dsv += gV[j] * sk * R[j][1] * cs[j];
+    }
+    gr.scale_u[i] = (float)dsu;
+    gr.scale_v[i] = (float)dsv;
+    // R of the unit quaternion (w, x, y, z): dR/dw, dR/dx, dR/dy, dR/dz, then the normalisation
+    const double dW[3][3] = {{0, -2 * z, 2 * y}, {2 * z, 0, -2 * x}, {-2 * y, 2 * x, 0}};
+    const double dX[3][3] = {{0, 2 * y, 2 * z}, {2 * y, -4 * x, -2 * w}, {2 * z, 2 * w, -4 * x}};
+    const double dY[3][3] = {{-4 * y, 2 * x, 2 * w}, {2 * x, 0, 2 * z}, {-2 * w, 2 * z, -4 * y}};
+    const double dZ[3][3] = {{-4 * z, -2 * w, 2 * x}, {2 * w, -4 * z, 2 * y}, {2 * x, 2 * y, 0}};
+    double gq[4] = {0, 0, 0, 0};
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+            gq[0] += GR[r][cc] * dW[r][cc];
+            gq[1] += GR[r][cc] * dX[r][cc];
+            gq[2] += GR[r][cc] * dY[r][cc];
+            gq[3] += GR[r][cc] * dZ[r][cc];
+        }
+    const double qh[4] = {w, x, y, z};
+    const double dotp = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
+    gr.quat_w[i] = (float)((gq[0] - qh[0] * dotp) / qn);
+    gr.quat_x[i] = (float)((gq[1] - qh[1] * dotp) / qn);
+    gr.quat_y[i] = (float)((gq[2] - qh[2] * dotp) / qn);
+    gr.quat_z[i] = (float)((gq[3] - qh[3] * dotp) / qn);
+}
+
+static int tilt_queue_len(int nx, int ny);
+
+template <int C>
+static hipError_t launch_tilt_adjoint_c(const Consts &k, const TRec *rec, const int2 *rect, int64_t n,
+                                        const float2 *gspec, const int64_t *off, float *part, long long *counters,
+                                        int n_cu, hipStream_t s)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_tilt_adjoint<C>, TWG, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    const int nq = tilt_queue_len(k.nx, k.ny);
+    const int grid = std::max(1, std::min(n_cu * nb, nq));
+    hipLaunchKernelGGL(k_tilt_adjoint<C>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, gspec, off, part, nq, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_tilt_adjoint(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, const float2 *gspec,
+                               const int64_t *off, float *part, long long *counters, int n_cu, hipStream_t s)
+{
+    switch (k.C) {
+    case 1: return launch_tilt_adjoint_c<1>(k, rec, rect, n, gspec, off, part, counters, n_cu, s);
+    case 2: return launch_tilt_adjoint_c<2>(k, rec, rect, n, gspec, off, part, counters, n_cu, s);
+    case 3: return launch_tilt_adjoint_c<3>(k, rec, rect, n, gspec, off, part, counters, n_cu, s);
+    case 4: return launch_tilt_adjoint_c<4>(k, rec, rect, n, gspec, off, part, counters, n_cu, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tilt_grad_final(const TView &g, const Consts &k, const int2 *rect, const int64_t *off,
+                                  const float *part, const TGrads &gr, hipStream_t s)
+{
+    if (g.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((g.n * 64 + 255) / 256)), block(256);
+    switch (k.C) {
+    case 1: hipLaunchKernelGGL(k_tilt_grad_final<1>, grid, block, 0, s, g, k, rect, off, part, gr); break;
+    case 2: hipLaunchKernelGGL(k_tilt_grad_final<2>, grid, block, 0, s, g, k, rect, off, part, gr); break;
+    case 3: hipLaunchKernelGGL(k_tilt_grad_final<3>, grid, block, 0, s, g, k, rect, off, part, gr); break;
+    case 4: hipLaunchKernelGGL(k_tilt_grad_final<4>, grid, block, 0, s, g, k, rect, off, part, gr); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int tilt_slot_floats(int C) { return tilt_nv(C); }
 
 hipError_t launch_tilt_records(const TView &g, const Consts &k, TRec *rec, int2 *rect, long long *counters,
                                hipStream_t s)

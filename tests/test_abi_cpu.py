@@ -82,12 +82,13 @@ def test_tilted_struct_layout_and_workspace_on_the_host(tmp_path):
     assert lib.gws_workspace_size_tilted(None, ctypes.byref(prob), 1000, ctypes.byref(sz)) == 0
     assert lib.gws_workspace_size_tilted(None, ctypes.byref(prob), 100000, ctypes.byref(sz2)) == 0
     spec = 3 * 1920 * 1080 * 8
-    assert spec + 1000 * 104 <= sz.value < spec + 1000 * 104 + 4096
-    assert sz2.value - sz.value >= 99000 * 104 - 512   # each area rounded to 256 bytes
+    assert spec + 1000 * 112 <= sz.value < spec + 1000 * 112 + 8192
+    assert sz2.value - sz.value >= 99000 * 112 - 1024   # each area rounded to 256 bytes
     assert lib.gws_workspace_size_tilted(None, ctypes.byref(prob), -1, ctypes.byref(sz)) == -1
     bad = gws.Problem(1921, 1080)._c()
     assert lib.gws_workspace_size_tilted(None, ctypes.byref(bad), 10, ctypes.byref(sz)) != 0
     assert lib.gws_forward_tilted(None, ctypes.byref(prob), None, None, None, 0, None) == -1
+    assert lib.gws_backward_tilted(None, ctypes.byref(prob), None, None, None, None, 0, None) == -1
 
 
 def test_holographics_validates_on_the_host():

@@ -3,7 +3,9 @@ field and spectrum on small grids (one to three wavelengths, ragged tile edges, 
 degrees at the workloads' 8 um pitch, and 20-28 degree tilts on fine grids whose band reaches
 the evanescent edge), edge cases (no Gaussians, culled ones, a flipped description of the same
 disk, a rotation about z alone against the in-plane path), determinism, and the 100k-Gaussian
-1080 x 1920 x 3 workload on sampled frequencies."""
+1080 x 1920 x 3 workload on sampled frequencies; the adjoint against the float64 autograd oracle
+(oracle/tilted_grad.py) on the same kinds of grids, with culled and zero-opacity Gaussians, and
+for sampled Gaussians of the 100k workload."""
 import dataclasses
 
 import numpy as np
@@ -12,6 +14,7 @@ import pytest
 import gwsgen
 import oracle
 import oracle.tilted as otl
+import oracle.tilted_grad as otg
 from gwsgen import Grid
 from gpu_util import dft_ready, problem, rel_l2, scene_to_torch, stratified_freqs, to_numpy
 
@@ -166,3 +169,86 @@ def test_tilted_workload_100k_sampled(ctx):
     log("tilted 100k sampled spectrum: rel L2 %.3e" % e)
     assert e < TOL
     assert np.all(np.isfinite(to_numpy(u)))
+
+
+# ---- adjoint -------------------------------------------------------------------------------
+
+GRAD_TOL = 1e-4
+BWD_CASES = [
+    (96, 80, 8e-6, gwsgen.RGB, 40, 921, (2.0, 20.0), 2.0),
+    (48, 40, 8e-6, (520e-9,), 20, 922, (1.0, 6.0), 3.0),
+    (128, 96, 1e-6, (520e-9, 450e-9), 24, 923, (1.0, 4.0), 25.0),
+    (64, 72, 0.25e-6, (633e-9,), 16, 924, (2.0, 6.0), 28.0),
+]
+
+
+def grads_rel(got, ref, names):
+    out = {}
+    for k in names:
+        g = np.asarray(got[k], dtype=np.float64).ravel()
+        r = np.asarray(ref[k], dtype=np.float64).ravel()
+        out[k] = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+    return out
+
+
+@pytest.mark.parametrize("case", BWD_CASES, ids=["%dx%d-%dl-t%g" % (c[0], c[1], len(c[3]), c[7]) for c in BWD_CASES])
+def test_tilted_backward_matches_oracle(ctx, case):
+    import torch
+    nx, ny, pitch, lams, n, seed, sig, tilt = case
+    grid = Grid(nx, ny, pitch, pitch, lams)
+    scene = gwsgen.make_tilted_scene(n, grid, seed, depth_range=(-10e-3, 10e-3), sigma_px=sig, tilt_max_deg=tilt)
+    G = gwsgen.make_target(grid, seed + 1)
+    got = ctx.backward_tilted(problem(grid), scene_to_torch(scene), torch.from_numpy(G).cuda())
+    got = {k: to_numpy(v) for k, v in got.items()}
+    ref = otg.backward(scene, grid, G)
+    e = grads_rel(got, ref, otg.PARAMS)
+    log("tilted backward %dx%d pitch %g C=%d tilt<=%g: %s" % (nx, ny, pitch, len(lams), tilt,
+                                                             {k: "%.2e" % v for k, v in e.items()}))
+    assert max(e.values()) < GRAD_TOL, e
+
+
+def test_tilted_backward_culled_zero_opacity_and_determinism(ctx):
+    import torch
+    grid = Grid(64, 48, 8e-6, 8e-6, gwsgen.RGB)
+    sc = gwsgen.make_tilted_scene(10, grid, 925, tilt_max_deg=2.0)
+    sc.opacity[0] = 0.0            # kept by the adjoint: its opacity gradient is not zero
+    sc.scale_u[1] = 0.0            # culled: zeros
+    sc.mean_x[2] = np.nan          # culled: zeros
+    G = gwsgen.make_target(grid, 926)
+    Gt = torch.from_numpy(G).cuda()
+    g = scene_to_torch(sc)
+    a = {k: to_numpy(v) for k, v in ctx.backward_tilted(problem(grid), g, Gt).items()}
+    b = {k: to_numpy(v) for k, v in ctx.backward_tilted(problem(grid), g, Gt).items()}
+    for k in otg.PARAMS:
+        assert np.array_equal(a[k], b[k]), k
+    for k in otg.PARAMS:
+        v = a[k][:, 1:3] if k == "amplitude" else a[k][1:3]
+        assert np.all(v == 0), k
+    good = np.array([0] + list(range(3, 10)))
+    ref = otg.backward(sc.subset(good), grid, G)
+    got = {k: (a[k][:, good] if k == "amplitude" else a[k][good]) for k in otg.PARAMS}
+    e = grads_rel(got, ref, otg.PARAMS)
+    log("tilted backward with culled and zero-opacity Gaussians: %s" % {k: "%.2e" % v for k, v in e.items()})
+    assert max(e.values()) < GRAD_TOL, e
+    assert abs(a["opacity"][0]) > 0
+
+
+def test_tilted_backward_workload_100k_sampled(ctx):
+    """Gradients of the tilted100k workload in the launch configuration the bench times, checked
+    for four sampled Gaussians (each Gaussian's gradient depends only on its own term and the
+    given field gradient, so the oracle computes it alone)."""
+    import torch
+    grid = Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_tilted_scene(100_000, grid, 1005, depth_range=(-10e-3, 10e-3), tilt_max_deg=2.0)
+    G = gwsgen.make_target(grid, 1006)
+    got = ctx.backward_tilted(problem(grid), scene_to_torch(scene), torch.from_numpy(G).cuda())
+    got = {k: to_numpy(v) for k, v in got.items()}
+    rng = np.random.default_rng(927)
+    for i in rng.choice(scene.n, 4, replace=False):
+        log("tilted 100k backward: oracle for Gaussian %d" % i)
+        ref = otg.backward(scene.subset([i]), grid, G)
+        for k in otg.PARAMS:
+            g = got[k][:, i] if k == "amplitude" else got[k][i]
+            r = np.ravel(ref[k])
+            err = np.max(np.abs(np.ravel(g) - r)) / max(np.max(np.abs(r)), 1e-300)
+            assert err < 1e-3, (i, k, np.ravel(g), r)
