@@ -702,7 +702,8 @@ def tilted_support_triples(scene, grid, step=8, chunk=2048):
 
 def bench_tilted(args):
     """100k tilted Gaussians (tilts up to 2 degrees about random in-plane axes, the fwd100k
-    distributions otherwise) at 1080x1920x3: forward (records, accumulation, inverse FFT)."""
+    distributions otherwise) at 1080x1920x3: forward (records, accumulation, inverse FFT), then
+    the training step (forward, L2 loss, backward)."""
     import numpy as np
     import torch
 
@@ -731,6 +732,31 @@ def bench_tilted(args):
     st = ctx.stats()
     ms = e0.elapsed_time(e1) / args.steps
     stage = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
+    # the training step: forward, L2 loss and its field gradient, backward (every gradient)
+    target = torch.from_numpy(gwsgen.make_target(grid, 2005)).to(dev)
+    G = torch.empty_like(field)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in g.items()}
+
+    def train_step():
+        ctx.forward_tilted(prob, g, out=field)
+        ctx.l2_loss_grad(field, target, G, loss)
+        ctx.backward_tilted(prob, g, G, out=grads)
+
+    for _ in range(max(1, args.warmup)):
+        train_step()
+    torch.cuda.synchronize()
+    ctx.read_profile()
+    ctx.set_profiling(True)
+    e0.record()
+    for _ in range(args.steps):
+        train_step()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    prof_b = ctx.read_profile()
+    ms_fb = e0.elapsed_time(e1) / args.steps
+    stage_fb = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof_b.items() if v[1]}
     C = grid.n_lambda
     triples = tilted_support_triples(scene, grid)
     evaluated = float(st["n_pairs_evaluated"])   # (Gaussian, frequency, wavelength) triples
@@ -750,7 +776,15 @@ def bench_tilted(args):
                         "work_per_launch": "%.4g transcendental ops (= %.4g (Gaussian, frequency, wavelength) triples "
                                            "inside the 1e-7 support x (1 exp2 + 1 sin + 1 cos))" % (3 * triples, triples),
                         "evaluated_frac": 3 * evaluated / t_acc / PEAK_TRANS,
-                        "evaluated_over_support": evaluated / triples}}
+                        "evaluated_over_support": evaluated / triples},
+           "fwd_bwd": {"ms_per_step": ms_fb, "holograms_per_s": 1e3 / ms_fb, "stage_ms": stage_fb,
+                       "adjoint_roofline": {
+                           "bound": "alu", "achieved": 3 * triples / (stage_fb["adjoint"] * 1e-3) / 1e12,
+                           "peak": PEAK_TRANS / 1e12, "unit": "TOP/s",
+                           "frac": 3 * triples / (stage_fb["adjoint"] * 1e-3) / PEAK_TRANS},
+                       "note": "forward + L2 loss + backward (every parameter's gradient); the backward "
+                               "synchronises once to size its partial-sum buffer"}}
+    log("bench tilted100k: fwd+bwd %.3f ms; stages %s" % (ms_fb, {k: round(v, 4) for k, v in stage_fb.items()}))
     print(json.dumps(out), flush=True)
 
 
