@@ -755,6 +755,7 @@ def bench_tilted(args):
     torch.cuda.synchronize()
     ctx.set_profiling(False)
     prof_b = ctx.read_profile()
+    st_b = ctx.stats()
     ms_fb = e0.elapsed_time(e1) / args.steps
     stage_fb = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof_b.items() if v[1]}
     C = grid.n_lambda
@@ -781,7 +782,8 @@ def bench_tilted(args):
                        "adjoint_roofline": {
                            "bound": "alu", "achieved": 3 * triples / (stage_fb["adjoint"] * 1e-3) / 1e12,
                            "peak": PEAK_TRANS / 1e12, "unit": "TOP/s",
-                           "frac": 3 * triples / (stage_fb["adjoint"] * 1e-3) / PEAK_TRANS},
+                           "frac": 3 * triples / (stage_fb["adjoint"] * 1e-3) / PEAK_TRANS,
+                           "evaluated_over_support": float(st_b["n_pairs_evaluated"]) / triples},
                        "note": "forward + L2 loss + backward (every parameter's gradient); the backward "
                                "synchronises once to size its partial-sum buffer"}}
     log("bench tilted100k: fwd+bwd %.3f ms; stages %s" % (ms_fb, {k: round(v, 4) for k, v in stage_fb.items()}))

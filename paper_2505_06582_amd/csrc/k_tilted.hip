@@ -454,48 +454,65 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
 //   P_c = Re sum_m conj(Gs_c) g_c,     I0 = sum Im rho,   Sx = sum m_x Im rho,  Sy = sum m_y Im rho,
 //   Z = sum k_z Im rho,                SU_j = sum u x_j Re rho,  SV_j = sum v x_j Re rho,
 //   SN_j = sum x_j Re rho / w,         x = (m_x, m_y, k_z)
-// carry the whole gradient (chain rule in k_tilt_grad_final).  The kernel is the forward's tile
-// walk; each wavefront reduces a staged Gaussian's sums over its sub-tile, the work-group adds its
-// four sub-tiles in a fixed order and writes one slot per (Gaussian, tile) -- slot off[i] + the
-// tile's place in Gaussian i's rectangle -- so every slot is written once, and the per-Gaussian
-// sums over slots run in a fixed order: results are bitwise reproducible.
+// carry the whole gradient (chain rule in k_tilt_grad_final).
+//
+// The kernel walks the forward's tiles with the work split the other way: the work-group builds
+// the tile's per-frequency tables once in LDS (per wavelength D_c(m) - D_c(m0), log2 of
+// |Gs_c| / (k_z lambda_c), arg Gs_c / 2 pi and k_z), and each wavefront takes whole staged
+// Gaussians over the 32 x 32 tile (lane l: column l % 32 and rows l / 32 + 2 f, f < 16), so a
+// Gaussian's sums over the tile come out of one transposed cross-lane reduction and go straight
+// to its slot for the tile -- off[i] + the tile's place in Gaussian i's rectangle.  Every slot is
+// written once and the per-Gaussian sums over slots run in a fixed order: results are bitwise
+// reproducible.  The ramp m . r (0.32 fixed point) is formed exactly per lane and row in integer
+// arithmetic; the carrier's FP64 base is taken at the tile centre.
 // ---------------------------------------------------------------------------------
 __host__ __device__ constexpr int tilt_nv(int c) { return c + 13; }
 __host__ __device__ constexpr int tilt_nvp(int c) { return tilt_nv(c) <= 16 ? 16 : 24; }
-// The adjoint holds 2 x 4 x C per-lane tables and C + 13 running sums: two wavefronts per SIMD.
-constexpr int TILT_ADJ_WAVES = 2;
+constexpr int TA_F = 16;   // row pairs of a tile: lane l holds rows l / 32 + 2 f
+// Wavefronts per SIMD: three up to three wavelengths (the tables take 16 KB per wavelength, so
+// three work-groups share a CU), two for four.
+__host__ __device__ constexpr int tilt_adj_waves(int c) { return c <= 3 ? 3 : 2; }
 
+// One staged Gaussian's sums at a lane's frequencies (bit f * C + c of `rows`: wavelength c
+// reaches row pair f).  The weights m_x (the lane's column) and m_y (one per row pair) are
+// applied once per lane and once per row pair: per term only the unweighted and the
+// k_z-weighted sums run.  x on return: P_c, I0, Sx, Sy, Z, SU(x,y,z), SV(x,y,z), SN(x,y,z).
+// WIDE (tiles where |z| (D_c(m) - D_c(m0)) can exceed 16 revolutions): that product reduced in
+// FP64.
 template <int C, bool WIDE>
-static __device__ __forceinline__ void tilt_adj_eval(uint32_t rows, float U1, float U2, float V1, float V2,
-                                                     float N1, float N2, float z, float ryf, float mx,
-                                                     const float (&u0)[C], const float (&v0)[C],
-                                                     const float (&w0)[C], const float (&bx)[C],
-                                                     const float (&amp)[C], const float (&kz0)[C],
-                                                     const float (&dyf)[TF], const float (&myf)[TF],
-                                                     const float (&dD)[TF][C], const float (&lkz)[TF][C],
+static __device__ __forceinline__ void tilt_adj_eval(uint64_t rows, const float4 (&tab)[TA_F][C][64], int lane,
+                                                     float U1, float U2, float V1, float V2, float N1, float N2,
+                                                     float z, float dy0, float my0, float mx, uint32_t r0, uint32_t r2,
+                                                     const float (&u0)[C], const float (&v0)[C], const float (&w0)[C],
+                                                     const float (&kc)[C], const float (&amp)[C],
                                                      const double (&D0)[C], const double (&il)[C], double iwx,
-                                                     double iwy, const float2 (&gs)[TF][C][64], int lane,
-                                                     float (&x)[tilt_nvp(C)])
+                                                     double iwy, float (&x)[tilt_nvp(C)])
 {
-#pragma unroll
-    for (int f = 0; f < TF; ++f) {
-        const float my = myf[f];
+    float aI = 0.0f, aU = 0.0f, aV = 0.0f, aS = 0.0f;   // unweighted: times m_x at the end
+    // the row pairs from the first to the last one the support reaches
+    const int f0 = __builtin_ctzll(rows) / C, f1 = (63 - __builtin_clzll(rows)) / C;
+    uint32_t rm = r0 + (uint32_t)f0 * r2;   // the lane's ramp m . r in 0.32 fixed point (exact, wraps mod 1)
+    float dy = dy0 + (float)(2 * f0), my = my0 + (float)(2 * f0);   // row offset from the tile centre, row index
+#pragma unroll 2
+    for (int f = f0; f <= f1; ++f, rm += r2, dy += 2.0f, my += 2.0f) {
+        const uint32_t fb = (uint32_t)(rows >> (f * C)) & ((1u << C) - 1u);
+        if (fb == 0) continue;
+        const float rf = (float)(int32_t)rm * 0x1p-32f;   // in revolutions, one rounding
+        float tI = 0.0f, tU = 0.0f, tV = 0.0f, tS = 0.0f;   // this row pair's sums over the wavelengths
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            if (!(rows & (1u << (c * TF + f)))) continue;
-            const float d = dD[f][c];
-            const float u = fmaf(U2, d, fmaf(U1, dyf[f], u0[c]));
-            const float v = fmaf(V2, d, fmaf(V1, dyf[f], v0[c]));
-            const float kw = fmaf(N2, d, fmaf(N1, dyf[f], w0[c]));
-            const float2 g = gs[f][c][lane];   // (|Gs|, arg Gs / 2 pi)
-            const float eg = __builtin_amdgcn_exp2f(-fmaf(u, u, fmaf(v, v, -lkz[f][c]))) * g.x;
-            const float t = fmaf(-dyf[f], ryf, bx[c]) - g.y;
+            if (!(fb & (1u << c))) continue;
+            const float4 tv = tab[f][c][lane];   // D_c(m) - D_c(m0), log2(|Gs| / (k_z lambda)), arg Gs / 2 pi, k_z
+            const float d = tv.x;
+            const float u = fmaf(U2, d, fmaf(U1, dy, u0[c]));
+            const float v = fmaf(V2, d, fmaf(V1, dy, v0[c]));
+            const float kw = fmaf(N2, d, fmaf(N1, dy, w0[c]));
+            const float eg = __builtin_amdgcn_exp2f(-fmaf(u, u, fmaf(v, v, -tv.y)));
+            const float t = (kc[c] - rf) - tv.z;
             float th;
             if (!WIDE) {
                 th = fmaf(-z, d, t);
             } else {
-                // D_c(m) - D_c(m0) again in FP64 and the product reduced in FP64 (this path is
-                // taken only where |z| (D_c(m) - D_c(m0)) can exceed 16 revolutions)
                 const double nux = mx * iwx, nuy = my * iwy, nu2 = nux * nux + nuy * nuy;
                 const double w2 = il[c] * il[c] - nu2;
                 const double dd = w2 > 0.0 ? -nu2 / (il[c] + sqrt(w2)) - D0[c] : 0.0;
@@ -507,43 +524,53 @@ static __device__ __forceinline__ void tilt_adj_eval(uint32_t rows, float U1, fl
             const float gr = eg * cs, gi = eg * sn;
             const float aw = fabsf(kw);
             x[c] = fmaf(aw, gr, x[c]);               // P_c
-            const float rr = amp[c] * aw * gr, ri = amp[c] * aw * gi;
-            const float kz = kz0[c] + d;
-            x[C + 0] += ri;                          // I0
-            x[C + 1] = fmaf(mx, ri, x[C + 1]);       // Sx
-            x[C + 2] = fmaf(my, ri, x[C + 2]);       // Sy
-            x[C + 3] = fmaf(kz, ri, x[C + 3]);       // Z
-            const float ur = u * rr, vr = v * rr;
-            x[C + 4] = fmaf(ur, mx, x[C + 4]);
-            x[C + 5] = fmaf(ur, my, x[C + 5]);
-            x[C + 6] = fmaf(ur, kz, x[C + 6]);
-            x[C + 7] = fmaf(vr, mx, x[C + 7]);
-            x[C + 8] = fmaf(vr, my, x[C + 8]);
-            x[C + 9] = fmaf(vr, kz, x[C + 9]);
-            const float sr = copysignf(amp[c], kw) * gr;   // Re rho / w
-            x[C + 10] = fmaf(sr, mx, x[C + 10]);
-            x[C + 11] = fmaf(sr, my, x[C + 11]);
-            x[C + 12] = fmaf(sr, kz, x[C + 12]);
+            const float kz = tv.w;
+            const float ak = amp[c] * aw, kak = kz * ak;
+            const float rr = ak * gr, kr = kak * gr;
+            const float sa = copysignf(amp[c], kw);   // Re rho / w = sa gr
+            tI = fmaf(ak, gi, tI);
+            x[C + 3] = fmaf(kak, gi, x[C + 3]);      // Z
+            tU = fmaf(u, rr, tU);
+            x[C + 6] = fmaf(u, kr, x[C + 6]);        // SUz
+            tV = fmaf(v, rr, tV);
+            x[C + 9] = fmaf(v, kr, x[C + 9]);        // SVz
+            tS = fmaf(sa, gr, tS);
+            x[C + 12] = fmaf(kz * sa, gr, x[C + 12]);   // SNz
         }
+        x[C + 2] = fmaf(my, tI, x[C + 2]);           // Sy
+        x[C + 5] = fmaf(my, tU, x[C + 5]);           // SUy
+        x[C + 8] = fmaf(my, tV, x[C + 8]);           // SVy
+        x[C + 11] = fmaf(my, tS, x[C + 11]);         // SNy
+        aI += tI;
+        aU += tU;
+        aV += tV;
+        aS += tS;
     }
+    x[C + 0] = aI;
+    x[C + 1] = mx * aI;                              // Sx
+    x[C + 4] = mx * aU;                              // SUx
+    x[C + 7] = mx * aV;                              // SVx
+    x[C + 10] = mx * aS;                             // SNx
 }
 
+static __device__ __forceinline__ float rl_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+static __device__ __forceinline__ uint32_t rl_u(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
 template <int C>
-__global__ void __launch_bounds__(TWG, TILT_ADJ_WAVES) k_tilt_adjoint(Consts k, const TRec *__restrict__ rec,
-                                                                        const int2 *__restrict__ rect, int64_t n,
-                                                                        const float2 *__restrict__ gspec,
-                                                                        const int64_t *__restrict__ off,
-                                                                        float *__restrict__ part, int n_queue,
-                                                                        long long *__restrict__ counters)
+__global__ void __launch_bounds__(TWG, tilt_adj_waves(C)) k_tilt_adjoint(Consts k, const TRec *__restrict__ rec,
+                                                                          const int2 *__restrict__ rect, int64_t n,
+                                                                          const float2 *__restrict__ gspec,
+                                                                          const int64_t *__restrict__ off,
+                                                                          float *__restrict__ part, int n_queue,
+                                                                          long long *__restrict__ counters)
 {
-    constexpr int TE = te_floats(C);
     constexpr int NV = tilt_nv(C), NVP = tilt_nvp(C);
     __shared__ int s_idx[TWG];
     __shared__ int s_cnt[4];
     __shared__ int s_tile;
-    __shared__ __align__(16) float s_w[4][64][TE];
-    __shared__ float2 s_g[4][TF][C][64];
-    __shared__ float s_part[4][64][NV];
+    __shared__ int s_e[4];
+    __shared__ float s_dm[4][C];
+    __shared__ float4 s_t[TA_F][C][64];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hx = k.nx / 2, hy = k.ny / 2;
@@ -553,11 +580,8 @@ __global__ void __launch_bounds__(TWG, TILT_ADJ_WAVES) k_tilt_adjoint(Consts k, 
     for (int c = 0; c < C; ++c) ilam[c] = k.inv_lambda[c];
     const float lim = (float)(k.tau2 * (1.0 + 1e-5)) + 1e-4f;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int col = lane & 15, row0 = lane >> 4;
-    const float dxf = (float)(col - 8);
-    float dyf[TF];
-#pragma unroll
-    for (int f = 0; f < TF; ++f) dyf[f] = (float)(row0 + 4 * f - 8);
+    const int col = lane & 31, row0 = lane >> 5;
+    const float dxf = (float)(col - 16);
     long long pairs = 0;
 
     for (;;) {
@@ -569,59 +593,78 @@ __global__ void __launch_bounds__(TWG, TILT_ADJ_WAVES) k_tilt_adjoint(Consts k, 
         int tx, ty;
         ring_tile(q, &tx, &ty);
         if (tx * TT >= hx || (tx + 1) * TT <= -hx || ty * TT >= hy || (ty + 1) * TT <= -hy) continue;
-        const int sx0 = tx * TT + (wave & 1) * 16, sy0 = ty * TT + (wave >> 1) * 16;
-        const int cx = sx0 + 8, cy = sy0 + 8;
-        const int mxp = sx0 + col;
-        const float mxw = (float)mxp;
+        const int mx0 = tx * TT, my0 = ty * TT, cx = mx0 + 16, cy = my0 + 16;
         double D0[C];
-        float dD[TF][C], lkz[TF][C], dmax[C], kz0[C], myf[TF];
         {
             const double ncx = cx / Wx, ncy = cy / Wy;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                D0[c] = dprop_t(ncx * ncx + ncy * ncy, k.inv_lambda[c]);
-                kz0[c] = (float)(k.inv_lambda[c] + D0[c]);
-                dmax[c] = 0.0f;
-            }
+            for (int c = 0; c < C; ++c) D0[c] = dprop_t(ncx * ncx + ncy * ncy, ilam[c]);
         }
+        // The tile's tables: |Gs| first (its largest binary exponent e_t over the tile is taken
+        // out of the logarithm, and the tile's sums are scaled by 2^e_t when written).
+        float dm[C];
+        int emax = -1000;
 #pragma unroll
-        for (int f = 0; f < TF; ++f) {
-            const int myp = sy0 + row0 + 4 * f;
-            myf[f] = (float)myp;
-            const double nux = mxp / Wx, nuy = myp / Wy;
-            const double nu2 = nux * nux + nuy * nuy;
+        for (int c = 0; c < C; ++c) dm[c] = 0.0f;
+        for (int p = tid; p < TA_F * 64; p += TWG) {
+            const int l = p & 63, f = p >> 6;
+            const int mxp = mx0 + (l & 31), myp = my0 + (l >> 5) + 2 * f;
+            const double nux = mxp / Wx, nuy = myp / Wy, nu2 = nux * nux + nuy * nuy;
             const bool in_grid = mxp >= -hx && mxp < hx && myp >= -hy && myp < hy;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const double il = k.inv_lambda[c];
+                const double il = ilam[c];
                 const double w2 = il * il - nu2;
-                float2 gv = make_float2(0.0f, 0.0f);
+                float4 tv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // evanescent: no contribution
                 if (w2 > 0.0) {
                     const double kz = sqrt(w2);
-                    const double dd = -nu2 / (il + kz) - D0[c];
-                    dD[f][c] = (float)dd;
-                    lkz[f][c] = (float)log2(il / kz);
+                    tv.x = (float)(-nu2 / (il + kz) - D0[c]);
+                    tv.w = (float)kz;
                     if (in_grid) {
-                        const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
-                        const float2 g = gspec[((int64_t)c * k.ny + my) * k.nx + mx];
-                        gv = make_float2(hypotf(g.x, g.y), atan2f(g.y, g.x) * 0.15915494309189535f);
+                        const int gx = mxp < 0 ? mxp + k.nx : mxp, gy = myp < 0 ? myp + k.ny : myp;
+                        const float2 g = gspec[((int64_t)c * k.ny + gy) * k.nx + gx];
+                        tv.y = hypotf(g.x, g.y);
+                        tv.z = atan2f(g.y, g.x) * 0.15915494309189535f;
+                        if (tv.y > 0.0f) emax = max(emax, ilogbf(tv.y));
                     }
-                } else {
-                    dD[f][c] = 0.0f;
-                    lkz[f][c] = -1000.0f;
                 }
-                s_g[wave][f][c][lane] = gv;   // outside the grid |Gs| = 0: no contribution
-                dmax[c] = fmaxf(dmax[c], fabsf(dD[f][c]));
+                dm[c] = fmaxf(dm[c], fabsf(tv.x));
+                s_t[f][c][l] = tv;
             }
         }
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            for (int o = 32; o >= 1; o >>= 1) dmax[c] = fmaxf(dmax[c], __shfl_xor(dmax[c], o));
-        float dmax_all = 0.0f;
+            for (int o = 32; o >= 1; o >>= 1) dm[c] = fmaxf(dm[c], __shfl_xor(dm[c], o));
+        for (int o = 32; o >= 1; o >>= 1) emax = max(emax, __shfl_xor(emax, o));
+        if (lane == 0) {
+            s_e[wave] = emax;
 #pragma unroll
-        for (int c = 0; c < C; ++c) dmax_all = fmaxf(dmax_all, dmax[c]);
-        const int rlo = max(sy0, -hy), rhi = min(sy0 + 15, hy - 1);
-        const bool wave_live = (max(sx0, -hx) <= min(sx0 + 15, hx - 1)) && (rlo <= rhi);
+            for (int c = 0; c < C; ++c) s_dm[wave][c] = dm[c];
+        }
+        __syncthreads();
+        const int et = max(max(s_e[0], s_e[1]), max(s_e[2], s_e[3]));
+        const int es = et > -1000 ? et : 0;
+        float dmax[C], dmax_all = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            dmax[c] = fmaxf(fmaxf(s_dm[0][c], s_dm[1][c]), fmaxf(s_dm[2][c], s_dm[3][c]));
+            dmax_all = fmaxf(dmax_all, dmax[c]);
+        }
+        // the same entries, by the same threads: |Gs| -> log2(|Gs| 2^-e_t / (k_z lambda))
+        for (int p = tid; p < TA_F * 64; p += TWG) {
+            const int l = p & 63, f = p >> 6;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float4 tv = s_t[f][c][l];
+                tv.y = (tv.y > 0.0f && tv.w > 0.0f)
+                           ? fmaxf((float)(log2(ilam[c] / (double)tv.w) + (double)log2f(ldexpf(tv.y, -es))), -1000.0f)
+                           : -1000.0f;
+                s_t[f][c][l] = tv;
+            }
+        }
+        __syncthreads();
+        const int rlo = max(my0, -hy), rhi = min(my0 + TT - 1, hy - 1);
+        const int mxp = mx0 + col, myl = my0 + row0;
 
         for (int64_t base = 0; base < n; base += TWG) {
             const int64_t gi = base + tid;
@@ -644,124 +687,124 @@ __global__ void __launch_bounds__(TWG, TILT_ADJ_WAVES) k_tilt_adjoint(Consts k, 
             }
             if (pred) s_idx[offs + __popcll(bal & lt)] = (int)gi;
             __syncthreads();
-            // groups of 64 staged Gaussians, every wavefront taking part in each group's barriers
-            for (int j0 = 0; j0 < total; j0 += 64) {
-                const int j = j0 + lane;
+            // staging: lane l of wavefront w holds staged Gaussian 4 l + w at the tile centre
+            const int j = 4 * lane + wave;
+            uint64_t rows = 0;
+            int64_t slot = 0;
+            float eU0 = 0, eU1 = 0, eU2 = 0, eV0 = 0, eV1 = 0, eV2 = 0, eN0 = 0, eN1 = 0, eN2 = 0, ez = 0;
+            float eu0[C], ev0[C], ew0[C], ekc[C], eamp[C];
+            uint32_t erx = 0, ery = 0;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) s_part[wave][lane][v] = 0.0f;
-                uint32_t rows = 0;
-                if (wave_live && j < total) {
-                    const TRec &r = rec[s_idx[j]];
-                    const float4 *src = reinterpret_cast<const float4 *>(&r);
-                    const float4 a0 = src[0], a1 = src[1], a2 = src[2];
-                    const float U0 = a0.x, U1 = a0.y, U2 = a0.z, V0 = a0.w, V1 = a1.x, V2 = a1.y;
-                    const float N0 = a1.z, N1 = a1.w, N2 = a2.x, z = a2.y;
-                    float *e = &s_w[wave][lane][0];
-                    const double ramp_rev =
-                        (double)((uint32_t)cx * __float_as_uint(a2.z) + (uint32_t)cy * __float_as_uint(a2.w)) *
-                        (1.0 / 4294967296.0);
-                    const float ez0 = fabsf(U0) * 8.0f + fabsf(U1) * 1.5f, fz0 = fabsf(V0) * 8.0f + fabsf(V1) * 1.5f;
+            for (int c = 0; c < C; ++c) eu0[c] = ev0[c] = ew0[c] = ekc[c] = eamp[c] = 0.0f;
+            if (j < total) {
+                const int gidx = s_idx[j];
+                const TRec &r = rec[gidx];
+                const float4 *src = reinterpret_cast<const float4 *>(&r);
+                const float4 a0 = src[0], a1 = src[1], a2 = src[2];
+                eU0 = a0.x; eU1 = a0.y; eU2 = a0.z; eV0 = a0.w; eV1 = a1.x; eV2 = a1.y;
+                eN0 = a1.z; eN1 = a1.w; eN2 = a2.x; ez = a2.y;
+                erx = __float_as_uint(a2.z);
+                ery = __float_as_uint(a2.w);
+                const float ez0 = fabsf(eU0) * 16.0f + fabsf(eU1) * 0.5f, fz0 = fabsf(eV0) * 16.0f + fabsf(eV1) * 0.5f;
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        const double kzc = k.inv_lambda[c] + D0[c];
-                        const float u0 = (float)((double)U0 * cx + (double)U1 * cy + (double)U2 * kzc);
-                        const float v0 = (float)((double)V0 * cx + (double)V1 * cy + (double)V2 * kzc);
-                        const float kap = r.kappa[c];
-                        float bs;
-                        if (k.phase_mode == 1) {
-                            const float vv = kap - ((float)cx * r.rxf + (float)cy * r.ryf) - z * (float)D0[c];
-                            bs = vv - floorf(vv);
-                        } else {
-                            bs = (float)frac_t((double)kap - ramp_rev - (double)z * D0[c]);
-                        }
-                        e[13 + c] = u0;
-                        e[13 + C + c] = v0;
-                        e[13 + 2 * C + c] = (float)((double)N0 * cx + (double)N1 * cy + (double)N2 * kzc);
-                        e[13 + 3 * C + c] = bs;
-                        e[13 + 4 * C + c] = r.amp[c];
-                        const float eu = fmaf(fabsf(U2), dmax[c], ez0), ev = fmaf(fabsf(V2), dmax[c], fz0);
-#pragma unroll
-                        for (int f = 0; f < TF; ++f) {
-                            const int b0 = sy0 + 4 * f;
-                            if (b0 + 3 < rlo || b0 > rhi) continue;
-                            const float dyc = (float)(4 * f) - 6.5f;
-                            const float mu = fmaxf(fabsf(fmaf(U1, dyc, u0)) - eu, 0.0f);
-                            const float mv = fmaxf(fabsf(fmaf(V1, dyc, v0)) - ev, 0.0f);
-                            if (fmaf(mu, mu, mv * mv) <= lim) rows |= 1u << (c * TF + f);
-                        }
+                for (int c = 0; c < C; ++c) {
+                    const double kzc = ilam[c] + D0[c];
+                    eu0[c] = (float)((double)eU0 * cx + (double)eU1 * cy + (double)eU2 * kzc);
+                    ev0[c] = (float)((double)eV0 * cx + (double)eV1 * cy + (double)eV2 * kzc);
+                    ew0[c] = (float)((double)eN0 * cx + (double)eN1 * cy + (double)eN2 * kzc);
+                    const float kap = r.kappa[c];
+                    if (k.phase_mode == 1) {
+                        const float vv = kap - ez * (float)D0[c];
+                        ekc[c] = vv - floorf(vv);
+                    } else {
+                        ekc[c] = (float)frac_t((double)kap - (double)ez * D0[c]);
                     }
-                    if (rows) {
-                        reinterpret_cast<float4 *>(e)[0] = a0;
-                        reinterpret_cast<float4 *>(e)[1] = a1;
-                        reinterpret_cast<float4 *>(e)[2] = make_float4(N2, z, r.rxf, r.ryf);
-                        e[12] = __uint_as_float(rows);
-                        pairs += __popc(rows) * 64;
+                    eamp[c] = r.amp[c];
+                    // row pairs the support can reach: bounds of u and v over the pair
+                    const float eu = fmaf(fabsf(eU2), dmax[c], ez0), ev = fmaf(fabsf(eV2), dmax[c], fz0);
+#pragma unroll
+                    for (int f = 0; f < TA_F; ++f) {
+                        const int b0 = my0 + 2 * f;
+                        if (b0 + 1 < rlo || b0 > rhi) continue;
+                        const float dyc = (float)(2 * f) - 15.5f;
+                        const float mu = fmaxf(fabsf(fmaf(eU1, dyc, eu0[c])) - eu, 0.0f);
+                        const float mv = fmaxf(fabsf(fmaf(eV1, dyc, ev0[c])) - ev, 0.0f);
+                        if (fmaf(mu, mu, mv * mv) <= lim) rows |= 1ull << (f * C + c);
                     }
                 }
-                uint64_t live = __ballot(rows != 0);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                while (live) {
-                    const int ei = __builtin_ctzll(live);
-                    live &= live - 1;
-                    const float *w = &s_w[wave][ei][0];
-                    const float U0 = w[0], U1 = w[1], U2 = w[2], V0 = w[3], V1 = w[4], V2 = w[5];
-                    const float N0 = w[6], N1 = w[7], N2 = w[8], z = w[9], rxf = w[10], ryf = w[11];
-                    const uint32_t erows = __builtin_amdgcn_readfirstlane(__float_as_uint(w[12]));
-                    const float lux = U0 * dxf, lvx = V0 * dxf, lwx = N0 * dxf;
-                    float u0[C], v0[C], w0[C], bx[C], amp[C];
+                const int2 b = rect[gidx];
+                const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
+                const int ty0 = (int)(int16_t)(b.y & 0xffff);
+                slot = off[gidx] + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
+                pairs += (long long)__popcll(rows) * 64;
+                if (!rows) {   // the rectangle reaches the tile, the support does not: its slot holds zeros
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        u0[c] = w[13 + c] + lux;
-                        v0[c] = w[13 + C + c] + lvx;
-                        w0[c] = w[13 + 2 * C + c] + lwx;
-                        bx[c] = __builtin_amdgcn_fractf(fmaf(-dxf, rxf, w[13 + 3 * C + c]));
-                        amp[c] = w[13 + 4 * C + c];
-                    }
-                    float x[NVP];
-#pragma unroll
-                    for (int v = 0; v < NVP; ++v) x[v] = 0.0f;
-                    if (fabsf(z) * dmax_all > 16.0f)
-                        tilt_adj_eval<C, true>(erows, U1, U2, V1, V2, N1, N2, z, ryf, mxw, u0, v0, w0, bx, amp, kz0,
-                                               dyf, myf, dD, lkz, D0, ilam, 1.0 / Wx, 1.0 / Wy, s_g[wave], lane, x);
-                    else
-                        tilt_adj_eval<C, false>(erows, U1, U2, V1, V2, N1, N2, z, ryf, mxw, u0, v0, w0, bx, amp, kz0,
-                                                dyf, myf, dD, lkz, D0, ilam, 1.0 / Wx, 1.0 / Wy, s_g[wave], lane, x);
-                    // sums over the wavefront: after the transposed butterfly register j of lane l
-                    // holds value 2 (4 b5 + 2 b4 + b3) + j (and + 16 for the second block)
-                    float y0 = 0.0f;
-                    float xa[16];
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) xa[v] = x[v];
-                    reduce_transposed<16, false>(xa, y0, lane);
-                    const int g8 = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-                    if ((lane & 7) == 0) {
-#pragma unroll
-                        for (int jj = 0; jj < 2; ++jj)
-                            if (2 * g8 + jj < NV) s_part[wave][ei][2 * g8 + jj] = xa[jj];
-                    }
-                    if constexpr (NVP > 16) {
-                        float xb[8];
-#pragma unroll
-                        for (int v = 0; v < 8; ++v) xb[v] = x[16 + v];
-                        reduce_transposed<8, false>(xb, y0, lane);
-                        if ((lane & 7) == 0 && 16 + g8 < NV) s_part[wave][ei][16 + g8] = xb[0];
-                    }
+                    for (int v = 0; v < NV; ++v) part[slot * NV + v] = 0.0f;
                 }
-                __syncthreads();   // every wavefront's sums of this group are in LDS
-                const int cnt = min(64, total - j0);
-                for (int t = tid; t < cnt * NV; t += TWG) {
-                    const int jj = t / NV, v = t - jj * NV;
-                    const int gidx = s_idx[j0 + jj];
-                    const int2 b = rect[gidx];
-                    const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
-                    const int ty0 = (int)(int16_t)(b.y & 0xffff);
-                    const int64_t slot = off[gidx] + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
-                    part[slot * NV + v] = ((s_part[0][jj][v] + s_part[1][jj][v]) + s_part[2][jj][v]) + s_part[3][jj][v];
-                }
-                __syncthreads();   // before the next group overwrites the sums
             }
+            uint64_t live = __ballot(rows != 0);
+            while (live) {
+                const int ei = __builtin_ctzll(live);
+                live &= live - 1;
+                const float U0 = rl_f(eU0, ei), U1 = rl_f(eU1, ei), U2 = rl_f(eU2, ei);
+                const float V0 = rl_f(eV0, ei), V1 = rl_f(eV1, ei), V2 = rl_f(eV2, ei);
+                const float N0 = rl_f(eN0, ei), N1 = rl_f(eN1, ei), N2 = rl_f(eN2, ei), z = rl_f(ez, ei);
+                const uint64_t erows = ((uint64_t)rl_u((uint32_t)(rows >> 32), ei) << 32) | rl_u((uint32_t)rows, ei);
+                const int64_t eslot = (int64_t)(((uint64_t)rl_u((uint32_t)((uint64_t)slot >> 32), ei) << 32) |
+                                                rl_u((uint32_t)slot, ei));
+                float u0[C], v0[C], w0[C], kc[C], amp[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    u0[c] = fmaf(U0, dxf, rl_f(eu0[c], ei));
+                    v0[c] = fmaf(V0, dxf, rl_f(ev0[c], ei));
+                    w0[c] = fmaf(N0, dxf, rl_f(ew0[c], ei));
+                    kc[c] = rl_f(ekc[c], ei);
+                    amp[c] = rl_f(eamp[c], ei);
+                }
+                // the ramp at the lane's first frequency (m_x, m_y0) and its step over two rows
+                const uint32_t rx = rl_u(erx, ei), ry = rl_u(ery, ei);
+                uint32_t r0;
+                if (k.phase_mode == 1) {
+                    // FP32 ramp (the record's rounded r): m_x r_x + m_y r_y, its fraction
+                    const float vv = (float)mxp * ((float)(int32_t)rx * 0x1p-32f) + (float)myl * ((float)(int32_t)ry * 0x1p-32f);
+                    r0 = (uint32_t)(int64_t)((vv - floorf(vv)) * 4294967296.0f);
+                } else {
+                    r0 = (uint32_t)mxp * rx + (uint32_t)myl * ry;
+                }
+                const uint32_t r2 = 2u * ry;
+                float x[NVP];
+#pragma unroll
+                for (int v = 0; v < NVP; ++v) x[v] = 0.0f;
+                const float dy0 = (float)(row0 - 16), myf0 = (float)myl, mxw = (float)mxp;
+                if (fabsf(z) * dmax_all > 16.0f)
+                    tilt_adj_eval<C, true>(erows, s_t, lane, U1, U2, V1, V2, N1, N2, z, dy0, myf0, mxw, r0, r2, u0, v0,
+                                           w0, kc, amp, D0, ilam, 1.0 / Wx, 1.0 / Wy, x);
+                else
+                    tilt_adj_eval<C, false>(erows, s_t, lane, U1, U2, V1, V2, N1, N2, z, dy0, myf0, mxw, r0, r2, u0, v0,
+                                            w0, kc, amp, D0, ilam, 1.0 / Wx, 1.0 / Wy, x);
+                // sums over the wavefront: after the transposed butterfly register j of lane l
+                // holds value 2 (4 b5 + 2 b4 + b3) + j (and + 16 for the second block)
+                float y0 = 0.0f;
+                float xa[16];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) xa[v] = x[v];
+                reduce_transposed<16, false>(xa, y0, lane);
+                const int g8 = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+                float *dst = part + eslot * NV;
+                if ((lane & 7) == 0) {
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj)
+                        if (2 * g8 + jj < NV) dst[2 * g8 + jj] = ldexpf(xa[jj], es);
+                }
+                if constexpr (NVP > 16) {
+                    float xb[8];
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) xb[v] = x[16 + v];
+                    reduce_transposed<8, false>(xb, y0, lane);
+                    if ((lane & 7) == 0 && 16 + g8 < NV) dst[16 + g8] = ldexpf(xb[0], es);
+                }
+            }
+            __syncthreads();   // before the next chunk overwrites the staged indices
         }
     }
     pairs = wave_sum_i64(pairs);
