@@ -44,6 +44,7 @@ int main(void) {
     bad |= gws_forward(NULL, &p, NULL, NULL, NULL, 0, NULL) == GWS_OK;
     bad |= gws_forward_tilted(NULL, &p, NULL, NULL, NULL, 0, NULL) == GWS_OK;
     bad |= gws_backward(NULL, &p, NULL, NULL, NULL, NULL, 0, NULL) == GWS_OK;
+    bad |= gws_backward_tilted(NULL, &p, NULL, NULL, NULL, NULL, 0, NULL) == GWS_OK;
     bad |= gws_destroy(NULL) != GWS_OK;
     printf("%s\n", bad ? "FAIL" : "OK");
     return bad;

@@ -233,6 +233,28 @@ def test_tilted_backward_culled_zero_opacity_and_determinism(ctx):
     assert abs(a["opacity"][0]) > 0
 
 
+def test_tilted_fp32_phase_mode(ctx):
+    """phase_mode 1 (the carrier and ramp bases formed in FP32 instead of FP64): on a grid whose
+    phases stay small it still meets the oracle, forward and backward, and differs from the FP64
+    bases only by FP32 rounding."""
+    import torch
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_tilted_scene(40, grid, 928, depth_range=(-2e-3, 2e-3), tilt_max_deg=2.0)
+    g = scene_to_torch(scene)
+    u1 = to_numpy(ctx.forward_tilted(problem(grid, phase_mode=1), g))
+    u0 = to_numpy(ctx.forward_tilted(problem(grid), g))
+    ref = otl.forward(scene, grid)
+    e1, e01 = rel_l2(u1, ref), rel_l2(u1, u0)
+    G = gwsgen.make_target(grid, 929)
+    got = {k: to_numpy(v) for k, v in ctx.backward_tilted(problem(grid, phase_mode=1), g,
+                                                          torch.from_numpy(G).cuda()).items()}
+    eg = grads_rel(got, otg.backward(scene, grid, G), otg.PARAMS)
+    log("tilted phase_mode 1: field rel L2 %.2e (vs FP64 bases %.2e), gradients %s"
+        % (e1, e01, {k: "%.2e" % v for k, v in eg.items()}))
+    assert e1 < 1e-4 and e01 < 1e-4
+    assert max(eg.values()) < 1e-3, eg
+
+
 def test_tilted_backward_workload_100k_sampled(ctx):
     """Gradients of the tilted100k workload in the launch configuration the bench times, checked
     for four sampled Gaussians (each Gaussian's gradient depends only on its own term and the
