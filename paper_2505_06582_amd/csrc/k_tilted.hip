@@ -19,9 +19,9 @@
 //
 // Precision: u, v, w are large sums of nearly cancelling terms (R31 k_z alone reaches
 // ~1e2 in exp2 units at a few degrees of tilt), so as the phase they are split into an FP64
-// base at the centre of each 16 x 16 sub-tile (per sub-tile and Gaussian, one lane per
-// Gaussian) and FP32 deltas per lane: u = u0 + U_x dx + U_y dy + U_z (D_c(m) - D_c(m0)),
-// D_c = k_z,c - 1/lambda_c.
+// base at the centre of each 16 x 16 sub-tile in the forward (of each 32 x 32 tile in the
+// adjoint), formed per Gaussian by one lane, and FP32 deltas per lane:
+// u = u0 + U_x dx + U_y dy + U_z (D_c(m) - D_c(m0)), D_c = k_z,c - 1/lambda_c.
 //
 // Work.  The support of a tilted Gaussian sits near n_xy / lambda_c (n = R e_z, the disk's
 // normal), one off-centre patch per wavelength, so the in-plane path's DC-centred binning does
