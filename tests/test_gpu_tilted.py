@@ -21,6 +21,7 @@ from gpu_util import dft_ready, problem, rel_l2, scene_to_torch, stratified_freq
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+FOUR = (638e-9, 520e-9, 450e-9, 405e-9)
 
 
 @pytest.fixture(scope="module")
@@ -42,6 +43,7 @@ CASES = [
     (48, 40, 8e-6, (520e-9,), 60, 903, (1.0, 6.0), 3.0),
     (128, 96, 1e-6, (520e-9, 450e-9), 120, 904, (1.0, 4.0), 25.0),
     (64, 72, 0.25e-6, (633e-9,), 80, 905, (2.0, 6.0), 28.0),   # band past 1/lambda: evanescent corners
+    (64, 48, 8e-6, FOUR, 60, 906, (2.0, 20.0), 2.0),             # four wavelengths (the problem's maximum)
 ]
 
 
@@ -179,6 +181,7 @@ BWD_CASES = [
     (48, 40, 8e-6, (520e-9,), 20, 922, (1.0, 6.0), 3.0),
     (128, 96, 1e-6, (520e-9, 450e-9), 24, 923, (1.0, 4.0), 25.0),
     (64, 72, 0.25e-6, (633e-9,), 16, 924, (2.0, 6.0), 28.0),
+    (64, 48, 8e-6, FOUR, 16, 930, (2.0, 20.0), 2.0),
 ]
 
 
