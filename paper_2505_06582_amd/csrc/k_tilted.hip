@@ -600,8 +600,9 @@ __global__ void __launch_bounds__(TWG, tilt_adj_waves(C)) k_tilt_adjoint(Consts 
 #pragma unroll
             for (int c = 0; c < C; ++c) D0[c] = dprop_t(ncx * ncx + ncy * ncy, ilam[c]);
         }
-        // The tile's tables: |Gs| first (its largest binary exponent e_t over the tile is taken
-        // out of the logarithm, and the tile's sums are scaled by 2^e_t when written).
+        // The tile's tables: |Gs| first (its largest finite binary exponent e_t over the tile is
+        // taken out of the logarithm, and the tile's sums are scaled by 2^e_t when written; an
+        // infinite |Gs| still reaches the sums as one).
         float dm[C];
         int emax = -1000;
 #pragma unroll
@@ -625,7 +626,7 @@ __global__ void __launch_bounds__(TWG, tilt_adj_waves(C)) k_tilt_adjoint(Consts 
                         const float2 g = gspec[((int64_t)c * k.ny + gy) * k.nx + gx];
                         tv.y = hypotf(g.x, g.y);
                         tv.z = atan2f(g.y, g.x) * 0.15915494309189535f;
-                        if (tv.y > 0.0f) emax = max(emax, ilogbf(tv.y));
+                        if (tv.y > 0.0f && tv.y <= 3.4028234663852886e38f) emax = max(emax, ilogbf(tv.y));
                     }
                 }
                 dm[c] = fmaxf(dm[c], fabsf(tv.x));
