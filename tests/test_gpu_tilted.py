@@ -260,8 +260,9 @@ def test_tilted_fp32_phase_mode(ctx):
 
 def test_tilted_backward_workload_100k_sampled(ctx):
     """Gradients of the tilted100k workload in the launch configuration the bench times, checked
-    for four sampled Gaussians (each Gaussian's gradient depends only on its own term and the
-    given field gradient, so the oracle computes it alone)."""
+    for eight Gaussians -- the narrowest and the widest, the most tilted, the deepest, and four
+    drawn at random (each Gaussian's gradient depends only on its own term and the given field
+    gradient, so the oracle computes it alone)."""
     import torch
     grid = Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
     scene = gwsgen.make_tilted_scene(100_000, grid, 1005, depth_range=(-10e-3, 10e-3), tilt_max_deg=2.0)
@@ -269,11 +270,20 @@ def test_tilted_backward_workload_100k_sampled(ctx):
     got = ctx.backward_tilted(problem(grid), scene_to_torch(scene), torch.from_numpy(G).cuda())
     got = {k: to_numpy(v) for k, v in got.items()}
     rng = np.random.default_rng(927)
-    for i in rng.choice(scene.n, 4, replace=False):
+    smin = np.minimum(scene.scale_u, scene.scale_v)
+    smax = np.maximum(scene.scale_u, scene.scale_v)
+    tilt = scene.quat_x.astype(np.float64) ** 2 + scene.quat_y.astype(np.float64) ** 2
+    picks = [int(np.argmin(smin)), int(np.argmax(smax)), int(np.argmax(tilt)), int(np.argmax(np.abs(scene.depth)))]
+    picks += [int(i) for i in rng.choice(scene.n, 4, replace=False)]
+    refs = []
+    for i in picks:
         log("tilted 100k backward: oracle for Gaussian %d" % i)
-        ref = otg.backward(scene.subset([i]), grid, G)
-        for k in otg.PARAMS:
-            g = got[k][:, i] if k == "amplitude" else got[k][i]
-            r = np.ravel(ref[k])
-            err = np.max(np.abs(np.ravel(g) - r)) / max(np.max(np.abs(r)), 1e-300)
-            assert err < 1e-3, (i, k, np.ravel(g), r)
+        refs.append(otg.backward(scene.subset([i]), grid, G))
+    for k in otg.PARAMS:
+        g = np.stack([np.ravel(got[k][:, i] if k == "amplitude" else got[k][i]) for i in picks])
+        r = np.stack([np.ravel(ref[k]) for ref in refs])
+        e = rel_l2(g, r)
+        log("  %-9s rel L2 over the sample %.3e" % (k, e))
+        # over the sample, and componentwise with an absolute floor of 1e-4 x the sample's norm
+        assert e < 1e-4, (k, e)
+        assert np.all(np.abs(g - r) <= 1e-3 * np.abs(r) + 1e-4 * np.linalg.norm(r)), (k, g, r)
