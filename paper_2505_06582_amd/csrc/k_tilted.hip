@@ -458,7 +458,8 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
 //
 // The kernel walks the forward's tiles with the work split the other way: the work-group builds
 // the tile's per-frequency tables once in LDS (per wavelength D_c(m) - D_c(m0), log2 of
-// |Gs_c| / (k_z lambda_c), arg Gs_c / 2 pi and k_z), and each wavefront takes whole staged
+// |Gs_c| 2^-e_t / (k_z lambda_c) with 2^e_t the tile's scale of |Gs|, arg Gs_c / 2 pi and k_z),
+// and each wavefront takes whole staged
 // Gaussians over the 32 x 32 tile (lane l: column l % 32 and rows l / 32 + 2 f, f < 16), so a
 // Gaussian's sums over the tile come out of one transposed cross-lane reduction and go straight
 // to its slot for the tile -- off[i] + the tile's place in Gaussian i's rectangle.  Every slot is
@@ -502,7 +503,7 @@ static __device__ __forceinline__ void tilt_adj_eval(uint64_t rows, const float4
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             if (!(fb & (1u << c))) continue;
-            const float4 tv = tab[f][c][lane];   // D_c(m) - D_c(m0), log2(|Gs| / (k_z lambda)), arg Gs / 2 pi, k_z
+            const float4 tv = tab[f][c][lane];   // D_c(m) - D_c(m0), log2(|Gs| 2^-e_t / (k_z lambda)), arg Gs / 2 pi, k_z
             const float d = tv.x;
             const float u = fmaf(U2, d, fmaf(U1, dy, u0[c]));
             const float v = fmaf(V2, d, fmaf(V1, dy, v0[c]));
