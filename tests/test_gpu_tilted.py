@@ -210,6 +210,21 @@ def test_tilted_backward_matches_oracle(ctx, case):
     assert max(e.values()) < GRAD_TOL, e
 
 
+def test_tilted_backward_split_bf16_transform(ctx):
+    """The adjoint with the split-bf16 MFMA DFT taking the field gradient to Gs."""
+    import torch
+    import paper_2505_06582_amd as gws
+    grid = Grid(96, 80, 8e-6, 8e-6, gwsgen.RGB)
+    scene = gwsgen.make_tilted_scene(30, grid, 931, depth_range=(-10e-3, 10e-3))
+    G = gwsgen.make_target(grid, 932)
+    got = ctx.backward_tilted(problem(grid, xform=gws.XFORM_DFT_BF16X3), scene_to_torch(scene),
+                              torch.from_numpy(G).cuda())
+    got = {k: to_numpy(v) for k, v in got.items()}
+    e = grads_rel(got, otg.backward(scene, grid, G), otg.PARAMS)
+    log("tilted backward, split-bf16 transform: %s" % {k: "%.2e" % v for k, v in e.items()})
+    assert max(e.values()) < GRAD_TOL, e
+
+
 def test_tilted_backward_culled_zero_opacity_and_determinism(ctx):
     import torch
     grid = Grid(64, 48, 8e-6, 8e-6, gwsgen.RGB)
