@@ -17,6 +17,7 @@ import threading
 from typing import Dict, Optional, Sequence
 
 __all__ = ["LIB_PATH", "GwsError", "Problem", "Context", "load_library", "render", "GaussianWaveSplat",
+           "render_tilted", "TiltedGaussianWaveSplat", "TILTED_PARAMS",
            "STATUS", "XFORM_FFT_FP32", "XFORM_DFT_BF16X3", "check_gaussians", "check_tensor", "check_offsets"]
 
 # The in-tree build; GWS_LIBRARY names another build of the same library (e.g. to compare two).
@@ -723,3 +724,42 @@ def render(prob: Problem, mean_x, mean_y, depth, cov_xx, cov_xy, cov_yy, opacity
     """Differentiable field of the Gaussians at the SLM plane, (n_lambda, ny, nx) complex64."""
     return GaussianWaveSplat.function().apply(prob, mean_x, mean_y, depth, cov_xx, cov_xy, cov_yy, opacity,
                                               amplitude, phase)
+
+
+class TiltedGaussianWaveSplat:
+    """torch.autograd.Function wrapper for tilted Gaussians: field = gws_forward_tilted(params);
+    backward through gws_backward_tilted (every parameter's gradient is computed in one call)."""
+
+    _fn = None
+
+    @classmethod
+    def function(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(fctx, prob, *params):
+                    g = {k: v.detach().contiguous() for k, v in zip(TILTED_PARAMS, params)}
+                    fctx.prob = prob
+                    fctx.save_for_backward(*[g[k] for k in TILTED_PARAMS])
+                    return context(params[0].device.index or 0).forward_tilted(prob, g)
+
+                @staticmethod
+                def backward(fctx, grad_field):
+                    saved = dict(zip(TILTED_PARAMS, fctx.saved_tensors))
+                    dev = saved["mean_x"].device.index or 0
+                    grads = context(dev).backward_tilted(fctx.prob, saved, grad_field.contiguous())
+                    return (None,) + tuple(grads[k] if fctx.needs_input_grad[i + 1] else None
+                                           for i, k in enumerate(TILTED_PARAMS))
+
+            cls._fn = _F
+        return cls._fn
+
+
+def render_tilted(prob: Problem, mean_x, mean_y, depth, quat_w, quat_x, quat_y, quat_z, scale_u, scale_v, opacity,
+                  amplitude, phase):
+    """Differentiable field of tilted Gaussians (fields TILTED_PARAMS) at the SLM plane,
+    (n_lambda, ny, nx) complex64."""
+    return TiltedGaussianWaveSplat.function().apply(prob, mean_x, mean_y, depth, quat_w, quat_x, quat_y, quat_z,
+                                                    scale_u, scale_v, opacity, amplitude, phase)

@@ -225,6 +225,33 @@ def test_tilted_backward_split_bf16_transform(ctx):
     assert max(e.values()) < GRAD_TOL, e
 
 
+def test_render_tilted_autograd(ctx):
+    """The torch.autograd.Function path (render_tilted + loss.backward) against the float64
+    autograd oracle of the same loss, and bitwise against a direct backward_tilted call."""
+    import torch
+    import paper_2505_06582_amd as gws
+    grid = Grid(64, 48, 8e-6, 8e-6, (520e-9, 638e-9))
+    scene = gwsgen.make_tilted_scene(12, grid, 933, depth_range=(-5e-3, 5e-3), tilt_max_deg=10.0)
+    t = gwsgen.make_target(grid, 934)   # a random target: no cancellation in the loss's gradient
+    prob = problem(grid)
+    params = {k: v.clone().requires_grad_(True) for k, v in scene_to_torch(scene).items()}
+    u = gws.render_tilted(prob, *[params[k] for k in gws.TILTED_PARAMS])
+    tt = torch.from_numpy(t.astype(np.complex64)).cuda()
+    r = u - tt
+    loss = torch.sum(r.real ** 2 + r.imag ** 2)   # its field gradient is exactly 2 (u - t)
+    loss.backward()
+    # the same step by hand: dL/dRe u + j dL/dIm u = 2 (u - t)
+    direct = ctx.backward_tilted(prob, scene_to_torch(scene), (2 * (u.detach() - tt)).contiguous())
+    for k in gws.TILTED_PARAMS:
+        assert torch.equal(params[k].grad, direct[k]), k
+    # the oracle's gradient for the same field gradient (the loss's own cancellations would
+    # otherwise magnify the FP32 field's rounding)
+    G = 2 * (to_numpy(u.detach()).astype(np.complex128) - t.astype(np.complex64).astype(np.complex128))
+    e = grads_rel({k: to_numpy(params[k].grad) for k in gws.TILTED_PARAMS}, otg.backward(scene, grid, G), otg.PARAMS)
+    log("render_tilted autograd: %s" % {k: "%.2e" % v for k, v in e.items()})
+    assert max(e.values()) < GRAD_TOL, e
+
+
 def test_tilted_backward_culled_zero_opacity_and_determinism(ctx):
     import torch
     grid = Grid(64, 48, 8e-6, 8e-6, gwsgen.RGB)
