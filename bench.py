@@ -136,6 +136,8 @@ def main():
         return bench_fwd10k(args)
     if args.workload == "tilted100k":
         return bench_tilted(args)
+    if args.workload == "sizes":
+        return bench_sizes(args)
     log("bench: generating workload %s" % args.workload)
     scene, grid = gwsgen.workload(args.workload)
     target = gwsgen.make_target(grid, 2003)
@@ -616,6 +618,66 @@ def bench_focal(args):
                         "kernel": "focal stack (e^{jP}, forward FFT, per-plane transfer + inverse FFT, |u|^2)",
                         "work_per_launch": "(4 + 4 K) bytes per pixel and wavelength"}}
     print(json.dumps(out), flush=True)
+
+
+def bench_sizes(args):
+    """Throughput against scene size: the fwdbwd100k distributions (1080x1920x3, depths
+    U(-10, 10) mm) at 1k ... 1M Gaussians; per size the forward alone and the training step
+    (forward, L2 loss, backward without the depth gradient), and the work inside the supports."""
+    import numpy as np
+    import torch
+
+    import gwsgen
+    import paper_2505_06582_amd as gws
+    grid = gwsgen.Grid(1920, 1080, 8e-6, 8e-6, gwsgen.RGB)
+    ctx = gws.context(0)
+    dev = torch.device("cuda", 0)
+    prob = gws.Problem.from_grid(grid, tile_config=args.tile_config)
+    target = torch.from_numpy(gwsgen.make_target(grid, 2003)).to(dev)
+    field = torch.empty((grid.n_lambda, grid.ny, grid.nx), dtype=torch.complex64, device=dev)
+    G = torch.empty_like(field)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for j, n in enumerate((1_000, 3_000, 10_000, 30_000, 100_000, 300_000, 1_000_000)):
+        scene = gwsgen.make_scene(n, grid, 1100 + j, depth_range=(-10e-3, 10e-3))
+        g = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.fields().items()}
+        grads = {k: torch.empty_like(v) for k, v in g.items()}
+        steps = max(2, min(args.steps, int(2e6 // n)))
+
+        def fwd():
+            ctx.forward(prob, g, out=field)
+
+        def step():
+            ctx.forward(prob, g, out=field)
+            ctx.l2_loss_grad(field, target, grad=G, loss=loss)
+            ctx.backward(prob, g, G, out=grads, want_depth=False)
+
+        out = {"gaussians": n, "steps": steps}
+        for name, fn in (("forward", fwd), ("fwd_bwd", step)):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out[name + "_ms"] = e0.elapsed_time(e1) / steps
+        pairs = ellipse_support_points(scene, grid)
+        out["support_pairs"] = pairs
+        out["fwd_bwd_pairs_per_s"] = 2 * pairs / (out["fwd_bwd_ms"] * 1e-3)
+        log("bench sizes: %7d Gaussians: forward %.3f ms, fwd+bwd %.3f ms, %.3g support pairs"
+            % (n, out["forward_ms"], out["fwd_bwd_ms"], pairs))
+        rows.append(out)
+        del g, grads
+    big = rows[-1]
+    print(json.dumps({"metric": "holograms/s against scene size, 1080x1920x3 fwd+bwd",
+                      "value": 1e3 / big["fwd_bwd_ms"], "unit": "holograms/s (at 1M Gaussians)", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": big["fwd_bwd_ms"],
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": "sizes: 1k-1M Gaussians, 1080x1920x3"},
+                      "sizes": rows}), flush=True)
 
 
 def bench_fwd10k(args):

@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(1024) k_bin_backward(const int32_t *__restrict
     }
     if (threadIdx.x == 0) {
         const unsigned long long S = red[0];
-        long long trb = 8;
+        long long trb = 1;
         // items <= S / TRB + nchunks <= max_bitems
         const long long room = max_bitems - nchunks;
         if (room > 0) {
