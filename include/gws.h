@@ -242,16 +242,19 @@ typedef struct gws_tilted_gaussians {
 
 /* Bytes of workspace gws_forward_tilted and gws_backward_tilted need for n Gaussians
  * (host-only; ctx may be NULL): 112 bytes per Gaussian (record, tile rectangle, slot offset),
- * the spectrum, and the split-bf16 DFT's planes when problem->xform selects it. */
+ * the spectrum, from 16384 Gaussians up to 8 partial spectra (one per 8192 Gaussians: the
+ * Gaussians reaching a tile are split into parts worked on separately and added in part
+ * order), and the split-bf16 DFT's planes when problem->xform selects it. */
 gws_status gws_workspace_size_tilted(const gws_ctx *ctx, const gws_problem *problem, int64_t n, size_t *bytes);
 
 /* Forward of tilted Gaussians: field (and optionally spectrum) as gws_forward.  Takes the
  * order-invariant blend and on-axis illumination only: blend = GWS_BLEND_EXACT or a non-zero
  * ref_nu returns GWS_ERR_UNSUPPORTED.  eps_support cuts each term where its Gaussian factor
  * is below eps (the Jacobian factor |det J| is not part of the test).  Steps on the stream:
- * records and tile rectangles in input order, spectrum accumulation (one persistent launch,
- * every frequency written once, sum in input order: bitwise reproducible), inverse 2D
- * transform.  No host synchronisation. */
+ * records and tile rectangles in input order, spectrum accumulation (one persistent launch;
+ * each part of the Gaussians writes every frequency of a tile once, sums in input order, and
+ * the parts' spectra are added in part order: bitwise reproducible), inverse 2D transform.
+ * No host synchronisation. */
 gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *problem, const gws_tilted_gaussians *g,
                               const gws_output *out, void *workspace, size_t workspace_bytes, void *stream);
 

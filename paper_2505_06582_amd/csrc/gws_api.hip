@@ -1065,7 +1065,7 @@ extern "C" gws_status gws_forward_noalloc(gws_ctx *ctx, const gws_problem *prob,
 // Tilted Gaussians
 // ---------------------------------------------------------------------------------
 struct TiltLayout {
-    size_t off_rec, off_rect, off_counters, off_spectrum, off_dftws, off_off, off_bsum, total;
+    size_t off_rec, off_rect, off_counters, off_spectrum, off_partial, off_dftws, off_off, off_bsum, total;
 };
 
 static TiltLayout tilt_layout(const gws_problem *p, int64_t n)
@@ -1077,6 +1077,9 @@ static TiltLayout tilt_layout(const gws_problem *p, int64_t n)
     L.off_rect = take((size_t)std::max<int64_t>(n, 1) * sizeof(int2));
     L.off_counters = take(CTR_COUNT * sizeof(long long));
     L.off_spectrum = take((size_t)p->n_lambda * p->nx * p->ny * sizeof(float2));
+    // the forward's partial spectra when a tile's Gaussians are split into parts
+    const int np = tilt_parts(n);
+    L.off_partial = take(np > 1 ? (size_t)np * p->n_lambda * p->nx * p->ny * sizeof(float2) : 0);
     L.off_dftws = take(p->xform == GWS_XFORM_DFT_BF16X3 ? dft_bf16x3_workspace(p->nx, p->ny, p->n_lambda) : 0);
     // the adjoint's slot offsets (n + 1) and the scan's block totals
     L.off_off = take((size_t)(n + 1) * sizeof(int64_t));
@@ -1142,7 +1145,8 @@ extern "C" gws_status gws_forward_tilted(gws_ctx *ctx, const gws_problem *prob, 
     }
     {
         StageScope sc(ctx, s, ST_ACCUM);
-        HIP_CHECK(ctx, launch_tilt_accumulate(k, rec, rect, g->n, spectrum, counters, ctx->n_cu, s));
+        float2 *partial = tilt_parts(g->n) > 1 ? (float2 *)(base + L.off_partial) : nullptr;
+        HIP_CHECK(ctx, launch_tilt_accumulate(k, rec, rect, g->n, spectrum, partial, counters, ctx->n_cu, s));
     }
     {
         StageScope sc(ctx, s, ST_XFORM_INV);

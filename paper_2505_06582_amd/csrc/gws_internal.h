@@ -514,8 +514,12 @@ hipError_t launch_dft_bf16x3(Plan &p, int batch, int direction, const float2 *in
 size_t dft_bf16x3_workspace(int nx, int ny, int batch);
 hipError_t launch_tilt_records(const TView &g, const Consts &k, TRec *rec, int2 *rect, long long *counters,
                                hipStream_t s);
+// Parts a tile's Gaussians are split into (one work item each) for n Gaussians; the forward
+// writes one partial spectrum per part (partial: parts x C x ny x nx, NULL for one part) and
+// adds them in part order.
+int tilt_parts(int64_t n);
 hipError_t launch_tilt_accumulate(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, float2 *spectrum,
-                                  long long *counters, int n_cu, hipStream_t s);
+                                  float2 *partial, long long *counters, int n_cu, hipStream_t s);
 hipError_t launch_tilt_offsets(const int2 *rect, int64_t n, int64_t *off, int64_t *bsum, hipStream_t s);
 hipError_t launch_tilt_adjoint(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, const float2 *gspec,
                                const int64_t *off, float *part, long long *counters, int n_cu, hipStream_t s);

@@ -31,8 +31,10 @@
 // every Gaussian's rectangle in input order (8 bytes each, L2-resident), stages the ones that
 // reach the tile, and each wavefront tests them against its 16 x 16 sub-tile and 4-row blocks
 // (bounds of u and v over the block), forms the FP64 bases and evaluates.  Every frequency of
-// the grid belongs to one tile, so the spectrum is written once with no partial sums, and the
-// order of the sum is fixed: results are bitwise reproducible.
+// the grid belongs to one tile; from 16384 Gaussians a tile's Gaussians are split into parts
+// (one work item each, so the crowded tiles do not hold the launch's tail) whose partial
+// spectra are added in part order.  The order of every sum is fixed: results are bitwise
+// reproducible.
 #include "gws_internal.h"
 
 namespace gws {
@@ -40,6 +42,9 @@ namespace gws {
 constexpr int TT = 32;          // tile side (frequencies)
 constexpr int TF = 4;           // 4-row blocks per sub-tile (16 rows)
 constexpr int TWG = 256;        // threads per work-group (4 wavefronts, one 16 x 16 sub-tile each)
+// A tile's Gaussians are split into up to this many parts (one work item each; one per 8192
+// Gaussians) so that the tiles every support crowds do not hold a launch's tail.
+constexpr int TILT_PARTS_MAX = 8;
 
 static __device__ __forceinline__ bool finite_t(float v) { return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u; }
 static __device__ __forceinline__ double frac_t(double v) { return v - floor(v); }
@@ -237,7 +242,8 @@ __host__ __device__ constexpr int tilt_waves(int c) { return c <= 1 ? 4 : (c <= 
 template <int C>
 __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k, const TRec *__restrict__ rec,
                                                            const int2 *__restrict__ rect, int64_t n,
-                                                           float2 *__restrict__ spectrum, int n_queue,
+                                                           float2 *__restrict__ spectrum,
+                                                           float2 *__restrict__ partial, int n_queue, int nparts,
                                                            long long *__restrict__ counters)
 {
     constexpr int TE = te_floats(C);
@@ -265,9 +271,15 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
         const int q = s_tile;
         __syncthreads();
         if (q >= n_queue) break;
+        // item q: part q % nparts of the Gaussians (input order) on tile q / nparts of the ring;
+        // with several parts each writes its own partial spectrum of the tile
+        const int qt = q / nparts, qp = q - qt * nparts;
         int tx, ty;
-        ring_tile(q, &tx, &ty);
+        ring_tile(qt, &tx, &ty);
         if (tx * TT >= hx || (tx + 1) * TT <= -hx || ty * TT >= hy || (ty + 1) * TT <= -hy) continue;
+        const int64_t g_lo = n * qp / nparts, g_hi = n * (qp + 1) / nparts;
+        float2 *__restrict__ dst =
+            nparts > 1 ? partial + (int64_t)qp * C * k.ny * k.nx : spectrum;
         // this wavefront's 16 x 16 sub-tile and its per-lane tables
         const int sx0 = tx * TT + (wave & 1) * 16, sy0 = ty * TT + (wave >> 1) * 16;
         const int cx = sx0 + 8, cy = sy0 + 8;
@@ -318,10 +330,10 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
         const int rlo = max(sy0, -hy), rhi = min(sy0 + 15, hy - 1);
         const bool wave_live = (max(sx0, -hx) <= min(sx0 + 15, hx - 1)) && (rlo <= rhi);
 
-        for (int64_t base = 0; base < n; base += TWG) {
+        for (int64_t base = g_lo; base < g_hi; base += TWG) {
             const int64_t gi = base + tid;
             bool pred = false;
-            if (gi < n) {
+            if (gi < g_hi) {
                 const int2 b = rect[gi];
                 const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
                 const int ty0 = (int)(int16_t)(b.y & 0xffff), ty1 = b.y >> 16;
@@ -429,7 +441,7 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
             }
             __syncthreads();
         }
-        // every frequency of the tile is written once (zeros where no Gaussian reaches)
+        // every frequency of the tile is written once per part (zeros where no Gaussian reaches)
 #pragma unroll
         for (int f = 0; f < TF; ++f) {
             const int myp = sy0 + row0 + 4 * f;
@@ -437,7 +449,7 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
                 const int mx = mxp < 0 ? mxp + k.nx : mxp, my = myp < 0 ? myp + k.ny : myp;
 #pragma unroll
                 for (int c = 0; c < C; ++c)
-                    spectrum[((int64_t)c * k.ny + my) * k.nx + mx] = make_float2(acc_re[f][c], acc_im[f][c]);
+                    dst[((int64_t)c * k.ny + my) * k.nx + mx] = make_float2(acc_re[f][c], acc_im[f][c]);
             }
         }
     }
@@ -563,7 +575,7 @@ __global__ void __launch_bounds__(TWG, tilt_adj_waves(C)) k_tilt_adjoint(Consts 
                                                                           const float2 *__restrict__ gspec,
                                                                           const int64_t *__restrict__ off,
                                                                           float *__restrict__ part, int n_queue,
-                                                                          long long *__restrict__ counters)
+                                                                          int nparts, long long *__restrict__ counters)
 {
     constexpr int NV = tilt_nv(C), NVP = tilt_nvp(C);
     __shared__ int s_idx[TWG];
@@ -591,9 +603,12 @@ __global__ void __launch_bounds__(TWG, tilt_adj_waves(C)) k_tilt_adjoint(Consts 
         const int q = s_tile;
         __syncthreads();
         if (q >= n_queue) break;
+        // item q: part q % nparts of the Gaussians (input order) on tile q / nparts of the ring
+        const int qt = q / nparts, qp = q - qt * nparts;
         int tx, ty;
-        ring_tile(q, &tx, &ty);
+        ring_tile(qt, &tx, &ty);
         if (tx * TT >= hx || (tx + 1) * TT <= -hx || ty * TT >= hy || (ty + 1) * TT <= -hy) continue;
+        const int64_t g_lo = n * qp / nparts, g_hi = n * (qp + 1) / nparts;
         const int mx0 = tx * TT, my0 = ty * TT, cx = mx0 + 16, cy = my0 + 16;
         double D0[C];
         {
@@ -668,10 +683,10 @@ __global__ void __launch_bounds__(TWG, tilt_adj_waves(C)) k_tilt_adjoint(Consts 
         const int rlo = max(my0, -hy), rhi = min(my0 + TT - 1, hy - 1);
         const int mxp = mx0 + col, myl = my0 + row0;
 
-        for (int64_t base = 0; base < n; base += TWG) {
+        for (int64_t base = g_lo; base < g_hi; base += TWG) {
             const int64_t gi = base + tid;
             bool pred = false;
-            if (gi < n) {
+            if (gi < g_hi) {
                 const int2 b = rect[gi];
                 const int tx0 = (int)(int16_t)(b.x & 0xffff), tx1 = b.x >> 16;
                 const int ty0 = (int)(int16_t)(b.y & 0xffff), ty1 = b.y >> 16;
@@ -987,9 +1002,13 @@ static hipError_t launch_tilt_adjoint_c(const Consts &k, const TRec *rec, const 
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_tilt_adjoint<C>, TWG, 0) != hipSuccess ||
         nb < 1)
         nb = 1;
-    const int nq = tilt_queue_len(k.nx, k.ny);
+    // each tile's Gaussians split into parts taken as separate items (each (Gaussian, tile) slot
+    // is still written once), so the tiles every support crowds do not hold the launch's tail
+    const int nparts = tilt_parts(n);
+    const int nq = tilt_queue_len(k.nx, k.ny) * nparts;
     const int grid = std::max(1, std::min(n_cu * nb, nq));
-    hipLaunchKernelGGL(k_tilt_adjoint<C>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, gspec, off, part, nq, counters);
+    hipLaunchKernelGGL(k_tilt_adjoint<C>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, gspec, off, part, nq, nparts,
+                       counters);
     return hipGetLastError();
 }
 
@@ -1044,8 +1063,25 @@ static int tilt_queue_len(int nx, int ny)
 template <int C>
 static const void *tilt_kernel() { return (const void *)k_tilt_accumulate<C>; }
 
+// The parts' partial spectra added in part order (fixed, so the result is reproducible).
+__global__ void __launch_bounds__(256) k_tilt_sum_parts(const float2 *__restrict__ partial, int nparts, int64_t m,
+                                                        float2 *__restrict__ spectrum)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        float2 a = partial[i];
+        for (int p = 1; p < nparts; ++p) {
+            const float2 b = partial[(int64_t)p * m + i];
+            a.x += b.x;
+            a.y += b.y;
+        }
+        spectrum[i] = a;
+    }
+}
+
+int tilt_parts(int64_t n) { return (int)std::min<int64_t>(TILT_PARTS_MAX, std::max<int64_t>(1, n / 8192)); }
+
 hipError_t launch_tilt_accumulate(const Consts &k, const TRec *rec, const int2 *rect, int64_t n, float2 *spectrum,
-                                  long long *counters, int n_cu, hipStream_t s)
+                                  float2 *partial, long long *counters, int n_cu, hipStream_t s)
 {
     const void *kp = nullptr;
     switch (k.C) {
@@ -1057,13 +1093,20 @@ hipError_t launch_tilt_accumulate(const Consts &k, const TRec *rec, const int2 *
     }
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, TWG, 0) != hipSuccess || nb < 1) nb = 1;
-    const int nq = tilt_queue_len(k.nx, k.ny);
+    const int np = tilt_parts(n);
+    if (np > 1 && !partial) return hipErrorInvalidValue;
+    const int nq = tilt_queue_len(k.nx, k.ny) * np;
     const int grid = std::max(1, std::min(n_cu * nb, nq));
     switch (k.C) {
-    case 1: hipLaunchKernelGGL(k_tilt_accumulate<1>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
-    case 2: hipLaunchKernelGGL(k_tilt_accumulate<2>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
-    case 3: hipLaunchKernelGGL(k_tilt_accumulate<3>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
-    default: hipLaunchKernelGGL(k_tilt_accumulate<4>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, nq, counters); break;
+    case 1: hipLaunchKernelGGL(k_tilt_accumulate<1>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, partial, nq, np, counters); break;
+    case 2: hipLaunchKernelGGL(k_tilt_accumulate<2>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, partial, nq, np, counters); break;
+    case 3: hipLaunchKernelGGL(k_tilt_accumulate<3>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, partial, nq, np, counters); break;
+    default: hipLaunchKernelGGL(k_tilt_accumulate<4>, dim3(grid), dim3(TWG), 0, s, k, rec, rect, n, spectrum, partial, nq, np, counters); break;
+    }
+    if (np > 1) {
+        const int64_t m = (int64_t)k.C * k.ny * k.nx;
+        const int blocks = (int)std::min<int64_t>((m + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_tilt_sum_parts, dim3(blocks), dim3(256), 0, s, (const float2 *)partial, np, m, spectrum);
     }
     return hipGetLastError();
 }

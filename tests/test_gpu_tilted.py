@@ -44,6 +44,7 @@ CASES = [
     (128, 96, 1e-6, (520e-9, 450e-9), 120, 904, (1.0, 4.0), 25.0),
     (64, 72, 0.25e-6, (633e-9,), 80, 905, (2.0, 6.0), 28.0),   # band past 1/lambda: evanescent corners
     (64, 48, 8e-6, FOUR, 60, 906, (2.0, 20.0), 2.0),             # four wavelengths (the problem's maximum)
+    (64, 48, 8e-6, (520e-9,), 20000, 907, (2.0, 20.0), 2.0),     # tiles' Gaussians in two parts
 ]
 
 
@@ -171,6 +172,9 @@ def test_tilted_workload_100k_sampled(ctx):
     log("tilted 100k sampled spectrum: rel L2 %.3e" % e)
     assert e < TOL
     assert np.all(np.isfinite(to_numpy(u)))
+    # eight parts per tile, added in part order: the same field again, bit for bit
+    u2 = ctx.forward_tilted(problem(grid), scene_to_torch(scene))
+    assert np.array_equal(to_numpy(u), to_numpy(u2))
 
 
 # ---- adjoint -------------------------------------------------------------------------------
