@@ -468,8 +468,8 @@ __global__ void __launch_bounds__(TWG, tilt_waves(C)) k_tilt_accumulate(Consts k
 //   SN_j = sum x_j Re rho / w,         x = (m_x, m_y, k_z)
 // carry the whole gradient (chain rule in k_tilt_grad_final).
 //
-// The kernel walks the forward's tiles with the work split the other way: the work-group builds
-// the tile's per-frequency tables once in LDS (per wavelength D_c(m) - D_c(m0), log2 of
+// The kernel walks the forward's (tile, part of the Gaussians) items with the work split the
+// other way: the work-group builds the tile's per-frequency tables in LDS (per wavelength D_c(m) - D_c(m0), log2 of
 // |Gs_c| 2^-e_t / (k_z lambda_c) with 2^e_t the tile's scale of |Gs|, arg Gs_c / 2 pi and k_z),
 // and each wavefront takes whole staged
 // Gaussians over the 32 x 32 tile (lane l: column l % 32 and rows l / 32 + 2 f, f < 16), so a
