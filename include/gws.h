@@ -102,7 +102,10 @@ typedef struct gws_problem {
                                   accumulation F, tile 32 x 8F; base chunk of candidates per
                                   work item) from {(4,512),(4,1024),(8,1024),(8,512),(2,1024),
                                   (4,2048),(2,512),(2,2048),(8,2048)}; the default is 2 =
-                                  (4,1024).  The order-invariant adjoint's geometry is fixed. */
+                                  (4,1024).  The chunk is capped at n / 16 (at least 128) for
+                                  each scene of n Gaussians, so a small scene's crowded tiles
+                                  still split into several work items.  The order-invariant
+                                  adjoint's geometry is fixed. */
     double ref_nu_x, ref_nu_y; /* transverse frequency (cycles per metre) of the reference plane
                                   wave that illuminates every Gaussian (Sec. 4.1): each
                                   Gaussian's wavefront is multiplied by exp(+j 2 pi nu_r . x), x

@@ -813,8 +813,11 @@ static gws_status forward_run(gws_ctx *ctx, const gws_problem *prob, int S, cons
             uint32_t *vals = nullptr;
             st = run_prep(ctx, k, scene_view(g, offsets[i], BL.n[i]), L, B, s, &keys, &vals);
             if (st != GWS_OK) return st;
+            // the configuration's chunk of candidates per work item, capped at n / 16 (at least 128)
+            // so that a small scene's crowded tiles still split into several items
+            const int chunk = (int)std::min<int64_t>(kTileCfg[cfg - 1][1], std::max<int64_t>(128, BL.n[i] / 16));
             HIP_CHECK(ctx, launch_bin_forward(*p, B.bucket_hist, B.cum, B.tile_L, B.tile_slots, B.items, L.max_items,
-                                              L.max_slots, kTileCfg[cfg - 1][1], B.counters, s));
+                                              L.max_slots, chunk, B.counters, s));
             tab.s[i] = FwdScene{B.rec, B.tile_L, B.items, B.tile_slots, B.partials, spectra + (int64_t)i * CM, B.counters};
             ctrs[i] = B.counters;
         }
