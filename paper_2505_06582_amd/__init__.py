@@ -435,13 +435,13 @@ class Context:
         torch = _torch()
         n = check_gaussians(g, prob.n_lambda, TILTED_PARAMS)
         check_tensor(grad_field, "grad_field", (prob.n_lambda, prob.ny, prob.nx), "complex64")
-        gs = _tilted_struct(g, prob.n_lambda)
         grads = dict(out) if out is not None else {}
-        for k in TILTED_PARAMS:
+        for k in TILTED_PARAMS:   # every size checked before any address is taken
             if grads.get(k) is None:
                 grads[k] = torch.empty_like(g[k])
             elif n > 0:
                 check_tensor(grads[k], "grad " + k, tuple(g[k].shape), "float32")
+        gs = _tilted_struct(g, prob.n_lambda)
         gr = _TiltedGrads()
         for k in TILTED_PARAMS:
             setattr(gr, k, _dptr(grads[k]) if n > 0 else None)

@@ -140,3 +140,39 @@ def test_render_refuses_four_wavelength_depth_gradient_at_forward_time():
     p = lambda: torch.zeros(3, requires_grad=True)
     with pytest.raises(ValueError, match="depth gradient"):
         gws.render(prob, p(), p(), p(), p(), p(), p(), p(), torch.zeros(4, 3, requires_grad=True), p())
+
+
+def test_tilted_calls_reject_bad_sizes_before_the_library():
+    grid = gwsgen.Grid(32, 16, 8e-6, 8e-6, gwsgen.RGB)
+    sc = gwsgen.make_tilted_scene(5, grid, 4)
+    g = {k: torch.from_numpy(np.ascontiguousarray(v)) for k, v in sc.fields().items()}
+    prob = gws.Problem.from_grid(grid)
+    ctx = shell()
+    bad = dict(g)
+    bad["quat_z"] = torch.zeros(4)
+    with pytest.raises(ValueError, match="quat_z"):
+        ctx.forward_tilted(prob, bad)
+    missing = {k: v for k, v in g.items() if k != "scale_v"}
+    with pytest.raises(ValueError, match="scale_v"):
+        ctx.forward_tilted(prob, missing)
+    with pytest.raises(ValueError, match="out"):
+        ctx.forward_tilted(prob, g, out=torch.zeros((3, grid.ny, grid.nx + 2), dtype=torch.complex64))
+    with pytest.raises(ValueError, match="grad_field"):
+        ctx.backward_tilted(prob, g, torch.zeros((2, grid.ny, grid.nx), dtype=torch.complex64))
+    G = torch.zeros((3, grid.ny, grid.nx), dtype=torch.complex64)
+    out = {k: torch.zeros_like(v) for k, v in g.items()}
+    out["amplitude"] = torch.zeros(5)
+    with pytest.raises(ValueError, match="amplitude"):
+        ctx.backward_tilted(prob, g, G, out=out)
+    with pytest.raises(ValueError, match="CUDA"):
+        ctx.forward_tilted(prob, g)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr)
