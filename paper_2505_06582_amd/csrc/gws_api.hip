@@ -355,7 +355,7 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd,
     const int ntiles = ntiles_for(p->nx, p->ny, 2);
     L.n = n;
     L.F = f_fwd;
-    L.sort_blocks = (int)std::max<int64_t>(1, (n + 4095) / 4096);
+    L.sort_blocks = sort_blocks_for(n);
     const size_t part_bytes = (size_t)fwd_max_slots_f4(n) * C * 4 * WG * sizeof(float2);
     L.max_slots = (int64_t)(part_bytes / ((size_t)C * f_fwd * WG * sizeof(float2)));
     L.max_items = L.max_slots / 2 + ntiles + 1;
@@ -469,7 +469,7 @@ static ExactLayout exact_layout(const gws_problem *p, int64_t n)
 {
     ExactLayout L;
     const size_t M = (size_t)p->nx * p->ny;
-    L.sort_blocks = (int)std::max<int64_t>(1, (n + 4095) / 4096);
+    L.sort_blocks = sort_blocks_for(n);
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
     L.off_keys_a = take(sizeof(uint64_t) * n);

@@ -392,6 +392,8 @@ enum Counter {
 // ---- kernel launchers (each enqueues on `stream`, returns hipError_t) ----
 hipError_t launch_keys(const GView &g, const Consts &k, uint64_t *keys, uint32_t *vals,
                        uint32_t *bucket_hist, long long *counters, hipStream_t s);
+// Blocks (and 256-entry histograms) radix_sort_48 uses for n keys.
+int sort_blocks_for(int64_t n);
 hipError_t radix_sort_48(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b,
                          uint32_t *block_hist, int64_t n, int nblocks, hipStream_t s,
                          uint64_t **keys_out, uint32_t **vals_out);

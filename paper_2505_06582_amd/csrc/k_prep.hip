@@ -73,15 +73,22 @@ hipError_t launch_keys(const GView &g, const Consts &k, uint64_t *keys, uint32_t
 }
 
 // ---------------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits.  Each block owns SORT_TILE consecutive keys.
+// Stable LSD radix sort, 8-bit digits.  Each block owns ITEMS x 256 consecutive keys: 16 per
+// thread, or 4 for up to 32768 keys, where more, shorter blocks finish each pass sooner.
 // ---------------------------------------------------------------------------------
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+static int sort_items(int64_t n) { return n <= 32768 ? 4 : 16; }
+int sort_blocks_for(int64_t n)
+{
+    const int64_t tile = (int64_t)SORT_THREADS * sort_items(n);
+    return (int)std::max<int64_t>(1, (n + tile - 1) / tile);
+}
 
+template <int ITEMS>
 __global__ void __launch_bounds__(SORT_THREADS) k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
                                                             uint32_t *__restrict__ block_hist, int nblocks)
 {
+    constexpr int SORT_ITEMS = ITEMS, SORT_TILE = SORT_THREADS * ITEMS;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -118,6 +125,7 @@ __global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *__restrict__ block
     }
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(SORT_THREADS) k_sort_scatter(const uint64_t *__restrict__ keys_in,
                                                                const uint32_t *__restrict__ vals_in,
                                                                uint64_t *__restrict__ keys_out,
@@ -125,6 +133,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_sort_scatter(const uint64_t *_
                                                                int shift, const uint32_t *__restrict__ block_hist,
                                                                int nblocks)
 {
+    constexpr int SORT_ITEMS = ITEMS, SORT_TILE = SORT_THREADS * ITEMS;
     __shared__ uint32_t run[256];          // running output offset per digit for this block
     __shared__ uint32_t wave_cnt[SORT_THREADS / 64][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -174,12 +183,23 @@ hipError_t radix_sort_48(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, u
     uint64_t *ki = keys_a, *ko = keys_b;
     uint32_t *vi = vals_a, *vo = vals_b;
     if (n > 0) {
+        if (nblocks != sort_blocks_for(n)) return hipErrorInvalidValue;   // the caller's histogram area
+        const bool small = sort_items(n) == 4;
         for (int pass = 0; pass < 6; ++pass) {
             const int shift = 8 * pass;
-            hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, ki, n, shift, block_hist, nblocks);
+            if (small)
+                hipLaunchKernelGGL(k_sort_hist<4>, dim3(nblocks), dim3(SORT_THREADS), 0, s, ki, n, shift, block_hist,
+                                   nblocks);
+            else
+                hipLaunchKernelGGL(k_sort_hist<16>, dim3(nblocks), dim3(SORT_THREADS), 0, s, ki, n, shift, block_hist,
+                                   nblocks);
             hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, block_hist, 256 * nblocks);
-            hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
-                               block_hist, nblocks);
+            if (small)
+                hipLaunchKernelGGL(k_sort_scatter<4>, dim3(nblocks), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
+                                   block_hist, nblocks);
+            else
+                hipLaunchKernelGGL(k_sort_scatter<16>, dim3(nblocks), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n,
+                                   shift, block_hist, nblocks);
             uint64_t *tk = ki; ki = ko; ko = tk;
             uint32_t *tv = vi; vi = vo; vo = tv;
         }
