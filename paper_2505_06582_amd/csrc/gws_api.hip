@@ -365,7 +365,7 @@ static Layout make_layout(const gws_problem *p, int64_t n, int f_fwd, int f_bwd,
     // DC) do not leave the launch's tail to a few work-groups, for small scenes as for large
     // (1k Gaussians at 1080 x 1920 x 3: fwd+bwd 4.2 -> 1.8 ms; 100k: 21.1 -> 20.7 ms)
     const int64_t nchunks = (n + ADJ_MIN_CHUNK - 1) / ADJ_MIN_CHUNK;
-    L.max_bitems = nchunks + 8192;
+    L.max_bitems = nchunks + std::min<int64_t>(8192, nchunks * ntiles);   // no more items than (chunk, tile) pairs
     L.max_bslots = L.max_bitems;
     const int hx = p->nx / 2, hy = p->ny / 2, SY = sub_h(f_bwd);
     L.sx_min = floor_div(-hx, SUBX);
