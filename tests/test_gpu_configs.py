@@ -57,6 +57,40 @@ def test_fwd10k_full_scene_sampled_by_band(ctx):
     check_spectrum_and_transform(scene, grid, to_numpy(field), to_numpy(spec), 1024, 21, "fwd10k")
 
 
+def test_autotune_at_full_size(tmp_path):
+    """The autotuner at 1080 x 1920 x 3 with the 10k workload: it records its timings under this
+    grid's key, a new context takes the recorded choice from the cache file, the forward under
+    that choice meets the oracle on band-sampled spectrum entries, and both contexts give the
+    same field bit for bit."""
+    import os
+    import paper_2505_06582_amd as gws
+    scene, grid = gwsgen.workload("fwd10k")
+    prob = problem(grid)
+    cache = str(tmp_path / "tune.jsonl")
+    t = gws.Context(0)
+    try:
+        t.autotune(prob, scene.n, cache)
+        text = open(cache).read()
+        log("autotune at 1080x1920x3, 10k Gaussians: %s" % text.strip()[-300:])
+        assert '"nx": 1920' in text and '"ny": 1080' in text and '"tile_config"' in text
+        g = scene_to_torch(scene)
+        field, spec = t.forward(prob, g, want_spectrum=True)
+        cfg = t.stats()["tile_config"]
+        assert 1 <= cfg <= 9
+        check_spectrum_and_transform(scene, grid, to_numpy(field), to_numpy(spec), 512, 23, "fwd10k tuned")
+        os.environ["GWS_TUNE_CACHE"] = cache
+        try:
+            c2 = gws.Context(0)
+            f2 = c2.forward(prob, g)
+            assert c2.stats()["tile_config"] == cfg
+            assert np.array_equal(to_numpy(f2), to_numpy(field))
+            c2.close()
+        finally:
+            del os.environ["GWS_TUNE_CACHE"]
+    finally:
+        t.close()
+
+
 @pytest.fixture(scope="module")
 def batched16():
     counts = gwsgen.batched_counts(16)
